@@ -1,0 +1,277 @@
+/*
+ * hc.h -- C ABI of the Hadamard-code light-path library (gfx950 / MI355X).
+ *
+ * Spectral rendering multiplies n-sample spectra element-wise along light
+ * paths and integrates the result against colour-matching functions.  The
+ * Hadamard-code method (Yu, Guarnera, Guarnera, "Compact Hadamard Latent
+ * Codes for Efficient Spectral Rendering", arXiv 2602.18741) replaces the
+ * n samples by k = 3B non-negative linear codes z = W_enc s (Eq. 4), takes
+ * the element-wise product block by block on B RGB-style triplets (Eq. 6),
+ * and decodes once per frame with W_dec and the colour-matching matrix.
+ * This library evaluates both forms for batches of light paths on one GPU.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns hc_status.  HC_OK (0) means the work was enqueued.
+ *   On any other status nothing was enqueued and hc_last_error() returns a
+ *   thread-local description of the first problem found.
+ * - Pointers are device pointers unless stated otherwise.  The caller owns
+ *   and allocates every buffer; the library never allocates, frees or keeps a
+ *   pointer past the return of the call.  Scratch memory is passed in as an
+ *   explicit workspace.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  The
+ *   calls only enqueue work on it; there is no implicit synchronisation.
+ *   Faults inside kernels surface at the caller's next synchronisation.
+ * - float4 data (spectra rows, code rows, latent images) needs 16-byte aligned
+ *   base pointers and row strides (ld) that are multiples of 4 floats.
+ * - Latent rows use the blocked "RGBx" layout: code channel c lives at float
+ *   offset 4*(c/3) + c%3 of its row, so block b (channels 3b..3b+2, one RGB
+ *   pass of Sec. 6.1) is the 16-byte slot [4b, 4b+4) and its 4th float is 0.
+ *   A row of a k-channel code therefore needs ld >= 4*ceil(k/3) floats.  A k
+ *   that is not a multiple of 3 is treated as k padded with zero channels.
+ * - Limits: 1 <= n <= 128 spectral samples, 1 <= k <= 48 code channels,
+ *   spp >= 1, path length 0..255, light id < 2^24, fewer than 2^32 vertex
+ *   records and texels per call.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hc_status;
+#define HC_OK 0
+#define HC_EINVAL 1       /* null pointer or invalid scalar argument */
+#define HC_ESHAPE 2       /* sizes or strides out of the supported range */
+#define HC_EALIGN 3       /* pointer or stride misaligned */
+#define HC_ENOMEM 4       /* workspace too small */
+#define HC_EDEVICE 5      /* a HIP call or kernel launch failed */
+#define HC_EUNSUPPORTED 6 /* valid request that this build does not handle */
+
+/* Name of a status code ("HC_OK", ...).  Static string, never NULL. */
+const char* hc_status_string(hc_status s);
+/* Description of the last error on the calling thread ("" if none).  Valid
+ * until the next hc_* call on the same thread. */
+const char* hc_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t hc_version(void);
+
+/*
+ * Light-path records (a host struct holding device pointers).
+ * Paths are pixel-major: pixel q owns paths [q*spp, (q+1)*spp).
+ *   hdr[p]        uint32: light id in bits 0-23, number of reflectance
+ *                 vertices L_p (0..255) in bits 24-31.  L_p = 0 means the
+ *                 path sees the light directly.
+ *   pix_first[q]  uint32: index of pixel q's first vertex record.  A pixel's
+ *                 paths store their vertices back to back, in path order.
+ *   vtx[2*j]      uint32 texel (or material) index of vertex record j,
+ *   vtx[2*j+1]    IEEE-754 bits of its float32 weight.  8-byte aligned.
+ * Records outside the assets (texel >= n_texels, light >= n_illum, or a
+ * pixel whose records run past n_vertices) are clamped to the last valid
+ * index so that no read leaves the buffers; the value computed for such a
+ * pixel is unspecified.  hc_check_paths detects them.
+ */
+typedef struct hc_paths {
+    int64_t n_pixels;
+    int32_t spp;
+    int32_t reserved0;
+    const uint32_t* hdr;
+    const uint32_t* pix_first;
+    const uint32_t* vtx;
+    int64_t n_vertices;
+} hc_paths;
+
+/* Spectral assets: reflectance rows refl[t*ld + i] (n_texels x n, i < n) and
+ * light rows illum[l*ld_illum + i] (n_illum x n).  float32, 16-byte aligned,
+ * ld and ld_illum multiples of 4 and >= n. */
+typedef struct hc_spectral_assets {
+    const float* refl;
+    int64_t n_texels;
+    int32_t n;
+    int32_t reserved0;
+    int64_t ld;
+    const float* illum;
+    int32_t n_illum;
+    int32_t reserved1;
+    int64_t ld_illum;
+} hc_spectral_assets;
+
+/* Latent assets: encoded texels codes[t*ld + ...] and encoded lights
+ * illum_codes[l*ld_illum + ...] in the blocked RGBx layout, k channels. */
+typedef struct hc_latent_assets {
+    const float* codes;
+    int64_t n_texels;
+    int32_t k;
+    int32_t reserved0;
+    int64_t ld;
+    const float* illum_codes;
+    int32_t n_illum;
+    int32_t reserved1;
+    int64_t ld_illum;
+} hc_latent_assets;
+
+/*
+ * hc_encode -- linear encoder z = W_enc s of Eq. 4, applied to m spectra.
+ *   E  : k x n row-major float32 (W_enc, non-negative in the method).
+ *   S  : m rows of n float32 samples, row stride ld_s floats.
+ *   Z  : m latent rows (blocked RGBx layout), row stride ld_z >= 4*ceil(k/3).
+ *        Every float of Z[i, 0:ld_z) is written; pad positions get 0.
+ * Used once per asset (textures, materials and lights are encoded once,
+ * Fig. 2b).
+ */
+hc_status hc_encode(const float* E, int32_t k, int32_t n, const float* S, int64_t m,
+                    int64_t ld_s, float* Z, int64_t ld_z, void* stream);
+
+/*
+ * hc_shade_spectral -- plain spectral form.  For each path p of pixel q:
+ *   S_p = light_{id_p} * prod_{v < L_p} (w_{p,v} * refl_{t_{p,v}})   (element-wise
+ *   products over n samples: the scale and multiply operations of Sec. 3),
+ *   x_p = T S_p (T = T_cmf, 3 x n row-major float32, quadrature folded in),
+ *   xyz[q] = (1/spp) sum_{p in q} x_p.
+ *   xyz: n_pixels x 3 float32, contiguous.
+ */
+hc_status hc_shade_spectral(const hc_paths* paths, const hc_spectral_assets* assets,
+                            const float* T, float* xyz, void* stream);
+
+/*
+ * hc_shade_latent -- latent form (Eq. 6 blockwise products, Sec. 6.1 passes).
+ * For each path p of pixel q and code block b in [block_first,
+ * block_first + block_count):
+ *   Z_p^(b) = code(light_{id_p})^(b) (.) prod_{v < L_p} (w_{p,v} * code(t_{p,v})^(b)),
+ *   zimg[q]^(b) = (1/spp) sum_{p in q} Z_p^(b)
+ * written to the 16-byte slot b of row q of zimg (row stride ld_zimg floats;
+ * the slot's 4th float is written 0; other slots are untouched).
+ * block_count = ceil(k/3) with block_first = 0 is the fused call; a call per
+ * block is one "RGB pass", and the passes re-assemble into the same image.
+ * Each channel's arithmetic does not depend on the blocks in the call, so
+ * fused and per-pass images are bitwise equal.
+ */
+hc_status hc_shade_latent(const hc_paths* paths, const hc_latent_assets* assets,
+                          int32_t block_first, int32_t block_count, float* zimg,
+                          int64_t ld_zimg, void* stream);
+
+/*
+ * hc_decode_xyz -- decode a latent image once per frame (Eq. 4, right; Fig. 2b).
+ *   D: n x k row-major float32 (W_dec).  T: 3 x n row-major float32.
+ *   zimg: n_pixels latent rows (blocked layout), stride ld_zimg.
+ *   xyz[q] = T (D z_q), n_pixels x 3 contiguous float32.
+ *   spectra (nullable): spectra[q*ld_spectra + i] = (D z_q)_i for i < n;
+ *   ld_spectra >= n (any alignment of 4 bytes).
+ */
+hc_status hc_decode_xyz(const float* D, int32_t n, int32_t k, const float* T,
+                        const float* zimg, int64_t n_pixels, int64_t ld_zimg, float* xyz,
+                        float* spectra, int64_t ld_spectra, void* stream);
+
+/*
+ * hc_check_paths -- count invalid records (see hc_paths).
+ *   counts: 3 device uint64: [0] paths whose light id >= n_illum,
+ *   [1] vertex records (counted once per pixel range covering them) whose
+ *   texel >= n_texels, [2] pixels whose records run past n_vertices (their
+ *   vertices are not examined).  The call overwrites counts.
+ */
+hc_status hc_check_paths(const hc_paths* paths, int64_t n_texels, int32_t n_illum,
+                         uint64_t* counts, void* stream);
+
+/*
+ * Codec fitting (Sec. 4.3 objectives with softplus weights, Eq. 5).
+ *
+ * Parameters Wt_E (k x n) and Wt_D (n x k), row-major; the codec is
+ * E = softplus_beta(Wt_E), D = softplus_beta(Wt_D).  On a batch of N pairs
+ * (a_i, b_i) the loss is
+ *   L = (1/N) sum_i ( |D E a_i - a_i|^2 + |D E b_i - b_i|^2
+ *                     + lambda |D (E a_i (.) E b_i) - a_i * b_i|^2 ),
+ * the reconstruction term L_rec plus lambda times the squared-error part of
+ * L_e2e.  The call writes L and, if requested, dL/dWt_E and dL/dWt_D
+ * (hand-derived backward), and optionally applies one Adam step.
+ *
+ * dtype: 0 = float32 everywhere, 1 = float64 everywhere (parameters, data,
+ * outputs, Adam state).  Partial sums are accumulated in float64 and reduced
+ * in a fixed order, so results are deterministic.
+ * Batch rows: row i of the a-batch is A[idx_a[i]*ld_a ...] when idx_a is
+ * not NULL, else A[i*ld_a ...]; likewise b.  Indices must be < rows_a
+ * (rows_b); out-of-range indices are clamped.
+ */
+typedef struct hc_adam {
+    void* m_E;          /* k x n first moments (dtype) */
+    void* v_E;          /* k x n second moments */
+    void* m_D;          /* n x k */
+    void* v_D;
+    int64_t* step;      /* device counter: steps taken; incremented by the call */
+    double lr, beta1, beta2, eps;
+} hc_adam;
+
+typedef struct hc_codec_args {
+    int32_t k, n;
+    int32_t dtype;
+    int32_t reserved0;
+    double beta;        /* softplus sharpness (10 in the paper) */
+    double lambda;      /* weight of the product term */
+    void* Wt_E;         /* updated in place when adam != NULL */
+    void* Wt_D;
+    const void* A;
+    const void* B;
+    int64_t ld_a, ld_b; /* row strides in elements */
+    int64_t rows_a, rows_b;
+    const uint32_t* idx_a;  /* nullable */
+    const uint32_t* idx_b;  /* nullable */
+    int64_t N;          /* batch size, >= 1 */
+    void* loss;         /* device scalar (dtype) */
+    void* grad_E;       /* nullable, k x n */
+    void* grad_D;       /* nullable, n x k */
+    const hc_adam* adam;    /* host pointer, nullable */
+    void* workspace;
+    size_t workspace_bytes;
+    void* stream;
+} hc_codec_args;
+
+/* Bytes of workspace hc_codec_step needs for this shape (8-byte aligned). */
+size_t hc_codec_workspace_size(int32_t k, int32_t n, int64_t N);
+hc_status hc_codec_step(const hc_codec_args* args);
+
+/* E = softplus_beta(Wt_E), D = softplus_beta(Wt_D) as float32 (Eq. 5); the
+ * matrices hc_encode and hc_decode_xyz take.  dtype of Wt_* as above. */
+hc_status hc_codec_weights(const void* Wt_E, const void* Wt_D, int32_t k, int32_t n,
+                           int32_t dtype, double beta, float* E, float* D, void* stream);
+
+/*
+ * Synthetic light-path generator (workload input, not part of the method).
+ * Draws come from SplitMix64's output function mix64 applied to
+ * key + (counter + 1) * 0x9E3779B97F4A7C15 with key = mix64(mix64(seed) + stream):
+ *   path p (stream 1): r = rand(p); L = l_min + ((r & 0xFFFFFFFF) * (l_max-l_min+1) >> 32);
+ *                      light = (r >> 32) * n_illum >> 32
+ *   vertex v of path p (stream 2): r = rand(p*256 + v);
+ *                      texel = (r & 0xFFFFFFFF) * n_tex >> 32; weight = (r >> 40) * 2^-24
+ * Two steps: hc_gen_path_headers writes hdr, pix_first and the total vertex
+ * count (device uint64); the caller reads the total, allocates vtx and calls
+ * hc_gen_path_vertices.  workspace: hc_gen_workspace_size(n_pixels) bytes.
+ */
+typedef struct hc_path_gen {
+    int64_t n_pixels;
+    int32_t spp;
+    int32_t l_min, l_max;
+    int32_t n_illum;
+    int64_t n_tex;
+    uint64_t seed;
+} hc_path_gen;
+
+size_t hc_gen_workspace_size(int64_t n_pixels);
+hc_status hc_gen_path_headers(const hc_path_gen* g, uint32_t* hdr, uint32_t* pix_first,
+                              uint64_t* n_vertices, void* workspace, size_t workspace_bytes,
+                              void* stream);
+hc_status hc_gen_path_vertices(const hc_path_gen* g, const uint32_t* pix_first, uint32_t* vtx,
+                               int64_t n_vertices, void* stream);
+/* count indices uniform in [0, n) at counters ctr0 + i of stream 3 of seed;
+ * if ctr_scale_dev is not NULL the counter base is ctr0 + (*ctr_scale_dev) * count
+ * (a device step counter, so a captured graph draws new indices per replay). */
+hc_status hc_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* ctr_scale_dev,
+                         int64_t count, int64_t n, uint32_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HC_H */

@@ -1,0 +1,304 @@
+// C ABI entry points: argument validation, then the launchers.
+// Nothing is enqueued unless every check passes.
+
+#include <cstdarg>
+#include <cstring>
+
+#include "hc_internal.hpp"
+
+namespace hc {
+
+static thread_local char g_err[512];
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+hc_status launch_status(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s: launch failed: %s", what, hipGetErrorString(e));
+        return HC_EDEVICE;
+    }
+    return HC_OK;
+}
+
+}  // namespace hc
+
+using namespace hc;
+
+#define HC_REQUIRE(cond, code, ...)  \
+    do {                             \
+        if (!(cond)) {               \
+            set_error(__VA_ARGS__);  \
+            return (code);           \
+        }                            \
+    } while (0)
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+hc_status check_paths_struct(const hc_paths* P, const char* fn) {
+    HC_REQUIRE(P != nullptr, HC_EINVAL, "%s: paths is NULL", fn);
+    HC_REQUIRE(P->n_pixels >= 0, HC_ESHAPE, "%s: n_pixels < 0", fn);
+    HC_REQUIRE(P->spp >= 1, HC_ESHAPE, "%s: spp must be >= 1 (got %d)", fn, P->spp);
+    HC_REQUIRE(P->n_vertices >= 0 && P->n_vertices < (int64_t(1) << 32), HC_ESHAPE,
+               "%s: n_vertices must be in [0, 2^32)", fn);
+    HC_REQUIRE(P->n_pixels <= (int64_t(1) << 40) / P->spp, HC_ESHAPE, "%s: too many paths", fn);
+    if (P->n_pixels > 0) {
+        HC_REQUIRE(P->hdr && P->pix_first, HC_EINVAL, "%s: hdr/pix_first is NULL", fn);
+        HC_REQUIRE(aligned4(P->hdr) && aligned4(P->pix_first), HC_EALIGN,
+                   "%s: hdr/pix_first must be 4-byte aligned", fn);
+    }
+    if (P->n_vertices > 0) {
+        HC_REQUIRE(P->vtx != nullptr, HC_EINVAL, "%s: vtx is NULL", fn);
+        HC_REQUIRE(aligned8(P->vtx), HC_EALIGN, "%s: vtx must be 8-byte aligned", fn);
+    }
+    return HC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hc_status_string(hc_status s) {
+    switch (s) {
+        case HC_OK: return "HC_OK";
+        case HC_EINVAL: return "HC_EINVAL";
+        case HC_ESHAPE: return "HC_ESHAPE";
+        case HC_EALIGN: return "HC_EALIGN";
+        case HC_ENOMEM: return "HC_ENOMEM";
+        case HC_EDEVICE: return "HC_EDEVICE";
+        case HC_EUNSUPPORTED: return "HC_EUNSUPPORTED";
+        default: return "HC_UNKNOWN";
+    }
+}
+
+const char* hc_last_error(void) { return g_err; }
+
+int32_t hc_version(void) { return 100; }
+
+hc_status hc_encode(const float* E, int32_t k, int32_t n, const float* S, int64_t m, int64_t ld_s,
+                    float* Z, int64_t ld_z, void* stream) {
+    clear_error();
+    const char* fn = "hc_encode";
+    HC_REQUIRE(k >= 1 && k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, k, kMaxK);
+    HC_REQUIRE(n >= 1 && n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, n, kMaxN);
+    HC_REQUIRE(m >= 0 && m < (int64_t(1) << 32), HC_ESHAPE, "%s: m outside [0, 2^32)", fn);
+    const int64_t nb = ceil_div(k, 3);
+    HC_REQUIRE(ld_s >= n && ld_s % 4 == 0, HC_ESHAPE, "%s: ld_s=%lld must be >= n and a multiple of 4",
+               fn, (long long)ld_s);
+    HC_REQUIRE(ld_z >= 4 * nb && ld_z % 4 == 0, HC_ESHAPE,
+               "%s: ld_z=%lld must be >= 4*ceil(k/3)=%lld and a multiple of 4", fn, (long long)ld_z,
+               (long long)(4 * nb));
+    if (m == 0) return HC_OK;
+    HC_REQUIRE(E && S && Z, HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned4(E) && aligned16(S) && aligned16(Z), HC_EALIGN,
+               "%s: S and Z need 16-byte alignment, E 4-byte", fn);
+    return launch_encode(E, k, n, S, m, ld_s, Z, ld_z, as_stream(stream));
+}
+
+hc_status hc_shade_spectral(const hc_paths* paths, const hc_spectral_assets* A, const float* T,
+                            float* xyz, void* stream) {
+    clear_error();
+    const char* fn = "hc_shade_spectral";
+    hc_status s = check_paths_struct(paths, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(A != nullptr, HC_EINVAL, "%s: assets is NULL", fn);
+    HC_REQUIRE(A->n >= 1 && A->n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, A->n, kMaxN);
+    HC_REQUIRE(A->ld >= A->n && A->ld % 4 == 0 && A->ld_illum >= A->n && A->ld_illum % 4 == 0,
+               HC_ESHAPE, "%s: ld/ld_illum must be >= n and multiples of 4", fn);
+    HC_REQUIRE(A->n_texels >= 1 && A->n_texels < (int64_t(1) << 32), HC_ESHAPE,
+               "%s: n_texels outside [1, 2^32)", fn);
+    HC_REQUIRE(A->n_illum >= 1 && A->n_illum <= (1 << 24), HC_ESHAPE, "%s: n_illum outside [1, 2^24]",
+               fn);
+    if (paths->n_pixels == 0) return HC_OK;
+    HC_REQUIRE(A->refl && A->illum && T && xyz, HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned16(A->refl) && aligned16(A->illum), HC_EALIGN,
+               "%s: refl/illum need 16-byte alignment", fn);
+    HC_REQUIRE(aligned4(T) && aligned4(xyz), HC_EALIGN, "%s: T/xyz need 4-byte alignment", fn);
+    return launch_shade_spectral(*paths, *A, T, xyz, as_stream(stream));
+}
+
+hc_status hc_shade_latent(const hc_paths* paths, const hc_latent_assets* A, int32_t block_first,
+                          int32_t block_count, float* zimg, int64_t ld_zimg, void* stream) {
+    clear_error();
+    const char* fn = "hc_shade_latent";
+    hc_status s = check_paths_struct(paths, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(A != nullptr, HC_EINVAL, "%s: assets is NULL", fn);
+    HC_REQUIRE(A->k >= 1 && A->k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, A->k, kMaxK);
+    const int nb = int(ceil_div(A->k, 3));
+    HC_REQUIRE(block_first >= 0 && block_count >= 1 && block_first + block_count <= nb, HC_ESHAPE,
+               "%s: blocks [%d, %d) outside the code's %d blocks", fn, block_first,
+               block_first + block_count, nb);
+    HC_REQUIRE(A->ld >= 4 * nb && A->ld % 4 == 0 && A->ld_illum >= 4 * nb && A->ld_illum % 4 == 0,
+               HC_ESHAPE, "%s: ld/ld_illum must be >= 4*ceil(k/3) and multiples of 4", fn);
+    HC_REQUIRE(ld_zimg >= 4 * nb && ld_zimg % 4 == 0, HC_ESHAPE,
+               "%s: ld_zimg must be >= 4*ceil(k/3) and a multiple of 4", fn);
+    HC_REQUIRE(A->n_texels >= 1 && A->n_texels < (int64_t(1) << 32), HC_ESHAPE,
+               "%s: n_texels outside [1, 2^32)", fn);
+    HC_REQUIRE(A->n_illum >= 1 && A->n_illum <= (1 << 24), HC_ESHAPE, "%s: n_illum outside [1, 2^24]",
+               fn);
+    if (paths->n_pixels == 0) return HC_OK;
+    HC_REQUIRE(A->codes && A->illum_codes && zimg, HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned16(A->codes) && aligned16(A->illum_codes) && aligned16(zimg), HC_EALIGN,
+               "%s: codes/illum_codes/zimg need 16-byte alignment", fn);
+    return launch_shade_latent(*paths, *A, block_first, block_count, zimg, ld_zimg,
+                               as_stream(stream));
+}
+
+hc_status hc_decode_xyz(const float* D, int32_t n, int32_t k, const float* T, const float* zimg,
+                        int64_t n_pixels, int64_t ld_zimg, float* xyz, float* spectra,
+                        int64_t ld_spectra, void* stream) {
+    clear_error();
+    const char* fn = "hc_decode_xyz";
+    HC_REQUIRE(k >= 1 && k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, k, kMaxK);
+    HC_REQUIRE(n >= 1 && n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, n, kMaxN);
+    HC_REQUIRE(n_pixels >= 0 && n_pixels < (int64_t(1) << 34), HC_ESHAPE, "%s: bad n_pixels", fn);
+    const int64_t nb = ceil_div(k, 3);
+    HC_REQUIRE(ld_zimg >= 4 * nb && ld_zimg % 4 == 0, HC_ESHAPE,
+               "%s: ld_zimg must be >= 4*ceil(k/3) and a multiple of 4", fn);
+    if (spectra) HC_REQUIRE(ld_spectra >= n, HC_ESHAPE, "%s: ld_spectra < n", fn);
+    if (n_pixels == 0) return HC_OK;
+    HC_REQUIRE(D && T && zimg && xyz, HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned16(zimg) && aligned4(D) && aligned4(T) && aligned4(xyz) &&
+                   (!spectra || aligned4(spectra)),
+               HC_EALIGN, "%s: zimg needs 16-byte alignment, the rest 4-byte", fn);
+    return launch_decode(D, n, k, T, zimg, n_pixels, ld_zimg, xyz, spectra, ld_spectra,
+                         as_stream(stream));
+}
+
+hc_status hc_check_paths(const hc_paths* paths, int64_t n_texels, int32_t n_illum, uint64_t* counts,
+                         void* stream) {
+    clear_error();
+    const char* fn = "hc_check_paths";
+    hc_status s = check_paths_struct(paths, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(counts != nullptr && aligned8(counts), HC_EINVAL, "%s: counts NULL or misaligned", fn);
+    HC_REQUIRE(n_texels >= 0 && n_illum >= 0, HC_ESHAPE, "%s: negative asset sizes", fn);
+    return launch_check_paths(*paths, n_texels, n_illum, counts, as_stream(stream));
+}
+
+size_t hc_codec_workspace_size(int32_t k, int32_t n, int64_t N) {
+    if (k < 1 || k > kMaxK || n < 1 || n > kMaxN || N < 1) return 0;
+    return codec_workspace_size(k, n, N);
+}
+
+hc_status hc_codec_step(const hc_codec_args* a) {
+    clear_error();
+    const char* fn = "hc_codec_step";
+    HC_REQUIRE(a != nullptr, HC_EINVAL, "%s: args is NULL", fn);
+    HC_REQUIRE(a->k >= 1 && a->k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, a->k, kMaxK);
+    HC_REQUIRE(a->n >= 1 && a->n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, a->n, kMaxN);
+    HC_REQUIRE(a->dtype == 0 || a->dtype == 1, HC_EINVAL, "%s: dtype must be 0 or 1", fn);
+    HC_REQUIRE(a->N >= 1 && a->N < (int64_t(1) << 31), HC_ESHAPE, "%s: N outside [1, 2^31)", fn);
+    HC_REQUIRE(a->beta > 0, HC_EINVAL, "%s: beta must be > 0", fn);
+    HC_REQUIRE(a->ld_a >= a->n && a->ld_b >= a->n, HC_ESHAPE, "%s: ld_a/ld_b < n", fn);
+    HC_REQUIRE(a->Wt_E && a->Wt_D && a->A && a->B && a->loss, HC_EINVAL, "%s: NULL pointer", fn);
+    if (a->idx_a) HC_REQUIRE(a->rows_a >= 1, HC_ESHAPE, "%s: rows_a must be >= 1 with idx_a", fn);
+    if (a->idx_b) HC_REQUIRE(a->rows_b >= 1, HC_ESHAPE, "%s: rows_b must be >= 1 with idx_b", fn);
+    if (!a->idx_a) HC_REQUIRE(a->rows_a >= a->N, HC_ESHAPE, "%s: rows_a < N without idx_a", fn);
+    if (!a->idx_b) HC_REQUIRE(a->rows_b >= a->N, HC_ESHAPE, "%s: rows_b < N without idx_b", fn);
+    const size_t esz = a->dtype ? 8 : 4;
+    auto al = [&](const void* p) { return (reinterpret_cast<uintptr_t>(p) % esz) == 0; };
+    HC_REQUIRE(al(a->Wt_E) && al(a->Wt_D) && al(a->A) && al(a->B) && al(a->loss) &&
+                   (!a->grad_E || al(a->grad_E)) && (!a->grad_D || al(a->grad_D)),
+               HC_EALIGN, "%s: arrays must be aligned to their element size", fn);
+    if (a->adam) {
+        const hc_adam* m = a->adam;
+        HC_REQUIRE(m->m_E && m->v_E && m->m_D && m->v_D && m->step, HC_EINVAL,
+                   "%s: adam state has a NULL pointer", fn);
+        HC_REQUIRE(al(m->m_E) && al(m->v_E) && al(m->m_D) && al(m->v_D) && aligned8(m->step),
+                   HC_EALIGN, "%s: adam state misaligned", fn);
+        HC_REQUIRE(m->lr > 0 && m->beta1 >= 0 && m->beta1 < 1 && m->beta2 >= 0 && m->beta2 < 1 &&
+                       m->eps > 0,
+                   HC_EINVAL, "%s: adam hyper-parameters out of range", fn);
+    }
+    const size_t need = codec_workspace_size(a->k, a->n, a->N);
+    HC_REQUIRE(a->workspace != nullptr && a->workspace_bytes >= need && aligned8(a->workspace),
+               HC_ENOMEM, "%s: workspace needs %zu bytes (8-byte aligned), got %zu", fn, need,
+               a->workspace_bytes);
+    return launch_codec_step(*a);
+}
+
+hc_status hc_codec_weights(const void* Wt_E, const void* Wt_D, int32_t k, int32_t n, int32_t dtype,
+                           double beta, float* E, float* D, void* stream) {
+    clear_error();
+    const char* fn = "hc_codec_weights";
+    HC_REQUIRE(k >= 1 && k <= kMaxK && n >= 1 && n <= kMaxN, HC_ESHAPE, "%s: bad k or n", fn);
+    HC_REQUIRE(dtype == 0 || dtype == 1, HC_EINVAL, "%s: dtype must be 0 or 1", fn);
+    HC_REQUIRE(beta > 0, HC_EINVAL, "%s: beta must be > 0", fn);
+    HC_REQUIRE(Wt_E && Wt_D && E && D, HC_EINVAL, "%s: NULL pointer", fn);
+    return launch_codec_weights(Wt_E, Wt_D, k, n, dtype, beta, E, D, as_stream(stream));
+}
+
+size_t hc_gen_workspace_size(int64_t n_pixels) {
+    return n_pixels < 0 ? 0 : gen_workspace_size(n_pixels);
+}
+
+static hc_status check_gen(const hc_path_gen* g, const char* fn) {
+    HC_REQUIRE(g != nullptr, HC_EINVAL, "%s: spec is NULL", fn);
+    HC_REQUIRE(g->n_pixels >= 0 && g->spp >= 1, HC_ESHAPE, "%s: bad n_pixels/spp", fn);
+    HC_REQUIRE(g->n_pixels <= (int64_t(1) << 40) / g->spp, HC_ESHAPE, "%s: too many paths", fn);
+    HC_REQUIRE(0 <= g->l_min && g->l_min <= g->l_max && g->l_max <= 255, HC_ESHAPE,
+               "%s: need 0 <= l_min <= l_max <= 255", fn);
+    HC_REQUIRE(g->n_illum >= 1 && g->n_illum <= (1 << 24), HC_ESHAPE, "%s: n_illum outside [1, 2^24]",
+               fn);
+    HC_REQUIRE(g->n_tex >= 1 && g->n_tex < (int64_t(1) << 32), HC_ESHAPE,
+               "%s: n_tex outside [1, 2^32)", fn);
+    return HC_OK;
+}
+
+hc_status hc_gen_path_headers(const hc_path_gen* g, uint32_t* hdr, uint32_t* pix_first,
+                              uint64_t* n_vertices, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+    clear_error();
+    const char* fn = "hc_gen_path_headers";
+    hc_status s = check_gen(g, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(n_vertices && aligned8(n_vertices), HC_EINVAL, "%s: n_vertices NULL/misaligned", fn);
+    if (g->n_pixels > 0) {
+        HC_REQUIRE(hdr && pix_first && aligned4(hdr) && aligned4(pix_first), HC_EINVAL,
+                   "%s: hdr/pix_first NULL or misaligned", fn);
+    }
+    const size_t need = gen_workspace_size(g->n_pixels);
+    HC_REQUIRE(workspace_bytes >= need && (need == 0 || (workspace && aligned8(workspace))), HC_ENOMEM,
+               "%s: workspace needs %zu bytes, got %zu", fn, need, workspace_bytes);
+    return launch_gen_headers(*g, hdr, pix_first, n_vertices, workspace, workspace_bytes,
+                              as_stream(stream));
+}
+
+hc_status hc_gen_path_vertices(const hc_path_gen* g, const uint32_t* pix_first, uint32_t* vtx,
+                               int64_t n_vertices, void* stream) {
+    clear_error();
+    const char* fn = "hc_gen_path_vertices";
+    hc_status s = check_gen(g, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(n_vertices >= 0 && n_vertices < (int64_t(1) << 32), HC_ESHAPE,
+               "%s: n_vertices outside [0, 2^32)", fn);
+    if (g->n_pixels == 0) return HC_OK;
+    HC_REQUIRE(pix_first && aligned4(pix_first), HC_EINVAL, "%s: pix_first NULL/misaligned", fn);
+    HC_REQUIRE(n_vertices == 0 || (vtx && aligned8(vtx)), HC_EINVAL, "%s: vtx NULL/misaligned", fn);
+    return launch_gen_vertices(*g, pix_first, vtx, n_vertices, as_stream(stream));
+}
+
+hc_status hc_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* ctr_scale_dev, int64_t count,
+                         int64_t n, uint32_t* out, void* stream) {
+    clear_error();
+    const char* fn = "hc_gen_indices";
+    HC_REQUIRE(count >= 0 && count < (int64_t(1) << 40), HC_ESHAPE, "%s: bad count", fn);
+    HC_REQUIRE(n >= 1 && n < (int64_t(1) << 32), HC_ESHAPE, "%s: n outside [1, 2^32)", fn);
+    if (count == 0) return HC_OK;
+    HC_REQUIRE(out && aligned4(out), HC_EINVAL, "%s: out NULL/misaligned", fn);
+    HC_REQUIRE(!ctr_scale_dev || aligned8(ctr_scale_dev), HC_EALIGN, "%s: counter misaligned", fn);
+    return launch_gen_indices(seed, ctr0, ctr_scale_dev, count, n, out, as_stream(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/hc.h"
+
+namespace hc {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+// Checks the launch that was just enqueued.
+hc_status launch_status(const char* what);
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+inline bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+inline bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+constexpr int kWave = 64;
+constexpr int kMaxN = 128;
+constexpr int kMaxK = 48;
+constexpr int kMaxBlocks = kMaxK / 3;  // 16 float4 slots per latent row
+
+// ---------------------------------------------------------------- device helpers
+
+__device__ __forceinline__ float4 ld4(const float* p) {
+    return *reinterpret_cast<const float4*>(p);
+}
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+__device__ __forceinline__ float4 mul4(float4 a, float4 b) {
+    return make_float4(a.x * b.x, a.y * b.y, a.z * b.z, a.w * b.w);
+}
+__device__ __forceinline__ float4 scale4(float4 a, float s) {
+    return make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
+}
+__device__ __forceinline__ float4 add4(float4 a, float4 b) {
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+
+// Lane-level shuffles inside one 64-wide wavefront.
+__device__ __forceinline__ float shfl_xor(float v, int mask) { return __shfl_xor(v, mask, kWave); }
+__device__ __forceinline__ uint32_t shfl_up_u32(uint32_t v, int d) {
+    return static_cast<uint32_t>(__shfl_up(static_cast<int>(v), d, kWave));
+}
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int lane) {
+    return static_cast<uint32_t>(__shfl(static_cast<int>(v), lane, kWave));
+}
+
+// ---------------------------------------------------------------- launchers (per TU)
+
+hc_status launch_encode(const float* E, int k, int n, const float* S, int64_t m, int64_t ld_s,
+                        float* Z, int64_t ld_z, hipStream_t st);
+hc_status launch_decode(const float* D, int n, int k, const float* T, const float* zimg,
+                        int64_t n_pixels, int64_t ld_zimg, float* xyz, float* spectra,
+                        int64_t ld_spectra, hipStream_t st);
+hc_status launch_shade_spectral(const hc_paths& P, const hc_spectral_assets& A, const float* T,
+                                float* xyz, hipStream_t st);
+hc_status launch_shade_latent(const hc_paths& P, const hc_latent_assets& A, int block_first,
+                              int block_count, float* zimg, int64_t ld_zimg, hipStream_t st);
+hc_status launch_check_paths(const hc_paths& P, int64_t n_texels, int32_t n_illum,
+                             uint64_t* counts, hipStream_t st);
+hc_status launch_codec_step(const hc_codec_args& a);
+size_t codec_workspace_size(int k, int n, int64_t N);
+hc_status launch_codec_weights(const void* we, const void* wd, int k, int n, int dtype,
+                               double beta, float* E, float* D, hipStream_t st);
+size_t gen_workspace_size(int64_t n_pixels);
+hc_status launch_gen_headers(const hc_path_gen& g, uint32_t* hdr, uint32_t* pix_first,
+                             uint64_t* n_vertices, void* ws, size_t ws_bytes, hipStream_t st);
+hc_status launch_gen_vertices(const hc_path_gen& g, const uint32_t* pix_first, uint32_t* vtx,
+                              int64_t n_vertices, hipStream_t st);
+hc_status launch_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* scale, int64_t count,
+                             int64_t n, uint32_t* out, hipStream_t st);
+
+}  // namespace hc

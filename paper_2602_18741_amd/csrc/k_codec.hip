@@ -1,0 +1,436 @@
+// Codec fitting: loss, hand-written gradient and Adam for the non-negative
+// linear codec E = softplus(Wt_E), D = softplus(Wt_D).
+//
+// Three kernels per step, all deterministic (fixed summation orders, no
+// floating-point atomics):
+//   1. weights : E, D = softplus_beta(Wt) into the workspace; bumps the Adam
+//                step counter.
+//   2. partials: each workgroup takes tiles of TP pairs; `lpp` lanes per pair
+//                compute u = E a, v = E b, h = u*v, the residuals
+//                r_a = D u - a, r_b = D v - b, r_h = D h - a*b, and the
+//                back-propagated code gradients, staged in LDS; then every
+//                thread contracts over the tile's pairs for its gradient
+//                elements (float64 sums) and writes one partial row per
+//                workgroup.
+//   3. finish  : one wavefront per gradient element sums the partial rows
+//                (fixed order, float64), scales by 2/N, applies the softplus
+//                slope logistic(beta Wt) and optionally the Adam update.
+
+#include "hc_internal.hpp"
+
+namespace hc {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxRows = 1024;          // partial rows (workgroups of kernel 2)
+constexpr size_t kTileLdsBytes = 49152;
+
+__device__ __forceinline__ float dexp(float x) { return expf(x); }
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+__device__ __forceinline__ float dlog1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double dlog1p(double x) { return log1p(x); }
+
+template <typename F>
+__device__ __forceinline__ F softplus(F x, F beta) {
+    const F ax = x < F(0) ? -x : x;
+    return (x > F(0) ? x : F(0)) + dlog1p(dexp(-beta * ax)) / beta;
+}
+
+// logistic(beta x), the slope of softplus_beta at x
+__device__ __forceinline__ double slope(double x, double beta) {
+    const double e = exp(-beta * (x < 0 ? -x : x));
+    return x >= 0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
+}
+
+// ------------------------------------------------------------------ kernel 1
+
+template <typename F>
+__global__ __launch_bounds__(kThreads) void codec_weights_kernel(const F* we, const F* wd, int kn,
+                                                                 F beta, F* E, F* D,
+                                                                 int64_t* step, int64_t* ws_step) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e < kn) {
+        E[e] = softplus(we[e], beta);
+        D[e] = softplus(wd[e], beta);
+    }
+    if (step && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t t = *step + 1;
+        *ws_step = t;
+        *step = t;
+    }
+}
+
+template <typename F>
+__global__ __launch_bounds__(kThreads) void codec_weights_f32_kernel(const F* we, const F* wd, int kn,
+                                                                     F beta, float* E, float* D) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e < kn) {
+        E[e] = float(softplus(we[e], beta));
+        D[e] = float(softplus(wd[e], beta));
+    }
+}
+
+// ------------------------------------------------------------------ kernel 2
+
+template <typename F>
+struct PartialArgs {
+    int k, n, npad, tp, lpp;
+    F lam;
+    const F* E;  // k x n
+    const F* D;  // n x k
+    const F* A;
+    const F* B;
+    int64_t ld_a, ld_b, rows_a, rows_b;
+    const uint32_t* idx_a;
+    const uint32_t* idx_b;
+    int64_t N, n_tiles;
+    double* part;  // gridDim.x rows of 2kn + 1
+    int ed_in_lds;
+};
+
+template <typename F>
+__global__ __launch_bounds__(kThreads) void codec_partials_kernel(PartialArgs<F> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    F* sm = reinterpret_cast<F*>(smem_raw);
+    const int k = a.k, n = a.n, np = a.npad, tp = a.tp, lpp = a.lpp;
+    const int kn = k * n;
+    const int tid = threadIdx.x;
+    const F* Ep = a.E;
+    const F* Dp = a.D;
+    F* base = sm;
+    if (a.ed_in_lds) {
+        for (int i = tid; i < kn; i += kThreads) {
+            sm[i] = a.E[i];
+            sm[kn + i] = a.D[i];
+        }
+        Ep = sm;
+        Dp = sm + kn;
+        base = sm + 2 * kn;
+    }
+    F* AA = base;
+    F* BB = AA + tp * np;
+    F* RA = BB + tp * np;
+    F* RB = RA + tp * np;
+    F* RH = RB + tp * np;
+    F* U = RH + tp * np;
+    F* V = U + tp * k;
+    F* H = V + tp * k;
+    F* GU = H + tp * k;
+    F* GV = GU + tp * k;
+
+    const int pair = tid / lpp;
+    const int part = tid % lpp;
+    double loss_acc = 0.0;
+    double* prow = a.part + int64_t(blockIdx.x) * (2 * kn + 1);
+    bool first_tile = true;
+
+    for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const int64_t gi = tile * tp + pair;
+        const bool valid = pair < tp && gi < a.N;
+        __syncthreads();  // the previous tile's contraction has finished with LDS
+        if (pair < tp) {
+            int64_t ra = 0, rb = 0;
+            if (valid) {
+                ra = a.idx_a ? min<int64_t>(a.idx_a[gi], a.rows_a - 1) : gi;
+                rb = a.idx_b ? min<int64_t>(a.idx_b[gi], a.rows_b - 1) : gi;
+            }
+            for (int i = part; i < n; i += lpp) {
+                AA[pair * np + i] = valid ? a.A[ra * a.ld_a + i] : F(0);
+                BB[pair * np + i] = valid ? a.B[rb * a.ld_b + i] : F(0);
+            }
+        }
+        __syncthreads();
+        // codes u = E a, v = E b and their product h (Eq. 4, Eq. 6)
+        if (pair < tp) {
+            for (int j = part; j < k; j += lpp) {
+                F su = 0, sv = 0;
+                for (int i = 0; i < n; ++i) {
+                    const F e = Ep[j * n + i];
+                    su += e * AA[pair * np + i];
+                    sv += e * BB[pair * np + i];
+                }
+                U[pair * k + j] = su;
+                V[pair * k + j] = sv;
+                H[pair * k + j] = su * sv;
+            }
+        }
+        __syncthreads();
+        // residuals of the two reconstructions and of the decoded product
+        if (pair < tp) {
+            for (int i = part; i < n; i += lpp) {
+                F du = 0, dv = 0, dh = 0;
+                for (int j = 0; j < k; ++j) {
+                    const F d = Dp[i * k + j];
+                    du += d * U[pair * k + j];
+                    dv += d * V[pair * k + j];
+                    dh += d * H[pair * k + j];
+                }
+                const F ai = AA[pair * np + i], bi = BB[pair * np + i];
+                const F ra = du - ai, rb = dv - bi, rh = dh - ai * bi;
+                if (valid)
+                    loss_acc += double(ra) * double(ra) + double(rb) * double(rb) +
+                                double(a.lam) * double(rh) * double(rh);
+                RA[pair * np + i] = valid ? ra : F(0);
+                RB[pair * np + i] = valid ? rb : F(0);
+                RH[pair * np + i] = valid ? a.lam * rh : F(0);
+            }
+        }
+        __syncthreads();
+        // code-space gradients: D^T r_a + g_h * v and D^T r_b + g_h * u with g_h = lam D^T r_h
+        if (pair < tp) {
+            for (int j = part; j < k; j += lpp) {
+                F gu = 0, gv = 0, gh = 0;
+                for (int i = 0; i < n; ++i) {
+                    const F d = Dp[i * k + j];
+                    gu += d * RA[pair * np + i];
+                    gv += d * RB[pair * np + i];
+                    gh += d * RH[pair * np + i];
+                }
+                GU[pair * k + j] = gu + gh * V[pair * k + j];
+                GV[pair * k + j] = gv + gh * U[pair * k + j];
+            }
+        }
+        __syncthreads();
+        // contraction over the tile's pairs; elements [0, kn) are dL/dE
+        // (k x n), [kn, 2kn) are dL/dD (n x k), both without the 2/N factor
+        for (int e = tid; e < 2 * kn; e += kThreads) {
+            double s = 0.0;
+            if (e < kn) {
+                const int j = e / n, i = e % n;
+                for (int p = 0; p < tp; ++p)
+                    s += double(GU[p * k + j]) * double(AA[p * np + i]) +
+                         double(GV[p * k + j]) * double(BB[p * np + i]);
+            } else {
+                const int e2 = e - kn;
+                const int i = e2 / k, j = e2 % k;
+                for (int p = 0; p < tp; ++p)
+                    s += double(RA[p * np + i]) * double(U[p * k + j]) +
+                         double(RB[p * np + i]) * double(V[p * k + j]) +
+                         double(RH[p * np + i]) * double(H[p * k + j]);
+            }
+            prow[e] = first_tile ? s : prow[e] + s;
+        }
+        first_tile = false;
+    }
+    // workgroup sum of the loss terms, fixed order
+    __shared__ double s_loss[kThreads / kWave];
+    for (int m = kWave / 2; m >= 1; m >>= 1) loss_acc += __shfl_xor(loss_acc, m, kWave);
+    if ((tid & (kWave - 1)) == 0) s_loss[tid / kWave] = loss_acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / kWave; ++w) t += s_loss[w];
+        prow[2 * kn] = t;
+    }
+}
+
+// ------------------------------------------------------------------ kernel 3
+
+template <typename F>
+struct FinishArgs {
+    int k, n;
+    double beta, inv_n;
+    const double* part;
+    int rows;
+    F* we;
+    F* wd;
+    F* loss;
+    F* grad_e;
+    F* grad_d;
+    // Adam
+    F* m_e;
+    F* v_e;
+    F* m_d;
+    F* v_d;
+    const int64_t* ws_step;
+    double lr, beta1, beta2, eps;
+    int adam;
+};
+
+template <typename F>
+__global__ __launch_bounds__(kThreads) void codec_finish_kernel(FinishArgs<F> a) {
+    const int kn = a.k * a.n;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int e = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    if (e > 2 * kn) return;
+    const int64_t stride = 2 * kn + 1;
+    double s = 0.0;
+    for (int r = lane; r < a.rows; r += kWave) s += a.part[r * stride + e];
+    for (int m = kWave / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, kWave);
+    if (lane != 0) return;
+    if (e == 2 * kn) {
+        *a.loss = F(s * a.inv_n);
+        return;
+    }
+    const bool isE = e < kn;
+    const int idx = isE ? e : e - kn;
+    F* w = isE ? a.we : a.wd;
+    const double wt = double(w[idx]);
+    const double g = 2.0 * s * a.inv_n * slope(wt, a.beta);
+    F* gout = isE ? a.grad_e : a.grad_d;
+    if (gout) gout[idx] = F(g);
+    if (a.adam) {
+        F* m = isE ? a.m_e : a.m_d;
+        F* v = isE ? a.v_e : a.v_d;
+        const double t = double(*a.ws_step);
+        const double mm = a.beta1 * double(m[idx]) + (1.0 - a.beta1) * g;
+        const double vv = a.beta2 * double(v[idx]) + (1.0 - a.beta2) * g * g;
+        const double bc1 = 1.0 - pow(a.beta1, t);
+        const double bc2 = 1.0 - pow(a.beta2, t);
+        const double denom = sqrt(vv) / sqrt(bc2) + a.eps;
+        m[idx] = F(mm);
+        v[idx] = F(vv);
+        w[idx] = F(wt - (a.lr / bc1) * mm / denom);
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+struct Plan {
+    int tp, lpp, npad, ed_in_lds;
+    int64_t n_tiles, grid;
+    size_t lds;
+};
+
+Plan plan(int k, int n, int64_t N, size_t esz) {
+    Plan p;
+    p.npad = n | 1;  // odd row stride spreads the pairs of a wave over LDS banks
+    const size_t ed = size_t(2) * k * n * esz;
+    p.ed_in_lds = ed <= 16384;
+    const size_t per_pair = (size_t(5) * p.npad + size_t(5) * k) * esz;
+    const size_t budget = kTileLdsBytes - (p.ed_in_lds ? ed : 0);
+    int tp = 64;
+    while (tp > 4 && size_t(tp) * per_pair > budget) tp >>= 1;
+    p.tp = tp;
+    p.lpp = kThreads / tp;
+    p.lds = size_t(tp) * per_pair + (p.ed_in_lds ? ed : 0);
+    p.n_tiles = ceil_div(N, tp);
+    p.grid = std::min<int64_t>(p.n_tiles, kMaxRows);
+    return p;
+}
+
+size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
+
+struct Workspace {
+    void* E;
+    void* D;
+    double* part;
+    int64_t* step;
+};
+
+Workspace carve(void* ws, int k, int n, int64_t rows, size_t esz) {
+    char* p = static_cast<char*>(ws);
+    Workspace w;
+    const size_t kn = size_t(k) * n;
+    w.E = p;
+    p += align8(kn * esz);
+    w.D = p;
+    p += align8(kn * esz);
+    w.part = reinterpret_cast<double*>(p);
+    p += size_t(rows) * (2 * kn + 1) * sizeof(double);
+    w.step = reinterpret_cast<int64_t*>(p);
+    return w;
+}
+
+template <typename F>
+hc_status run(const hc_codec_args& a) {
+    const int k = a.k, n = a.n, kn = k * n;
+    hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
+    const Plan pl = plan(k, n, a.N, sizeof(F));
+    Workspace ws = carve(a.workspace, k, n, pl.grid, sizeof(F));
+    const int g0 = int(ceil_div(kn, kThreads));
+    hipLaunchKernelGGL(codec_weights_kernel<F>, dim3(g0), dim3(kThreads), 0, st,
+                       static_cast<const F*>(a.Wt_E), static_cast<const F*>(a.Wt_D), kn,
+                       F(a.beta), static_cast<F*>(ws.E), static_cast<F*>(ws.D),
+                       a.adam ? a.adam->step : nullptr, ws.step);
+    hc_status s = launch_status("hc_codec_step");
+    if (s != HC_OK) return s;
+
+    PartialArgs<F> p;
+    p.k = k;
+    p.n = n;
+    p.npad = pl.npad;
+    p.tp = pl.tp;
+    p.lpp = pl.lpp;
+    p.lam = F(a.lambda);
+    p.E = static_cast<const F*>(ws.E);
+    p.D = static_cast<const F*>(ws.D);
+    p.A = static_cast<const F*>(a.A);
+    p.B = static_cast<const F*>(a.B);
+    p.ld_a = a.ld_a;
+    p.ld_b = a.ld_b;
+    p.rows_a = a.rows_a;
+    p.rows_b = a.rows_b;
+    p.idx_a = a.idx_a;
+    p.idx_b = a.idx_b;
+    p.N = a.N;
+    p.n_tiles = pl.n_tiles;
+    p.part = ws.part;
+    p.ed_in_lds = pl.ed_in_lds;
+    hipLaunchKernelGGL(codec_partials_kernel<F>, dim3(uint32_t(pl.grid)), dim3(kThreads), pl.lds, st,
+                       p);
+    s = launch_status("hc_codec_step");
+    if (s != HC_OK) return s;
+
+    FinishArgs<F> f;
+    f.k = k;
+    f.n = n;
+    f.beta = a.beta;
+    f.inv_n = 1.0 / double(a.N);
+    f.part = ws.part;
+    f.rows = int(pl.grid);
+    f.we = static_cast<F*>(a.Wt_E);
+    f.wd = static_cast<F*>(a.Wt_D);
+    f.loss = static_cast<F*>(a.loss);
+    f.grad_e = static_cast<F*>(a.grad_E);
+    f.grad_d = static_cast<F*>(a.grad_D);
+    f.adam = a.adam != nullptr;
+    if (a.adam) {
+        f.m_e = static_cast<F*>(a.adam->m_E);
+        f.v_e = static_cast<F*>(a.adam->v_E);
+        f.m_d = static_cast<F*>(a.adam->m_D);
+        f.v_d = static_cast<F*>(a.adam->v_D);
+        f.lr = a.adam->lr;
+        f.beta1 = a.adam->beta1;
+        f.beta2 = a.adam->beta2;
+        f.eps = a.adam->eps;
+    } else {
+        f.m_e = f.v_e = f.m_d = f.v_d = nullptr;
+        f.lr = f.beta1 = f.beta2 = f.eps = 0.0;
+    }
+    f.ws_step = ws.step;
+    const int g2 = int(ceil_div(2 * kn + 1, kThreads / kWave));
+    hipLaunchKernelGGL(codec_finish_kernel<F>, dim3(g2), dim3(kThreads), 0, st, f);
+    return launch_status("hc_codec_step");
+}
+
+}  // namespace
+
+size_t codec_workspace_size(int k, int n, int64_t N) {
+    // the float64 plan has the smallest tiles, hence the most partial rows
+    const Plan pl = plan(k, n, N, sizeof(double));
+    const size_t kn = size_t(k) * n;
+    return 2 * align8(kn * sizeof(double)) + size_t(pl.grid) * (2 * kn + 1) * sizeof(double) +
+           sizeof(int64_t);
+}
+
+hc_status launch_codec_step(const hc_codec_args& a) {
+    return a.dtype == 1 ? run<double>(a) : run<float>(a);
+}
+
+hc_status launch_codec_weights(const void* we, const void* wd, int k, int n, int dtype, double beta,
+                               float* E, float* D, hipStream_t st) {
+    const int kn = k * n;
+    const int g = int(ceil_div(kn, kThreads));
+    if (dtype == 1)
+        hipLaunchKernelGGL(codec_weights_f32_kernel<double>, dim3(g), dim3(kThreads), 0, st,
+                           static_cast<const double*>(we), static_cast<const double*>(wd), kn, beta,
+                           E, D);
+    else
+        hipLaunchKernelGGL(codec_weights_f32_kernel<float>, dim3(g), dim3(kThreads), 0, st,
+                           static_cast<const float*>(we), static_cast<const float*>(wd), kn,
+                           float(beta), E, D);
+    return launch_status("hc_codec_weights");
+}
+
+}  // namespace hc

@@ -1,0 +1,214 @@
+// Synthetic light-path records and random indices from a counter-based
+// generator: SplitMix64's output function (Steele, Lea and Flood, OOPSLA
+// 2014) applied to key + (counter + 1) * 0x9E3779B97F4A7C15, with
+// key = mix64(mix64(seed) + stream).  Any path is reproducible on its own.
+
+#include "hc_internal.hpp"
+
+namespace hc {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kScanItems = 4;                      // items per thread in the scan
+constexpr int kScanTile = kThreads * kScanItems;   // pixels per scan block
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t stream) {
+    return mix64(mix64(seed) + stream);
+}
+__device__ __forceinline__ uint64_t rand64(uint64_t key, uint64_t ctr) {
+    return mix64(key + (ctr + 1) * kGolden);
+}
+__device__ __forceinline__ uint32_t range32(uint64_t r, uint64_t n) {
+    return static_cast<uint32_t>(((r & 0xFFFFFFFFull) * n) >> 32);
+}
+
+struct GenArgs {
+    int64_t n_pixels;
+    int spp, l_min, l_span;  // l_span = l_max - l_min + 1
+    uint32_t n_illum;
+    uint64_t n_tex;
+    uint64_t key_path, key_vtx;
+};
+
+__device__ __forceinline__ uint32_t path_length(const GenArgs& g, uint64_t p) {
+    return uint32_t(g.l_min) + range32(rand64(g.key_path, p), uint64_t(g.l_span));
+}
+
+// hdr of every path, and each pixel's vertex count into pix_first
+__global__ __launch_bounds__(kThreads) void gen_headers_kernel(GenArgs g, uint32_t* hdr,
+                                                               uint32_t* counts) {
+    const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (q >= g.n_pixels) return;
+    uint32_t sum = 0;
+    for (int j = 0; j < g.spp; ++j) {
+        const uint64_t p = uint64_t(q) * g.spp + j;
+        const uint64_t r = rand64(g.key_path, p);
+        const uint32_t len = uint32_t(g.l_min) + range32(r, uint64_t(g.l_span));
+        const uint32_t light = static_cast<uint32_t>(((r >> 32) * g.n_illum) >> 32);
+        hdr[p] = light | (len << 24);
+        sum += len;
+    }
+    counts[q] = sum;
+}
+
+// Exclusive scan of the per-pixel counts (reduce, scan of block sums, scan).
+__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* s_tmp, uint64_t& total) {
+    // inclusive scan inside the wave
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint64_t x = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) s_tmp[wave] = x;
+    __syncthreads();
+    uint64_t off = 0;
+    for (int w = 0; w < wave; ++w) off += s_tmp[w];
+    total = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) total += s_tmp[w];
+    __syncthreads();
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* counts, int64_t n,
+                                                               uint64_t* block_sums) {
+    __shared__ uint64_t s_tmp[kThreads / kWave];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    uint64_t v = 0;
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) v += counts[base + i];
+    uint64_t total;
+    block_exclusive_scan(v, s_tmp, total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// single workgroup: exclusive scan of the block sums in place, total out
+__global__ __launch_bounds__(kThreads) void scan_blocks_kernel(uint64_t* block_sums, int64_t nb,
+                                                               uint64_t* total_out) {
+    __shared__ uint64_t s_tmp[kThreads / kWave];
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
+        const int64_t b = b0 + threadIdx.x;
+        const uint64_t v = b < nb ? block_sums[b] : 0;
+        uint64_t total;
+        const uint64_t ex = block_exclusive_scan(v, s_tmp, total);
+        if (b < nb) block_sums[b] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_apply_kernel(uint32_t* counts, int64_t n,
+                                                              const uint64_t* block_offsets) {
+    __shared__ uint64_t s_tmp[kThreads / kWave];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    uint32_t c[kScanItems];
+    uint64_t v = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        c[i] = (base + i < n) ? counts[base + i] : 0u;
+        v += c[i];
+    }
+    uint64_t total;
+    uint64_t run = block_offsets[blockIdx.x] + block_exclusive_scan(v, s_tmp, total);
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) counts[base + i] = static_cast<uint32_t>(run);
+        run += c[i];
+    }
+}
+
+// one thread per path; a path's first record is its pixel's first record plus
+// the lengths of the pixel's earlier paths (recomputed from the generator)
+__global__ __launch_bounds__(kThreads) void gen_vertices_kernel(GenArgs g, const uint32_t* pix_first,
+                                                                uint32_t* vtx, uint64_t n_vertices) {
+    const int64_t p = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (p >= g.n_pixels * g.spp) return;
+    const int64_t q = p / g.spp;
+    const int j = int(p - q * g.spp);
+    uint64_t first = pix_first[q];
+    for (int jj = 0; jj < j; ++jj) first += path_length(g, uint64_t(q) * g.spp + jj);
+    const uint32_t len = path_length(g, uint64_t(p));
+    for (uint32_t v = 0; v < len; ++v) {
+        const uint64_t jv = first + v;
+        if (jv >= n_vertices) break;
+        const uint64_t r = rand64(g.key_vtx, uint64_t(p) * 256u + v);
+        const uint32_t texel = range32(r, g.n_tex);
+        const float w = float(uint32_t(r >> 40)) * (1.0f / 16777216.0f);
+        reinterpret_cast<uint2*>(vtx)[jv] = make_uint2(texel, __float_as_uint(w));
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void gen_indices_kernel(uint64_t key, uint64_t ctr0,
+                                                               const int64_t* scale, int64_t count,
+                                                               uint64_t n, uint32_t* out) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t base = ctr0 + (scale ? uint64_t(*scale) * uint64_t(count) : 0ull);
+    out[i] = range32(rand64(key, base + uint64_t(i)), n);
+}
+
+GenArgs make_args(const hc_path_gen& g) {
+    GenArgs a;
+    a.n_pixels = g.n_pixels;
+    a.spp = g.spp;
+    a.l_min = g.l_min;
+    a.l_span = g.l_max - g.l_min + 1;
+    a.n_illum = static_cast<uint32_t>(g.n_illum);
+    a.n_tex = static_cast<uint64_t>(g.n_tex);
+    a.key_path = stream_key(g.seed, 1);
+    a.key_vtx = stream_key(g.seed, 2);
+    return a;
+}
+
+}  // namespace
+
+size_t gen_workspace_size(int64_t n_pixels) {
+    return size_t(ceil_div(n_pixels, kScanTile) + 1) * sizeof(uint64_t);
+}
+
+hc_status launch_gen_headers(const hc_path_gen& g, uint32_t* hdr, uint32_t* pix_first,
+                             uint64_t* n_vertices, void* ws, size_t, hipStream_t st) {
+    const GenArgs a = make_args(g);
+    uint64_t* block_sums = static_cast<uint64_t*>(ws);
+    const int64_t nb = ceil_div(g.n_pixels, kScanTile);
+    if (g.n_pixels > 0) {
+        hipLaunchKernelGGL(gen_headers_kernel, dim3(uint32_t(ceil_div(g.n_pixels, kThreads))),
+                           dim3(kThreads), 0, st, a, hdr, pix_first);
+        hc_status s = launch_status("hc_gen_path_headers");
+        if (s != HC_OK) return s;
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3(uint32_t(nb)), dim3(kThreads), 0, st, pix_first,
+                           g.n_pixels, block_sums);
+        s = launch_status("hc_gen_path_headers");
+        if (s != HC_OK) return s;
+    }
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kThreads), 0, st, block_sums, nb,
+                       reinterpret_cast<uint64_t*>(n_vertices));
+    hc_status s = launch_status("hc_gen_path_headers");
+    if (s != HC_OK || g.n_pixels == 0) return s;
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(uint32_t(nb)), dim3(kThreads), 0, st, pix_first,
+                       g.n_pixels, block_sums);
+    return launch_status("hc_gen_path_headers");
+}
+
+hc_status launch_gen_vertices(const hc_path_gen& g, const uint32_t* pix_first, uint32_t* vtx,
+                              int64_t n_vertices, hipStream_t st) {
+    const GenArgs a = make_args(g);
+    const int64_t n_paths = g.n_pixels * g.spp;
+    hipLaunchKernelGGL(gen_vertices_kernel, dim3(uint32_t(ceil_div(n_paths, kThreads))), dim3(kThreads),
+                       0, st, a, pix_first, vtx, uint64_t(n_vertices));
+    return launch_status("hc_gen_path_vertices");
+}
+
+hc_status launch_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* scale, int64_t count,
+                             int64_t n, uint32_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(gen_indices_kernel, dim3(uint32_t(ceil_div(count, kThreads))), dim3(kThreads), 0,
+                       st, stream_key(seed, 3), ctr0, scale, count, uint64_t(n), out);
+    return launch_status("hc_gen_indices");
+}
+
+}  // namespace hc

@@ -1,0 +1,244 @@
+"""Torch-tensor front end of the C ABI.
+
+Each function checks tensor devices / dtypes, allocates outputs with torch
+(the caching allocator supplies device memory) and calls the library on the
+current HIP stream.  No computation of the method happens here.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on the GPU")
+
+
+def blocks(k: int) -> int:
+    """Number of RGB-style passes B for a k-channel code (k padded to 3B)."""
+    return (k + 2) // 3
+
+
+def latent_width(k: int) -> int:
+    """Floats per latent row in the blocked RGBx layout."""
+    return 4 * blocks(k)
+
+
+def to_blocked(z: torch.Tensor, k: int | None = None) -> torch.Tensor:
+    """Re-pack plain (m, k) codes into the blocked RGBx layout (m, 4B)."""
+    k = k or z.shape[1]
+    m = z.shape[0]
+    out = torch.zeros(m, blocks(k), 4, dtype=z.dtype, device=z.device)
+    zp = torch.zeros(m, 3 * blocks(k), dtype=z.dtype, device=z.device)
+    zp[:, :k] = z
+    out[:, :, :3] = zp.view(m, blocks(k), 3)
+    return out.view(m, latent_width(k))
+
+
+def from_blocked(zb: torch.Tensor, k: int) -> torch.Tensor:
+    """Plain (m, k) view of blocked RGBx rows."""
+    m = zb.shape[0]
+    return zb[:, :latent_width(k)].reshape(m, blocks(k), 4)[:, :, :3].reshape(m, 3 * blocks(k))[:, :k]
+
+
+def padded(x: torch.Tensor, ld: int | None = None) -> torch.Tensor:
+    """Copy of a (m, n) float32 tensor with rows padded to a multiple of 4 floats."""
+    m, n = x.shape
+    ld = ld or 4 * ((n + 3) // 4)
+    out = torch.zeros(m, ld, dtype=torch.float32, device=x.device)
+    out[:, :n] = x
+    return out
+
+
+@dataclass
+class Paths:
+    """Device light-path records (see include/hc.h for the format)."""
+    hdr: torch.Tensor        # uint32 / int32 [n_pixels * spp]
+    pix_first: torch.Tensor  # [n_pixels]
+    vtx: torch.Tensor        # [n_vertices, 2]
+    n_pixels: int
+    spp: int
+
+    @property
+    def n_vertices(self) -> int:
+        return int(self.vtx.shape[0]) if self.vtx is not None else 0
+
+    def c(self) -> _lib.Paths:
+        return _lib.Paths(self.n_pixels, self.spp, 0, self.hdr.data_ptr(), self.pix_first.data_ptr(),
+                          self.vtx.data_ptr() if self.n_vertices else None, self.n_vertices)
+
+    @staticmethod
+    def from_numpy(hdr, pix_first, vtx, spp: int, device="cuda") -> "Paths":
+        import numpy as np
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(device)  # noqa: E731
+        vt = t(vtx.reshape(-1, 2)) if vtx.size else torch.zeros(0, 2, dtype=torch.int32, device=device)
+        return Paths(t(hdr), t(pix_first), vt, int(hdr.size // spp), spp)
+
+
+def encode(E: torch.Tensor, S: torch.Tensor, n: int | None = None, ld_z: int | None = None,
+           out: torch.Tensor | None = None) -> torch.Tensor:
+    """Codes of the rows of S (rows padded to a multiple of 4 floats) in the
+    blocked layout: z = E s (Eq. 4)."""
+    _dev(E, S, out)
+    k, nE = E.shape
+    n = n or nE
+    m, ld_s = S.shape
+    ld_z = ld_z or latent_width(k)
+    if out is None:
+        out = torch.empty(m, ld_z, dtype=torch.float32, device=S.device)
+    check(load().hc_encode(_ptr(E.contiguous()), k, n, _ptr(S), m, ld_s, _ptr(out), out.stride(0),
+                           _stream()), "hc_encode")
+    return out
+
+
+def shade_spectral(paths: Paths, refl: torch.Tensor, illum: torch.Tensor, T: torch.Tensor, n: int,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per-pixel XYZ of the spectral form; refl/illum rows padded to 4 floats."""
+    _dev(refl, illum, T, out)
+    if out is None:
+        out = torch.empty(paths.n_pixels, 3, dtype=torch.float32, device=refl.device)
+    A = _lib.SpectralAssets(refl.data_ptr(), refl.shape[0], n, 0, refl.stride(0), illum.data_ptr(),
+                            illum.shape[0], 0, illum.stride(0))
+    P = paths.c()
+    check(load().hc_shade_spectral(C.byref(P), C.byref(A), _ptr(T.contiguous()), _ptr(out), _stream()),
+          "hc_shade_spectral")
+    return out
+
+
+def shade_latent(paths: Paths, codes: torch.Tensor, illum_codes: torch.Tensor, k: int,
+                 block_first: int = 0, block_count: int | None = None,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Latent image (blocked layout) of the latent form.  block_count=None is
+    the fused call over all B passes."""
+    _dev(codes, illum_codes, out)
+    nb = blocks(k)
+    block_count = nb - block_first if block_count is None else block_count
+    if out is None:
+        out = torch.zeros(paths.n_pixels, latent_width(k), dtype=torch.float32, device=codes.device)
+    A = _lib.LatentAssets(codes.data_ptr(), codes.shape[0], k, 0, codes.stride(0),
+                          illum_codes.data_ptr(), illum_codes.shape[0], 0, illum_codes.stride(0))
+    P = paths.c()
+    check(load().hc_shade_latent(C.byref(P), C.byref(A), block_first, block_count, _ptr(out),
+                                 out.stride(0), _stream()), "hc_shade_latent")
+    return out
+
+
+def decode_xyz(D: torch.Tensor, T: torch.Tensor, zimg: torch.Tensor, k: int, spectra: bool = False,
+               out: torch.Tensor | None = None):
+    """XYZ (and optionally decoded spectra) of a blocked latent image."""
+    _dev(D, T, zimg, out)
+    n = D.shape[0]
+    m = zimg.shape[0]
+    if out is None:
+        out = torch.empty(m, 3, dtype=torch.float32, device=zimg.device)
+    sp = torch.empty(m, n, dtype=torch.float32, device=zimg.device) if spectra else None
+    check(load().hc_decode_xyz(_ptr(D.contiguous()), n, k, _ptr(T.contiguous()), _ptr(zimg), m,
+                               zimg.stride(0), _ptr(out), _ptr(sp), n, _stream()), "hc_decode_xyz")
+    return (out, sp) if spectra else out
+
+
+def check_paths(paths: Paths, n_texels: int, n_illum: int) -> torch.Tensor:
+    """Device int64[3]: bad light ids, bad texel ids, bad pixel ranges."""
+    counts = torch.empty(3, dtype=torch.int64, device=paths.hdr.device)
+    P = paths.c()
+    check(load().hc_check_paths(C.byref(P), n_texels, n_illum, _ptr(counts), _stream()),
+          "hc_check_paths")
+    return counts
+
+
+def codec_weights(we: torch.Tensor, wd: torch.Tensor, beta: float = 10.0):
+    """float32 E = softplus(we), D = softplus(wd) (Eq. 5)."""
+    _dev(we, wd)
+    k, n = we.shape
+    E = torch.empty(k, n, dtype=torch.float32, device=we.device)
+    D = torch.empty(n, k, dtype=torch.float32, device=we.device)
+    dt = 1 if we.dtype == torch.float64 else 0
+    check(load().hc_codec_weights(_ptr(we.contiguous()), _ptr(wd.contiguous()), k, n, dt, beta,
+                                  _ptr(E), _ptr(D), _stream()), "hc_codec_weights")
+    return E, D
+
+
+class CodecWorkspace:
+    """Scratch memory for codec steps of one shape (kept across steps)."""
+
+    def __init__(self, k: int, n: int, N: int, device):
+        self.bytes = int(load().hc_codec_workspace_size(k, n, N))
+        self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+
+
+def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a=None, idx_b=None,
+               loss=None, grad_e=None, grad_d=None, adam: dict | None = None,
+               workspace: CodecWorkspace | None = None):
+    """One loss/gradient (and optional Adam) evaluation on the GPU.
+
+    A, B: (rows, n) tensors of the parameters' dtype; with idx_a/idx_b the
+    batch rows are gathered by index.  adam: dict with m_E, v_E, m_D, v_D,
+    step (int64 device tensor), lr, beta1, beta2, eps.  Returns the loss tensor.
+    """
+    _dev(we, wd, A, B)
+    k, n = we.shape
+    dt = 1 if we.dtype == torch.float64 else 0
+    if loss is None:
+        loss = torch.empty((), dtype=we.dtype, device=we.device)
+    workspace = workspace or CodecWorkspace(k, n, N, we.device)
+    ad = None
+    if adam is not None:
+        ad = _lib.Adam(adam["m_E"].data_ptr(), adam["v_E"].data_ptr(), adam["m_D"].data_ptr(),
+                       adam["v_D"].data_ptr(), adam["step"].data_ptr(), adam.get("lr", 1e-3),
+                       adam.get("beta1", 0.9), adam.get("beta2", 0.999), adam.get("eps", 1e-8))
+    args = _lib.CodecArgs(
+        k, n, dt, 0, beta, lam, we.data_ptr(), wd.data_ptr(), A.data_ptr(), B.data_ptr(),
+        A.stride(0), B.stride(0), A.shape[0], B.shape[0],
+        None if idx_a is None else idx_a.data_ptr(), None if idx_b is None else idx_b.data_ptr(),
+        N, loss.data_ptr(), None if grad_e is None else grad_e.data_ptr(),
+        None if grad_d is None else grad_d.data_ptr(), C.pointer(ad) if ad is not None else None,
+        workspace.buf.data_ptr(), workspace.bytes, torch.cuda.current_stream().cuda_stream)
+    check(load().hc_codec_step(C.byref(args)), "hc_codec_step")
+    return loss
+
+
+def gen_paths(n_pixels: int, spp: int, l_min: int, l_max: int, n_tex: int, n_illum: int, seed: int,
+              device="cuda") -> Paths:
+    """Generate a frame's records on the GPU (same draws as synth.gen_paths)."""
+    g = _lib.PathGen(n_pixels, spp, l_min, l_max, n_illum, n_tex, seed)
+    hdr = torch.empty(n_pixels * spp, dtype=torch.int32, device=device)
+    pf = torch.empty(n_pixels, dtype=torch.int32, device=device)
+    total = torch.empty(1, dtype=torch.int64, device=device)
+    wsb = int(load().hc_gen_workspace_size(n_pixels))
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=device)
+    check(load().hc_gen_path_headers(C.byref(g), _ptr(hdr), _ptr(pf), _ptr(total), _ptr(ws), wsb,
+                                     _stream()), "hc_gen_path_headers")
+    nv = int(total.item())
+    if nv >= 1 << 32:
+        raise ValueError(f"{nv} vertex records exceed the 2^32 limit of one frame")
+    vtx = torch.empty(nv, 2, dtype=torch.int32, device=device)
+    check(load().hc_gen_path_vertices(C.byref(g), _ptr(pf), _ptr(vtx), nv, _stream()),
+          "hc_gen_path_vertices")
+    return Paths(hdr, pf, vtx, n_pixels, spp)
+
+
+def gen_indices(seed: int, count: int, n: int, ctr0: int = 0, step: torch.Tensor | None = None,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """count uniform indices in [0, n) (same draws as synth.uniform_indices)."""
+    dev = step.device if step is not None else "cuda"
+    if out is None:
+        out = torch.empty(count, dtype=torch.int32, device=dev)
+    check(load().hc_gen_indices(seed, ctr0, _ptr(step), count, n, _ptr(out), _stream()),
+          "hc_gen_indices")
+    return out

@@ -1,0 +1,97 @@
+"""The C-ABI library loads, exports every declared function, and rejects
+bad arguments on the host before touching the GPU (no compute calls)."""
+
+import ctypes as C
+
+import pytest
+
+from paper_2602_18741_amd import _lib
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_every_declared_function_is_exported(lib):
+    names = _lib.declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib._PROTOS, f"{name} has no ctypes prototype"
+
+
+def test_status_strings(lib):
+    assert _lib.status_name(_lib.HC_OK) == "HC_OK"
+    assert _lib.status_name(_lib.HC_ESHAPE) == "HC_ESHAPE"
+    assert _lib.status_name(99) == "HC_UNKNOWN"
+    assert lib.hc_version() >= 100
+
+
+def test_struct_sizes_match_header():
+    # sizes implied by include/hc.h on LP64
+    assert C.sizeof(_lib.Paths) == 48
+    assert C.sizeof(_lib.SpectralAssets) == 56
+    assert C.sizeof(_lib.LatentAssets) == 56
+    assert C.sizeof(_lib.Adam) == 72
+    assert C.sizeof(_lib.PathGen) == 40
+
+
+def _err(status):
+    return status, _lib.load().hc_last_error().decode()
+
+
+def test_encode_rejects_bad_shapes(lib):
+    s, msg = _err(lib.hc_encode(None, 0, 31, None, 10, 32, None, 8, None))
+    assert s == _lib.HC_ESHAPE and "k=0" in msg
+    s, msg = _err(lib.hc_encode(None, 6, 129, None, 10, 132, None, 8, None))
+    assert s == _lib.HC_ESHAPE
+    s, msg = _err(lib.hc_encode(None, 6, 31, None, 10, 31, None, 8, None))
+    assert s == _lib.HC_ESHAPE and "ld_s" in msg
+    s, msg = _err(lib.hc_encode(None, 6, 31, None, 10, 32, None, 6, None))
+    assert s == _lib.HC_ESHAPE and "ld_z" in msg
+    s, msg = _err(lib.hc_encode(None, 6, 31, None, 10, 32, None, 8, None))
+    assert s == _lib.HC_EINVAL
+    # misaligned pointers (never dereferenced: the check comes first)
+    s, msg = _err(lib.hc_encode(C.c_void_p(0x1000), 6, 31, C.c_void_p(0x1004), 10, 32,
+                                C.c_void_p(0x2000), 8, None))
+    assert s == _lib.HC_EALIGN
+    # an empty batch is a valid no-op
+    assert lib.hc_encode(None, 6, 31, None, 0, 32, None, 8, None) == _lib.HC_OK
+
+
+def test_shade_rejects_bad_records(lib):
+    P = _lib.Paths(10, 0, 0, None, None, None, 0)
+    A = _lib.SpectralAssets(None, 1, 31, 0, 32, None, 1, 0, 32)
+    s, msg = _err(lib.hc_shade_spectral(C.byref(P), C.byref(A), None, None, None))
+    assert s == _lib.HC_ESHAPE and "spp" in msg
+    P = _lib.Paths(10, 4, 0, None, None, None, 0)
+    s, msg = _err(lib.hc_shade_spectral(C.byref(P), C.byref(A), None, None, None))
+    assert s == _lib.HC_EINVAL
+    P = _lib.Paths(10, 4, 0, 0x1000, 0x1000, 0x1004, 5)
+    L = _lib.LatentAssets(0x1000, 4, 6, 0, 8, 0x1000, 2, 0, 8)
+    s, msg = _err(lib.hc_shade_latent(C.byref(P), C.byref(L), 0, 2, C.c_void_p(0x1000), 8, None))
+    assert s == _lib.HC_EALIGN and "vtx" in msg
+    P = _lib.Paths(10, 4, 0, 0x1000, 0x1000, 0x1000, 5)
+    s, msg = _err(lib.hc_shade_latent(C.byref(P), C.byref(L), 1, 2, C.c_void_p(0x1000), 8, None))
+    assert s == _lib.HC_ESHAPE and "blocks" in msg
+    P = _lib.Paths(0, 4, 0, None, None, None, 0)
+    assert lib.hc_shade_latent(C.byref(P), C.byref(L), 0, 2, None, 8, None) == _lib.HC_OK
+
+
+def test_codec_step_rejects_small_workspace(lib):
+    need = lib.hc_codec_workspace_size(6, 31, 65536)
+    assert need > 0
+    args = _lib.CodecArgs(6, 31, 0, 0, 10.0, 1.0, 0x1000, 0x1000, 0x1000, 0x1000, 31, 31,
+                          65536, 65536, None, None, 65536, 0x1000, None, None, None,
+                          0x1000, need - 8, None)
+    s, msg = _err(lib.hc_codec_step(C.byref(args)))
+    assert s == _lib.HC_ENOMEM and str(need) in msg
+    args.dtype = 2
+    assert lib.hc_codec_step(C.byref(args)) == _lib.HC_EINVAL
+
+
+def test_gen_rejects_bad_lengths(lib):
+    g = _lib.PathGen(16, 4, 3, 2, 8, 64, 1)
+    s, msg = _err(lib.hc_gen_path_headers(C.byref(g), None, None, None, None, 0, None))
+    assert s == _lib.HC_ESHAPE and "l_min" in msg

@@ -1,0 +1,157 @@
+"""GPU codec-fit step (loss, hand-written gradient, Adam) against the oracle.
+
+Gradients: per element |g - g_ref| <= 1e-4 max(|g_ref|, 1e-3 |g_ref|_inf)
+and |g - g_ref|_2 <= 1e-4 |g_ref|_2 (float32 instance); the float64 instance
+matches the oracle to 1e-10 and central finite differences of the oracle's
+loss to 1e-7.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import codec as oc
+from tests.gpu_util import to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_18741_amd import ops as o
+    return o
+
+
+def _grad_ok(g, ref, rel=1e-4):
+    g, ref = np.asarray(g, np.float64), np.asarray(ref, np.float64)
+    floor = 1e-3 * np.abs(ref).max()
+    elem = (np.abs(g - ref) <= rel * np.maximum(np.abs(ref), floor)).all()
+    norm = np.linalg.norm(g - ref) <= rel * np.linalg.norm(ref)
+    return bool(elem and norm)
+
+
+def _pairs(n, N, seed):
+    rng = np.random.default_rng(seed)
+    return (synth.reflectances(rng, n, N),
+            synth.illuminant_table(rng, n, N // 2, N - N // 2))
+
+
+@pytest.mark.parametrize("n,k", [(31, 6), (31, 9), (81, 9), (81, 6)])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_loss_and_gradient_fp32(ops, n, k, seed):
+    N = 65536 if seed == 0 else 4099
+    rng = np.random.default_rng(seed)
+    we, wd = synth.codec_init(rng, k, n)
+    A, B = _pairs(n, N, 100 + seed)
+    ge = torch.empty(k, n, device="cuda")
+    gd = torch.empty(n, k, device="cuda")
+    loss = ops.codec_step(torch.from_numpy(we).cuda(), torch.from_numpy(wd).cuda(),
+                          torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), N,
+                          grad_e=ge, grad_d=gd)
+    torch.cuda.synchronize()
+    L, rge, rgd = oc.loss_and_grad(we, wd, A, B, 1.0, 10.0)
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert _grad_ok(to_np(ge), rge) and _grad_ok(to_np(gd), rgd)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_fp64_gradient_matches_oracle_and_finite_differences(ops, seed):
+    n, k, N = 31, 6, 512
+    rng = np.random.default_rng(200 + seed)
+    we, wd = (x.astype(np.float64) for x in synth.codec_init(rng, k, n))
+    A, B = (x.astype(np.float64) for x in _pairs(n, N, 300 + seed))
+    ge = torch.empty(k, n, dtype=torch.float64, device="cuda")
+    gd = torch.empty(n, k, dtype=torch.float64, device="cuda")
+    loss = ops.codec_step(torch.from_numpy(we).cuda(), torch.from_numpy(wd).cuda(),
+                          torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), N, grad_e=ge,
+                          grad_d=gd)
+    torch.cuda.synchronize()
+    L, rge, rgd = oc.loss_and_grad(we, wd, A, B)
+    assert abs(float(loss) - L) <= 1e-12 * L
+    assert np.allclose(to_np(ge), rge, rtol=1e-10, atol=1e-13 * np.abs(rge).max())
+    assert np.allclose(to_np(gd), rgd, rtol=1e-10, atol=1e-13 * np.abs(rgd).max())
+    h = 1e-6
+    scale = max(np.abs(rge).max(), np.abs(rgd).max())
+    for idx in [(int(rng.integers(k)), int(rng.integers(n))) for _ in range(4)]:
+        wp, wm = we.copy(), we.copy()
+        wp[idx] += h
+        wm[idx] -= h
+        fd = (oc.loss(wp, wd, A, B) - oc.loss(wm, wd, A, B)) / (2 * h)
+        assert abs(fd - to_np(ge)[idx]) <= 1e-7 * scale
+
+
+def test_gather_by_index_equals_explicit_batch(ops):
+    n, k, N = 31, 6, 5000
+    rng = np.random.default_rng(4)
+    we, wd = synth.codec_init(rng, k, n)
+    pa, pb = _pairs(n, 20000, 5)
+    ia = synth.uniform_indices(1, 0, N, 20000)
+    ib = synth.uniform_indices(2, 0, N, 20000)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()  # noqa: E731
+    g1 = [torch.empty(k, n, device="cuda"), torch.empty(n, k, device="cuda")]
+    g2 = [torch.empty(k, n, device="cuda"), torch.empty(n, k, device="cuda")]
+    l1 = ops.codec_step(t(we), t(wd), t(pa), t(pb), N, idx_a=t(ia.view(np.int32)),
+                        idx_b=t(ib.view(np.int32)), grad_e=g1[0], grad_d=g1[1])
+    l2 = ops.codec_step(t(we), t(wd), t(pa[ia]), t(pb[ib]), N, grad_e=g2[0], grad_d=g2[1])
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2) and torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])
+
+
+def test_step_is_deterministic(ops):
+    n, k, N = 81, 9, 65536
+    rng = np.random.default_rng(6)
+    we, wd = synth.codec_init(rng, k, n)
+    A, B = _pairs(n, N, 7)
+    outs = []
+    for _ in range(2):
+        ge = torch.empty(k, n, device="cuda")
+        gd = torch.empty(n, k, device="cuda")
+        loss = ops.codec_step(torch.from_numpy(we).cuda(), torch.from_numpy(wd).cuda(),
+                              torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), N,
+                              grad_e=ge, grad_d=gd)
+        outs.append((loss.clone(), ge, gd))
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(outs[0], outs[1]))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_adam_steps_match_oracle(ops, dtype):
+    """Ten fused steps (gradient + Adam in place) against the oracle's gradient
+    and Adam applied step by step."""
+    n, k, N = 31, 6, 2048
+    rng = np.random.default_rng(8)
+    we, wd = (x.astype(np.float64) for x in synth.codec_init(rng, k, n))
+    A, B = _pairs(n, N, 9)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x.astype(npdt))).cuda()  # noqa: E731
+    Wt_E, Wt_D, At, Bt = t(we), t(wd), t(A), t(B)
+    st = dict(m_E=torch.zeros_like(Wt_E), v_E=torch.zeros_like(Wt_E), m_D=torch.zeros_like(Wt_D),
+              v_D=torch.zeros_like(Wt_D), step=torch.zeros(1, dtype=torch.int64, device="cuda"),
+              lr=1e-3)
+    opt = oc.Adam([we.shape, wd.shape], lr=1e-3)
+    ref = [we.astype(npdt).astype(np.float64), wd.astype(npdt).astype(np.float64)]
+    ws = ops.CodecWorkspace(k, n, N, "cuda")
+    # smallest |gradient| relative to the largest, per element over the steps:
+    # Adam's first steps move each weight by about lr * sign(g), so where |g|
+    # is at the float32 rounding level the sign itself is not determined
+    weak = [np.full(we.shape, np.inf), np.full(wd.shape, np.inf)]
+    for _ in range(10):
+        ops.codec_step(Wt_E, Wt_D, At, Bt, N, adam=st, workspace=ws)
+        _, ge, gd = oc.loss_and_grad(ref[0], ref[1], A.astype(npdt), B.astype(npdt))
+        top = max(np.abs(ge).max(), np.abs(gd).max())
+        weak = [np.minimum(weak[0], np.abs(ge) / top), np.minimum(weak[1], np.abs(gd) / top)]
+        ref = opt.step(ref, [ge, gd])
+    torch.cuda.synchronize()
+    assert int(st["step"].item()) == 10
+    if dtype == torch.float64:
+        assert np.allclose(to_np(Wt_E), ref[0], rtol=1e-10, atol=1e-12)
+        assert np.allclose(to_np(Wt_D), ref[1], rtol=1e-10, atol=1e-12)
+    else:
+        for got, want, w in zip((to_np(Wt_E), to_np(Wt_D)), ref, weak):
+            firm = w > 1e-4
+            assert firm.mean() > 0.95
+            assert np.abs(got - want)[firm].max() <= 2e-6
+            assert np.abs(got - want).max() <= 2 * 10 * 1e-3
