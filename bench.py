@@ -1,0 +1,311 @@
+"""Benchmark of the latent (k = 6) and spectral (n = 31) light-path paths on one GPU.
+
+Workload: 1920 x 1080 pixels, 16 samples per pixel, path length uniform in
+1..4 reflectance vertices, a 1024^2 x 31 Perlin-blended spectral texture
+sampled at uniform random texels, 32 lights (16 Planckian, 16 narrow-band).
+All inputs are seeded synthetic data resident in HBM before timing.
+
+A timed step is one latent frame: encode the texture and the lights with the
+codec (Eq. 4), shade every path in code space with the fused B = 2 blockwise
+passes and the per-pixel sample mean (Eq. 6), decode the latent image to XYZ.
+`value` is path-vertices per second of that step.  The spectral form of the
+same frame is timed the same way for the latent/spectral speedup, and the
+CIEDE2000 of latent against spectral XYZ is reported under a codec fitted on
+the GPU beforehand.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "1920x1080 px, 16 spp, path length 1-4, 1024^2 x 31 Perlin texture, 32 lights, latent k=6"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ CPU baseline (oracle)
+
+_W = None
+
+
+def _oracle_chunk(pixels):
+    """Oracle latent pipeline (FP64) on a chunk of frame pixels; returns
+    (path-vertices, seconds)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import shade as osh
+    from synth import records_of_pixels
+    w = _W
+    hdr, pf, vtx = records_of_pixels(w["paths"], pixels)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        osh.render_latent_xyz(hdr, pf, vtx, w["paths"].spp, w["refl"], w["illum"], w["E"], w["D"],
+                              w["T"])
+        dt = time.perf_counter() - t0
+    return int(vtx.shape[0]), dt
+
+
+def cpu_baseline(w, n_pixels=None, chunk=32768):
+    """Time the oracle on a pixel sample of the frame with a pool of worker
+    processes (forked before any GPU use, one BLAS thread each)."""
+    import multiprocessing as mp
+    import numpy as np
+    global _W
+    _W = w
+    workers = max(1, min(16, os.cpu_count() or 1))
+    if n_pixels is None:
+        n_pixels = w["paths"].n_pixels
+    rng = np.random.default_rng(12)
+    pix = np.sort(rng.choice(w["paths"].n_pixels, n_pixels, replace=False))
+    chunks = [pix[i:i + chunk] for i in range(0, n_pixels, chunk)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_chunk, chunks)
+        wall = time.perf_counter() - t0
+    verts = sum(r[0] for r in res)
+    return {"value": verts / wall, "unit": "path-vertices/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n_pixels} pixels of the frame ({verts} path-vertices), FP64 numpy "
+                      f"latent pipeline (encode, shade, decode) in {len(chunks)} chunks, "
+                      f"{wall:.2f} s wall, {sum(r[1] for r in res):.1f} core-s"}
+
+
+# ------------------------------------------------------------------ GPU part
+
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "shade_latent_1080p16_traffic.json")
+
+
+def kernel_source_sha():
+    """Digest of the sources the latent shading kernel is built from."""
+    h = hashlib.sha256()
+    for f in ("k_latent.hip", "shade_common.hpp", "hc_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2602_18741_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _counter_mean(csv_path, kernel_substr, counter):
+    import csv
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
+            if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {kernel_substr} in {csv_path}")
+    return sum(vals) / len(vals)
+
+
+def record_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """Write the HBM traffic of one latent shading launch from rocprofv3 --pmc
+    CSVs: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the kernel, each
+    scaled by the ratio of the true bytes of a 1 GiB device copy to what the
+    same counter reads for that copy."""
+    gib_kib = float(1 << 20)
+    f_scale = gib_kib / _counter_mean(copy_fetch_csv, "copyBuffer", "FETCH_SIZE")
+    w_scale = gib_kib / _counter_mean(copy_write_csv, "copyBuffer", "WRITE_SIZE")
+    fetch = _counter_mean(fetch_csv, "shade_latent_kernel", "FETCH_SIZE") * 1024 * f_scale
+    write = _counter_mean(write_csv, "shade_latent_kernel", "WRITE_SIZE") * 1024 * w_scale
+    d = {"kernel": "shade_latent_kernel<2>", "workload": WORKLOAD,
+         "kernel_source_sha": kernel_source_sha(), "fetch_scale": f_scale, "write_scale": w_scale,
+         "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+         "hbm_bytes_per_launch": fetch + write}
+    json.dump(d, open(TRAFFIC_JSON, "w"), indent=1)
+    print(json.dumps(d))
+
+
+def measured_traffic(bytes_alg):
+    """HBM bytes per shade_latent launch from the committed counter profile,
+    if it was taken with the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    d = json.load(open(TRAFFIC_JSON))
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--k", type=int, default=6)
+    ap.add_argument("--codec-steps", type=int, default=2000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--record-traffic", nargs=4, metavar="CSV",
+                    help="fetch, write, copy-fetch, copy-write counter CSVs -> traffic record")
+    ap.add_argument("--only", choices=["latent", "spectral", "copy"],
+                    help="run only the timed steps of one form (or a 1 GiB device copy), "
+                         "for profilers; prints no JSON")
+    args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path "
+              "(rows would shard by pixel range with no exchange step).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import synth
+
+    if args.only == "copy":
+        import torch
+        x = torch.ones(1 << 28, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(args.warmup + args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copied 1 GiB", args.warmup + args.steps, "times")
+        return
+
+    t_setup = time.time()
+    w = synth.workload(1, k=args.k)
+    spec = w["paths"]
+    log(f"inputs generated in {time.time() - t_setup:.1f} s")
+    cpu = None if (args.no_cpu or args.only) else cpu_baseline(w)
+    if cpu:
+        log("cpu baseline:", cpu["sample"])
+
+    import torch
+    from paper_2602_18741_amd import colour, ops
+    from paper_2602_18741_amd.codec_fit import CodecFit
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    k, n = args.k, 31
+    refl = ops.padded(torch.from_numpy(w["refl"]).to(dev))
+    illum = ops.padded(torch.from_numpy(w["illum"]).to(dev))
+    T = torch.from_numpy(w["T"]).to(dev)
+    P = ops.gen_paths(spec.n_pixels, spec.spp, spec.l_min, spec.l_max, spec.n_tex, spec.n_illum,
+                      spec.seed, device=dev)
+    bad = ops.check_paths(P, spec.n_tex, spec.n_illum)
+    assert int(bad.sum()) == 0, "generated records failed the check"
+    nv, npath, npx = P.n_vertices, spec.n_paths, spec.n_pixels
+    log(f"frame: {npx} px, {npath} paths, {nv} path-vertices")
+
+    # ---- codec fit on the GPU (reflectance / light pools, Adam, graph replay)
+    pa, pb = synth.workloads.codec_pools(n, 1 << 20 if not args.only else 1 << 16)
+    we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
+    fit = CodecFit(we0, wd0, torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev),
+                   batch=65536, lam=1.0, beta=10.0, lr=1e-3, seed=2)
+    codec_steps = 1 if args.only else args.codec_steps
+    fit.run(1)
+    fit.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = float(fit.run(codec_steps - 1))
+    torch.cuda.synchronize()
+    codec_ms = (time.perf_counter() - t0) * 1e3 / max(1, codec_steps - 1)
+    E, D = fit.weights()
+    log(f"codec fit: {fit.steps_done} steps, final loss {loss:.4g}, {codec_ms * 1e3:.1f} us/step")
+
+    codes = torch.empty(spec.n_tex, ops.latent_width(k), device=dev)
+    lcodes = torch.empty(spec.n_illum, ops.latent_width(k), device=dev)
+    zimg = torch.zeros(npx, ops.latent_width(k), device=dev)
+    xyz_l = torch.empty(npx, 3, device=dev)
+    xyz_s = torch.empty(npx, 3, device=dev)
+
+    def latent_step(ev=None):
+        ops.encode(E, refl, n=n, out=codes)
+        ops.encode(E, illum, n=n, out=lcodes)
+        if ev:
+            ev[0].record()
+        ops.shade_latent(P, codes, lcodes, k, out=zimg)
+        if ev:
+            ev[1].record()
+        ops.decode_xyz(D, T, zimg, k, out=xyz_l)
+
+    def spectral_step(ev=None):
+        if ev:
+            ev[0].record()
+        ops.shade_spectral(P, refl, illum, T, n, out=xyz_s)
+        if ev:
+            ev[1].record()
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e in evs:
+            step(e)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        kern = sum(a.elapsed_time(b) for a, b in evs) / args.steps / 1e3
+        return wall, kern
+
+    if args.only:
+        wall, kern = timed(latent_step if args.only == "latent" else spectral_step)
+        log(f"{args.only}: step {wall * 1e3:.3f} ms, shade kernel {kern * 1e3:.3f} ms")
+        return
+    lat_wall, lat_kern = timed(latent_step)
+    spe_wall, spe_kern = timed(spectral_step)
+    log(f"latent step {lat_wall * 1e3:.3f} ms (shade {lat_kern * 1e3:.3f} ms); "
+        f"spectral step {spe_wall * 1e3:.3f} ms")
+
+    bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
+    bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
+    achieved = bytes_lat / lat_kern / 1e9
+    traffic = measured_traffic(bytes_lat)
+
+    de = colour.frame_difference(xyz_s.cpu().numpy(), xyz_l.cpu().numpy())
+    log(f"CIEDE2000 latent vs spectral: mean {de['mean']:.3f}, p95 {de['p95']:.3f}")
+
+    serving = None
+    if not args.no_serve:
+        try:
+            from paper_2602_18741_amd.serve import bench_serving
+            serving = bench_serving(dev)
+        except ImportError:
+            serving = None
+
+    out = {
+        "metric": "path-vertices/s latent k=6 vs spectral n=31; HBM GB/s; p99 frame ms",
+        "value": nv / lat_wall,
+        "unit": "path-vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": lat_wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "pixels": npx, "spp": spec.spp, "paths": npath,
+                   "path_vertices": nv, "k": k, "n": n, "texels": spec.n_tex,
+                   "lights": spec.n_illum, "step": "encode texture+lights, shade latent, decode"},
+        "roofline": {"bound": "hbm", "kernel": "shade_latent_kernel<2>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes": bytes_lat,
+                     "kernel_ms": lat_kern * 1e3},
+        "cpu_baseline": cpu,
+        "spectral": {"value": nv / spe_wall, "unit": "path-vertices/s", "ms_per_step": spe_wall * 1e3,
+                     "kernel_ms": spe_kern * 1e3, "achieved_GBs": bytes_spe / spe_kern / 1e9,
+                     "algorithmic_bytes": bytes_spe},
+        "speedup_latent_vs_spectral": spe_wall / lat_wall,
+        "shade_speedup_latent_vs_spectral": spe_kern / lat_kern,
+        "ciede2000_latent_vs_spectral": de,
+        "codec_fit": {"steps": fit.steps_done, "batch": 65536, "final_loss": loss,
+                      "us_per_step": codec_ms * 1e3},
+        "serving": serving,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,95 @@
+"""Fitting the non-negative linear codec on the GPU (Sec. 4.3 objectives).
+
+Each step draws N (reflectance, light) pairs by index from device-resident
+pools with the counter-based index generator (the counter base is the Adam
+step counter, so a captured graph draws fresh pairs on every replay), then
+runs hc_codec_step with the fused Adam update.  The step can be captured
+once in a HIP graph and replayed.  State (parameters, Adam moments, step)
+round-trips through .npz checkpoints.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import ops
+
+
+class CodecFit:
+    def __init__(self, we0: np.ndarray, wd0: np.ndarray, pool_a: torch.Tensor, pool_b: torch.Tensor,
+                 batch: int = 65536, lam: float = 1.0, beta: float = 10.0, lr: float = 1e-3,
+                 seed: int = 0, dtype=torch.float32):
+        dev = pool_a.device
+        self.k, self.n = we0.shape
+        self.N, self.lam, self.beta, self.seed = batch, lam, beta, seed
+        self.Wt_E = torch.tensor(we0, dtype=dtype, device=dev)
+        self.Wt_D = torch.tensor(wd0, dtype=dtype, device=dev)
+        self.pool_a = pool_a.to(dtype).contiguous()
+        self.pool_b = pool_b.to(dtype).contiguous()
+        self.adam = dict(m_E=torch.zeros_like(self.Wt_E), v_E=torch.zeros_like(self.Wt_E),
+                         m_D=torch.zeros_like(self.Wt_D), v_D=torch.zeros_like(self.Wt_D),
+                         step=torch.zeros(1, dtype=torch.int64, device=dev), lr=lr,
+                         beta1=0.9, beta2=0.999, eps=1e-8)
+        self.idx_a = torch.empty(batch, dtype=torch.int32, device=dev)
+        self.idx_b = torch.empty(batch, dtype=torch.int32, device=dev)
+        self.loss = torch.zeros((), dtype=dtype, device=dev)
+        self.ws = ops.CodecWorkspace(self.k, self.n, batch, dev)
+        self.graph = None
+
+    def _step(self):
+        # indices for step t use counters [t*N, (t+1)*N) of two seeded streams
+        ops.gen_indices(2 * self.seed + 1, self.N, self.pool_a.shape[0], step=self.adam["step"],
+                        out=self.idx_a)
+        ops.gen_indices(2 * self.seed + 2, self.N, self.pool_b.shape[0], step=self.adam["step"],
+                        out=self.idx_b)
+        ops.codec_step(self.Wt_E, self.Wt_D, self.pool_a, self.pool_b, self.N, lam=self.lam,
+                       beta=self.beta, idx_a=self.idx_a, idx_b=self.idx_b, loss=self.loss,
+                       adam=self.adam, workspace=self.ws)
+
+    def capture(self):
+        """Record one step in a HIP graph (warm-up step first, as graph capture
+        needs the kernels loaded).  Later run() calls replay it."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self._step()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+
+    def run(self, steps: int):
+        for _ in range(steps):
+            if self.graph is not None:
+                self.graph.replay()
+            else:
+                self._step()
+        return self.loss
+
+    @property
+    def steps_done(self) -> int:
+        return int(self.adam["step"].item())
+
+    def weights(self):
+        """float32 E = softplus(Wt_E) (k x n) and D = softplus(Wt_D) (n x k)."""
+        return ops.codec_weights(self.Wt_E, self.Wt_D, self.beta)
+
+    def state_dict(self) -> dict:
+        d = {k: v.detach().cpu().numpy() for k, v in self.adam.items() if torch.is_tensor(v)}
+        d.update(Wt_E=self.Wt_E.cpu().numpy(), Wt_D=self.Wt_D.cpu().numpy(),
+                 meta=np.array([self.N, self.seed], dtype=np.int64),
+                 hyper=np.array([self.lam, self.beta, self.adam["lr"]], dtype=np.float64))
+        return d
+
+    def load_state_dict(self, d: dict):
+        for name in ("m_E", "v_E", "m_D", "v_D", "step"):
+            self.adam[name].copy_(torch.from_numpy(np.asarray(d[name])))
+        self.Wt_E.copy_(torch.from_numpy(np.asarray(d["Wt_E"])))
+        self.Wt_D.copy_(torch.from_numpy(np.asarray(d["Wt_D"])))
+
+    def save(self, path: str):
+        np.savez(path, **self.state_dict())
+
+    def load(self, path: str):
+        with np.load(path, allow_pickle=False) as f:
+            self.load_state_dict({k: f[k] for k in f.files})

@@ -34,6 +34,7 @@ from .paths import (  # noqa: F401
     PathSpec,
     gen_paths,
     path_records,
+    records_of_pixels,
     uniform_indices,
 )
 from .workloads import workload  # noqa: F401

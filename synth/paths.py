@@ -152,6 +152,22 @@ def path_records(spec: PathSpec, paths: np.ndarray):
             np.where(live, weight, np.float32(0)).astype(np.float32))
 
 
+def records_of_pixels(spec: PathSpec, pixels):
+    """Record arrays (hdr, pix_first, vtx) of a subset of a frame's pixels,
+    in the frame's layout, drawn without generating the whole frame."""
+    pixels = np.asarray(pixels, dtype=np.int64)
+    paths = (pixels[:, None] * spec.spp + np.arange(spec.spp)[None, :]).ravel()
+    length, light, tex, wt = path_records(spec, paths)
+    hdr = (light | (length << 24)).astype(np.uint32)
+    per_px = length.reshape(-1, spec.spp).sum(axis=1)
+    pf = np.zeros(pixels.size, dtype=np.uint32)
+    if pixels.size > 1:
+        pf[1:] = np.cumsum(per_px[:-1])
+    live = np.arange(tex.shape[1])[None, :] < length[:, None]
+    vtx = np.stack([tex[live].astype(np.uint32), wt[live].view(np.uint32)], axis=1)
+    return hdr, pf, vtx
+
+
 def uniform_indices(seed: int, ctr0: int, count: int, n: int) -> np.ndarray:
     """count indices uniform in [0, n) drawn at counters ctr0 .. ctr0+count-1."""
     r = rand64(stream_key(seed, STREAM_INDEX), np.arange(ctr0, ctr0 + count, dtype=np.uint64))
