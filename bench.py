@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--codec-steps", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=200,
+                    help="requests per arrival rate in the serving measurement")
     ap.add_argument("--record-traffic", nargs=4, metavar="CSV",
                     help="fetch, write, copy-fetch, copy-write counter CSVs -> traffic record")
     ap.add_argument("--only", choices=["latent", "spectral", "copy"],
@@ -267,11 +269,14 @@ def main():
 
     serving = None
     if not args.no_serve:
-        try:
-            from paper_2602_18741_amd.serve import bench_serving
-            serving = bench_serving(dev)
-        except ImportError:
-            serving = None
+        from paper_2602_18741_amd.serve import bench_serving
+        del P, zimg
+        torch.cuda.empty_cache()
+        t0 = time.time()
+        serving = bench_serving(dev, count=args.serve_count, E=E.cpu(), D=D.cpu())
+        log(f"serving measured in {time.time() - t0:.1f} s: " + ", ".join(
+            f"{form} {r} fps p50 {v['p50_ms']:.2f} p99 {v['p99_ms']:.2f} ms"
+            for form in ("latent", "spectral") for r, v in serving[form].items()))
 
     out = {
         "metric": "path-vertices/s latent k=6 vs spectral n=31; HBM GB/s; p99 frame ms",

@@ -177,6 +177,75 @@ hc_status hc_check_paths(const hc_paths* paths, int64_t n_texels, int32_t n_illu
                          uint64_t* counts, void* stream);
 
 /*
+ * Table-driven launches for serving many frames at once.
+ *
+ * A frame table entry describes one frame in either form: its records (as
+ * hc_paths), its texture (`tex`: latent codes in the blocked layout, or
+ * spectral rows) and light table (`lights`: light codes or light spectra),
+ * the latent image it writes (latent form only) and its n_pixels x 3 XYZ
+ * output.  A tile names a frame and a pixel range [begin, end).  The tables
+ * and the tile / job counts live in device memory, so a captured HIP graph
+ * can replay the same launches with new contents; each launch runs a fixed
+ * grid of `grid` workgroups that walk the table.  Tile entries whose frame
+ * index is out of [0, n_frames) are skipped and pixel ranges are clipped to
+ * the frame; the frame entries themselves must satisfy the preconditions of
+ * hc_shade_latent / hc_shade_spectral (they are not checked on the device).
+ * Per-pixel results equal those of the single-frame calls bit for bit: a
+ * pixel's samples are reduced inside one wavefront in the same order.
+ */
+typedef struct hc_frame {
+    const uint32_t* hdr;
+    const uint32_t* pix_first;
+    const uint32_t* vtx;
+    int64_t n_pixels;
+    int64_t n_vertices;
+    int32_t spp;
+    int32_t n_illum;
+    const float* tex;
+    int64_t n_texels;
+    int64_t ld_tex;
+    const float* lights;
+    int64_t ld_lights;
+    float* image;       /* latent image rows (latent form), stride ld_image */
+    int64_t ld_image;
+    float* xyz;         /* n_pixels x 3 */
+} hc_frame;
+
+typedef struct hc_tile {
+    int32_t frame;
+    int32_t reserved0;
+    int64_t begin;
+    int64_t end;
+} hc_tile;
+
+/* Latent shading (all B blocks fused) of the tiles; k shared by all frames. */
+hc_status hc_shade_latent_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
+                                const int32_t* n_tiles, int32_t max_tiles, int32_t k, int32_t grid,
+                                void* stream);
+/* Spectral shading of the tiles (n samples, T = T_cmf 3 x n) into frame xyz. */
+hc_status hc_shade_spectral_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
+                                  const int32_t* n_tiles, int32_t max_tiles, int32_t n,
+                                  const float* T, int32_t grid, void* stream);
+/* Decode of the tiles' latent pixels to XYZ with one codec (as hc_decode_xyz). */
+hc_status hc_decode_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
+                          const int32_t* n_tiles, int32_t max_tiles, const float* D, int32_t n,
+                          int32_t k, const float* T, int32_t grid, void* stream);
+
+/* Encode of many spectra arrays with one encoder (as hc_encode, rows
+ * [begin, end) of S into Z); jobs and n_jobs in device memory. */
+typedef struct hc_encode_job {
+    const float* S;
+    float* Z;
+    int64_t ld_s;
+    int64_t ld_z;
+    int64_t begin;
+    int64_t end;
+} hc_encode_job;
+
+hc_status hc_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int32_t max_jobs,
+                         const float* E, int32_t k, int32_t n, int32_t grid, void* stream);
+
+/*
  * Codec fitting (Sec. 4.3 objectives with softplus weights, Eq. 5).
  *
  * Parameters Wt_E (k x n) and Wt_D (n x k), row-major; the codec is

@@ -60,6 +60,20 @@ class PathGen(C.Structure):
                 ("n_tex", i64), ("seed", u64)]
 
 
+class Frame(C.Structure):
+    _fields_ = [("hdr", vp), ("pix_first", vp), ("vtx", vp), ("n_pixels", i64), ("n_vertices", i64),
+                ("spp", i32), ("n_illum", i32), ("tex", vp), ("n_texels", i64), ("ld_tex", i64),
+                ("lights", vp), ("ld_lights", i64), ("image", vp), ("ld_image", i64), ("xyz", vp)]
+
+
+class Tile(C.Structure):
+    _fields_ = [("frame", i32), ("reserved0", i32), ("begin", i64), ("end", i64)]
+
+
+class EncodeJob(C.Structure):
+    _fields_ = [("S", vp), ("Z", vp), ("ld_s", i64), ("ld_z", i64), ("begin", i64), ("end", i64)]
+
+
 _PROTOS = {
     "hc_status_string": (C.c_char_p, [i32]),
     "hc_last_error": (C.c_char_p, []),
@@ -72,6 +86,10 @@ _PROTOS = {
     "hc_codec_workspace_size": (sz, [i32, i32, i64]),
     "hc_codec_step": (i32, [C.POINTER(CodecArgs)]),
     "hc_codec_weights": (i32, [vp, vp, i32, i32, i32, f64, vp, vp, vp]),
+    "hc_shade_latent_tiles": (i32, [vp, i32, vp, vp, i32, i32, i32, vp]),
+    "hc_shade_spectral_tiles": (i32, [vp, i32, vp, vp, i32, i32, vp, i32, vp]),
+    "hc_decode_tiles": (i32, [vp, i32, vp, vp, i32, vp, i32, i32, vp, i32, vp]),
+    "hc_encode_jobs": (i32, [vp, vp, i32, vp, i32, i32, i32, vp]),
     "hc_gen_workspace_size": (sz, [i64]),
     "hc_gen_path_headers": (i32, [C.POINTER(PathGen), vp, vp, vp, vp, sz, vp]),
     "hc_gen_path_vertices": (i32, [C.POINTER(PathGen), vp, vp, i64, vp]),

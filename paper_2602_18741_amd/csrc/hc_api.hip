@@ -175,6 +175,67 @@ hc_status hc_decode_xyz(const float* D, int32_t n, int32_t k, const float* T, co
                          as_stream(stream));
 }
 
+static hc_status check_tables(const void* frames, int32_t n_frames, const void* tiles,
+                              const int32_t* n_tiles, int32_t max_tiles, int32_t grid, const char* fn) {
+    HC_REQUIRE(frames && tiles && n_tiles, HC_EINVAL, "%s: NULL table pointer", fn);
+    HC_REQUIRE(aligned8(frames) && aligned8(tiles) && aligned4(n_tiles), HC_EALIGN,
+               "%s: tables must be 8-byte aligned", fn);
+    HC_REQUIRE(n_frames >= 1 && max_tiles >= 1, HC_ESHAPE, "%s: n_frames and max_tiles must be >= 1",
+               fn);
+    HC_REQUIRE(grid >= 1 && grid <= 65536, HC_ESHAPE, "%s: grid must be in [1, 65536]", fn);
+    return HC_OK;
+}
+
+hc_status hc_shade_latent_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
+                                const int32_t* n_tiles, int32_t max_tiles, int32_t k, int32_t grid,
+                                void* stream) {
+    clear_error();
+    const char* fn = "hc_shade_latent_tiles";
+    hc_status s = check_tables(frames, n_frames, tiles, n_tiles, max_tiles, grid, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(k >= 1 && k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, k, kMaxK);
+    return launch_shade_latent_tiles(frames, n_frames, tiles, n_tiles, max_tiles, k, grid,
+                                     as_stream(stream));
+}
+
+hc_status hc_shade_spectral_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
+                                  const int32_t* n_tiles, int32_t max_tiles, int32_t n, const float* T,
+                                  int32_t grid, void* stream) {
+    clear_error();
+    const char* fn = "hc_shade_spectral_tiles";
+    hc_status s = check_tables(frames, n_frames, tiles, n_tiles, max_tiles, grid, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(n >= 1 && n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, n, kMaxN);
+    HC_REQUIRE(T && aligned4(T), HC_EINVAL, "%s: T NULL or misaligned", fn);
+    return launch_shade_spectral_tiles(frames, n_frames, tiles, n_tiles, max_tiles, n, T, grid,
+                                       as_stream(stream));
+}
+
+hc_status hc_decode_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
+                          const int32_t* n_tiles, int32_t max_tiles, const float* D, int32_t n,
+                          int32_t k, const float* T, int32_t grid, void* stream) {
+    clear_error();
+    const char* fn = "hc_decode_tiles";
+    hc_status s = check_tables(frames, n_frames, tiles, n_tiles, max_tiles, grid, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(k >= 1 && k <= kMaxK && n >= 1 && n <= kMaxN, HC_ESHAPE, "%s: bad k or n", fn);
+    HC_REQUIRE(D && T && aligned4(D) && aligned4(T), HC_EINVAL, "%s: D/T NULL or misaligned", fn);
+    return launch_decode_tiles(frames, n_frames, tiles, n_tiles, max_tiles, D, n, k, T, grid,
+                               as_stream(stream));
+}
+
+hc_status hc_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int32_t max_jobs,
+                         const float* E, int32_t k, int32_t n, int32_t grid, void* stream) {
+    clear_error();
+    const char* fn = "hc_encode_jobs";
+    HC_REQUIRE(jobs && n_jobs && E, HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned8(jobs) && aligned4(n_jobs) && aligned4(E), HC_EALIGN, "%s: misaligned table",
+               fn);
+    HC_REQUIRE(k >= 1 && k <= kMaxK && n >= 1 && n <= kMaxN, HC_ESHAPE, "%s: bad k or n", fn);
+    HC_REQUIRE(max_jobs >= 1 && grid >= 1 && grid <= 65536, HC_ESHAPE, "%s: bad max_jobs or grid", fn);
+    return launch_encode_jobs(jobs, n_jobs, max_jobs, E, k, n, grid, as_stream(stream));
+}
+
 hc_status hc_check_paths(const hc_paths* paths, int64_t n_texels, int32_t n_illum, uint64_t* counts,
                          void* stream) {
     clear_error();

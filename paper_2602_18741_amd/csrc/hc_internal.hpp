@@ -65,6 +65,17 @@ hc_status launch_shade_spectral(const hc_paths& P, const hc_spectral_assets& A, 
                                 float* xyz, hipStream_t st);
 hc_status launch_shade_latent(const hc_paths& P, const hc_latent_assets& A, int block_first,
                               int block_count, float* zimg, int64_t ld_zimg, hipStream_t st);
+hc_status launch_shade_latent_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
+                                    const int32_t* n_tiles, int max_tiles, int k, int grid,
+                                    hipStream_t st);
+hc_status launch_shade_spectral_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
+                                      const int32_t* n_tiles, int max_tiles, int n, const float* T,
+                                      int grid, hipStream_t st);
+hc_status launch_decode_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
+                              const int32_t* n_tiles, int max_tiles, const float* D, int n, int k,
+                              const float* T, int grid, hipStream_t st);
+hc_status launch_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int max_jobs,
+                             const float* E, int k, int n, int grid, hipStream_t st);
 hc_status launch_check_paths(const hc_paths& P, int64_t n_texels, int32_t n_illum,
                              uint64_t* counts, hipStream_t st);
 hc_status launch_codec_step(const hc_codec_args& a);

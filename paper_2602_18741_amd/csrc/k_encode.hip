@@ -20,21 +20,25 @@ struct EncodeArgs {
     int rows;        // rows per block (256 / 128 / 64)
 };
 
-// Block: stage `rows` spectra (coalesced float4 loads) and E in LDS, then one
-// thread per row accumulates the k codes over the n samples in order.
+// Stage E (zero rows past k) into LDS.
 template <int NB>
-__global__ __launch_bounds__(kThreads) void encode_kernel(EncodeArgs a) {
-    extern __shared__ float smem[];
-    const int stride = 4 * a.nq + 1;  // odd stride: a thread's row reads hit distinct banks
-    float* s_rows = smem;
-    float* s_E = smem + a.rows * stride;
+__device__ __forceinline__ void stage_encoder(const float* E, int k, int n, float* s_E) {
+    for (int i = threadIdx.x; i < 3 * NB * n; i += kThreads) s_E[i] = (i < k * n) ? E[i] : 0.f;
+}
+
+// Encode rows [r0, r0 + nrows) (nrows <= rows per block): stage the spectra
+// with coalesced float4 loads, then one thread per row accumulates the codes
+// over the n samples in order.  Starts and ends with a block barrier.
+template <int NB>
+__device__ __forceinline__ void encode_rows(const float* s_E, float* s_rows, int n, int nq,
+                                            const float* S, int64_t ld_s, float* Z, int64_t ld_z,
+                                            int64_t r0, int nrows) {
+    const int stride = 4 * nq + 1;  // odd stride: a thread's row reads hit distinct banks
     const int tid = threadIdx.x;
-    for (int i = tid; i < 3 * NB * a.n; i += kThreads) s_E[i] = (i < a.k * a.n) ? a.E[i] : 0.f;
-    const int64_t r0 = int64_t(blockIdx.x) * a.rows;
-    const int nrows = int(min<int64_t>(a.rows, a.m - r0));
-    for (int i = tid; i < nrows * a.nq; i += kThreads) {
-        const int r = i / a.nq, c = i % a.nq;
-        const float4 v = ld4(a.S + (r0 + r) * a.ld_s + 4 * c);
+    __syncthreads();
+    for (int i = tid; i < nrows * nq; i += kThreads) {
+        const int r = i / nq, c = i % nq;
+        const float4 v = ld4(S + (r0 + r) * ld_s + 4 * c);
         float* d = s_rows + r * stride + 4 * c;
         d[0] = v.x;
         d[1] = v.y;
@@ -42,21 +46,52 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncodeArgs a) {
         d[3] = v.w;
     }
     __syncthreads();
-    if (tid >= nrows) return;
-    const float* s = s_rows + tid * stride;
-    // channels past k read zero rows of E (staged that way), so they stay 0
-    float z[3 * NB];
+    if (tid < nrows) {
+        const float* s = s_rows + tid * stride;
+        // channels past k read zero rows of E (staged that way), so they stay 0
+        float z[3 * NB];
 #pragma unroll
-    for (int c = 0; c < 3 * NB; ++c) z[c] = 0.f;
-    for (int i = 0; i < a.n; ++i) {
-        const float si = s[i];
+        for (int c = 0; c < 3 * NB; ++c) z[c] = 0.f;
+        for (int i = 0; i < n; ++i) {
+            const float si = s[i];
 #pragma unroll
-        for (int c = 0; c < 3 * NB; ++c) z[c] += s_E[c * a.n + i] * si;
+            for (int c = 0; c < 3 * NB; ++c) z[c] += s_E[c * n + i] * si;
+        }
+        float* out = Z + (r0 + tid) * ld_z;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) st4(out + 4 * b, make_float4(z[3 * b], z[3 * b + 1], z[3 * b + 2], 0.f));
+        for (int64_t f = 4 * NB; f < ld_z; f += 4) st4(out + f, make_float4(0.f, 0.f, 0.f, 0.f));
     }
-    float* out = a.Z + (r0 + tid) * a.ld_z;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) st4(out + 4 * b, make_float4(z[3 * b], z[3 * b + 1], z[3 * b + 2], 0.f));
-    for (int64_t f = 4 * NB; f < a.ld_z; f += 4) st4(out + f, make_float4(0.f, 0.f, 0.f, 0.f));
+}
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void encode_kernel(EncodeArgs a) {
+    extern __shared__ float smem[];
+    float* s_E = smem + a.rows * (4 * a.nq + 1);
+    stage_encoder<NB>(a.E, a.k, a.n, s_E);
+    const int64_t r0 = int64_t(blockIdx.x) * a.rows;
+    const int nrows = int(min<int64_t>(a.rows, a.m - r0));
+    encode_rows<NB>(s_E, smem, a.n, a.nq, a.S, a.ld_s, a.Z, a.ld_z, r0, nrows);
+}
+
+// Persistent launch over an encode job table (rows [begin, end) of one
+// spectra array each); block b takes jobs b, b + grid, ...
+template <int NB>
+__global__ __launch_bounds__(kThreads) void encode_jobs_kernel(const hc_encode_job* jobs,
+                                                               const int32_t* n_jobs_dev, int max_jobs,
+                                                               const float* E, int k, int n, int rows) {
+    extern __shared__ float smem[];
+    const int nq = (n + 3) / 4;
+    float* s_E = smem + rows * (4 * nq + 1);
+    stage_encoder<NB>(E, k, n, s_E);
+    const int n_jobs = min(*n_jobs_dev, max_jobs);
+    for (int j = blockIdx.x; j < n_jobs; j += gridDim.x) {
+        const hc_encode_job job = jobs[j];
+        for (int64_t r0 = job.begin; r0 < job.end; r0 += rows) {
+            const int nrows = int(min<int64_t>(rows, job.end - r0));
+            encode_rows<NB>(s_E, smem, n, nq, job.S, job.ld_s, job.Z, job.ld_z, r0, nrows);
+        }
+    }
 }
 
 struct DecodeArgs {
@@ -70,26 +105,28 @@ struct DecodeArgs {
     int64_t ld_s;
 };
 
-// One thread per pixel.  Each block first forms M = T D (3 x k) in LDS.
+// M = T D (3 x 3NB, zero columns past k) into LDS; D too when spectra are
+// requested.
 template <int NB>
-__global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
-    __shared__ float s_M[3 * kMaxK];
-    extern __shared__ float s_D[];  // n x k, only when spectra are requested
-    const int tid = threadIdx.x;
-    for (int e = tid; e < 9 * NB; e += kThreads) {
+__device__ __forceinline__ void stage_decoder(const float* D, const float* T, int n, int k, float* s_M,
+                                              float* s_D) {
+    for (int e = threadIdx.x; e < 9 * NB; e += kThreads) {
         const int ch = e / (3 * NB), c = e % (3 * NB);
         float acc = 0.f;
-        if (c < a.k)
-            for (int i = 0; i < a.n; ++i) acc += a.T[ch * a.n + i] * a.D[i * a.k + c];
+        if (c < k)
+            for (int i = 0; i < n; ++i) acc += T[ch * n + i] * D[i * k + c];
         s_M[e] = acc;
     }
-    if (a.spectra)
-        for (int e = tid; e < a.n * a.k; e += kThreads) s_D[e] = a.D[e];
-    __syncthreads();
-    const int64_t q = int64_t(blockIdx.x) * kThreads + tid;
-    if (q >= a.n_pixels) return;
+    if (s_D)
+        for (int e = threadIdx.x; e < n * k; e += kThreads) s_D[e] = D[e];
+}
+
+template <int NB>
+__device__ __forceinline__ void decode_pixel(const float* s_M, const float* s_D, int n, int k,
+                                             const float* zimg, int64_t ld_z, float* xyz, float* spectra,
+                                             int64_t ld_s, int64_t q) {
     float z[3 * NB];
-    const float* row = a.zimg + q * a.ld_z;
+    const float* row = zimg + q * ld_z;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const float4 v = ld4(row + 4 * b);
@@ -97,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
         z[3 * b + 1] = v.y;
         z[3 * b + 2] = v.z;
     }
-    // M has zero columns past k (see above), so padded channels add nothing
+    // M has zero columns past k, so padded channels add nothing
     float x = 0.f, y = 0.f, w = 0.f;
 #pragma unroll
     for (int c = 0; c < 3 * NB; ++c) {
@@ -105,19 +142,59 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
         y += s_M[3 * NB + c] * z[c];
         w += s_M[6 * NB + c] * z[c];
     }
-    float* o = a.xyz + q * 3;
+    float* o = xyz + q * 3;
     o[0] = x;
     o[1] = y;
     o[2] = w;
-    if (a.spectra) {
-        float* sp = a.spectra + q * a.ld_s;
-        for (int i = 0; i < a.n; ++i) {
+    if (spectra) {
+        float* sp = spectra + q * ld_s;
+        for (int i = 0; i < n; ++i) {
             float acc = 0.f;
-            for (int c = 0; c < a.k; ++c) acc += s_D[i * a.k + c] * z[c];
+            for (int c = 0; c < k; ++c) acc += s_D[i * k + c] * z[c];
             sp[i] = acc;
         }
     }
 }
+
+// One thread per pixel.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
+    __shared__ float s_M[3 * kMaxK];
+    extern __shared__ float s_D[];  // n x k, only when spectra are requested
+    stage_decoder<NB>(a.D, a.T, a.n, a.k, s_M, a.spectra ? s_D : nullptr);
+    __syncthreads();
+    const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (q >= a.n_pixels) return;
+    decode_pixel<NB>(s_M, s_D, a.n, a.k, a.zimg, a.ld_z, a.xyz, a.spectra, a.ld_s, q);
+}
+
+// Persistent launch over a tile table: each tile's pixels of frames[f].image
+// are decoded to frames[f].xyz.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void decode_tiles_kernel(const hc_frame* frames, int n_frames,
+                                                                const hc_tile* tiles,
+                                                                const int32_t* n_tiles_dev, int max_tiles,
+                                                                const float* D, int n, int k,
+                                                                const float* T) {
+    __shared__ float s_M[3 * kMaxK];
+    stage_decoder<NB>(D, T, n, k, s_M, nullptr);
+    __syncthreads();
+    const int n_tiles = min(*n_tiles_dev, max_tiles);
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const hc_tile tile = tiles[t];
+        if (tile.frame < 0 || tile.frame >= n_frames) continue;
+        const hc_frame& fr = frames[tile.frame];
+        const int64_t begin = tile.begin < 0 ? 0 : tile.begin;
+        const int64_t end = tile.end > fr.n_pixels ? fr.n_pixels : tile.end;
+        for (int64_t q = begin + threadIdx.x; q < end; q += kThreads)
+            decode_pixel<NB>(s_M, nullptr, n, k, fr.image, fr.ld_image, fr.xyz, nullptr, 0, q);
+    }
+}
+
+#define HC_NB_CASES(M) \
+    M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
+
+int rows_per_block(int nq) { return nq <= 8 ? 256 : (nq <= 16 ? 128 : 64); }
 
 }  // namespace
 
@@ -133,15 +210,14 @@ hc_status launch_encode(const float* E, int k, int n, const float* S, int64_t m,
     a.ld_s = ld_s;
     a.Z = Z;
     a.ld_z = ld_z;
-    a.rows = a.nq <= 8 ? 256 : (a.nq <= 16 ? 128 : 64);
+    a.rows = rows_per_block(a.nq);
     const int nb = (k + 2) / 3;
     const size_t lds = (size_t(a.rows) * (4 * a.nq + 1) + size_t(3 * nb) * n) * sizeof(float);
     const uint32_t blocks = uint32_t(ceil_div(m, a.rows));
     switch (nb) {
 #define HC_ENC(NB) \
     case NB: hipLaunchKernelGGL(encode_kernel<NB>, dim3(blocks), dim3(kThreads), lds, st, a); break;
-        HC_ENC(1) HC_ENC(2) HC_ENC(3) HC_ENC(4) HC_ENC(5) HC_ENC(6) HC_ENC(7) HC_ENC(8)
-        HC_ENC(9) HC_ENC(10) HC_ENC(11) HC_ENC(12) HC_ENC(13) HC_ENC(14) HC_ENC(15) HC_ENC(16)
+        HC_NB_CASES(HC_ENC)
 #undef HC_ENC
         default:
             set_error("hc_encode: k=%d unsupported", k);
@@ -176,14 +252,52 @@ hc_status launch_decode(const float* D, int n, int k, const float* T, const floa
     case NB:                                                                                     \
         hipLaunchKernelGGL(decode_kernel<NB>, dim3(uint32_t(blocks)), dim3(kThreads), lds, st, a); \
         break;
-        HC_DEC(1) HC_DEC(2) HC_DEC(3) HC_DEC(4) HC_DEC(5) HC_DEC(6) HC_DEC(7) HC_DEC(8)
-        HC_DEC(9) HC_DEC(10) HC_DEC(11) HC_DEC(12) HC_DEC(13) HC_DEC(14) HC_DEC(15) HC_DEC(16)
+        HC_NB_CASES(HC_DEC)
 #undef HC_DEC
         default:
             set_error("hc_decode_xyz: k=%d unsupported", k);
             return HC_EUNSUPPORTED;
     }
     return launch_status("hc_decode_xyz");
+}
+
+hc_status launch_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int max_jobs,
+                             const float* E, int k, int n, int grid, hipStream_t st) {
+    const int nq = (n + 3) / 4;
+    const int rows = rows_per_block(nq);
+    const int nb = (k + 2) / 3;
+    const size_t lds = (size_t(rows) * (4 * nq + 1) + size_t(3 * nb) * n) * sizeof(float);
+    switch (nb) {
+#define HC_ENCJ(NB)                                                                                  \
+    case NB:                                                                                         \
+        hipLaunchKernelGGL(encode_jobs_kernel<NB>, dim3(grid), dim3(kThreads), lds, st, jobs, n_jobs, \
+                           max_jobs, E, k, n, rows);                                                 \
+        break;
+        HC_NB_CASES(HC_ENCJ)
+#undef HC_ENCJ
+        default:
+            set_error("hc_encode_jobs: k=%d unsupported", k);
+            return HC_EUNSUPPORTED;
+    }
+    return launch_status("hc_encode_jobs");
+}
+
+hc_status launch_decode_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
+                              const int32_t* n_tiles, int max_tiles, const float* D, int n, int k,
+                              const float* T, int grid, hipStream_t st) {
+    switch ((k + 2) / 3) {
+#define HC_DECT(NB)                                                                                  \
+    case NB:                                                                                         \
+        hipLaunchKernelGGL(decode_tiles_kernel<NB>, dim3(grid), dim3(kThreads), 0, st, frames, n_frames, \
+                           tiles, n_tiles, max_tiles, D, n, k, T);                                   \
+        break;
+        HC_NB_CASES(HC_DECT)
+#undef HC_DECT
+        default:
+            set_error("hc_decode_tiles: k=%d unsupported", k);
+            return HC_EUNSUPPORTED;
+    }
+    return launch_status("hc_decode_tiles");
 }
 
 }  // namespace hc

@@ -3,9 +3,12 @@
 // larger spp loops over rounds of 64 paths).  Per vertex a lane gathers the
 // 16-byte blocks of the texel's code (blocked RGBx layout) and multiplies
 // them into its product, block by block (the blockwise Hadamard product);
-// the light code comes from LDS; the per-pixel sample mean is an xor
-// butterfly across the pixel's lanes.  Every index read from the records is
-// clamped to its buffer.
+// the light code comes from LDS when the table fits; the per-pixel sample
+// mean is an xor butterfly across the pixel's lanes.  Every index read from
+// the records is clamped to its buffer.
+//
+// Two launches share the per-wave code: one frame per launch, or a fixed
+// grid walking a tile table that spans many frames (serving).
 
 #include "shade_common.hpp"
 
@@ -13,9 +16,7 @@ namespace hc {
 namespace {
 using namespace shade;
 
-// ------------------------------------------------------------------ latent form
-
-struct LatentArgs {
+struct LatentFrame {
     PathView P;
     const float* codes;
     int64_t ld;
@@ -27,30 +28,29 @@ struct LatentArgs {
     float* zimg;
     int64_t ld_z;
     float inv_spp;
-    int lights_in_lds;
 };
 
+// Stage the light codes of blocks [block_first, block_first + NB) in LDS.
 template <int NB>
-__global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentArgs a) {
-#pragma clang fp contract(off)
-    extern __shared__ float4 s_light[];
-    if (a.lights_in_lds) {
-        for (uint32_t i = threadIdx.x; i < a.n_illum * NB; i += kBlock) {
-            const uint32_t l = i / NB, b = i % NB;
-            s_light[i] = ld4(a.lcodes + int64_t(l) * a.ld_l + 4 * (a.block_first + int(b)));
-        }
-        __syncthreads();
+__device__ __forceinline__ void stage_lights(const LatentFrame& f, float4* s_light) {
+    for (uint32_t i = threadIdx.x; i < f.n_illum * NB; i += kBlock) {
+        const uint32_t l = i / NB, b = i % NB;
+        s_light[i] = ld4(f.lcodes + int64_t(l) * f.ld_l + 4 * (f.block_first + int(b)));
     }
-    const PathView& P = a.P;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
-    const int64_t q0 = wave * P.pw;
-    if (q0 >= P.n_pixels) return;  // whole wave leaves together; no barrier follows
+}
 
-    const int seg = P.spp_pad;                // lanes per pixel segment
+// The calling wave shades pixels [q0, min(q0 + pw, q_end)).  s_light is the
+// staged light table or nullptr.
+template <int NB>
+__device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, int64_t q_end,
+                                             const float4* s_light) {
+#pragma clang fp contract(off)
+    const PathView& P = f.P;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int seg = P.spp_pad;  // lanes per pixel segment
     const int j0 = lane % seg;
     const int64_t q = q0 + lane / seg;
-    const bool pix_ok = q < P.n_pixels;
+    const bool pix_ok = q < q_end;
     uint32_t next = pix_ok ? P.pix_first[q] : 0u;
 
     float4 acc[NB];
@@ -83,8 +83,8 @@ __global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentArgs a) {
                 float4 row[U][NB];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t t = min(rec[u].x, a.n_tex - 1u);
-                    const float* rp = a.codes + int64_t(t) * a.ld + 4 * a.block_first;
+                    const uint32_t t = min(rec[u].x, f.n_tex - 1u);
+                    const float* rp = f.codes + int64_t(t) * f.ld + 4 * f.block_first;
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
                         row[u][b] = (jv + u < end) ? ld4(rp + 4 * b) : make_float4(1.f, 1.f, 1.f, 1.f);
@@ -96,12 +96,11 @@ __global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentArgs a) {
                     wprod *= __uint_as_float(rec[u].y);
                 }
             }
-            const uint32_t lid = min(h & 0xFFFFFFu, a.n_illum - 1u);
+            const uint32_t lid = min(h & 0xFFFFFFu, f.n_illum - 1u);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const float4 lc = a.lights_in_lds
-                                      ? s_light[lid * NB + b]
-                                      : ld4(a.lcodes + int64_t(lid) * a.ld_l + 4 * (a.block_first + b));
+                const float4 lc = s_light ? s_light[lid * NB + b]
+                                          : ld4(f.lcodes + int64_t(lid) * f.ld_l + 4 * (f.block_first + b));
                 acc[b] = add4(acc[b], mul4(scale4(lc, wprod), prod[b]));
             }
         }
@@ -116,67 +115,127 @@ __global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentArgs a) {
         }
     }
     if (pix_ok && j0 == 0) {
-        float* out = a.zimg + q * a.ld_z + 4 * a.block_first;
+        float* out = f.zimg + q * f.ld_z + 4 * f.block_first;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            st4(out + 4 * b, make_float4(acc[b].x * a.inv_spp, acc[b].y * a.inv_spp,
-                                         acc[b].z * a.inv_spp, 0.f));
+            st4(out + 4 * b, make_float4(acc[b].x * f.inv_spp, acc[b].y * f.inv_spp,
+                                         acc[b].z * f.inv_spp, 0.f));
         }
     }
 }
 
 template <int NB>
-hc_status launch_latent_nb(const LatentArgs& a, int64_t blocks, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(shade_latent_kernel<NB>, dim3(uint32_t(blocks)), dim3(kBlock), lds, st, a);
-    return launch_status("hc_shade_latent");
+__global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentFrame f, int lights_in_lds) {
+    extern __shared__ float4 s_light[];
+    if (lights_in_lds) {
+        stage_lights<NB>(f, s_light);
+        __syncthreads();
+    }
+    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t q0 = wave * f.P.pw;
+    if (q0 >= f.P.n_pixels) return;  // whole wave leaves together; no barrier follows
+    latent_group<NB>(f, q0, f.P.n_pixels, lights_in_lds ? s_light : nullptr);
 }
+
+// Persistent launch over a tile table: block b takes tiles b, b + grid, ...
+// and its waves split each tile's pixel groups.  Light codes are staged per
+// tile when they fit in the LDS budget.
+template <int NB>
+__global__ __launch_bounds__(kBlock) void shade_latent_tiles_kernel(const hc_frame* frames, int n_frames,
+                                                                    const hc_tile* tiles,
+                                                                    const int32_t* n_tiles_dev,
+                                                                    int max_tiles) {
+    extern __shared__ float4 s_light[];
+    const int n_tiles = min(*n_tiles_dev, max_tiles);
+    const int wave = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        int64_t begin, end;
+        const hc_tile tile = tiles[t];
+        if (!tile_range(tile, frames, n_frames, begin, end)) continue;  // uniform over the block
+        const hc_frame& fr = frames[tile.frame];
+        LatentFrame f;
+        f.P = make_view(fr.hdr, fr.pix_first, fr.vtx, fr.n_pixels, fr.n_vertices, fr.spp, kWave);
+        f.codes = fr.tex;
+        f.ld = fr.ld_tex;
+        f.n_tex = static_cast<uint32_t>(fr.n_texels);
+        f.lcodes = fr.lights;
+        f.ld_l = fr.ld_lights;
+        f.n_illum = static_cast<uint32_t>(fr.n_illum);
+        f.block_first = 0;
+        f.zimg = fr.image;
+        f.ld_z = fr.ld_image;
+        f.inv_spp = 1.0f / static_cast<float>(fr.spp);
+        const bool lds = size_t(f.n_illum) * NB * sizeof(float4) <= kLightLdsBytes;
+        __syncthreads();  // the previous tile's waves are done with s_light
+        if (lds) stage_lights<NB>(f, s_light);
+        __syncthreads();
+        const int64_t groups = (end - begin + f.P.pw - 1) / f.P.pw;
+        for (int64_t g = wave; g < groups; g += kWavesPerBlock)
+            latent_group<NB>(f, begin + g * f.P.pw, end, lds ? s_light : nullptr);
+    }
+}
+
+#define HC_NB_CASES(M) \
+    M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
 
 }  // namespace
 
 hc_status launch_shade_latent(const hc_paths& P, const hc_latent_assets& A, int block_first,
                               int block_count, float* zimg, int64_t ld_zimg, hipStream_t st) {
-    LatentArgs a;
-    a.P = make_view(P, kWave);
-    a.codes = A.codes;
-    a.ld = A.ld;
-    a.n_tex = static_cast<uint32_t>(A.n_texels);
-    a.lcodes = A.illum_codes;
-    a.ld_l = A.ld_illum;
-    a.n_illum = static_cast<uint32_t>(A.n_illum);
-    a.block_first = block_first;
-    a.zimg = zimg;
-    a.ld_z = ld_zimg;
-    a.inv_spp = 1.0f / static_cast<float>(P.spp);
+    LatentFrame f;
+    f.P = make_view(P, kWave);
+    f.codes = A.codes;
+    f.ld = A.ld;
+    f.n_tex = static_cast<uint32_t>(A.n_texels);
+    f.lcodes = A.illum_codes;
+    f.ld_l = A.ld_illum;
+    f.n_illum = static_cast<uint32_t>(A.n_illum);
+    f.block_first = block_first;
+    f.zimg = zimg;
+    f.ld_z = ld_zimg;
+    f.inv_spp = 1.0f / static_cast<float>(P.spp);
     const size_t lds_need = size_t(A.n_illum) * block_count * sizeof(float4);
-    a.lights_in_lds = lds_need <= kLightLdsBytes;
-    const size_t lds = a.lights_in_lds ? lds_need : 0;
-    const int64_t waves = ceil_div(P.n_pixels, a.P.pw);
+    const int lights_in_lds = lds_need <= kLightLdsBytes;
+    const size_t lds = lights_in_lds ? lds_need : 0;
+    const int64_t waves = ceil_div(P.n_pixels, f.P.pw);
     const int64_t blocks = ceil_div(waves, kWavesPerBlock);
     if (blocks > 0x7FFFFFFF) {
         set_error("hc_shade_latent: frame too large for one launch");
         return HC_ESHAPE;
     }
     switch (block_count) {
-        case 1: return launch_latent_nb<1>(a, blocks, lds, st);
-        case 2: return launch_latent_nb<2>(a, blocks, lds, st);
-        case 3: return launch_latent_nb<3>(a, blocks, lds, st);
-        case 4: return launch_latent_nb<4>(a, blocks, lds, st);
-        case 5: return launch_latent_nb<5>(a, blocks, lds, st);
-        case 6: return launch_latent_nb<6>(a, blocks, lds, st);
-        case 7: return launch_latent_nb<7>(a, blocks, lds, st);
-        case 8: return launch_latent_nb<8>(a, blocks, lds, st);
-        case 9: return launch_latent_nb<9>(a, blocks, lds, st);
-        case 10: return launch_latent_nb<10>(a, blocks, lds, st);
-        case 11: return launch_latent_nb<11>(a, blocks, lds, st);
-        case 12: return launch_latent_nb<12>(a, blocks, lds, st);
-        case 13: return launch_latent_nb<13>(a, blocks, lds, st);
-        case 14: return launch_latent_nb<14>(a, blocks, lds, st);
-        case 15: return launch_latent_nb<15>(a, blocks, lds, st);
-        case 16: return launch_latent_nb<16>(a, blocks, lds, st);
+#define HC_CASE(NB)                                                                          \
+    case NB:                                                                                 \
+        hipLaunchKernelGGL(shade_latent_kernel<NB>, dim3(uint32_t(blocks)), dim3(kBlock), lds, st, f, \
+                           lights_in_lds);                                                   \
+        break;
+        HC_NB_CASES(HC_CASE)
+#undef HC_CASE
         default:
             set_error("hc_shade_latent: block_count %d unsupported", block_count);
             return HC_EUNSUPPORTED;
     }
+    return launch_status("hc_shade_latent");
+}
+
+hc_status launch_shade_latent_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
+                                    const int32_t* n_tiles, int max_tiles, int k, int grid,
+                                    hipStream_t st) {
+    const int nb = int(ceil_div(k, 3));
+    const size_t lds = kLightLdsBytes;
+    switch (nb) {
+#define HC_CASE(NB)                                                                               \
+    case NB:                                                                                      \
+        hipLaunchKernelGGL(shade_latent_tiles_kernel<NB>, dim3(grid), dim3(kBlock), lds, st, frames, \
+                           n_frames, tiles, n_tiles, max_tiles);                                  \
+        break;
+        HC_NB_CASES(HC_CASE)
+#undef HC_CASE
+        default:
+            set_error("hc_shade_latent_tiles: k=%d unsupported", k);
+            return HC_EUNSUPPORTED;
+    }
+    return launch_status("hc_shade_latent_tiles");
 }
 
 }  // namespace hc

@@ -8,15 +8,13 @@ namespace hc {
 namespace {
 using namespace shade;
 
-// G lanes per path, G dividing 64; a lane owns the float4 chunks
-// c = qq*G + sub (qq < Q) of the n samples, so one load instruction covers G
-// consecutive chunks of each path's texel row (one 128-byte line for G = 8).
-#ifndef HC_SPECTRAL_LANES
-#define HC_SPECTRAL_LANES 8
-#endif
-constexpr int kSpecLanes = HC_SPECTRAL_LANES;
+// G lanes per path; a lane owns the float4 chunks c = qq*G + sub (qq < Q) of
+// the n samples, so one load instruction covers G consecutive chunks of each
+// path's texel row: one 128-byte line for G = 8.  (2 and 4 lanes per path
+// measured the same at n = 31.)
+constexpr int kSpecLanes = 8;
 
-struct SpectralArgs {
+struct SpectralFrame {
     PathView P;
     const float* refl;
     int64_t ld;
@@ -29,26 +27,24 @@ struct SpectralArgs {
     const float* T;
     float* xyz;
     float inv_spp;
-    int lights_in_lds;
 };
 
-template <int G, int Q>
-__global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralArgs a) {
-    extern __shared__ float4 s_light[];
-    if (a.lights_in_lds) {
-        for (uint32_t i = threadIdx.x; i < a.n_illum * uint32_t(a.nq); i += kBlock) {
-            const uint32_t l = i / a.nq, c = i % a.nq;
-            s_light[i] = ld4(a.illum + int64_t(l) * a.ld_l + 4 * c);
-        }
-        __syncthreads();
+__device__ __forceinline__ void stage_lights(const SpectralFrame& f, float4* s_light) {
+    for (uint32_t i = threadIdx.x; i < f.n_illum * uint32_t(f.nq); i += kBlock) {
+        const uint32_t l = i / f.nq, c = i % f.nq;
+        s_light[i] = ld4(f.illum + int64_t(l) * f.ld_l + 4 * c);
     }
-    const PathView& P = a.P;
+}
+
+// The calling wave shades pixels [q0, min(q0 + pw, q_end)); s_light is the
+// staged light table or nullptr.
+template <int G, int Q>
+__device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q0, int64_t q_end,
+                                               const float4* s_light) {
+    const PathView& P = f.P;
     const int lane = threadIdx.x & (kWave - 1);
     const int sub = lane & (G - 1);
     const int slot = lane / G;
-    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
-    const int64_t q0 = wave * P.pw;
-    if (q0 >= P.n_pixels) return;
 
     // colour-matching weights of this lane's samples; zero past n
     float4 Tr[3][Q];
@@ -61,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralArgs a) 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = 4 * c + e;
-                w[e] = (i < a.n) ? a.T[ch * a.n + i] : 0.f;
+                w[e] = (i < f.n) ? f.T[ch * f.n + i] : 0.f;
             }
             Tr[ch][qq] = make_float4(w[0], w[1], w[2], w[3]);
         }
@@ -70,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralArgs a) 
     const int seg = P.spp_pad;  // slots per pixel segment
     const int j0 = slot % seg;
     const int64_t q = q0 + slot / seg;
-    const bool pix_ok = q < P.n_pixels;
+    const bool pix_ok = q < q_end;
     uint32_t next = pix_ok ? P.pix_first[q] : 0u;
     float ax = 0.f, ay = 0.f, az = 0.f;
 
@@ -99,12 +95,12 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralArgs a) 
                 float4 row[U][Q];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t t = min(rec[u].x, a.n_tex - 1u);
-                    const float* rp = a.refl + int64_t(t) * a.ld;
+                    const uint32_t t = min(rec[u].x, f.n_tex - 1u);
+                    const float* rp = f.refl + int64_t(t) * f.ld;
 #pragma unroll
                     for (int qq = 0; qq < Q; ++qq) {
                         const int c = qq * G + sub;
-                        row[u][qq] = (jv + u < end && c < a.nq) ? ld4(rp + 4 * c)
+                        row[u][qq] = (jv + u < end && c < f.nq) ? ld4(rp + 4 * c)
                                                                  : make_float4(1.f, 1.f, 1.f, 1.f);
                     }
                 }
@@ -115,21 +111,21 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralArgs a) 
                     wprod *= __uint_as_float(rec[u].y);
                 }
             }
-            const uint32_t lid = min(h & 0xFFFFFFu, a.n_illum - 1u);
+            const uint32_t lid = min(h & 0xFFFFFFu, f.n_illum - 1u);
 #pragma unroll
             for (int qq = 0; qq < Q; ++qq) {
                 const int c = qq * G + sub;
-                if (c < a.nq) {
-                    const float4 lt = a.lights_in_lds ? s_light[lid * a.nq + c]
-                                                      : ld4(a.illum + int64_t(lid) * a.ld_l + 4 * c);
+                if (c < f.nq) {
+                    const float4 lt = s_light ? s_light[lid * f.nq + c]
+                                              : ld4(f.illum + int64_t(lid) * f.ld_l + 4 * c);
                     float4 s = mul4(scale4(lt, wprod), prod[qq]);
                     // samples past n carry no colour weight; drop them so
                     // non-finite row padding cannot leak in
-                    if (4 * c + 3 >= a.n) {
-                        if (4 * c + 0 >= a.n) s.x = 0.f;
-                        if (4 * c + 1 >= a.n) s.y = 0.f;
-                        if (4 * c + 2 >= a.n) s.z = 0.f;
-                        if (4 * c + 3 >= a.n) s.w = 0.f;
+                    if (4 * c + 3 >= f.n) {
+                        if (4 * c + 0 >= f.n) s.x = 0.f;
+                        if (4 * c + 1 >= f.n) s.y = 0.f;
+                        if (4 * c + 2 >= f.n) s.z = 0.f;
+                        if (4 * c + 3 >= f.n) s.w = 0.f;
                     }
                     ax += Tr[0][qq].x * s.x + Tr[0][qq].y * s.y + Tr[0][qq].z * s.z + Tr[0][qq].w * s.w;
                     ay += Tr[1][qq].x * s.x + Tr[1][qq].y * s.y + Tr[1][qq].z * s.z + Tr[1][qq].w * s.w;
@@ -146,57 +142,127 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralArgs a) 
         az += shfl_xor(az, m);
     }
     if (pix_ok && sub == 0 && j0 == 0) {
-        float* out = a.xyz + q * 3;
-        out[0] = ax * a.inv_spp;
-        out[1] = ay * a.inv_spp;
-        out[2] = az * a.inv_spp;
+        float* out = f.xyz + q * 3;
+        out[0] = ax * f.inv_spp;
+        out[1] = ay * f.inv_spp;
+        out[2] = az * f.inv_spp;
     }
 }
 
 template <int G, int Q>
-hc_status launch_spectral_gq(const SpectralArgs& a, int64_t blocks, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((shade_spectral_kernel<G, Q>), dim3(uint32_t(blocks)), dim3(kBlock), lds, st, a);
+__global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralFrame f, int lights_in_lds) {
+    extern __shared__ float4 s_light[];
+    if (lights_in_lds) {
+        stage_lights(f, s_light);
+        __syncthreads();
+    }
+    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t q0 = wave * f.P.pw;
+    if (q0 >= f.P.n_pixels) return;
+    spectral_group<G, Q>(f, q0, f.P.n_pixels, lights_in_lds ? s_light : nullptr);
+}
+
+// Persistent launch over a tile table (see the latent form).
+template <int G, int Q>
+__global__ __launch_bounds__(kBlock) void shade_spectral_tiles_kernel(const hc_frame* frames, int n_frames,
+                                                                      const hc_tile* tiles,
+                                                                      const int32_t* n_tiles_dev,
+                                                                      int max_tiles, int n, const float* T) {
+    extern __shared__ float4 s_light[];
+    const int n_tiles = min(*n_tiles_dev, max_tiles);
+    const int wave = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        int64_t begin, end;
+        const hc_tile tile = tiles[t];
+        if (!tile_range(tile, frames, n_frames, begin, end)) continue;
+        const hc_frame& fr = frames[tile.frame];
+        SpectralFrame f;
+        f.P = make_view(fr.hdr, fr.pix_first, fr.vtx, fr.n_pixels, fr.n_vertices, fr.spp, kWave / G);
+        f.refl = fr.tex;
+        f.ld = fr.ld_tex;
+        f.n_tex = static_cast<uint32_t>(fr.n_texels);
+        f.illum = fr.lights;
+        f.ld_l = fr.ld_lights;
+        f.n_illum = static_cast<uint32_t>(fr.n_illum);
+        f.n = n;
+        f.nq = (n + 3) / 4;
+        f.T = T;
+        f.xyz = fr.xyz;
+        f.inv_spp = 1.0f / static_cast<float>(fr.spp);
+        const bool lds = size_t(f.n_illum) * f.nq * sizeof(float4) <= kLightLdsBytes;
+        __syncthreads();
+        if (lds) stage_lights(f, s_light);
+        __syncthreads();
+        const int64_t groups = (end - begin + f.P.pw - 1) / f.P.pw;
+        for (int64_t g = wave; g < groups; g += kWavesPerBlock)
+            spectral_group<G, Q>(f, begin + g * f.P.pw, end, lds ? s_light : nullptr);
+    }
+}
+
+template <int G, int Q>
+hc_status launch_spectral_gq(const SpectralFrame& f, int lights_in_lds, int64_t blocks, size_t lds,
+                             hipStream_t st) {
+    hipLaunchKernelGGL((shade_spectral_kernel<G, Q>), dim3(uint32_t(blocks)), dim3(kBlock), lds, st, f,
+                       lights_in_lds);
     return launch_status("hc_shade_spectral");
+}
+
+template <int G, int Q>
+hc_status launch_spectral_tiles_gq(const hc_frame* frames, int n_frames, const hc_tile* tiles,
+                                   const int32_t* n_tiles, int max_tiles, int n, const float* T, int grid,
+                                   hipStream_t st) {
+    hipLaunchKernelGGL((shade_spectral_tiles_kernel<G, Q>), dim3(grid), dim3(kBlock), kLightLdsBytes, st,
+                       frames, n_frames, tiles, n_tiles, max_tiles, n, T);
+    return launch_status("hc_shade_spectral_tiles");
 }
 
 }  // namespace
 
 hc_status launch_shade_spectral(const hc_paths& P, const hc_spectral_assets& A, const float* T,
                                 float* xyz, hipStream_t st) {
-    SpectralArgs a;
-    a.P = make_view(P, kWave / kSpecLanes);
-    a.refl = A.refl;
-    a.ld = A.ld;
-    a.n_tex = static_cast<uint32_t>(A.n_texels);
-    a.illum = A.illum;
-    a.ld_l = A.ld_illum;
-    a.n_illum = static_cast<uint32_t>(A.n_illum);
-    a.n = A.n;
-    a.nq = static_cast<int>(ceil_div(A.n, 4));
-    a.T = T;
-    a.xyz = xyz;
-    a.inv_spp = 1.0f / static_cast<float>(P.spp);
-    const size_t lds_need = size_t(A.n_illum) * a.nq * sizeof(float4);
-    a.lights_in_lds = lds_need <= kLightLdsBytes;
-    const size_t lds = a.lights_in_lds ? lds_need : 0;
-    const int64_t waves = ceil_div(P.n_pixels, a.P.pw);
+    SpectralFrame f;
+    f.P = make_view(P, kWave / kSpecLanes);
+    f.refl = A.refl;
+    f.ld = A.ld;
+    f.n_tex = static_cast<uint32_t>(A.n_texels);
+    f.illum = A.illum;
+    f.ld_l = A.ld_illum;
+    f.n_illum = static_cast<uint32_t>(A.n_illum);
+    f.n = A.n;
+    f.nq = static_cast<int>(ceil_div(A.n, 4));
+    f.T = T;
+    f.xyz = xyz;
+    f.inv_spp = 1.0f / static_cast<float>(P.spp);
+    const size_t lds_need = size_t(A.n_illum) * f.nq * sizeof(float4);
+    const int lights_in_lds = lds_need <= kLightLdsBytes;
+    const size_t lds = lights_in_lds ? lds_need : 0;
+    const int64_t waves = ceil_div(P.n_pixels, f.P.pw);
     const int64_t blocks = ceil_div(waves, kWavesPerBlock);
     if (blocks > 0x7FFFFFFF) {
         set_error("hc_shade_spectral: frame too large for one launch");
         return HC_ESHAPE;
     }
-    const int q = static_cast<int>(ceil_div(a.nq, kSpecLanes));
-    switch (q) {
-        case 1: return launch_spectral_gq<kSpecLanes, 1>(a, blocks, lds, st);
-        case 2: return launch_spectral_gq<kSpecLanes, 2>(a, blocks, lds, st);
-        case 3: return launch_spectral_gq<kSpecLanes, 3>(a, blocks, lds, st);
-        case 4: return launch_spectral_gq<kSpecLanes, 4>(a, blocks, lds, st);
-        case 5: return launch_spectral_gq<kSpecLanes, 5>(a, blocks, lds, st);
-        case 6: return launch_spectral_gq<kSpecLanes, 6>(a, blocks, lds, st);
-        case 7: return launch_spectral_gq<kSpecLanes, 7>(a, blocks, lds, st);
-        case 8: return launch_spectral_gq<kSpecLanes, 8>(a, blocks, lds, st);
+    switch (ceil_div(f.nq, kSpecLanes)) {
+        case 1: return launch_spectral_gq<kSpecLanes, 1>(f, lights_in_lds, blocks, lds, st);
+        case 2: return launch_spectral_gq<kSpecLanes, 2>(f, lights_in_lds, blocks, lds, st);
+        case 3: return launch_spectral_gq<kSpecLanes, 3>(f, lights_in_lds, blocks, lds, st);
+        case 4: return launch_spectral_gq<kSpecLanes, 4>(f, lights_in_lds, blocks, lds, st);
         default:
             set_error("hc_shade_spectral: n=%d unsupported", A.n);
+            return HC_EUNSUPPORTED;
+    }
+}
+
+hc_status launch_shade_spectral_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
+                                      const int32_t* n_tiles, int max_tiles, int n, const float* T,
+                                      int grid, hipStream_t st) {
+    switch (ceil_div(ceil_div(n, 4), kSpecLanes)) {
+        case 1: return launch_spectral_tiles_gq<kSpecLanes, 1>(frames, n_frames, tiles, n_tiles, max_tiles, n, T, grid, st);
+        case 2: return launch_spectral_tiles_gq<kSpecLanes, 2>(frames, n_frames, tiles, n_tiles, max_tiles, n, T, grid, st);
+        case 3: return launch_spectral_tiles_gq<kSpecLanes, 3>(frames, n_frames, tiles, n_tiles, max_tiles, n, T, grid, st);
+        case 4: return launch_spectral_tiles_gq<kSpecLanes, 4>(frames, n_frames, tiles, n_tiles, max_tiles, n, T, grid, st);
+        default:
+            set_error("hc_shade_spectral_tiles: n=%d unsupported", n);
             return HC_EUNSUPPORTED;
     }
 }

@@ -23,27 +23,35 @@ struct PathView {
     int rounds;   // rounds of paths per pixel
 };
 
-// Paths-per-wave layout shared by both forms: `slots` path slots per wave.
-inline PathView make_view(const hc_paths& P, int slots) {
+// Paths-per-wave layout: `slots` path slots per wave.  Up to `slots`
+// samples per pixel, a pixel takes spp rounded up to a power of two slots and
+// a wave holds slots / that many pixels; more samples loop over rounds.
+__host__ __device__ inline PathView make_view(const uint32_t* hdr, const uint32_t* pix_first,
+                                              const uint32_t* vtx, int64_t n_pixels,
+                                              int64_t n_vertices, int spp, int slots) {
     PathView v;
-    v.hdr = P.hdr;
-    v.pix_first = P.pix_first;
-    v.vtx = reinterpret_cast<const uint2*>(P.vtx);
-    v.n_pixels = P.n_pixels;
-    v.n_vertices = static_cast<uint32_t>(P.n_vertices);
-    v.spp = P.spp;
-    if (P.spp <= slots) {
+    v.hdr = hdr;
+    v.pix_first = pix_first;
+    v.vtx = reinterpret_cast<const uint2*>(vtx);
+    v.n_pixels = n_pixels;
+    v.n_vertices = static_cast<uint32_t>(n_vertices);
+    v.spp = spp;
+    if (spp <= slots) {
         int pad = 1;
-        while (pad < P.spp) pad <<= 1;
+        while (pad < spp) pad <<= 1;
         v.spp_pad = pad;
         v.pw = slots / pad;
         v.rounds = 1;
     } else {
         v.spp_pad = slots;
         v.pw = 1;
-        v.rounds = static_cast<int>(ceil_div(P.spp, slots));
+        v.rounds = (spp + slots - 1) / slots;
     }
     return v;
+}
+
+inline PathView make_view(const hc_paths& P, int slots) {
+    return make_view(P.hdr, P.pix_first, P.vtx, P.n_pixels, P.n_vertices, P.spp, slots);
 }
 
 // Exclusive prefix of `len` over the slots of one pixel segment of `seg`
@@ -64,6 +72,16 @@ __device__ __forceinline__ uint32_t segment_scan(uint32_t len, int j0, int seg, 
     return incl - len;
 }
 
+// Tile-table launches: a fixed grid walks the tiles; a tile's entries are
+// checked against the table sizes so a bad entry is skipped, not followed.
+__device__ __forceinline__ bool tile_range(const hc_tile& t, const hc_frame* frames, int n_frames,
+                                           int64_t& begin, int64_t& end) {
+    if (t.frame < 0 || t.frame >= n_frames) return false;
+    const int64_t np = frames[t.frame].n_pixels;
+    begin = t.begin < 0 ? 0 : t.begin;
+    end = t.end > np ? np : t.end;
+    return begin < end;
+}
 
 }  // namespace shade
 }  // namespace hc

@@ -1,0 +1,558 @@
+"""Continuous-batching frame server.
+
+Frames arrive as a stream of requests of mixed resolution, samples per pixel
+and path length.  The scheduler admits them while frame slots and a device
+memory budget allow (FIFO), keeps encoded assets resident across requests
+(encode on first use), and runs *iterations*: each iteration shades a
+bounded number of pixel tiles taken from all admitted frames, so a request
+that arrives while a large frame is in flight joins the next iteration
+instead of waiting for that frame to finish.  Frames whose last tile is in an
+iteration are decoded in the same iteration.
+
+On the GPU an iteration is one replay of a captured HIP graph holding the
+table-driven encode -> shade -> decode launches; the host only rewrites the
+small frame / tile / job tables (copied to the device before the replay) and
+launches the per-request path generators.  Up to two iterations are in
+flight, so table building overlaps device work.
+
+`Scheduler` holds the policy and is independent of the device; `GpuBackend`
+executes plans with libhc; tests drive the scheduler with a CPU fake backend.
+"""
+
+from __future__ import annotations
+
+import collections
+import ctypes as C
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+# ------------------------------------------------------------------ requests
+
+@dataclass
+class Request:
+    rid: int
+    asset: int
+    width: int
+    height: int
+    spp: int
+    l_min: int
+    l_max: int
+    seed: int
+    arrival: float = 0.0
+    keep_result: bool = False
+    # filled in by the server
+    state: str = "queued"        # queued -> active -> done | failed
+    next_pixel: int = 0          # first pixel not yet scheduled
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    error: str | None = None
+    result: object = None
+    slot: int = -1
+
+    @property
+    def n_pixels(self) -> int:
+        return self.width * self.height
+
+    @property
+    def expected_vertices(self) -> float:
+        return self.n_pixels * self.spp * 0.5 * (self.l_min + self.l_max)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+@dataclass
+class Plan:
+    """One iteration: assets to encode, shade tiles, decode tiles, frames
+    that complete when the iteration does."""
+    encode: list = field(default_factory=list)          # asset ids
+    shade: list = field(default_factory=list)           # (rid, begin, end)
+    decode: list = field(default_factory=list)          # (rid, begin, end)
+    finishing: list = field(default_factory=list)       # requests
+
+
+class Scheduler:
+    """Admission, tiling and completion bookkeeping (device independent).
+
+    backend must provide: request_bytes(req), prepare(req) (allocate, make
+    records, make the asset resident; returns True if the asset needs an
+    encode), launch(plan) -> handle, poll(handle) -> bool, release(req),
+    finish(req) (fetch results if kept).
+    """
+
+    def __init__(self, backend, max_frames: int = 64, mem_budget: float = 32e9,
+                 tile_pixels: int = 4096, iter_vertices: float = 40e6, max_inflight: int = 2,
+                 max_tiles: int = 8192, decode_pixels: int = 65536):
+        self.b = backend
+        self.max_frames = max_frames
+        self.mem_budget = mem_budget
+        self.tile_pixels = tile_pixels
+        self.iter_vertices = iter_vertices
+        self.max_inflight = max_inflight
+        self.max_tiles = max_tiles
+        self.decode_pixels = decode_pixels  # decode tiles are larger: 64 frames x 4K fit one table
+        self.queue: collections.deque[Request] = collections.deque()
+        self.active: list[Request] = []
+        self.free_slots = list(range(max_frames))[::-1]
+        self.mem_used = 0.0
+        self.inflight: collections.deque = collections.deque()
+        self.done: list[Request] = []
+        self.rejected: list[Request] = []
+        self.iterations = 0
+
+    # -------------------------------------------------------------- intake
+    def submit(self, req: Request):
+        need = self.b.request_bytes(req)
+        if need > self.mem_budget:
+            req.state, req.error = "failed", "request larger than the memory budget"
+            self.rejected.append(req)
+            return
+        self.queue.append(req)
+
+    def _admit(self, now: float):
+        new_assets = []
+        while self.queue and self.free_slots:
+            req = self.queue[0]
+            need = self.b.request_bytes(req)
+            if self.mem_used + need > self.mem_budget:
+                break  # FIFO: the head waits for memory, later requests wait behind it
+            self.queue.popleft()
+            req.slot = self.free_slots.pop()
+            self.mem_used += need
+            req.t_admit = now
+            try:
+                if self.b.prepare(req):
+                    new_assets.append(req.asset)
+            except Exception as e:  # noqa: BLE001 - a failed request must not stop the server
+                self._fail(req, f"prepare: {e}")
+                continue
+            req.state = "active"
+            self.active.append(req)
+        return new_assets
+
+    def _fail(self, req: Request, msg: str):
+        req.state, req.error = "failed", msg
+        req.t_done = time.perf_counter()
+        try:
+            self.b.release(req)
+        finally:
+            self.mem_used -= self.b.request_bytes(req)
+            self.free_slots.append(req.slot)
+            if req in self.active:
+                self.active.remove(req)
+            self.done.append(req)
+
+    # -------------------------------------------------------------- iterations
+    def _plan(self, new_assets) -> Plan | None:
+        """Tiles for the next iteration.  Every admitted frame with pixels
+        left gets one tile (so none starves); the rest of the vertex budget
+        goes to frames in order of least remaining work, which lets small
+        frames finish quickly beside large ones."""
+        plan = Plan(encode=sorted(set(new_assets)))
+        todo = [r for r in self.active if r.next_pixel < r.n_pixels]
+        per_px = {r.rid: r.spp * 0.5 * (r.l_min + r.l_max) for r in todo}
+        todo.sort(key=lambda r: ((r.n_pixels - r.next_pixel) * per_px[r.rid], r.arrival))
+        budget = self.iter_vertices
+
+        def take(req):
+            nonlocal budget
+            b = req.next_pixel
+            e = min(req.n_pixels, b + self.tile_pixels)
+            plan.shade.append((req.rid, b, e))
+            req.next_pixel = e
+            budget -= (e - b) * per_px[req.rid]
+
+        for req in todo:
+            if len(plan.shade) >= self.max_tiles:
+                break
+            take(req)
+        for req in todo:
+            while req.next_pixel < req.n_pixels and budget > 0 and len(plan.shade) < self.max_tiles:
+                take(req)
+        for req in todo:
+            if req.next_pixel >= req.n_pixels:
+                plan.finishing.append(req)
+                for b in range(0, req.n_pixels, self.decode_pixels):
+                    plan.decode.append((req.rid, b, min(req.n_pixels, b + self.decode_pixels)))
+        if not plan.shade and not plan.encode:
+            return None
+        return plan
+
+    def _complete(self, now: float):
+        while self.inflight and self.b.poll(self.inflight[0][0]):
+            _, plan = self.inflight.popleft()
+            for req in plan.finishing:
+                if req.state != "active":
+                    continue
+                req.t_done = now
+                try:
+                    self.b.finish(req)
+                    req.state = "done"
+                except Exception as e:  # noqa: BLE001
+                    req.state, req.error = "failed", f"finish: {e}"
+                self.b.release(req)
+                self.mem_used -= self.b.request_bytes(req)
+                self.free_slots.append(req.slot)
+                self.active.remove(req)
+                self.done.append(req)
+
+    def step(self, now: float | None = None) -> bool:
+        """One scheduling round; returns True if anything happened."""
+        now = time.perf_counter() if now is None else now
+        before = (len(self.done), len(self.inflight), len(self.queue))
+        self._complete(now)
+        if len(self.inflight) < self.max_inflight:
+            new_assets = self._admit(now)
+            plan = self._plan(new_assets)
+            if plan is not None:
+                try:
+                    handle = self.b.launch(plan)
+                except Exception as e:  # noqa: BLE001
+                    for req in {id(r): r for r in self.active}.values():
+                        if any(t[0] == req.rid for t in plan.shade):
+                            self._fail(req, f"launch: {e}")
+                    return True
+                self.inflight.append((handle, plan))
+                self.iterations += 1
+        return before != (len(self.done), len(self.inflight), len(self.queue))
+
+    @property
+    def idle(self) -> bool:
+        return not (self.queue or self.active or self.inflight)
+
+
+# ------------------------------------------------------------------ GPU backend
+
+class GpuBackend:
+    """Executes plans with the table-driven libhc launches, one captured
+    graph per form.  form: "latent" (encode -> shade -> decode) or
+    "spectral" (shade straight to XYZ)."""
+
+    def __init__(self, assets, lights, T, E=None, D=None, form: str = "latent", max_frames: int = 64,
+                 max_tiles: int = 8192, max_jobs: int = 4096, grid: int = 2048, device="cuda",
+                 use_graph: bool = True, asset_budget: float = 16e9):
+        import torch
+
+        from . import ops
+        from ._lib import Frame, Tile, EncodeJob, check, load
+        self.torch, self.ops, self.check, self.lib = torch, ops, check, load()
+        self.Frame, self.Tile, self.EncodeJob = Frame, Tile, EncodeJob
+        self.dev = torch.device(device)
+        self.form = form
+        self.assets = assets              # list of pinned host float32 (texels, ld) tensors
+        self.n = T.shape[1]
+        self.k = E.shape[0] if E is not None else 0
+        self.T = T.to(self.dev).contiguous()
+        self.E = None if E is None else E.to(self.dev).contiguous()
+        self.D = None if D is None else D.to(self.dev).contiguous()
+        self.max_frames, self.max_tiles, self.max_jobs, self.grid = max_frames, max_tiles, max_jobs, grid
+        self.stream = torch.cuda.Stream(device=self.dev)
+        lights_d = ops.padded(lights.to(self.dev))
+        with torch.cuda.stream(self.stream):
+            if form == "latent":
+                self.lights = torch.empty(lights.shape[0], ops.latent_width(self.k), device=self.dev)
+                ops.encode(self.E, lights_d, n=self.n, out=self.lights)
+            else:
+                self.lights = lights_d
+        self.stream.synchronize()
+        # device tables, and two pinned host copies used alternately
+        fb, tb, jb = C.sizeof(Frame), C.sizeof(Tile), C.sizeof(EncodeJob)
+        self.sizes = (max_frames * fb, max_tiles * tb, max_tiles * tb, max_jobs * jb, 16)
+        total = sum(self.sizes)
+        self.d_tables = torch.zeros(total, dtype=torch.uint8, device=self.dev)
+        self.h_tables = [torch.zeros(total, dtype=torch.uint8).pin_memory() for _ in range(2)]
+        self.h_events = [None, None]
+        self.flip = 0
+        offs = np.cumsum([0, *self.sizes])
+        base = self.d_tables.data_ptr()
+        self.d_frames, self.d_tiles, self.d_dtiles, self.d_jobs, self.d_counts = (
+            base + int(o) for o in offs[:5])
+        self.offs = offs
+        self.frames = (Frame * max_frames)()
+        self.reqs: dict[int, object] = {}
+        self.resident: collections.OrderedDict[int, object] = collections.OrderedDict()
+        self.asset_refs = collections.Counter()
+        self.asset_budget = asset_budget
+        self.asset_bytes = 0.0
+        self.pending_free = {}            # handle -> tensors kept alive until the iteration ends
+        self.graph = None
+        if use_graph:
+            self._capture()
+
+    # -------------------------------------------------------------- launches
+    def _launch_tables(self):
+        i32 = C.c_int32
+        st = self.stream.cuda_stream
+        cnt = self.d_counts
+        if self.form == "latent":
+            self.check(self.lib.hc_encode_jobs(self.d_jobs, cnt + 8, self.max_jobs, self.E.data_ptr(),
+                                               self.k, self.n, self.grid, st), "hc_encode_jobs")
+            self.check(self.lib.hc_shade_latent_tiles(self.d_frames, self.max_frames, self.d_tiles, cnt,
+                                                      self.max_tiles, self.k, self.grid, st),
+                       "hc_shade_latent_tiles")
+            self.check(self.lib.hc_decode_tiles(self.d_frames, self.max_frames, self.d_dtiles, cnt + 4,
+                                                self.max_tiles, self.D.data_ptr(), self.n, self.k,
+                                                self.T.data_ptr(), self.grid, st), "hc_decode_tiles")
+        else:
+            self.check(self.lib.hc_shade_spectral_tiles(self.d_frames, self.max_frames, self.d_tiles, cnt,
+                                                        self.max_tiles, self.n, self.T.data_ptr(),
+                                                        self.grid, st), "hc_shade_spectral_tiles")
+        del i32
+
+    def _capture(self):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            self._launch_tables()          # warm-up with all counts zero
+        self.stream.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=self.stream):
+            self._launch_tables()
+        self.graph = g
+
+    # -------------------------------------------------------------- scheduler hooks
+    def request_bytes(self, req) -> float:
+        paths = req.n_pixels * req.spp * (4 + 8 * req.l_max) + 4 * req.n_pixels
+        out = req.n_pixels * (12 + (16 * self.ops.blocks(self.k) if self.form == "latent" else 0))
+        return float(paths + out + 4096)
+
+    def _asset_tensor_bytes(self, host):
+        texels = host.shape[0]
+        return texels * (16 * self.ops.blocks(self.k) if self.form == "latent" else host.shape[1] * 4)
+
+    def prepare(self, req) -> bool:
+        torch, ops = self.torch, self.ops
+        new_asset = False
+        with torch.cuda.stream(self.stream):
+            if req.asset not in self.resident:
+                self._make_room()
+                host = self.assets[req.asset]
+                spectral = host.to(self.dev, non_blocking=True)
+                if self.form == "latent":
+                    tex = torch.empty(host.shape[0], ops.latent_width(self.k), device=self.dev)
+                    self._pending_spectral = getattr(self, "_pending_spectral", [])
+                    self._pending_spectral.append((req.asset, spectral, tex))
+                    new_asset = True
+                else:
+                    tex = spectral
+                self.resident[req.asset] = tex
+                self.asset_bytes += self._asset_tensor_bytes(host)
+            self.resident.move_to_end(req.asset)
+            self.asset_refs[req.asset] += 1
+            tex = self.resident[req.asset]
+            P = ops.Paths(torch.empty(req.n_pixels * req.spp, dtype=torch.int32, device=self.dev),
+                          torch.empty(req.n_pixels, dtype=torch.int32, device=self.dev),
+                          torch.empty(max(1, req.n_pixels * req.spp * req.l_max), 2, dtype=torch.int32,
+                                      device=self.dev), req.n_pixels, req.spp)
+            g = self._gen(req, P, tex.shape[0])
+            image = (torch.empty(req.n_pixels, ops.latent_width(self.k), device=self.dev)
+                     if self.form == "latent" else None)
+            xyz = torch.empty(req.n_pixels, 3, device=self.dev)
+        f = self.frames[req.slot]
+        f.hdr, f.pix_first, f.vtx = P.hdr.data_ptr(), P.pix_first.data_ptr(), P.vtx.data_ptr()
+        f.n_pixels, f.n_vertices, f.spp = req.n_pixels, P.vtx.shape[0], req.spp
+        f.n_illum, f.tex, f.n_texels, f.ld_tex = self.lights.shape[0], tex.data_ptr(), tex.shape[0], tex.stride(0)
+        f.lights, f.ld_lights = self.lights.data_ptr(), self.lights.stride(0)
+        f.image, f.ld_image = (image.data_ptr(), image.stride(0)) if image is not None else (None, 0)
+        f.xyz = xyz.data_ptr()
+        self.reqs[req.rid] = dict(P=P, image=image, xyz=xyz, gen=g, slot=req.slot)
+        return new_asset
+
+    def _gen(self, req, P, n_tex):
+        from ._lib import PathGen
+        g = PathGen(req.n_pixels, req.spp, req.l_min, req.l_max, self.lights.shape[0], n_tex, req.seed)
+        wsb = int(self.lib.hc_gen_workspace_size(req.n_pixels))
+        ws = self.torch.empty(max(8, wsb), dtype=self.torch.uint8, device=self.dev)
+        total = self.torch.empty(1, dtype=self.torch.int64, device=self.dev)
+        st = self.stream.cuda_stream
+        self.check(self.lib.hc_gen_path_headers(C.byref(g), P.hdr.data_ptr(), P.pix_first.data_ptr(),
+                                                total.data_ptr(), ws.data_ptr(), wsb, st),
+                   "hc_gen_path_headers")
+        self.check(self.lib.hc_gen_path_vertices(C.byref(g), P.pix_first.data_ptr(), P.vtx.data_ptr(),
+                                                 P.vtx.shape[0], st), "hc_gen_path_vertices")
+        return (ws, total)
+
+    def _make_room(self):
+        while self.asset_bytes > self.asset_budget:
+            for aid in self.resident:
+                if self.asset_refs[aid] == 0:
+                    host = self.assets[aid]
+                    del self.resident[aid]
+                    self.asset_bytes -= self._asset_tensor_bytes(host)
+                    break
+            else:
+                return  # everything resident is in use; go over budget rather than stall
+
+    def launch(self, plan):
+        torch = self.torch
+        h = self.h_tables[self.flip]
+        if self.h_events[self.flip] is not None:
+            self.h_events[self.flip].synchronize()   # the copy that last read this buffer is done
+        hp = h.data_ptr()
+        C.memmove(hp + int(self.offs[0]), C.addressof(self.frames), C.sizeof(self.frames))
+        tiles = (self.Tile * max(1, len(plan.shade)))()
+        for i, (rid, b, e) in enumerate(plan.shade):
+            tiles[i].frame, tiles[i].begin, tiles[i].end = self.reqs[rid]["slot"], b, e
+        C.memmove(hp + int(self.offs[1]), C.addressof(tiles), C.sizeof(self.Tile) * len(plan.shade))
+        dt = (self.Tile * max(1, len(plan.decode)))()
+        for i, (rid, b, e) in enumerate(plan.decode):
+            dt[i].frame, dt[i].begin, dt[i].end = self.reqs[rid]["slot"], b, e
+        C.memmove(hp + int(self.offs[2]), C.addressof(dt), C.sizeof(self.Tile) * len(plan.decode))
+        jobs = []
+        keep = []
+        for aid, spectral, tex in getattr(self, "_pending_spectral", []):
+            if aid in plan.encode:
+                for b in range(0, spectral.shape[0], 65536):
+                    jobs.append((spectral.data_ptr(), tex.data_ptr(), spectral.stride(0), tex.stride(0), b,
+                                 min(spectral.shape[0], b + 65536)))
+                keep.append(spectral)
+        self._pending_spectral = [p for p in getattr(self, "_pending_spectral", []) if p[0] not in plan.encode]
+        jt = (self.EncodeJob * max(1, len(jobs)))(*[self.EncodeJob(*j) for j in jobs])
+        C.memmove(hp + int(self.offs[3]), C.addressof(jt), C.sizeof(self.EncodeJob) * len(jobs))
+        if len(plan.shade) > self.max_tiles or len(plan.decode) > self.max_tiles or len(jobs) > self.max_jobs:
+            raise RuntimeError("iteration exceeds the table capacity")
+        counts = np.array([len(plan.shade), len(plan.decode), len(jobs), 0], dtype=np.int32)
+        C.memmove(hp + int(self.offs[4]), counts.ctypes.data, 16)
+        with torch.cuda.stream(self.stream):
+            self.d_tables.copy_(h, non_blocking=True)
+            ev_copy = torch.cuda.Event()
+            ev_copy.record(self.stream)
+            if self.graph is not None:
+                self.graph.replay()
+            else:
+                self._launch_tables()
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        self.h_events[self.flip] = ev_copy
+        self.flip ^= 1
+        self.pending_free[id(ev)] = keep
+        return ev
+
+    def poll(self, handle) -> bool:
+        if handle.query():
+            self.pending_free.pop(id(handle), None)
+            return True
+        return False
+
+    def finish(self, req):
+        if req.keep_result:
+            req.result = self.reqs[req.rid]["xyz"].cpu().numpy()
+
+    def release(self, req):
+        r = self.reqs.pop(req.rid, None)
+        if r is not None:
+            # the slot's table entry stays as is: no tile refers to it any more
+            self.asset_refs[req.asset] -= 1
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+# ------------------------------------------------------------------ workload and driver
+
+RESOLUTIONS = [(256, 256), (1280, 720), (1920, 1080), (3840, 2160)]
+
+
+def make_requests(rate: float, count: int, n_assets: int, seed: int, t0: float = 0.0,
+                  spps=(1, 4, 16), l_range=(1, 4)):
+    """Poisson arrivals at `rate` frames/s with resolution, spp and asset drawn
+    uniformly (the serving workload's distributions)."""
+    rng = np.random.default_rng([3, 5, seed])
+    t = t0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        w, h = RESOLUTIONS[rng.integers(len(RESOLUTIONS))]
+        out.append(Request(rid=i, asset=int(rng.integers(n_assets)), width=w, height=h,
+                           spp=int(rng.choice(spps)), l_min=l_range[0], l_max=l_range[1],
+                           seed=10_000 + i, arrival=t))
+    return out
+
+
+def run_stream(sched: Scheduler, requests, time_limit: float = 120.0, idle_sleep: float = 2e-5):
+    """Feed requests at their arrival times (seconds from now) and run the
+    scheduler until all are done.  Returns wall seconds."""
+    start = time.perf_counter()
+    pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    for r in pending:
+        r.arrival += start
+    while pending or not sched.idle:
+        now = time.perf_counter()
+        if now - start > time_limit:
+            raise TimeoutError("serving run exceeded its time limit")
+        while pending and pending[0].arrival <= now:
+            sched.submit(pending.popleft())
+        if not sched.step(now):
+            time.sleep(idle_sleep)
+    return time.perf_counter() - start
+
+
+def summarize(reqs, wall: float) -> dict:
+    ok = [r for r in reqs if r.state == "done"]
+    lat = np.array([r.latency for r in ok]) * 1e3
+    verts = sum(r.expected_vertices for r in ok)
+    return {"requests": len(reqs), "completed": len(ok),
+            "failed": sum(r.state == "failed" for r in reqs),
+            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+            "mean_ms": float(lat.mean()) if lat.size else None,
+            "frames_per_s": len(ok) / wall, "path_vertices_per_s": verts / wall, "wall_s": wall}
+
+
+def make_assets(n_assets: int = 32, n: int = 31, seed: int = 3):
+    """Spectral textures in pinned host memory: sides 512, 1024, 2048 in turn,
+    each a Perlin-weighted blend of its own 16 basis reflectances (weight maps
+    of the larger sides are the 512^2 map repeated per texel block)."""
+    import torch
+
+    import synth
+    w512 = synth.perlin_weights(3001, 512)
+    rng = np.random.default_rng([3, 1, seed])
+    ld = 4 * ((n + 3) // 4)
+    out = []
+    for a in range(n_assets):
+        side = (512, 1024, 2048)[a % 3]
+        f = side // 512
+        w = w512.reshape(512, 512, -1)
+        if f > 1:
+            w = np.repeat(np.repeat(w, f, axis=0), f, axis=1)
+        basis = synth.reflectances(rng, n, 16).astype(np.float32)
+        tex = torch.zeros(side * side, ld, dtype=torch.float32).pin_memory()
+        tex[:, :n] = torch.from_numpy(w.reshape(side * side, -1).astype(np.float32) @ basis)
+        out.append(tex)
+    return out
+
+
+def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=None, assets=None):
+    """p50 / p99 frame latency and throughput of latent and spectral serving of
+    the same request streams."""
+    import torch
+
+    import synth
+    n = 31
+    rng = np.random.default_rng([3, 0])
+    lights = torch.from_numpy(synth.illuminant_table(rng, n, 16, 16))
+    T = torch.from_numpy(synth.cmf_matrix(n))
+    if E is None:
+        E, D = (torch.from_numpy(x) for x in synth.codec_uniform(np.random.default_rng([3, 3]), 6, n))
+    assets = assets if assets is not None else make_assets(32, n)
+    out = {"rates_fps": list(rates), "requests_per_rate": count}
+    for form in ("latent", "spectral"):
+        be = GpuBackend(assets, lights, T, E, D, form=form, device=device)
+        res = {}
+        for rate in rates:
+            reqs = make_requests(rate, count, len(assets), seed=int(rate))
+            sched = Scheduler(be)
+            wall = run_stream(sched, reqs)
+            s = summarize(reqs, wall)
+            s["iterations"] = sched.iterations
+            res[str(rate)] = s
+        be.synchronize()
+        out[form] = res
+        del be
+        torch.cuda.empty_cache()
+    return out
