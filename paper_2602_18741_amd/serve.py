@@ -71,9 +71,25 @@ class Plan:
     """One iteration: assets to encode, shade tiles, decode tiles, frames
     that complete when the iteration does."""
     encode: list = field(default_factory=list)          # asset ids
-    shade: list = field(default_factory=list)           # (rid, begin, end)
-    decode: list = field(default_factory=list)          # (rid, begin, end)
+    shade: list = field(default_factory=list)           # spans (rid, begin, end, tile)
+    decode: list = field(default_factory=list)          # spans (rid, begin, end, tile)
     finishing: list = field(default_factory=list)       # requests
+    n_shade: int = 0                                    # tiles in the shade spans
+
+
+def span_tiles(spans):
+    """Expand spans (rid, begin, end, tile) into arrays (span index, begin,
+    end) of tiles [b, min(b + tile, end)) for b = begin, begin + tile, ..."""
+    if not spans:
+        z = np.zeros(0, np.int64)
+        return z, z, z
+    sp = np.array([(b, e, t) for _, b, e, t in spans], dtype=np.int64)
+    counts = -(-(sp[:, 1] - sp[:, 0]) // sp[:, 2])
+    idx = np.repeat(np.arange(len(spans)), counts)
+    first = np.repeat(np.cumsum(counts) - counts, counts)
+    begin = sp[idx, 0] + (np.arange(idx.size) - first) * sp[idx, 2]
+    end = np.minimum(begin + sp[idx, 2], sp[idx, 1])
+    return idx, begin, end
 
 
 class Scheduler:
@@ -86,12 +102,16 @@ class Scheduler:
     """
 
     def __init__(self, backend, max_frames: int = 64, mem_budget: float = 32e9,
-                 tile_pixels: int = 4096, iter_vertices: float = 40e6, max_inflight: int = 2,
-                 max_tiles: int = 8192, decode_pixels: int = 65536):
+                 tile_pixels: int | None = None, iter_vertices: float = 40e6, max_inflight: int = 2,
+                 max_tiles: int = 8192, decode_pixels: int = 65536, target_tiles: int = 4096):
         self.b = backend
         self.max_frames = max_frames
         self.mem_budget = mem_budget
+        # tile_pixels fixes the tile size; by default each frame's tiles hold
+        # about iter_vertices / target_tiles path-vertices, so an iteration
+        # carries enough tiles to occupy every workgroup of the launch
         self.tile_pixels = tile_pixels
+        self.target_tiles = target_tiles
         self.iter_vertices = iter_vertices
         self.max_inflight = max_inflight
         self.max_tiles = max_tiles
@@ -158,30 +178,49 @@ class Scheduler:
         per_px = {r.rid: r.spp * 0.5 * (r.l_min + r.l_max) for r in todo}
         todo.sort(key=lambda r: ((r.n_pixels - r.next_pixel) * per_px[r.rid], r.arrival))
         budget = self.iter_vertices
+        start = {r.rid: r.next_pixel for r in todo}
+        tiles = 0
 
-        def take(req):
-            nonlocal budget
+        def take(req, n_tiles):
+            nonlocal budget, tiles
+            t = self._tile(req)
             b = req.next_pixel
-            e = min(req.n_pixels, b + self.tile_pixels)
-            plan.shade.append((req.rid, b, e))
+            e = min(req.n_pixels, b + n_tiles * t)
             req.next_pixel = e
+            got = -(-(e - b) // t)
+            tiles += got
             budget -= (e - b) * per_px[req.rid]
 
         for req in todo:
-            if len(plan.shade) >= self.max_tiles:
+            if tiles >= self.max_tiles:
                 break
-            take(req)
+            take(req, 1)
         for req in todo:
-            while req.next_pixel < req.n_pixels and budget > 0 and len(plan.shade) < self.max_tiles:
-                take(req)
+            if budget <= 0 or tiles >= self.max_tiles:
+                break
+            left = req.n_pixels - req.next_pixel
+            if left <= 0:
+                continue
+            t = self._tile(req)
+            want = -(-min(left, int(budget / per_px[req.rid]) + 1) // t)
+            take(req, max(1, min(want, self.max_tiles - tiles)))
         for req in todo:
+            if req.next_pixel > start[req.rid]:
+                plan.shade.append((req.rid, start[req.rid], req.next_pixel, self._tile(req)))
             if req.next_pixel >= req.n_pixels:
                 plan.finishing.append(req)
-                for b in range(0, req.n_pixels, self.decode_pixels):
-                    plan.decode.append((req.rid, b, min(req.n_pixels, b + self.decode_pixels)))
+                plan.decode.append((req.rid, 0, req.n_pixels, self.decode_pixels))
+        plan.n_shade = tiles
         if not plan.shade and not plan.encode:
             return None
         return plan
+
+    def _tile(self, req) -> int:
+        if self.tile_pixels:
+            return self.tile_pixels
+        per_px = req.spp * 0.5 * (req.l_min + req.l_max)
+        px = self.iter_vertices / self.target_tiles / max(per_px, 1.0)
+        return int(min(65536, max(256, 256 * round(px / 256))))
 
     def _complete(self, now: float):
         while self.inflight and self.b.poll(self.inflight[0][0]):
@@ -214,7 +253,7 @@ class Scheduler:
                     handle = self.b.launch(plan)
                 except Exception as e:  # noqa: BLE001
                     for req in {id(r): r for r in self.active}.values():
-                        if any(t[0] == req.rid for t in plan.shade):
+                        if any(sp[0] == req.rid for sp in plan.shade):
                             self._fail(req, f"launch: {e}")
                     return True
                 self.inflight.append((handle, plan))
@@ -394,14 +433,8 @@ class GpuBackend:
             self.h_events[self.flip].synchronize()   # the copy that last read this buffer is done
         hp = h.data_ptr()
         C.memmove(hp + int(self.offs[0]), C.addressof(self.frames), C.sizeof(self.frames))
-        tiles = (self.Tile * max(1, len(plan.shade)))()
-        for i, (rid, b, e) in enumerate(plan.shade):
-            tiles[i].frame, tiles[i].begin, tiles[i].end = self.reqs[rid]["slot"], b, e
-        C.memmove(hp + int(self.offs[1]), C.addressof(tiles), C.sizeof(self.Tile) * len(plan.shade))
-        dt = (self.Tile * max(1, len(plan.decode)))()
-        for i, (rid, b, e) in enumerate(plan.decode):
-            dt[i].frame, dt[i].begin, dt[i].end = self.reqs[rid]["slot"], b, e
-        C.memmove(hp + int(self.offs[2]), C.addressof(dt), C.sizeof(self.Tile) * len(plan.decode))
+        n_sh = self._put_tiles(hp + int(self.offs[1]), plan.shade)
+        n_de = self._put_tiles(hp + int(self.offs[2]), plan.decode)
         jobs = []
         keep = []
         for aid, spectral, tex in getattr(self, "_pending_spectral", []):
@@ -413,9 +446,9 @@ class GpuBackend:
         self._pending_spectral = [p for p in getattr(self, "_pending_spectral", []) if p[0] not in plan.encode]
         jt = (self.EncodeJob * max(1, len(jobs)))(*[self.EncodeJob(*j) for j in jobs])
         C.memmove(hp + int(self.offs[3]), C.addressof(jt), C.sizeof(self.EncodeJob) * len(jobs))
-        if len(plan.shade) > self.max_tiles or len(plan.decode) > self.max_tiles or len(jobs) > self.max_jobs:
-            raise RuntimeError("iteration exceeds the table capacity")
-        counts = np.array([len(plan.shade), len(plan.decode), len(jobs), 0], dtype=np.int32)
+        if len(jobs) > self.max_jobs:
+            raise RuntimeError("iteration exceeds the encode table capacity")
+        counts = np.array([n_sh, n_de, len(jobs), 0], dtype=np.int32)
         C.memmove(hp + int(self.offs[4]), counts.ctypes.data, 16)
         with torch.cuda.stream(self.stream):
             self.d_tables.copy_(h, non_blocking=True)
@@ -431,6 +464,20 @@ class GpuBackend:
         self.flip ^= 1
         self.pending_free[id(ev)] = keep
         return ev
+
+    _TILE_DT = np.dtype([("frame", "<i4"), ("pad", "<i4"), ("begin", "<i8"), ("end", "<i8")])
+
+    def _put_tiles(self, dst: int, spans) -> int:
+        """Write the tiles of `spans` into the pinned table at address dst."""
+        idx, begin, end = span_tiles(spans)
+        if idx.size > self.max_tiles:
+            raise RuntimeError("iteration exceeds the tile table capacity")
+        arr = np.zeros(idx.size, self._TILE_DT)
+        if idx.size:
+            span_slot = np.array([self.reqs[sp[0]]["slot"] for sp in spans], dtype=np.int32)
+            arr["frame"], arr["begin"], arr["end"] = span_slot[idx], begin, end
+            C.memmove(dst, arr.ctypes.data, arr.nbytes)
+        return int(idx.size)
 
     def poll(self, handle) -> bool:
         if handle.query():

@@ -4,7 +4,7 @@ pixel, memory budget, FIFO admission, failure injection, interleaving."""
 import numpy as np
 import pytest
 
-from paper_2602_18741_amd.serve import Request, Scheduler, make_requests
+from paper_2602_18741_amd.serve import Request, Scheduler, make_requests, span_tiles
 
 
 class Handle:
@@ -48,9 +48,13 @@ class FakeBackend:
         if self.fail_launch_iteration == self.launches:
             raise RuntimeError("injected launch failure")
         self.encoded.extend(plan.encode)
-        for rid, b, e in plan.shade:
-            self.shaded[rid][b:e] += 1
-        for rid, b, e in plan.decode:
+        idx, begin, end = span_tiles(plan.shade)
+        assert idx.size == plan.n_shade
+        for i, b, e in zip(idx, begin, end):
+            self.shaded[plan.shade[i][0]][b:e] += 1
+        idx, begin, end = span_tiles(plan.decode)
+        for i, b, e in zip(idx, begin, end):
+            rid = plan.decode[i][0]
             assert (self.shaded[rid][b:e] == 1).all(), "decode before every pixel is shaded"
             self.decoded[rid][b:e] += 1
         return Handle(self.polls)
@@ -81,6 +85,13 @@ def drive(sched, reqs, max_steps=100000):
         if i == len(reqs) and sched.idle:
             return
     raise AssertionError("scheduler did not drain")
+
+
+def test_span_expansion():
+    idx, b, e = span_tiles([(7, 0, 10, 4), (9, 5, 6, 100), (3, 100, 112, 4)])
+    assert idx.tolist() == [0, 0, 0, 1, 2, 2, 2]
+    assert b.tolist() == [0, 4, 8, 5, 100, 104, 108]
+    assert e.tolist() == [4, 8, 10, 6, 104, 108, 112]
 
 
 def test_every_pixel_shaded_and_decoded_once():
