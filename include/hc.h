@@ -70,10 +70,10 @@ int32_t hc_version(void);
  *                 paths store their vertices back to back, in path order.
  *   vtx[2*j]      uint32 texel (or material) index of vertex record j,
  *   vtx[2*j+1]    IEEE-754 bits of its float32 weight.  8-byte aligned.
- * Records outside the assets (texel >= n_texels, light >= n_illum, or a
- * pixel whose records run past n_vertices) are clamped to the last valid
- * index so that no read leaves the buffers; the value computed for such a
- * pixel is unspecified.  hc_check_paths detects them.
+ * Records outside the assets (texel >= n_texels, light >= n_illum) are
+ * clamped to the last valid index and vertex records at or past n_vertices
+ * are skipped, so that no read leaves the buffers; the value computed for
+ * such a pixel is unspecified.  hc_check_paths detects them.
  */
 typedef struct hc_paths {
     int64_t n_pixels;
