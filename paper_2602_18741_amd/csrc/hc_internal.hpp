@@ -31,10 +31,30 @@ constexpr int kMaxBlocks = kMaxK / 3;  // 16 float4 slots per latent row
 
 // ---------------------------------------------------------------- device helpers
 
+// Device-memory accesses through the global address space: pointers read
+// from device tables would otherwise be generic and compile to flat
+// instructions.  Every buffer the library touches is global memory.
+#define HC_GLOBAL __attribute__((address_space(1)))
+typedef float hc_v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int hc_v2u __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ float4 ld4(const float* p) {
-    return *reinterpret_cast<const float4*>(p);
+    const hc_v4f v = *(const HC_GLOBAL hc_v4f*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+__device__ __forceinline__ void st4(float* p, float4 v) {
+    const hc_v4f t = {v.x, v.y, v.z, v.w};
+    *(HC_GLOBAL hc_v4f*)p = t;
+}
+__device__ __forceinline__ uint2 ldg_u2(const uint2* p) {
+    const hc_v2u v = *(const HC_GLOBAL hc_v2u*)p;
+    return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint32_t ldg_u32(const uint32_t* p) {
+    return *(const HC_GLOBAL uint32_t*)p;
+}
+__device__ __forceinline__ float ldg_f32(const float* p) { return *(const HC_GLOBAL float*)p; }
+__device__ __forceinline__ void stg_f32(float* p, float v) { *(HC_GLOBAL float*)p = v; }
 __device__ __forceinline__ float4 mul4(float4 a, float4 b) {
     return make_float4(a.x * b.x, a.y * b.y, a.z * b.z, a.w * b.w);
 }

@@ -143,15 +143,15 @@ __device__ __forceinline__ void decode_pixel(const float* s_M, const float* s_D,
         w += s_M[6 * NB + c] * z[c];
     }
     float* o = xyz + q * 3;
-    o[0] = x;
-    o[1] = y;
-    o[2] = w;
+    stg_f32(o + 0, x);
+    stg_f32(o + 1, y);
+    stg_f32(o + 2, w);
     if (spectra) {
         float* sp = spectra + q * ld_s;
         for (int i = 0; i < n; ++i) {
             float acc = 0.f;
             for (int c = 0; c < k; ++c) acc += s_D[i * k + c] * z[c];
-            sp[i] = acc;
+            stg_f32(sp + i, acc);
         }
     }
 }

@@ -39,9 +39,9 @@ __device__ __forceinline__ void stage_lights(const LatentFrame& f, float4* s_lig
     }
 }
 
-// The calling wave shades pixels [q0, min(q0 + pw, q_end)).  s_light is the
-// staged light table or nullptr.
-template <int NB>
+// The calling wave shades pixels [q0, min(q0 + pw, q_end)).  With LDS the
+// light codes come from the staged table s_light, else from global memory.
+template <int NB, bool LDS>
 __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, int64_t q_end,
                                              const float4* s_light) {
 #pragma clang fp contract(off)
@@ -51,7 +51,7 @@ __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, i
     const int j0 = lane % seg;
     const int64_t q = q0 + lane / seg;
     const bool pix_ok = q < q_end;
-    uint32_t next = pix_ok ? P.pix_first[q] : 0u;
+    uint32_t next = pix_ok ? ldg_u32(P.pix_first + q) : 0u;
 
     float4 acc[NB];
 #pragma unroll
@@ -60,7 +60,7 @@ __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, i
     for (int r = 0; r < P.rounds; ++r) {
         const int j = j0 + r * seg;
         const bool live = pix_ok && j < P.spp;
-        const uint32_t h = live ? P.hdr[q * P.spp + j] : 0u;
+        const uint32_t h = live ? ldg_u32(P.hdr + (q * P.spp + j)) : 0u;
         const uint32_t len = h >> 24;
         uint32_t total;
         const uint32_t first = next + segment_scan(len, j0, seg, 1, total);
@@ -76,15 +76,23 @@ __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, i
             // in flight before the first multiply; padding slots multiply by 1
             constexpr int U = NB <= 4 ? 4 : (NB <= 8 ? 2 : 1);
             for (uint32_t jv = first; jv < end; jv += U) {
+                // records first, all U in flight: slots past the path read the
+                // following (in-bounds) records, which the wave fetches anyway;
+                // their weights and rows are replaced by 1 below
                 uint2 rec[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    rec[u] = (jv + u < end) ? P.vtx[jv + u] : make_uint2(0u, 0x3F800000u);
+                for (int u = 0; u < U; ++u) rec[u] = ldg_u2(P.vtx + min(jv + u, P.n_vertices - 1u));
+                uint32_t tex[U];
+                float wt[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    tex[u] = min(rec[u].x, f.n_tex - 1u);
+                    wt[u] = (jv + u < end) ? __uint_as_float(rec[u].y) : 1.f;
+                }
                 float4 row[U][NB];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t t = min(rec[u].x, f.n_tex - 1u);
-                    const float* rp = f.codes + int64_t(t) * f.ld + 4 * f.block_first;
+                    const float* rp = f.codes + int64_t(tex[u]) * f.ld + 4 * f.block_first;
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
                         row[u][b] = (jv + u < end) ? ld4(rp + 4 * b) : make_float4(1.f, 1.f, 1.f, 1.f);
@@ -93,14 +101,14 @@ __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, i
                 for (int u = 0; u < U; ++u) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) prod[b] = mul4(prod[b], row[u][b]);
-                    wprod *= __uint_as_float(rec[u].y);
+                    wprod *= wt[u];
                 }
             }
             const uint32_t lid = min(h & 0xFFFFFFu, f.n_illum - 1u);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const float4 lc = s_light ? s_light[lid * NB + b]
-                                          : ld4(f.lcodes + int64_t(lid) * f.ld_l + 4 * (f.block_first + b));
+                const float4 lc = LDS ? s_light[lid * NB + b]
+                                      : ld4(f.lcodes + int64_t(lid) * f.ld_l + 4 * (f.block_first + b));
                 acc[b] = add4(acc[b], mul4(scale4(lc, wprod), prod[b]));
             }
         }
@@ -134,7 +142,10 @@ __global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentFrame f, int
     const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t q0 = wave * f.P.pw;
     if (q0 >= f.P.n_pixels) return;  // whole wave leaves together; no barrier follows
-    latent_group<NB>(f, q0, f.P.n_pixels, lights_in_lds ? s_light : nullptr);
+    if (lights_in_lds)
+        latent_group<NB, true>(f, q0, f.P.n_pixels, s_light);
+    else
+        latent_group<NB, false>(f, q0, f.P.n_pixels, s_light);
 }
 
 // Persistent launch over a tile table: block b takes tiles b, b + grid, ...
@@ -170,8 +181,12 @@ __global__ __launch_bounds__(kBlock) void shade_latent_tiles_kernel(const hc_fra
         if (lds) stage_lights<NB>(f, s_light);
         __syncthreads();
         const int64_t groups = (end - begin + f.P.pw - 1) / f.P.pw;
-        for (int64_t g = wave; g < groups; g += kWavesPerBlock)
-            latent_group<NB>(f, begin + g * f.P.pw, end, lds ? s_light : nullptr);
+        for (int64_t g = wave; g < groups; g += kWavesPerBlock) {
+            if (lds)
+                latent_group<NB, true>(f, begin + g * f.P.pw, end, s_light);
+            else
+                latent_group<NB, false>(f, begin + g * f.P.pw, end, s_light);
+        }
     }
 }
 

@@ -36,9 +36,9 @@ __device__ __forceinline__ void stage_lights(const SpectralFrame& f, float4* s_l
     }
 }
 
-// The calling wave shades pixels [q0, min(q0 + pw, q_end)); s_light is the
-// staged light table or nullptr.
-template <int G, int Q>
+// The calling wave shades pixels [q0, min(q0 + pw, q_end)).  With LDS the
+// light spectra come from the staged table s_light, else from global memory.
+template <int G, int Q, bool LDS>
 __device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q0, int64_t q_end,
                                                const float4* s_light) {
     const PathView& P = f.P;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = 4 * c + e;
-                w[e] = (i < f.n) ? f.T[ch * f.n + i] : 0.f;
+                w[e] = (i < f.n) ? ldg_f32(f.T + ch * f.n + i) : 0.f;
             }
             Tr[ch][qq] = make_float4(w[0], w[1], w[2], w[3]);
         }
@@ -67,13 +67,13 @@ __device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q
     const int j0 = slot % seg;
     const int64_t q = q0 + slot / seg;
     const bool pix_ok = q < q_end;
-    uint32_t next = pix_ok ? P.pix_first[q] : 0u;
+    uint32_t next = pix_ok ? ldg_u32(P.pix_first + q) : 0u;
     float ax = 0.f, ay = 0.f, az = 0.f;
 
     for (int r = 0; r < P.rounds; ++r) {
         const int j = j0 + r * seg;
         const bool live = pix_ok && j < P.spp;
-        const uint32_t h = live ? P.hdr[q * P.spp + j] : 0u;
+        const uint32_t h = live ? ldg_u32(P.hdr + (q * P.spp + j)) : 0u;
         const uint32_t len = h >> 24;
         uint32_t total;
         const uint32_t first = next + segment_scan(len, j0, seg, G, total);
@@ -88,15 +88,23 @@ __device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q
             // the first multiply; padding slots multiply by 1
             constexpr int U = Q <= 2 ? 4 : 2;
             for (uint32_t jv = first; jv < end; jv += U) {
+                // records first, all U in flight: slots past the path read the
+                // following (in-bounds) records, which the wave fetches anyway;
+                // their weights and rows are replaced by 1 below
                 uint2 rec[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    rec[u] = (jv + u < end) ? P.vtx[jv + u] : make_uint2(0u, 0x3F800000u);
+                for (int u = 0; u < U; ++u) rec[u] = ldg_u2(P.vtx + min(jv + u, P.n_vertices - 1u));
+                uint32_t tex[U];
+                float wt[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    tex[u] = min(rec[u].x, f.n_tex - 1u);
+                    wt[u] = (jv + u < end) ? __uint_as_float(rec[u].y) : 1.f;
+                }
                 float4 row[U][Q];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t t = min(rec[u].x, f.n_tex - 1u);
-                    const float* rp = f.refl + int64_t(t) * f.ld;
+                    const float* rp = f.refl + int64_t(tex[u]) * f.ld;
 #pragma unroll
                     for (int qq = 0; qq < Q; ++qq) {
                         const int c = qq * G + sub;
@@ -108,7 +116,7 @@ __device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q
                 for (int u = 0; u < U; ++u) {
 #pragma unroll
                     for (int qq = 0; qq < Q; ++qq) prod[qq] = mul4(prod[qq], row[u][qq]);
-                    wprod *= __uint_as_float(rec[u].y);
+                    wprod *= wt[u];
                 }
             }
             const uint32_t lid = min(h & 0xFFFFFFu, f.n_illum - 1u);
@@ -116,8 +124,8 @@ __device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q
             for (int qq = 0; qq < Q; ++qq) {
                 const int c = qq * G + sub;
                 if (c < f.nq) {
-                    const float4 lt = s_light ? s_light[lid * f.nq + c]
-                                              : ld4(f.illum + int64_t(lid) * f.ld_l + 4 * c);
+                    const float4 lt = LDS ? s_light[lid * f.nq + c]
+                                          : ld4(f.illum + int64_t(lid) * f.ld_l + 4 * c);
                     float4 s = mul4(scale4(lt, wprod), prod[qq]);
                     // samples past n carry no colour weight; drop them so
                     // non-finite row padding cannot leak in
@@ -143,9 +151,9 @@ __device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q
     }
     if (pix_ok && sub == 0 && j0 == 0) {
         float* out = f.xyz + q * 3;
-        out[0] = ax * f.inv_spp;
-        out[1] = ay * f.inv_spp;
-        out[2] = az * f.inv_spp;
+        stg_f32(out + 0, ax * f.inv_spp);
+        stg_f32(out + 1, ay * f.inv_spp);
+        stg_f32(out + 2, az * f.inv_spp);
     }
 }
 
@@ -159,7 +167,10 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralFrame f,
     const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t q0 = wave * f.P.pw;
     if (q0 >= f.P.n_pixels) return;
-    spectral_group<G, Q>(f, q0, f.P.n_pixels, lights_in_lds ? s_light : nullptr);
+    if (lights_in_lds)
+        spectral_group<G, Q, true>(f, q0, f.P.n_pixels, s_light);
+    else
+        spectral_group<G, Q, false>(f, q0, f.P.n_pixels, s_light);
 }
 
 // Persistent launch over a tile table (see the latent form).
@@ -194,8 +205,12 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_tiles_kernel(const hc_f
         if (lds) stage_lights(f, s_light);
         __syncthreads();
         const int64_t groups = (end - begin + f.P.pw - 1) / f.P.pw;
-        for (int64_t g = wave; g < groups; g += kWavesPerBlock)
-            spectral_group<G, Q>(f, begin + g * f.P.pw, end, lds ? s_light : nullptr);
+        for (int64_t g = wave; g < groups; g += kWavesPerBlock) {
+            if (lds)
+                spectral_group<G, Q, true>(f, begin + g * f.P.pw, end, s_light);
+            else
+                spectral_group<G, Q, false>(f, begin + g * f.P.pw, end, s_light);
+        }
     }
 }
 

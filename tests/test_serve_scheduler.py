@@ -17,7 +17,7 @@ class FakeBackend:
     """Records what the scheduler asks for; 'executes' a plan by counting
     which pixels were shaded and decoded."""
 
-    def __init__(self, fail_prepare=(), fail_launch_iteration=None, polls=2):
+    def __init__(self, fail_prepare=(), fail_launch_iteration=None, polls=2, upload_polls=0):
         self.fail_prepare = set(fail_prepare)
         self.fail_launch_iteration = fail_launch_iteration
         self.polls = polls
@@ -25,7 +25,8 @@ class FakeBackend:
         self.live_bytes = 0
         self.max_live = 0
         self.launches = 0
-        self.resident = set()
+        self.resident = {}          # asset -> [state, polls until arrived]
+        self.upload_polls = upload_polls
         self.encoded = []
 
     def request_bytes(self, req):
@@ -34,21 +35,34 @@ class FakeBackend:
     def prepare(self, req):
         if req.rid in self.fail_prepare:
             raise RuntimeError("injected prepare failure")
+        self.asset_of = getattr(self, "asset_of", {})
+        self.asset_of[req.rid] = req.asset
         self.shaded[req.rid] = np.zeros(req.n_pixels, np.int32)
         self.decoded[req.rid] = np.zeros(req.n_pixels, np.int32)
         self.live_bytes += self.request_bytes(req)
         self.max_live = max(self.max_live, self.live_bytes)
         self.order.append(req.rid)
-        new = req.asset not in self.resident
-        self.resident.add(req.asset)
-        return new
+        if req.asset not in self.resident:
+            self.resident[req.asset] = ["pending", self.upload_polls]
+
+    def asset_state(self, asset):
+        a = self.resident[asset]
+        if a[0] == "pending":
+            if a[1] <= 0:
+                a[0] = "needs_encode"
+            a[1] -= 1
+        return a[0]
 
     def launch(self, plan):
         self.launches += 1
         if self.fail_launch_iteration == self.launches:
             raise RuntimeError("injected launch failure")
         self.encoded.extend(plan.encode)
+        for a in plan.encode:
+            self.resident[a][0] = "ready"
         idx, begin, end = span_tiles(plan.shade)
+        for i in idx:
+            assert self.resident[self.asset_of[plan.shade[i][0]]][0] == "ready", "tile before its asset"
         assert idx.size == plan.n_shade
         for i, b, e in zip(idx, begin, end):
             self.shaded[plan.shade[i][0]][b:e] += 1
@@ -151,6 +165,21 @@ def test_launch_failure_fails_only_its_frames():
     assert all("launch" in r.error for r in failed)
     assert all(r.state == "done" for r in reqs if r not in failed)
     assert sched.mem_used == 0 and be.live_bytes == 0
+
+
+def test_frames_wait_for_their_asset_but_not_for_others():
+    """A frame whose asset is still arriving is not tiled; frames with
+    resident assets proceed meanwhile."""
+    be = FakeBackend(upload_polls=40)
+    sched = Scheduler(be, max_frames=8, mem_budget=1e12, tile_pixels=4096, iter_vertices=1e6)
+    first = Request(rid=0, asset=0, width=256, height=256, spp=1, l_min=1, l_max=4, seed=0, arrival=0.0)
+    drive(sched, [first])
+    be.upload_polls = 400
+    late = Request(rid=1, asset=1, width=256, height=256, spp=1, l_min=1, l_max=4, seed=1, arrival=1.0)
+    warm = Request(rid=2, asset=0, width=256, height=256, spp=1, l_min=1, l_max=4, seed=2, arrival=1.0001)
+    drive(sched, [late, warm])
+    assert late.state == warm.state == "done"
+    assert warm.t_done < late.t_done
 
 
 def test_small_frame_overtakes_a_large_one():
