@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "1920x1080 px, 16 spp, path length 1-4, 1024^2 x 31 Perlin texture, 32 lights, latent k=6"
+STRESS = ("3840x2160 px, 64 spp, path length 1-8, 4096^2 x 81 texture, 256 lights "
+          "(75% narrow-band), latent k=9")
 
 
 def log(*a):
@@ -51,8 +53,8 @@ def _oracle_chunk(pixels):
     hdr, pf, vtx = records_of_pixels(w["paths"], pixels)
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        osh.render_latent_xyz(hdr, pf, vtx, w["paths"].spp, w["refl"], w["illum"], w["E"], w["D"],
-                              w["T"])
+        osh.render_latent_xyz(hdr, pf, vtx, w["paths"].spp, w["refl"][:, :w["n"]], w["illum"], w["E"],
+                              w["D"], w["T"])
         dt = time.perf_counter() - t0
     return int(vtx.shape[0]), dt
 
@@ -146,6 +148,8 @@ def main():
                     help="requests per arrival rate in the serving measurement")
     ap.add_argument("--record-traffic", nargs=4, metavar="CSV",
                     help="fetch, write, copy-fetch, copy-write counter CSVs -> traffic record")
+    ap.add_argument("--stress", action="store_true",
+                    help="the 4K / 64 spp / n=81 / k=9 stress frame instead of the default frame")
     ap.add_argument("--only", choices=["latent", "spectral", "copy"],
                     help="run only the timed steps of one form (or a 1 GiB device copy), "
                          "for profilers; prints no JSON")
@@ -172,11 +176,17 @@ def main():
         log("copied 1 GiB", args.warmup + args.steps, "times")
         return
 
+    stress = args.stress
+    wid, k, n = (4, 9, 81) if stress else (1, args.k, 31)
+    # row strides that keep every texel row inside whole 128-byte lines:
+    # 81 samples -> 96 floats (3 lines), 9 channels -> 16 floats (64 B)
+    ld_tex = 96 if stress else 32
+    ld_z = 16 if stress else None
     t_setup = time.time()
-    w = synth.workload(1, k=args.k)
+    w = synth.workload(wid, k=k, ld_tex=ld_tex)
     spec = w["paths"]
     log(f"inputs generated in {time.time() - t_setup:.1f} s")
-    cpu = None if (args.no_cpu or args.only) else cpu_baseline(w)
+    cpu = None if (args.no_cpu or args.only or stress) else cpu_baseline(w)
     if cpu:
         log("cpu baseline:", cpu["sample"])
 
@@ -186,8 +196,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    k, n = args.k, 31
-    refl = ops.padded(torch.from_numpy(w["refl"]).to(dev))
+    refl = torch.from_numpy(w["refl"]).to(dev)
+    del w["refl"]
     illum = ops.padded(torch.from_numpy(w["illum"]).to(dev))
     T = torch.from_numpy(w["T"]).to(dev)
     P = ops.gen_paths(spec.n_pixels, spec.spp, spec.l_min, spec.l_max, spec.n_tex, spec.n_illum,
@@ -212,9 +222,12 @@ def main():
     codec_ms = (time.perf_counter() - t0) * 1e3 / max(1, codec_steps - 1)
     E, D = fit.weights()
     log(f"codec fit: {fit.steps_done} steps, final loss {loss:.4g}, {codec_ms * 1e3:.1f} us/step")
+    codec_steps_done = fit.steps_done
+    del fit, pa, pb
 
-    codes = torch.empty(spec.n_tex, ops.latent_width(k), device=dev)
-    lcodes = torch.empty(spec.n_illum, ops.latent_width(k), device=dev)
+    lw = ld_z or ops.latent_width(k)
+    codes = torch.empty(spec.n_tex, lw, device=dev)
+    lcodes = torch.empty(spec.n_illum, lw, device=dev)
     zimg = torch.zeros(npx, ops.latent_width(k), device=dev)
     xyz_l = torch.empty(npx, 3, device=dev)
     xyz_s = torch.empty(npx, 3, device=dev)
@@ -262,13 +275,13 @@ def main():
     bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
     bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
     achieved = bytes_lat / lat_kern / 1e9
-    traffic = measured_traffic(bytes_lat)
+    traffic = None if stress else measured_traffic(bytes_lat)
 
     de = colour.frame_difference(xyz_s.cpu().numpy(), xyz_l.cpu().numpy())
     log(f"CIEDE2000 latent vs spectral: mean {de['mean']:.3f}, p95 {de['p95']:.3f}")
 
     serving = None
-    if not args.no_serve:
+    if not (args.no_serve or stress):
         from paper_2602_18741_amd.serve import bench_serving
         del P, zimg
         torch.cuda.empty_cache()
@@ -280,6 +293,7 @@ def main():
 
     out = {
         "metric": "path-vertices/s latent k=6 vs spectral n=31; HBM GB/s; p99 frame ms",
+        "note": "stress workload: latent k=9 vs spectral n=81" if stress else None,
         "value": nv / lat_wall,
         "unit": "path-vertices/s",
         "n_gpus": 1,
@@ -291,10 +305,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "pixels": npx, "spp": spec.spp, "paths": npath,
+        "config": {"workload": STRESS if stress else WORKLOAD, "pixels": npx, "spp": spec.spp,
+                   "paths": npath,
                    "path_vertices": nv, "k": k, "n": n, "texels": spec.n_tex,
                    "lights": spec.n_illum, "step": "encode texture+lights, shade latent, decode"},
-        "roofline": {"bound": "hbm", "kernel": "shade_latent_kernel<2>", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": f"shade_latent_kernel<{ops.blocks(k)}>",
+                     "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": bytes_lat,
                      "kernel_ms": lat_kern * 1e3},
@@ -305,7 +321,7 @@ def main():
         "speedup_latent_vs_spectral": spe_wall / lat_wall,
         "shade_speedup_latent_vs_spectral": spe_kern / lat_kern,
         "ciede2000_latent_vs_spectral": de,
-        "codec_fit": {"steps": fit.steps_done, "batch": 65536, "final_loss": loss,
+        "codec_fit": {"steps": codec_steps_done, "batch": 65536, "final_loss": loss,
                       "us_per_step": codec_ms * 1e3},
         "serving": serving,
     }

@@ -65,17 +65,28 @@ def perlin_weights(seed: int, side: int, n_fields: int = 16, cells: int = 8,
 
 
 def perlin_texture(seed: int, side: int, basis: np.ndarray, ld: int | None = None,
-                   chunk_rows: int = 256) -> np.ndarray:
+                   chunk_rows: int = 256, base: int | None = None) -> np.ndarray:
     """side x side spectral texture: texel = sum_j weight_j * basis_j.
 
     `basis` is (n_fields, n) with entries in [0, 1]; the weights sum to 1, so
-    texels stay in [0, 1].  Returns (side*side, ld) float32 with columns
-    [n, ld) zero (ld defaults to n).
+    texels stay in [0, 1].  With `base` (dividing side), the weight field is
+    computed on a base x base grid and each weight covers a block of
+    (side/base)^2 texels, which keeps very large textures cheap to build.
+    Returns (side*side, ld) float32 with columns [n, ld) zero (ld defaults to n).
     """
     nf, n = basis.shape
     ld = n if ld is None else ld
     out = np.zeros((side * side, ld), dtype=np.float32)
     b64 = basis.astype(np.float64)
+    if base is not None and base < side:
+        f = side // base
+        w = perlin_weights(seed, base, nf)            # (base*base, nf)
+        blended = (w @ b64).astype(np.float32).reshape(base, base, n)
+        for r0 in range(0, side, chunk_rows):
+            r1 = min(side, r0 + chunk_rows)
+            rows = blended[np.arange(r0, r1) // f]     # (r1-r0, base, n)
+            out[r0 * side:r1 * side, :n] = np.repeat(rows, f, axis=1).reshape(-1, n)
+        return out
     for r0 in range(0, side, chunk_rows):
         r1 = min(side, r0 + chunk_rows)
         w = perlin_weights(seed, side, nf, rows=slice(r0, r1))

@@ -14,7 +14,8 @@ generator takes the integer seed ``1000 * c + 2``.
   narrow-band) at n in {31, 81}.
 * c = 3  serving: request stream (see the serving module).
 * c = 4  stress: n = 81, k = 9, 3840 x 2160 px, 64 spp, L in 1..8,
-  4096^2 x 81 texture, 256 lights (64 Planck, 192 narrow-band sigma 5-10).
+  4096^2 x 81 texture (Perlin weights on a 512^2 grid, one weight per 8x8
+  texel block), 256 lights (64 Planck, 192 narrow-band sigma 5-10).
 """
 
 from __future__ import annotations
@@ -60,7 +61,7 @@ def workload(c: int, *, width: int | None = None, height: int | None = None,
         basis = reflectances(t0, n, 16)
         illum = illuminant_table(t0, n, 64, 192, 5.0, 10.0)
         side = texture_side or 4096
-        refl = perlin_texture(4001, side, basis, ld=ld_tex)
+        refl = perlin_texture(4001, side, basis, ld=ld_tex, base=min(side, 512))
         w, h, s, lmin, lmax = 3840, 2160, 64, 1, 8
     else:
         raise ValueError(f"workload {c} has no frame inputs")
