@@ -50,7 +50,7 @@ typedef int32_t hc_status;
 #define HC_EALIGN 3       /* pointer or stride misaligned */
 #define HC_ENOMEM 4       /* workspace too small */
 #define HC_EDEVICE 5      /* a HIP call or kernel launch failed */
-#define HC_EUNSUPPORTED 6 /* valid request that this build does not handle */
+#define HC_EUNSUPPORTED 6 /* valid request outside the compiled kernel variants */
 
 /* Name of a status code ("HC_OK", ...).  Static string, never NULL. */
 const char* hc_status_string(hc_status s);
