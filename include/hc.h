@@ -250,20 +250,35 @@ hc_status hc_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int32
  *
  * Parameters Wt_E (k x n) and Wt_D (n x k), row-major; the codec is
  * E = softplus_beta(Wt_E), D = softplus_beta(Wt_D).  On a batch of N pairs
- * (a_i, b_i) the loss is
- *   L = (1/N) sum_i ( |D E a_i - a_i|^2 + |D E b_i - b_i|^2
- *                     + lambda |D (E a_i (.) E b_i) - a_i * b_i|^2 ),
- * the reconstruction term L_rec plus lambda times the squared-error part of
- * L_e2e.  The call writes L and, if requested, dL/dWt_E and dL/dWt_D
- * (hand-derived backward), and optionally applies one Adam step.
+ * (a_i, b_i), with u = E a, v = E b, h = u (.) v (blockwise product, Eq. 6),
+ * S_hat = D h and t = a * b, the objective is one of:
+ *
+ * HC_CODEC_L2 (objective 0):
+ *   L = (1/N) sum_i ( |D u - a|^2 + |D v - b|^2 + lambda |S_hat - t|^2 ),
+ *   the reconstruction term L_rec plus lambda times the squared-error part of
+ *   L_e2e, squared norms summed over the n samples.
+ * HC_CODEC_EQ8 (objective 1), the weighted four-term loss of Eq. 8, every
+ *   MSE a mean over a pair's elements and then over the batch:
+ *   L = w_e2e mean_i[ MSE(S_hat, t) (2 - cos(S_hat, t)) ]
+ *     + w_rec (MSE(D u, a) + MSE(D v, b)) + w_code MSE(h, E t)
+ *     + w_col MSE(T S_hat, T t),
+ *   cos(x, y) = x.y / (max(|x|, cos_eps) max(|y|, cos_eps)); T is the 3 x n
+ *   colour-matching matrix (dtype below).  The paper's weights are
+ *   (0.5, 0.75, 1.0, 0.5) (Sec. 4.5).
+ *
+ * The call writes L and, if requested, dL/dWt_E and dL/dWt_D (hand-derived
+ * backward), and optionally applies one Adam step.
  *
  * dtype: 0 = float32 everywhere, 1 = float64 everywhere (parameters, data,
- * outputs, Adam state).  Partial sums are accumulated in float64 and reduced
- * in a fixed order, so results are deterministic.
+ * T, outputs, Adam state).  Partial sums are accumulated in float64 and
+ * reduced in a fixed order, so results are deterministic.
  * Batch rows: row i of the a-batch is A[idx_a[i]*ld_a ...] when idx_a is
  * not NULL, else A[i*ld_a ...]; likewise b.  Indices must be < rows_a
  * (rows_b); out-of-range indices are clamped.
  */
+#define HC_CODEC_L2 0
+#define HC_CODEC_EQ8 1
+
 typedef struct hc_adam {
     void* m_E;          /* k x n first moments (dtype) */
     void* v_E;          /* k x n second moments */
@@ -276,9 +291,9 @@ typedef struct hc_adam {
 typedef struct hc_codec_args {
     int32_t k, n;
     int32_t dtype;
-    int32_t reserved0;
+    int32_t objective;  /* HC_CODEC_L2 or HC_CODEC_EQ8 */
     double beta;        /* softplus sharpness (10 in the paper) */
-    double lambda;      /* weight of the product term */
+    double lambda;      /* HC_CODEC_L2: weight of the product term */
     void* Wt_E;         /* updated in place when adam != NULL */
     void* Wt_D;
     const void* A;
@@ -295,9 +310,14 @@ typedef struct hc_codec_args {
     void* workspace;
     size_t workspace_bytes;
     void* stream;
+    /* HC_CODEC_EQ8 only (ignored otherwise): */
+    const void* T;      /* 3 x n, row-major */
+    double w_e2e, w_rec, w_code, w_col;  /* finite, >= 0 */
+    double cos_eps;     /* > 0; 1e-8 is customary */
 } hc_codec_args;
 
-/* Bytes of workspace hc_codec_step needs for this shape (8-byte aligned). */
+/* Bytes of workspace hc_codec_step needs for this shape, for either
+ * objective (8-byte aligned). */
 size_t hc_codec_workspace_size(int32_t k, int32_t n, int64_t N);
 hc_status hc_codec_step(const hc_codec_args* args);
 

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libhc.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "hc.h")
 
 HC_OK, HC_EINVAL, HC_ESHAPE, HC_EALIGN, HC_ENOMEM, HC_EDEVICE, HC_EUNSUPPORTED = range(7)
+HC_CODEC_L2, HC_CODEC_EQ8 = 0, 1
 
 vp = C.c_void_p
 i32, i64, u64, f64, sz = C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
@@ -47,12 +48,13 @@ class Adam(C.Structure):
 
 
 class CodecArgs(C.Structure):
-    _fields_ = [("k", i32), ("n", i32), ("dtype", i32), ("reserved0", i32),
+    _fields_ = [("k", i32), ("n", i32), ("dtype", i32), ("objective", i32),
                 ("beta", f64), ("lam", f64), ("Wt_E", vp), ("Wt_D", vp), ("A", vp), ("B", vp),
                 ("ld_a", i64), ("ld_b", i64), ("rows_a", i64), ("rows_b", i64),
                 ("idx_a", vp), ("idx_b", vp), ("N", i64), ("loss", vp), ("grad_E", vp),
                 ("grad_D", vp), ("adam", C.POINTER(Adam)), ("workspace", vp),
-                ("workspace_bytes", sz), ("stream", vp)]
+                ("workspace_bytes", sz), ("stream", vp), ("T", vp), ("w_e2e", f64), ("w_rec", f64),
+                ("w_code", f64), ("w_col", f64), ("cos_eps", f64)]
 
 
 class PathGen(C.Structure):

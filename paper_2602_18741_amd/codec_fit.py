@@ -19,10 +19,16 @@ from . import ops
 class CodecFit:
     def __init__(self, we0: np.ndarray, wd0: np.ndarray, pool_a: torch.Tensor, pool_b: torch.Tensor,
                  batch: int = 65536, lam: float = 1.0, beta: float = 10.0, lr: float = 1e-3,
-                 seed: int = 0, dtype=torch.float32):
+                 seed: int = 0, dtype=torch.float32, objective: str = "l2", T=None,
+                 weights=ops.EQ8_WEIGHTS):
+        """objective "l2" (two-term squared error weighted by lam) or "eq8"
+        (the four-term loss of Eq. 8 with `weights` and the 3 x n
+        colour-matching matrix T)."""
         dev = pool_a.device
         self.k, self.n = we0.shape
         self.N, self.lam, self.beta, self.seed = batch, lam, beta, seed
+        self.objective, self.eq8_weights = objective, tuple(float(w) for w in weights)
+        self.T = None if T is None else torch.as_tensor(np.asarray(T), dtype=dtype).to(dev).contiguous()
         self.Wt_E = torch.tensor(we0, dtype=dtype, device=dev)
         self.Wt_D = torch.tensor(wd0, dtype=dtype, device=dev)
         self.pool_a = pool_a.to(dtype).contiguous()
@@ -45,7 +51,8 @@ class CodecFit:
                         out=self.idx_b)
         ops.codec_step(self.Wt_E, self.Wt_D, self.pool_a, self.pool_b, self.N, lam=self.lam,
                        beta=self.beta, idx_a=self.idx_a, idx_b=self.idx_b, loss=self.loss,
-                       adam=self.adam, workspace=self.ws)
+                       adam=self.adam, workspace=self.ws, objective=self.objective, T=self.T,
+                       weights=self.eq8_weights)
 
     def capture(self):
         """Record one step in a HIP graph (warm-up step first, as graph capture

@@ -259,6 +259,15 @@ hc_status hc_codec_step(const hc_codec_args* a) {
     HC_REQUIRE(a->k >= 1 && a->k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, a->k, kMaxK);
     HC_REQUIRE(a->n >= 1 && a->n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, a->n, kMaxN);
     HC_REQUIRE(a->dtype == 0 || a->dtype == 1, HC_EINVAL, "%s: dtype must be 0 or 1", fn);
+    HC_REQUIRE(a->objective == HC_CODEC_L2 || a->objective == HC_CODEC_EQ8, HC_EINVAL,
+               "%s: objective must be HC_CODEC_L2 or HC_CODEC_EQ8", fn);
+    if (a->objective == HC_CODEC_EQ8) {
+        HC_REQUIRE(a->T != nullptr, HC_EINVAL, "%s: HC_CODEC_EQ8 needs T", fn);
+        const double w[4] = {a->w_e2e, a->w_rec, a->w_code, a->w_col};
+        for (double x : w)
+            HC_REQUIRE(x >= 0 && x < HUGE_VAL, HC_EINVAL, "%s: Eq. 8 weights must be finite and >= 0", fn);
+        HC_REQUIRE(a->cos_eps > 0 && a->cos_eps < HUGE_VAL, HC_EINVAL, "%s: cos_eps must be > 0", fn);
+    }
     HC_REQUIRE(a->N >= 1 && a->N < (int64_t(1) << 31), HC_ESHAPE, "%s: N outside [1, 2^31)", fn);
     HC_REQUIRE(a->beta > 0, HC_EINVAL, "%s: beta must be > 0", fn);
     HC_REQUIRE(a->ld_a >= a->n && a->ld_b >= a->n, HC_ESHAPE, "%s: ld_a/ld_b < n", fn);
@@ -270,7 +279,8 @@ hc_status hc_codec_step(const hc_codec_args* a) {
     const size_t esz = a->dtype ? 8 : 4;
     auto al = [&](const void* p) { return (reinterpret_cast<uintptr_t>(p) % esz) == 0; };
     HC_REQUIRE(al(a->Wt_E) && al(a->Wt_D) && al(a->A) && al(a->B) && al(a->loss) &&
-                   (!a->grad_E || al(a->grad_E)) && (!a->grad_D || al(a->grad_D)),
+                   (!a->grad_E || al(a->grad_E)) && (!a->grad_D || al(a->grad_D)) &&
+                   (a->objective != HC_CODEC_EQ8 || al(a->T)),
                HC_EALIGN, "%s: arrays must be aligned to their element size", fn);
     if (a->adam) {
         const hc_adam* m = a->adam;

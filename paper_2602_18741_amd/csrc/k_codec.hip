@@ -11,10 +11,16 @@
 //                back-propagated code gradients, staged in LDS; then every
 //                thread contracts over the tile's pairs for its gradient
 //                elements (float64 sums) and writes one partial row per
-//                workgroup.
+//                workgroup.  One kernel per objective: the two-term squared
+//                error, or the four-term loss of Eq. 8 (which also needs the
+//                per-pair norms and dot product of the cosine factor, reduced
+//                across the pair's lanes by shuffles, and the code of the
+//                spectral product for L_code).
 //   3. finish  : one wavefront per gradient element sums the partial rows
-//                (fixed order, float64), scales by 2/N, applies the softplus
-//                slope logistic(beta Wt) and optionally the Adam update.
+//                (fixed order, float64), scales by 2/N (two-term) or 1/N
+//                (Eq. 8, whose per-pair terms carry their own factors),
+//                applies the softplus slope logistic(beta Wt) and optionally
+//                the Adam update.
 
 #include "hc_internal.hpp"
 
@@ -86,6 +92,9 @@ struct PartialArgs {
     int64_t N, n_tiles;
     double* part;  // gridDim.x rows of 2kn + 1
     int ed_in_lds;
+    // Eq. 8 objective
+    const F* T;  // 3 x n
+    double w_e2e, w_rec, w_code, w_col, eps;
 };
 
 template <typename F>
@@ -224,12 +233,209 @@ __global__ __launch_bounds__(kThreads) void codec_partials_kernel(PartialArgs<F>
     }
 }
 
+
+// Four-term objective of Eq. 8.  Per pair (a, b), t = a*b:
+//   S = D h, r_h = S - t, M = |r_h|^2 / n, c = cos(S, t) with clamped norms,
+//   r_c = T r_h, d = h - E t;
+//   loss = w_e2e M (2 - c) + w_rec (|r_a|^2 + |r_b|^2)/n + w_code |d|^2/k + w_col |r_c|^2/3
+// Backward (per pair, summed here, / N in the finish kernel):
+//   g_S = w_e2e ((2 - c)(2/n) r_h - M dc/dS) + w_col (2/3) T^T r_c,
+//   dc/dS = t/(|S| m_t) - c S/|S|^2 if |S| > eps else t/(eps m_t), m_t = max(|t|, eps)
+//   g_h = D^T g_S + w_code (2/k) d,
+//   g_u = w_rec (2/n) D^T r_a + g_h*v, g_v = w_rec (2/n) D^T r_b + g_h*u
+//   dE += g_u a^T + g_v b^T - w_code (2/k) d t^T
+//   dD += w_rec (2/n)(r_a u^T + r_b v^T) + g_S h^T
+template <typename F>
+__global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArgs<F> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    F* sm = reinterpret_cast<F*>(smem_raw);
+    const int k = a.k, n = a.n, np = a.npad, tp = a.tp, lpp = a.lpp;
+    const int kn = k * n;
+    const int tid = threadIdx.x;
+    const F* Ep = a.E;
+    const F* Dp = a.D;
+    F* base = sm;
+    if (a.ed_in_lds) {
+        for (int i = tid; i < kn; i += kThreads) {
+            sm[i] = a.E[i];
+            sm[kn + i] = a.D[i];
+        }
+        Ep = sm;
+        Dp = sm + kn;
+        base = sm + 2 * kn;
+    }
+    F* AA = base;          // a
+    F* BB = AA + tp * np;  // b
+    F* TT = BB + tp * np;  // t = a*b
+    F* RA = TT + tp * np;  // r_a, then w_rec (2/n) r_a
+    F* RB = RA + tp * np;
+    F* SG = RB + tp * np;  // S, then g_S
+    F* U = SG + tp * np;
+    F* V = U + tp * k;
+    F* H = V + tp * k;
+    F* DC = H + tp * k;    // d = h - E t, then w_code (2/k) d
+    F* GU = DC + tp * k;
+    F* GV = GU + tp * k;
+
+    const int pair = tid / lpp;
+    const int part = tid % lpp;
+    const double inv_n = 1.0 / n;
+    double loss_acc = 0.0;
+    double* prow = a.part + int64_t(blockIdx.x) * (2 * kn + 1);
+    bool first_tile = true;
+
+    for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const int64_t gi = tile * tp + pair;
+        const bool valid = gi < a.N;
+        __syncthreads();  // the previous tile's contraction has finished with LDS
+        {
+            int64_t ra = 0, rb = 0;
+            if (valid) {
+                ra = a.idx_a ? min<int64_t>(a.idx_a[gi], a.rows_a - 1) : gi;
+                rb = a.idx_b ? min<int64_t>(a.idx_b[gi], a.rows_b - 1) : gi;
+            }
+            for (int i = part; i < n; i += lpp) {
+                const F ai = valid ? a.A[ra * a.ld_a + i] : F(0);
+                const F bi = valid ? a.B[rb * a.ld_b + i] : F(0);
+                AA[pair * np + i] = ai;
+                BB[pair * np + i] = bi;
+                TT[pair * np + i] = ai * bi;
+            }
+        }
+        __syncthreads();
+        // codes u = E a, v = E b, their product h (Eq. 4, Eq. 6), and d = h - E t
+        for (int j = part; j < k; j += lpp) {
+            F su = 0, sv = 0, st = 0;
+            for (int i = 0; i < n; ++i) {
+                const F e = Ep[j * n + i];
+                su += e * AA[pair * np + i];
+                sv += e * BB[pair * np + i];
+                st += e * TT[pair * np + i];
+            }
+            U[pair * k + j] = su;
+            V[pair * k + j] = sv;
+            H[pair * k + j] = su * sv;
+            DC[pair * k + j] = su * sv - st;
+        }
+        __syncthreads();
+        // reconstructions; per-lane partial sums of the pair's norms
+        double s_rr = 0, s_rh = 0, s_st = 0, s_ss = 0, s_tt = 0, s_c0 = 0, s_c1 = 0, s_c2 = 0, s_dd = 0;
+        for (int i = part; i < n; i += lpp) {
+            F du = 0, dv = 0, dh = 0;
+            for (int j = 0; j < k; ++j) {
+                const F d = Dp[i * k + j];
+                du += d * U[pair * k + j];
+                dv += d * V[pair * k + j];
+                dh += d * H[pair * k + j];
+            }
+            const F ra = du - AA[pair * np + i], rb = dv - BB[pair * np + i];
+            const F ti = TT[pair * np + i];
+            const F rh = dh - ti;
+            RA[pair * np + i] = ra;
+            RB[pair * np + i] = rb;
+            SG[pair * np + i] = dh;
+            s_rr += double(ra) * double(ra) + double(rb) * double(rb);
+            s_rh += double(rh) * double(rh);
+            s_st += double(dh) * double(ti);
+            s_ss += double(dh) * double(dh);
+            s_tt += double(ti) * double(ti);
+            s_c0 += double(a.T[i]) * double(rh);
+            s_c1 += double(a.T[n + i]) * double(rh);
+            s_c2 += double(a.T[2 * n + i]) * double(rh);
+        }
+        for (int j = part; j < k; j += lpp) s_dd += double(DC[pair * k + j]) * double(DC[pair * k + j]);
+        // reduce over the pair's lpp consecutive lanes (lpp divides the wavefront)
+        for (int m = 1; m < lpp; m <<= 1) {
+            s_rr += __shfl_xor(s_rr, m, kWave);
+            s_rh += __shfl_xor(s_rh, m, kWave);
+            s_st += __shfl_xor(s_st, m, kWave);
+            s_ss += __shfl_xor(s_ss, m, kWave);
+            s_tt += __shfl_xor(s_tt, m, kWave);
+            s_c0 += __shfl_xor(s_c0, m, kWave);
+            s_c1 += __shfl_xor(s_c1, m, kWave);
+            s_c2 += __shfl_xor(s_c2, m, kWave);
+            s_dd += __shfl_xor(s_dd, m, kWave);
+        }
+        const double M = s_rh * inv_n;
+        const double sn = sqrt(s_ss);
+        const double ns = sn > a.eps ? sn : a.eps;
+        const double tn = sqrt(s_tt);
+        const double nt = tn > a.eps ? tn : a.eps;
+        const double c = s_st / (ns * nt);
+        if (valid && part == 0)
+            loss_acc += a.w_e2e * M * (2.0 - c) + a.w_rec * s_rr * inv_n + a.w_code * s_dd / k +
+                        a.w_col * (s_c0 * s_c0 + s_c1 * s_c1 + s_c2 * s_c2) / 3.0;
+        // g_S = al r_h - bt t + bs S + T^T gc; r_a, r_b scaled by w_rec (2/n)
+        const F al = F(a.w_e2e * (2.0 - c) * 2.0 * inv_n);
+        const F bt = F(a.w_e2e * M / (ns * nt));
+        const F bs = F(sn > a.eps ? a.w_e2e * M * c / s_ss : 0.0);
+        const F g0 = F(a.w_col * (2.0 / 3.0) * s_c0), g1 = F(a.w_col * (2.0 / 3.0) * s_c1),
+                g2 = F(a.w_col * (2.0 / 3.0) * s_c2);
+        const F wr = F(a.w_rec * 2.0 * inv_n);
+        for (int i = part; i < n; i += lpp) {
+            const F S = SG[pair * np + i], ti = TT[pair * np + i];
+            const F gs = al * (S - ti) - bt * ti + bs * S + g0 * a.T[i] + g1 * a.T[n + i] +
+                         g2 * a.T[2 * n + i];
+            SG[pair * np + i] = valid ? gs : F(0);
+            RA[pair * np + i] = valid ? wr * RA[pair * np + i] : F(0);
+            RB[pair * np + i] = valid ? wr * RB[pair * np + i] : F(0);
+        }
+        __syncthreads();
+        // code-space gradients
+        const F wk = F(a.w_code * 2.0 / k);
+        for (int j = part; j < k; j += lpp) {
+            F gu = 0, gv = 0, gs = 0;
+            for (int i = 0; i < n; ++i) {
+                const F d = Dp[i * k + j];
+                gu += d * RA[pair * np + i];
+                gv += d * RB[pair * np + i];
+                gs += d * SG[pair * np + i];
+            }
+            const F dc = valid ? wk * DC[pair * k + j] : F(0);
+            const F gh = gs + dc;
+            DC[pair * k + j] = dc;
+            GU[pair * k + j] = gu + gh * V[pair * k + j];
+            GV[pair * k + j] = gv + gh * U[pair * k + j];
+        }
+        __syncthreads();
+        // contraction over the tile's pairs; [0, kn) is dL/dE, [kn, 2kn) dL/dD
+        for (int e = tid; e < 2 * kn; e += kThreads) {
+            double s = 0.0;
+            if (e < kn) {
+                const int j = e / n, i = e % n;
+                for (int p = 0; p < tp; ++p)
+                    s += double(GU[p * k + j]) * double(AA[p * np + i]) +
+                         double(GV[p * k + j]) * double(BB[p * np + i]) -
+                         double(DC[p * k + j]) * double(TT[p * np + i]);
+            } else {
+                const int e2 = e - kn;
+                const int i = e2 / k, j = e2 % k;
+                for (int p = 0; p < tp; ++p)
+                    s += double(RA[p * np + i]) * double(U[p * k + j]) +
+                         double(RB[p * np + i]) * double(V[p * k + j]) +
+                         double(SG[p * np + i]) * double(H[p * k + j]);
+            }
+            prow[e] = first_tile ? s : prow[e] + s;
+        }
+        first_tile = false;
+    }
+    __shared__ double s_loss[kThreads / kWave];
+    for (int m = kWave / 2; m >= 1; m >>= 1) loss_acc += __shfl_xor(loss_acc, m, kWave);
+    if ((tid & (kWave - 1)) == 0) s_loss[tid / kWave] = loss_acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / kWave; ++w) t += s_loss[w];
+        prow[2 * kn] = t;
+    }
+}
+
 // ------------------------------------------------------------------ kernel 3
 
 template <typename F>
 struct FinishArgs {
     int k, n;
-    double beta, inv_n;
+    double beta, inv_n, gscale;
     const double* part;
     int rows;
     F* we;
@@ -266,7 +472,7 @@ __global__ __launch_bounds__(kThreads) void codec_finish_kernel(FinishArgs<F> a)
     const int idx = isE ? e : e - kn;
     F* w = isE ? a.we : a.wd;
     const double wt = double(w[idx]);
-    const double g = 2.0 * s * a.inv_n * slope(wt, a.beta);
+    const double g = s * a.gscale * slope(wt, a.beta);
     F* gout = isE ? a.grad_e : a.grad_d;
     if (gout) gout[idx] = F(g);
     if (a.adam) {
@@ -292,12 +498,13 @@ struct Plan {
     size_t lds;
 };
 
-Plan plan(int k, int n, int64_t N, size_t esz) {
+Plan plan(int k, int n, int64_t N, size_t esz, int objective) {
     Plan p;
     p.npad = n | 1;  // odd row stride spreads the pairs of a wave over LDS banks
     const size_t ed = size_t(2) * k * n * esz;
     p.ed_in_lds = ed <= 16384;
-    const size_t per_pair = (size_t(5) * p.npad + size_t(5) * k) * esz;
+    const size_t rows_n = objective == HC_CODEC_EQ8 ? 6 : 5, rows_k = rows_n;
+    const size_t per_pair = (rows_n * p.npad + rows_k * k) * esz;
     const size_t budget = kTileLdsBytes - (p.ed_in_lds ? ed : 0);
     int tp = 64;
     while (tp > 4 && size_t(tp) * per_pair > budget) tp >>= 1;
@@ -336,7 +543,8 @@ template <typename F>
 hc_status run(const hc_codec_args& a) {
     const int k = a.k, n = a.n, kn = k * n;
     hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
-    const Plan pl = plan(k, n, a.N, sizeof(F));
+    const bool eq8 = a.objective == HC_CODEC_EQ8;
+    const Plan pl = plan(k, n, a.N, sizeof(F), a.objective);
     Workspace ws = carve(a.workspace, k, n, pl.grid, sizeof(F));
     const int g0 = int(ceil_div(kn, kThreads));
     hipLaunchKernelGGL(codec_weights_kernel<F>, dim3(g0), dim3(kThreads), 0, st,
@@ -367,8 +575,18 @@ hc_status run(const hc_codec_args& a) {
     p.n_tiles = pl.n_tiles;
     p.part = ws.part;
     p.ed_in_lds = pl.ed_in_lds;
-    hipLaunchKernelGGL(codec_partials_kernel<F>, dim3(uint32_t(pl.grid)), dim3(kThreads), pl.lds, st,
-                       p);
+    p.T = static_cast<const F*>(a.T);
+    p.w_e2e = a.w_e2e;
+    p.w_rec = a.w_rec;
+    p.w_code = a.w_code;
+    p.w_col = a.w_col;
+    p.eps = a.cos_eps;
+    if (eq8)
+        hipLaunchKernelGGL(codec_partials_eq8_kernel<F>, dim3(uint32_t(pl.grid)), dim3(kThreads), pl.lds,
+                           st, p);
+    else
+        hipLaunchKernelGGL(codec_partials_kernel<F>, dim3(uint32_t(pl.grid)), dim3(kThreads), pl.lds, st,
+                           p);
     s = launch_status("hc_codec_step");
     if (s != HC_OK) return s;
 
@@ -377,6 +595,7 @@ hc_status run(const hc_codec_args& a) {
     f.n = n;
     f.beta = a.beta;
     f.inv_n = 1.0 / double(a.N);
+    f.gscale = (eq8 ? 1.0 : 2.0) / double(a.N);
     f.part = ws.part;
     f.rows = int(pl.grid);
     f.we = static_cast<F*>(a.Wt_E);
@@ -407,10 +626,11 @@ hc_status run(const hc_codec_args& a) {
 }  // namespace
 
 size_t codec_workspace_size(int k, int n, int64_t N) {
-    // the float64 plan has the smallest tiles, hence the most partial rows
-    const Plan pl = plan(k, n, N, sizeof(double));
+    // the float64 plans have the smallest tiles, hence the most partial rows
+    const int64_t rows = std::max(plan(k, n, N, sizeof(double), HC_CODEC_L2).grid,
+                                  plan(k, n, N, sizeof(double), HC_CODEC_EQ8).grid);
     const size_t kn = size_t(k) * n;
-    return 2 * align8(kn * sizeof(double)) + size_t(pl.grid) * (2 * kn + 1) * sizeof(double) +
+    return 2 * align8(kn * sizeof(double)) + size_t(rows) * (2 * kn + 1) * sizeof(double) +
            sizeof(int64_t);
 }
 

@@ -182,18 +182,32 @@ class CodecWorkspace:
         self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=device)
 
 
+EQ8_WEIGHTS = (0.5, 0.75, 1.0, 0.5)   # w_e2e, w_rec, w_code, w_col of Eq. 8 (Sec. 4.5)
+
+
 def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a=None, idx_b=None,
                loss=None, grad_e=None, grad_d=None, adam: dict | None = None,
-               workspace: CodecWorkspace | None = None):
+               workspace: CodecWorkspace | None = None, objective: str = "l2", T=None,
+               weights=EQ8_WEIGHTS, cos_eps: float = 1e-8):
     """One loss/gradient (and optional Adam) evaluation on the GPU.
 
     A, B: (rows, n) tensors of the parameters' dtype; with idx_a/idx_b the
     batch rows are gathered by index.  adam: dict with m_E, v_E, m_D, v_D,
-    step (int64 device tensor), lr, beta1, beta2, eps.  Returns the loss tensor.
+    step (int64 device tensor), lr, beta1, beta2, eps.  objective "l2" is the
+    two-term squared error weighted by lam; "eq8" the four-term loss of
+    Eq. 8 with `weights` (w_e2e, w_rec, w_code, w_col) and the 3 x n
+    colour-matching matrix T (parameters' dtype).  Returns the loss tensor.
     """
     _dev(we, wd, A, B)
     k, n = we.shape
     dt = 1 if we.dtype == torch.float64 else 0
+    if objective not in ("l2", "eq8"):
+        raise ValueError(f"objective must be 'l2' or 'eq8', not {objective!r}")
+    eq8 = objective == "eq8"
+    if eq8:
+        if T is None or tuple(T.shape) != (3, n) or T.dtype != we.dtype or not T.is_contiguous():
+            raise ValueError("objective 'eq8' needs a contiguous 3 x n T of the parameters' dtype")
+        _dev(T)
     if loss is None:
         loss = torch.empty((), dtype=we.dtype, device=we.device)
     workspace = workspace or CodecWorkspace(k, n, N, we.device)
@@ -202,13 +216,16 @@ def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a
         ad = _lib.Adam(adam["m_E"].data_ptr(), adam["v_E"].data_ptr(), adam["m_D"].data_ptr(),
                        adam["v_D"].data_ptr(), adam["step"].data_ptr(), adam.get("lr", 1e-3),
                        adam.get("beta1", 0.9), adam.get("beta2", 0.999), adam.get("eps", 1e-8))
+    w = tuple(float(x) for x in weights) if eq8 else (0.0, 0.0, 0.0, 0.0)
     args = _lib.CodecArgs(
-        k, n, dt, 0, beta, lam, we.data_ptr(), wd.data_ptr(), A.data_ptr(), B.data_ptr(),
+        k, n, dt, _lib.HC_CODEC_EQ8 if eq8 else _lib.HC_CODEC_L2, beta, lam, we.data_ptr(),
+        wd.data_ptr(), A.data_ptr(), B.data_ptr(),
         A.stride(0), B.stride(0), A.shape[0], B.shape[0],
         None if idx_a is None else idx_a.data_ptr(), None if idx_b is None else idx_b.data_ptr(),
         N, loss.data_ptr(), None if grad_e is None else grad_e.data_ptr(),
         None if grad_d is None else grad_d.data_ptr(), C.pointer(ad) if ad is not None else None,
-        workspace.buf.data_ptr(), workspace.bytes, torch.cuda.current_stream().cuda_stream)
+        workspace.buf.data_ptr(), workspace.bytes, torch.cuda.current_stream().cuda_stream,
+        T.data_ptr() if eq8 else None, *w, cos_eps if eq8 else 0.0)
     check(load().hc_codec_step(C.byref(args)), "hc_codec_step")
     return loss
 

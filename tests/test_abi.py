@@ -91,6 +91,39 @@ def test_codec_step_rejects_small_workspace(lib):
     assert lib.hc_codec_step(C.byref(args)) == _lib.HC_EINVAL
 
 
+def test_codec_step_validates_the_eq8_objective(lib):
+    need = lib.hc_codec_workspace_size(6, 31, 65536)
+    args = _lib.CodecArgs(6, 31, 0, 0, 10.0, 1.0, 0x1000, 0x1000, 0x1000, 0x1000, 31, 31,
+                          65536, 65536, None, None, 65536, 0x1000, None, None, None,
+                          0x1000, need, None)
+    args.objective = 7
+    s, msg = _err(lib.hc_codec_step(C.byref(args)))
+    assert s == _lib.HC_EINVAL and "objective" in msg
+    args.objective = _lib.HC_CODEC_EQ8
+    s, msg = _err(lib.hc_codec_step(C.byref(args)))
+    assert s == _lib.HC_EINVAL and "needs T" in msg
+    args.T, args.w_e2e, args.w_rec, args.w_code, args.w_col, args.cos_eps = 0x1000, 0.5, 0.75, 1, -0.5, 1e-8
+    s, msg = _err(lib.hc_codec_step(C.byref(args)))
+    assert s == _lib.HC_EINVAL and "weights" in msg
+    args.w_col, args.cos_eps = float("nan"), 1e-8
+    assert lib.hc_codec_step(C.byref(args)) == _lib.HC_EINVAL
+    args.w_col, args.cos_eps = 0.5, 0.0
+    s, msg = _err(lib.hc_codec_step(C.byref(args)))
+    assert s == _lib.HC_EINVAL and "cos_eps" in msg
+    args.cos_eps = 1e-8
+    args.T = 0x1002                      # misaligned for float32
+    assert lib.hc_codec_step(C.byref(args)) == _lib.HC_EALIGN
+
+
+def test_workspace_covers_both_objectives(lib):
+    """The workspace size is the larger of the two objectives' needs: it
+    never shrinks as N grows and is at least the partial-row table of the
+    float64 plan."""
+    for k, n in ((6, 31), (9, 81), (48, 128)):
+        sizes = [lib.hc_codec_workspace_size(k, n, N) for N in (1, 7, 64, 4099, 65536, 1 << 20)]
+        assert sizes == sorted(sizes) and sizes[0] > 0
+
+
 def test_gen_rejects_bad_lengths(lib):
     g = _lib.PathGen(16, 4, 3, 2, 8, 64, 1)
     s, msg = _err(lib.hc_gen_path_headers(C.byref(g), None, None, None, None, 0, None))

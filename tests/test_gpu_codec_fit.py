@@ -70,3 +70,21 @@ def test_fit_reduces_the_loss(fitcls, pools):
     assert last < 0.5 * first
     E, D = f.weights()
     assert (E >= 0).all() and (D >= 0).all()
+
+
+def test_eq8_fit_graph_replay_and_descent(fitcls, pools):
+    """The Eq. 8 objective through the same loop: graph replays equal eager
+    steps bitwise, and 300 steps reduce the loss."""
+    T = synth.cmf_matrix(31)
+    eager = _fit(fitcls, pools, objective="eq8", T=T)
+    eager.run(6)
+    graphed = _fit(fitcls, pools, objective="eq8", T=T)
+    graphed.run(1)
+    graphed.capture()
+    graphed.run(5)
+    torch.cuda.synchronize()
+    assert _same(eager, graphed) and torch.equal(eager.loss, graphed.loss)
+    f = _fit(fitcls, pools, objective="eq8", T=T, lr=3e-3)
+    first = float(f.run(1))
+    last = float(f.run(300))
+    assert last < 0.5 * first
