@@ -21,10 +21,12 @@ What it computes (each function cites the passage it follows):
   L_rec and L_e2e parts of Eq. 8 without the cosine factor), its analytic
   gradient, and Adam.
 * ``records``: the light-path record format read by both forms.
+* ``multibounce.chain_xyz``: the cascaded products of the multi-bounce
+  evaluation (Eq. 10) in spectral and latent form.
 
 Pins: every function here is checked in the CPU test suite against closed
 forms, invariants, finite differences, exact rational brute force or
 library routines (see tests/test_oracle_*.py).
 """
 
-from . import codec, records, shade  # noqa: F401
+from . import codec, multibounce, records, shade  # noqa: F401

@@ -35,6 +35,7 @@ from .paths import (  # noqa: F401
     gen_paths,
     path_records,
     records_of_pixels,
+    chain_records,
     uniform_indices,
 )
 from .workloads import workload  # noqa: F401

@@ -168,6 +168,25 @@ def records_of_pixels(spec: PathSpec, pixels):
     return hdr, pf, vtx
 
 
+def chain_records(n_chains: int, bounces: int):
+    """Records of the multi-bounce chains: one pixel per (bounce b, chain c)
+    for b = 0 .. bounces, pixel b * n_chains + c, one sample whose path
+    starts at light c and meets b reflectances, texels c * bounces + v for
+    v < b, all weights 1 (b = 0 is the light seen directly).  Returns
+    (hdr uint32, pix_first uint32, vtx uint32 [V, 2]) in the frame layout."""
+    c = np.arange(n_chains, dtype=np.int64)
+    b = np.arange(bounces + 1, dtype=np.int64)
+    length = np.repeat(b, n_chains)
+    light = np.tile(c, bounces + 1)
+    hdr = (light | (length << 24)).astype(np.uint32)
+    pf = np.zeros(length.size, dtype=np.uint32)
+    pf[1:] = np.cumsum(length[:-1])
+    tex = np.concatenate([(c[:, None] * bounces + np.arange(bb)[None, :]).ravel() for bb in b])
+    vtx = np.stack([tex.astype(np.uint32),
+                    np.full(tex.size, np.float32(1.0)).view(np.uint32)], axis=1)
+    return hdr, pf, vtx
+
+
 def uniform_indices(seed: int, ctr0: int, count: int, n: int) -> np.ndarray:
     """count indices uniform in [0, n) drawn at counters ctr0 .. ctr0+count-1."""
     r = rand64(stream_key(seed, STREAM_INDEX), np.arange(ctr0, ctr0 + count, dtype=np.uint64))

@@ -2,7 +2,7 @@
 
 Seeds: every random draw for workload c and purpose j comes from
 ``numpy.random.default_rng([c, j])`` with j = 0 spectra tables, 1 texture,
-3 codec, 4 codec-fit pools, 5 serving arrivals; the counter-based path
+3 codec, 4 codec-fit pools, 5 serving arrivals, 6 multi-bounce chains; the counter-based path
 generator takes the integer seed ``1000 * c + 2``.
 
 * c = 0  tiny parity case: n = 31, k = 6, random U[0,1] codec, 64
@@ -11,7 +11,8 @@ generator takes the integer seed ``1000 * c + 2``.
 * c = 1  frame scale: 1920 x 1080 px, 16 spp, L in 1..4, 1024^2 x 31
   Perlin-blended texture of 16 basis reflectances, 32 lights (16 + 16).
 * c = 2  codec fit: pools of reflectances and lights (half Planck, half
-  narrow-band) at n in {31, 81}.
+  narrow-band) at n in {31, 81}; held-out chains for the multi-bounce
+  evaluation (purpose 6).
 * c = 3  serving: request stream (see the serving module).
 * c = 4  stress: n = 81, k = 9, 3840 x 2160 px, 64 spp, L in 1..8,
   4096^2 x 81 texture (Perlin weights on a 512^2 grid, one weight per 8x8
@@ -86,3 +87,15 @@ def codec_pools(n: int, count: int, seed_c: int = 2):
     refl = reflectances(rng, n, count)
     illum = illuminant_table(rng, n, count // 2, count - count // 2, 5.0, 15.0)
     return refl, illum
+
+
+def bounce_chains(n: int, count: int, bounces: int = 3):
+    """Held-out spectra of the multi-bounce evaluation: `count` lights (half
+    Planckian, half narrow-band) and bounces reflectances per chain, drawn
+    from the codec-fit generators with their own seed.  Returns
+    (refl (count * bounces, n) with chain c's reflectances in rows
+    c * bounces .. c * bounces + bounces - 1, lights (count, n)), float32."""
+    rng = _rng(2, 6)
+    refl = reflectances(rng, n, count * bounces)
+    lights = illuminant_table(rng, n, count // 2, count - count // 2, 5.0, 15.0)
+    return refl, lights

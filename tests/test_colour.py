@@ -47,3 +47,17 @@ def test_frame_difference_ignores_black_reference_pixels():
     ref = np.array([[0.2, 0.3, 0.1], [0.0, 0.0, 0.0], [0.5, 0.4, 0.9]])
     d = colour.frame_difference(ref, ref)
     assert d["pixels"] == 2 and d["mean"] == 0.0
+
+
+def test_cie94_chroma_and_hue_closed_forms():
+    """At equal lightness: a pure chroma change (same hue angle) gives
+    |dC| / (1 + 0.045 C_ref); a pure hue rotation (same chroma) gives
+    |da, db| / (1 + 0.015 C_ref), since then dH^2 = da^2 + db^2."""
+    c1, c2, h = 30.0, 36.0, np.radians(40.0)
+    ref = np.array([50.0, c1 * np.cos(h), c1 * np.sin(h)])
+    chroma = np.array([50.0, c2 * np.cos(h), c2 * np.sin(h)])
+    assert colour.cie94(ref, chroma) == pytest.approx(abs(c2 - c1) / (1 + 0.045 * c1), rel=1e-12)
+    g = np.radians(55.0)
+    hue = np.array([50.0, c1 * np.cos(g), c1 * np.sin(g)])
+    dab = np.hypot(*(hue[1:] - ref[1:]))
+    assert colour.cie94(ref, hue) == pytest.approx(dab / (1 + 0.015 * c1), rel=1e-12)

@@ -71,3 +71,16 @@ def test_mix64_is_a_bijection_sample():
     x = np.arange(1 << 16, dtype=np.uint64)
     assert np.unique(synth.mix64(x)).size == x.size
     assert synth.mix64(np.uint64(0)) == 0
+
+
+def test_chain_records_layout():
+    from oracle.records import unpack
+    C, bounces = 5, 3
+    hdr, pf, vtx = synth.chain_records(C, bounces)
+    length, light, first, texel, weight = unpack(hdr, pf, vtx, 1)
+    assert length.tolist() == [b for b in range(bounces + 1) for _ in range(C)]
+    assert light.tolist() == list(range(C)) * (bounces + 1)
+    assert (weight == 1.0).all() and vtx.shape[0] == C * (0 + 1 + 2 + 3)
+    for p in range(hdr.size):
+        b, c = divmod(p, C)
+        assert texel[first[p]:first[p] + b].tolist() == [c * bounces + v for v in range(b)]
