@@ -135,6 +135,42 @@ def measured_traffic(bytes_alg):
     return d.get("hbm_bytes_per_launch")
 
 
+MB_CHAINS = 1 << 18
+
+
+def multibounce_leg(args, dev, n, k, T, codecs):
+    """Multi-bounce chains (Eq. 10): both forms on MB_CHAINS held-out chains
+    of 3 bounces for each fitted codec; GPU time of one evaluation (encode,
+    both shades, decode) and the CIE94 report per bounce."""
+    import torch
+    import synth
+    from paper_2602_18741_amd import multibounce, ops
+    bounces = 3
+    r, l = synth.workloads.bounce_chains(n, MB_CHAINS, bounces)
+    r = ops.padded(torch.from_numpy(r).to(dev))
+    l = ops.padded(torch.from_numpy(l).to(dev))
+    paths = multibounce.chain_paths(MB_CHAINS, bounces, dev)
+    out = {"chains": MB_CHAINS, "bounces": bounces, "white": "equal-energy at the light's Y",
+           "cie94": {}}
+    for name, ((E_, D_), _) in codecs.items():
+        res = multibounce.chain_xyz(E_, D_, T, r, l, k, n, bounces, paths=paths)
+        out["cie94"][name] = multibounce.cie94_report(*res)
+    (E_, D_), _ = codecs["eq8"]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        multibounce.chain_xyz(E_, D_, T, r, l, k, n, bounces, paths=paths)
+    e1.record()
+    torch.cuda.synchronize()
+    out["ms_per_evaluation"] = e0.elapsed_time(e1) / reps
+    log("multi-bounce CIE94 mean per bounce: " + "; ".join(
+        f"{name} " + ", ".join(f"{b['mean']:.3f}" for b in rep) for name, rep in out["cie94"].items())
+        + f"; {out['ms_per_evaluation']:.3f} ms per evaluation of {MB_CHAINS} chains")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,26 +245,37 @@ def main():
     nv, npath, npx = P.n_vertices, spec.n_paths, spec.n_pixels
     log(f"frame: {npx} px, {npath} paths, {nv} path-vertices")
 
-    # ---- codec fit on the GPU (reflectance / light pools, Adam, graph replay)
+    # ---- codec fits on the GPU (reflectance / light pools, Adam, graph replay):
+    # the four-term loss of Eq. 8 (the codec the frames use) and the two-term
+    # squared error, for comparison
     pa, pb = synth.workloads.codec_pools(n, 1 << 20 if not args.only else 1 << 16)
+    pa, pb = torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev)
     we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
-    fit = CodecFit(we0, wd0, torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev),
-                   batch=65536, lam=1.0, beta=10.0, lr=1e-3, seed=2)
     codec_steps = 1 if args.only else args.codec_steps
-    recipe_steps = min(2000, codec_steps)
-    fit.run(1)
-    fit.capture()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss_recipe = float(fit.run(recipe_steps - 1))
-    torch.cuda.synchronize()
-    codec_ms = (time.perf_counter() - t0) * 1e3 / max(1, recipe_steps - 1)
-    loss = float(fit.run(codec_steps - recipe_steps))
-    E, D = fit.weights()
-    log(f"codec fit: loss {loss_recipe:.4g} after {recipe_steps} steps, {loss:.4g} after "
-        f"{fit.steps_done}; {codec_ms * 1e3:.1f} us/step")
-    codec_steps_done = fit.steps_done
-    del fit, pa, pb
+
+    def fit_codec(objective):
+        fit = CodecFit(we0, wd0, pa, pb, batch=65536, lam=1.0, beta=10.0, lr=1e-3, seed=2,
+                       objective=objective, T=w["T"])
+        recipe_steps = min(2000, codec_steps)
+        fit.run(1)
+        fit.capture()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss_recipe = float(fit.run(recipe_steps - 1))
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) * 1e6 / max(1, recipe_steps - 1)
+        loss = float(fit.run(codec_steps - recipe_steps))
+        log(f"codec fit ({objective}): loss {loss_recipe:.4g} after {recipe_steps} steps, "
+            f"{loss:.4g} after {fit.steps_done}; {us:.1f} us/step")
+        info = {"objective": objective, "steps": fit.steps_done, "batch": 65536, "lr": 1e-3,
+                "final_loss": loss, "loss_after_2000_steps": loss_recipe, "us_per_step": us}
+        return fit.weights(), info
+
+    codecs = {"eq8": fit_codec("eq8")}
+    if not args.only:
+        codecs["l2"] = fit_codec("l2")
+    (E, D), _ = codecs["eq8"]
+    del pa, pb
 
     lw = ld_z or ops.latent_width(k)
     codes = torch.empty(spec.n_tex, lw, device=dev)
@@ -283,7 +330,16 @@ def main():
     traffic = None if stress else measured_traffic(bytes_lat)
 
     de = colour.frame_difference(xyz_s.cpu().numpy(), xyz_l.cpu().numpy())
-    log(f"CIEDE2000 latent vs spectral: mean {de['mean']:.3f}, p95 {de['p95']:.3f}")
+    log(f"CIEDE2000 latent (Eq. 8 codec) vs spectral: mean {de['mean']:.3f}, p95 {de['p95']:.3f}")
+    E2, D2 = codecs["l2"][0]
+    ops.encode(E2, refl, n=n, out=codes)
+    ops.encode(E2, illum, n=n, out=lcodes)
+    ops.shade_latent(P, codes, lcodes, k, out=zimg)
+    ops.decode_xyz(D2, T, zimg, k, out=xyz_l)
+    de_l2 = colour.frame_difference(xyz_s.cpu().numpy(), xyz_l.cpu().numpy())
+    log(f"CIEDE2000 latent (two-term codec) vs spectral: mean {de_l2['mean']:.3f}, "
+        f"p95 {de_l2['p95']:.3f}")
+    bounce = multibounce_leg(args, dev, n, k, T, codecs)
 
     serving = None
     if not (args.no_serve or stress):
@@ -326,9 +382,9 @@ def main():
         "speedup_latent_vs_spectral": spe_wall / lat_wall,
         "shade_speedup_latent_vs_spectral": spe_kern / lat_kern,
         "ciede2000_latent_vs_spectral": de,
-        "codec_fit": {"steps": codec_steps_done, "batch": 65536, "lr": 1e-3, "final_loss": loss,
-                      "loss_after_2000_steps": loss_recipe,
-                      "us_per_step": codec_ms * 1e3},
+        "ciede2000_latent_vs_spectral_two_term_codec": de_l2,
+        "codec_fit": {name: info for name, (_, info) in codecs.items()},
+        "multibounce": bounce,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
