@@ -23,10 +23,12 @@ What it computes (each function cites the passage it follows):
 * ``records``: the light-path record format read by both forms.
 * ``multibounce.chain_xyz``: the cascaded products of the multi-bounce
   evaluation (Eq. 10) in spectral and latent form.
+* ``upsample``: the RGB-to-latent upsampling network of Sec. 5 (three fully
+  connected layers, width 128, SiLU between them).
 
 Pins: every function here is checked in the CPU test suite against closed
 forms, invariants, finite differences, exact rational brute force or
 library routines (see tests/test_oracle_*.py).
 """
 
-from . import codec, multibounce, records, shade  # noqa: F401
+from . import codec, multibounce, records, shade, upsample  # noqa: F401
