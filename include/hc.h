@@ -327,6 +327,40 @@ hc_status hc_codec_weights(const void* Wt_E, const void* Wt_D, int32_t k, int32_
                            int32_t dtype, double beta, float* E, float* D, void* stream);
 
 /*
+ * RGB-to-latent upsampling network (Sec. 5): for each of m texels with linear
+ * RGB colour c (row i of rgb, 3 floats, row stride ld_rgb >= 3),
+ *   z = W3 silu(W2 silu(W1 c + b1) + b2) + b3,  silu(x) = x / (1 + exp(-x)),
+ * hidden width 128 (three fully connected layers, Sec. 5.1), written to Z in
+ * the blocked RGBx code layout of hc_encode (ld_z >= 4 ceil(k/3); padding
+ * written as 0), ready for hc_shade_latent.  All weights are float32,
+ * row-major device arrays: W1 128 x 3, b1 128, W2 128 x 128, b2 128,
+ * W3 k x 128, b3 k (1 <= k <= 48).
+ *
+ * precision HC_MLP_F32: fp32 matrix-core products (v_mfma_f32_16x16x4_f32),
+ * fp32 activations.  HC_MLP_F16: the 128 x 128 and output layers take fp16
+ * operands (weights and activations rounded to fp16) with fp32
+ * accumulation on the fp16 matrix cores; layer 1 and the activations stay
+ * fp32.  The weights are read once per workgroup; rgb and Z are streamed.
+ * m = 0 enqueues nothing.
+ */
+#define HC_MLP_F32 0
+#define HC_MLP_F16 1
+
+typedef struct hc_mlp {
+    int32_t k;          /* output channels */
+    int32_t hidden;     /* must be 128 */
+    const float* W1;
+    const float* b1;
+    const float* W2;
+    const float* b2;
+    const float* W3;
+    const float* b3;
+} hc_mlp;
+
+hc_status hc_upsample(const hc_mlp* net, int32_t precision, const float* rgb, int64_t m,
+                      int64_t ld_rgb, float* Z, int64_t ld_z, void* stream);
+
+/*
  * Synthetic light-path generator (workload input, not part of the method).
  * Draws come from SplitMix64's output function mix64 applied to
  * key + (counter + 1) * 0x9E3779B97F4A7C15 with key = mix64(mix64(seed) + stream):

@@ -16,6 +16,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "hc.h")
 
 HC_OK, HC_EINVAL, HC_ESHAPE, HC_EALIGN, HC_ENOMEM, HC_EDEVICE, HC_EUNSUPPORTED = range(7)
 HC_CODEC_L2, HC_CODEC_EQ8 = 0, 1
+HC_MLP_F32, HC_MLP_F16 = 0, 1
 
 vp = C.c_void_p
 i32, i64, u64, f64, sz = C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
@@ -57,6 +58,11 @@ class CodecArgs(C.Structure):
                 ("w_code", f64), ("w_col", f64), ("cos_eps", f64)]
 
 
+class Mlp(C.Structure):
+    _fields_ = [("k", i32), ("hidden", i32), ("W1", vp), ("b1", vp), ("W2", vp), ("b2", vp),
+                ("W3", vp), ("b3", vp)]
+
+
 class PathGen(C.Structure):
     _fields_ = [("n_pixels", i64), ("spp", i32), ("l_min", i32), ("l_max", i32), ("n_illum", i32),
                 ("n_tex", i64), ("seed", u64)]
@@ -88,6 +94,7 @@ _PROTOS = {
     "hc_codec_workspace_size": (sz, [i32, i32, i64]),
     "hc_codec_step": (i32, [C.POINTER(CodecArgs)]),
     "hc_codec_weights": (i32, [vp, vp, i32, i32, i32, f64, vp, vp, vp]),
+    "hc_upsample": (i32, [vp, i32, vp, i64, i64, vp, i64, vp]),
     "hc_shade_latent_tiles": (i32, [vp, i32, vp, vp, i32, i32, i32, vp]),
     "hc_shade_spectral_tiles": (i32, [vp, i32, vp, vp, i32, i32, vp, i32, vp]),
     "hc_decode_tiles": (i32, [vp, i32, vp, vp, i32, vp, i32, i32, vp, i32, vp]),

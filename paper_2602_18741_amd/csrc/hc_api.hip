@@ -299,6 +299,28 @@ hc_status hc_codec_step(const hc_codec_args* a) {
     return launch_codec_step(*a);
 }
 
+hc_status hc_upsample(const hc_mlp* net, int32_t precision, const float* rgb, int64_t m,
+                      int64_t ld_rgb, float* Z, int64_t ld_z, void* stream) {
+    clear_error();
+    const char* fn = "hc_upsample";
+    HC_REQUIRE(net != nullptr, HC_EINVAL, "%s: net is NULL", fn);
+    HC_REQUIRE(net->hidden == 128, HC_EUNSUPPORTED, "%s: hidden width %d (only 128 is compiled)", fn,
+               net->hidden);
+    HC_REQUIRE(net->k >= 1 && net->k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, net->k, kMaxK);
+    HC_REQUIRE(precision == HC_MLP_F32 || precision == HC_MLP_F16, HC_EINVAL,
+               "%s: precision must be HC_MLP_F32 or HC_MLP_F16", fn);
+    HC_REQUIRE(m >= 0 && m < (int64_t(1) << 40), HC_ESHAPE, "%s: m=%lld out of range", fn, (long long)m);
+    HC_REQUIRE(ld_rgb >= 3, HC_ESHAPE, "%s: ld_rgb < 3", fn);
+    HC_REQUIRE(ld_z >= 4 * ceil_div(net->k, 3), HC_ESHAPE, "%s: ld_z < 4 ceil(k/3)", fn);
+    if (m == 0) return HC_OK;
+    HC_REQUIRE(net->W1 && net->b1 && net->W2 && net->b2 && net->W3 && net->b3 && rgb && Z, HC_EINVAL,
+               "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned4(net->W1) && aligned4(net->b1) && aligned4(net->W2) && aligned4(net->b2) &&
+                   aligned4(net->W3) && aligned4(net->b3) && aligned4(rgb) && aligned4(Z),
+               HC_EALIGN, "%s: arrays must be 4-byte aligned", fn);
+    return launch_upsample(*net, precision, rgb, m, ld_rgb, Z, ld_z, as_stream(stream));
+}
+
 hc_status hc_codec_weights(const void* Wt_E, const void* Wt_D, int32_t k, int32_t n, int32_t dtype,
                            double beta, float* E, float* D, void* stream) {
     clear_error();

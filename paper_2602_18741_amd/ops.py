@@ -230,6 +230,30 @@ def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a
     return loss
 
 
+def upsample(net: dict, rgb: torch.Tensor, k: int | None = None, precision: str = "f16",
+             ld_z: int | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Latent codes (blocked layout) of RGB texels through the upsampling
+    network (Sec. 5).  net: float32 device tensors W1 (128 x 3), b1, W2
+    (128 x 128), b2, W3 (k x 128), b3; rgb: (m, >= 3) float32.  precision
+    "f16" (fp16 matrix-core operands, fp32 accumulation) or "f32"."""
+    W = [net[x].contiguous() for x in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    _dev(*W, rgb, out)
+    if any(w.dtype != torch.float32 for w in W) or rgb.dtype != torch.float32:
+        raise ValueError("upsample takes float32 weights and colours")
+    k = k or W[4].shape[0]
+    if precision not in ("f16", "f32"):
+        raise ValueError(f"precision must be 'f16' or 'f32', not {precision!r}")
+    m = rgb.shape[0]
+    ld_z = ld_z or latent_width(k)
+    if out is None:
+        out = torch.empty(m, ld_z, dtype=torch.float32, device=rgb.device)
+    mlp = _lib.Mlp(k, W[0].shape[0], *(w.data_ptr() for w in W))
+    check(load().hc_upsample(C.byref(mlp), _lib.HC_MLP_F16 if precision == "f16" else _lib.HC_MLP_F32,
+                             _ptr(rgb), m, rgb.stride(0), _ptr(out), out.stride(0), _stream()),
+          "hc_upsample")
+    return out
+
+
 def gen_paths(n_pixels: int, spp: int, l_min: int, l_max: int, n_tex: int, n_illum: int, seed: int,
               device="cuda") -> Paths:
     """Generate a frame's records on the GPU (same draws as synth.gen_paths)."""

@@ -128,3 +128,26 @@ def test_gen_rejects_bad_lengths(lib):
     g = _lib.PathGen(16, 4, 3, 2, 8, 64, 1)
     s, msg = _err(lib.hc_gen_path_headers(C.byref(g), None, None, None, None, 0, None))
     assert s == _lib.HC_ESHAPE and "l_min" in msg
+
+
+def test_upsample_validates_before_launch(lib):
+    net = _lib.Mlp(6, 128, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
+    args = lambda prec=0, m=16, ld_rgb=3, ld_z=8: (C.byref(net), prec, 0x1000, m, ld_rgb, 0x1000, ld_z, None)  # noqa: E731
+    net.hidden = 64
+    s, msg = _err(lib.hc_upsample(*args()))
+    assert s == _lib.HC_EUNSUPPORTED and "hidden" in msg
+    net.hidden, net.k = 128, 0
+    assert lib.hc_upsample(*args()) == _lib.HC_ESHAPE
+    net.k = 49
+    assert lib.hc_upsample(*args()) == _lib.HC_ESHAPE
+    net.k = 6
+    assert lib.hc_upsample(*args(prec=2)) == _lib.HC_EINVAL
+    assert lib.hc_upsample(*args(ld_rgb=2)) == _lib.HC_ESHAPE
+    assert lib.hc_upsample(*args(ld_z=7)) == _lib.HC_ESHAPE
+    assert lib.hc_upsample(*args(m=-1)) == _lib.HC_ESHAPE
+    net.W2 = None
+    assert lib.hc_upsample(*args()) == _lib.HC_EINVAL
+    # an empty input enqueues nothing and needs no buffers
+    assert lib.hc_upsample(C.byref(net), 0, None, 0, 3, None, 8, None) == _lib.HC_OK
+    net.W2 = 0x1002
+    assert lib.hc_upsample(*args()) == _lib.HC_EALIGN
