@@ -66,3 +66,117 @@ def test_single_path_closed_form():
     inner = s / (1 + np.exp(-s))
     outer = a * inner / (1 + np.exp(-a * inner))
     assert np.allclose(ou.upsample(net, rgb), outer[:, None] * w[None, :], rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------------------ training objective
+
+def _batch(k, N, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.uniform(0, 1, (N, 3)), rng.uniform(0, 1, (N, k)), rng.uniform(0.05, 0.5, (3, k)),
+            np.array([0.95, 1.0, 1.08]))
+
+
+def test_lab_closed_forms():
+    white = np.array([0.95, 1.0, 1.08])
+    assert np.allclose(ou.lab(white[None], white), [[100.0, 0.0, 0.0]], atol=1e-12)
+    assert np.allclose(ou.lab(np.zeros((1, 3)), white), [[0.0, 0.0, 0.0]], atol=1e-12)
+    t = np.array([0.5, 0.02, 0.001, (6 / 29) ** 3])
+    grey = ou.lab(t[:, None] * white[None], white)
+    f = np.where(t > (6 / 29) ** 3, np.cbrt(t), t / (3 * (6 / 29) ** 2) + 4 / 29)
+    assert np.allclose(grey[:, 0], 116 * f - 16, rtol=1e-13) and np.allclose(grey[:, 1:], 0, atol=1e-12)
+    # the two branches meet at (6/29)^3
+    e = (6 / 29) ** 3
+    lo, hi = ou.lab(np.array([[e, e, e]]) * (1 - 1e-12), np.ones(3)), ou.lab(np.array([[e, e, e]]), np.ones(3))
+    assert abs(lo[0, 0] - hi[0, 0]) < 1e-8
+
+
+def test_mse_only_objective_has_the_linear_output_gradient():
+    """w_max = w_col = 0: L = mean (z - z_gt)^2, so dW3 = (2 / (N k)) d^T h2 and
+    db3 = (2 / (N k)) sum d, with d = z - z_gt."""
+    k, N = 6, 50
+    net = _net(k, seed=7)
+    rgb, zg, M, white = _batch(k, N, 8)
+    L, g = ou.upsample_loss_and_grad(net, rgb, zg, M, white, 0.0, 0.0)
+    _, h2 = ou.mlp_hidden(net, rgb)
+    d = ou.upsample(net, rgb) - zg
+    assert L == pytest.approx((d * d).mean(), rel=1e-14)
+    assert np.allclose(g["W3"], 2.0 / (N * k) * d.T @ h2, rtol=1e-12, atol=0)
+    assert np.allclose(g["b3"], 2.0 / (N * k) * d.sum(0), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_training_gradient_matches_central_differences(seed):
+    k, N = (6, 9, 16)[seed], 30
+    net = _net(k, seed=20 + seed)
+    rgb, zg, M, white = _batch(k, N, 30 + seed)
+    _, g = ou.upsample_loss_and_grad(net, rgb, zg, M, white)
+    scale = max(np.abs(v).max() for v in g.values())
+    rng = np.random.default_rng(seed)
+    h = 1e-6
+    for key in net:
+        W = net[key]
+        for flat in rng.choice(W.size, min(W.size, 12), replace=False):
+            idx = np.unravel_index(flat, W.shape)
+            p = dict(net)
+            wp, wm = W.copy(), W.copy()
+            wp[idx] += h
+            wm[idx] -= h
+            p[key] = wp
+            lp = ou.upsample_loss(p, rgb, zg, M, white)
+            p[key] = wm
+            lm = ou.upsample_loss(p, rgb, zg, M, white)
+            assert abs((lp - lm) / (2 * h) - g[key][idx]) <= 1e-7 * scale, (key, idx)
+
+
+def test_training_gradient_matches_torch_autograd():
+    """The objective written with torch's MSE, amax and norm (float64, CPU),
+    differentiated by autograd."""
+    import torch
+    import torch.nn.functional as F
+    k, N = 9, 64
+    net = _net(k, seed=40)
+    rgb, zg, M, white = _batch(k, N, 41)
+    L, g = ou.upsample_loss_and_grad(net, rgb, zg, M, white)
+    tn = {key: torch.tensor(v, dtype=torch.float64, requires_grad=True) for key, v in net.items()}
+    tc, tz, tM, tw = (torch.tensor(x, dtype=torch.float64) for x in (rgb, zg, M, white))
+    h1 = F.silu(tc @ tn["W1"].T + tn["b1"])
+    h2 = F.silu(h1 @ tn["W2"].T + tn["b2"])
+    z = h2 @ tn["W3"].T + tn["b3"]
+
+    def tlab(xyz):
+        t = xyz / tw
+        d = 6 / 29
+        f = torch.where(t > d ** 3, torch.sign(t) * torch.abs(t).clamp_min(1e-300) ** (1 / 3),
+                        t / (3 * d * d) + 4 / 29)
+        return torch.stack([116 * f[:, 1] - 16, 500 * (f[:, 0] - f[:, 1]), 200 * (f[:, 1] - f[:, 2])], 1)
+
+    de = torch.linalg.vector_norm(tlab(z @ tM.T) - tlab(tz @ tM.T), dim=1)
+    tl = F.mse_loss(z, tz) + 0.3 * (z - tz).abs().amax(dim=1).mean() + 0.05 * de.mean()
+    tl.backward()
+    assert L == pytest.approx(tl.item(), rel=1e-12)
+    for key in net:
+        assert np.allclose(g[key], tn[key].grad.numpy(), rtol=1e-9, atol=1e-12), key
+
+
+def test_adamw_with_clipping_matches_torch():
+    """oracle AdamW against torch.optim.AdamW after torch.nn.utils.clip_grad_norm_
+    over 30 steps; gradients large enough that clipping engages on some steps."""
+    import torch
+    rng = np.random.default_rng(50)
+    shapes = [(128, 3), (128,), (6, 128)]
+    w0 = [rng.normal(size=s) for s in shapes]
+    grads = [[rng.normal(size=s) * 10 ** rng.uniform(-3, 0.5) for s in shapes] for _ in range(30)]
+    opt = ou.AdamW(shapes, lr=2e-3, weight_decay=1e-5, max_norm=1.0)
+    ws = [w.copy() for w in w0]
+    tp = [torch.tensor(w, dtype=torch.float64, requires_grad=True) for w in w0]
+    topt = torch.optim.AdamW(tp, lr=2e-3, weight_decay=1e-5)
+    clipped = 0
+    for g in grads:
+        ws = opt.step(ws, g)
+        for p, gi in zip(tp, g):
+            p.grad = torch.tensor(gi, dtype=torch.float64)
+        clipped += float(torch.nn.utils.clip_grad_norm_(tp, 1.0)) > 1.0
+        topt.step()
+    assert 0 < clipped < 30
+    for w, p in zip(ws, tp):
+        assert np.allclose(w, p.detach().numpy(), rtol=1e-12, atol=1e-14)
