@@ -171,6 +171,92 @@ def multibounce_leg(args, dev, n, k, T, codecs):
     return out
 
 
+UP_SIDE = 4096           # RGB texture side for the upsampling throughput
+MFMA_F16_PEAK_TFS = 2500.0
+MFMA_F32_PEAK_TFS = 157.3
+
+
+def upsample_leg(args, dev, n, k, T, E, D, refl, illum, P, xyz_s, codes, lcodes, zimg, xyz_l):
+    """RGB-to-latent upsampling (Sec. 5): fit the network on the GPU against
+    the frozen codec (reflectance pool, AdamW), time it on a 4096^2 RGB
+    texture in both precisions, and shade the frame with the upsampled
+    texture codes (spectral lights encoded as usual)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2602_18741_amd import colour, ops
+    from paper_2602_18741_amd.upsample_fit import UpsampleFit, training_pairs
+    Tn = T.cpu().double().numpy()
+    Dn = D.cpu().double().numpy()
+    M = torch.from_numpy((Tn @ Dn).astype(np.float32)).to(dev)      # XYZ of a code
+    white = Tn.sum(axis=1)                                            # XYZ of the unit spectrum
+    pool, _ = synth.workloads.codec_pools(n, 1 << 18)
+    pool = ops.padded(torch.from_numpy(pool).to(dev))
+    rgb_pool, z_pool = training_pairs(E, T, pool, n)
+    fit = UpsampleFit(rgb_pool, z_pool, M, white, k, batch=1024, seed=4)
+    first = float(fit.run(1))
+    fit.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = float(fit.run(args.upsample_steps - 1))
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) * 1e6 / max(1, args.upsample_steps - 1)
+    net = fit.net()
+    log(f"upsampler fit: loss {first:.4g} -> {loss:.4g} in {fit.steps_done} steps, {us:.1f} us/step")
+
+    # held-out reflectances: colour error of upsampled codes against the truth and the codec
+    test, _ = synth.workloads.bounce_chains(n, 1 << 16, 1)
+    test = ops.padded(torch.from_numpy(test).to(dev))
+    rgb_t, z_t = training_pairs(E, T, test, n)
+    z_up = ops.upsample(net, rgb_t, k, precision="f16")
+    xyz_up = ops.decode_xyz(D, T, z_up, k).cpu().double().numpy()
+    xyz_codec = ops.decode_xyz(D, T, z_t, k).cpu().double().numpy()
+    xyz_true = test[:, :n].cpu().double().numpy() @ Tn.T
+    lab = lambda x: colour.xyz_to_lab(x, white)  # noqa: E731
+    de = lambda a, b: float(np.linalg.norm(lab(a) - lab(b), axis=1).mean())  # noqa: E731
+    quality = {"test_reflectances": int(test.shape[0]),
+               "de76_upsampled_vs_spectral": de(xyz_true, xyz_up),
+               "de76_upsampled_vs_codec": de(xyz_codec, xyz_up),
+               "de76_codec_vs_spectral": de(xyz_true, xyz_codec)}
+
+    # throughput on a 4096^2 RGB texture
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    rgb_big = torch.rand(UP_SIDE * UP_SIDE, 4, device=dev, generator=g)
+    out = torch.empty(UP_SIDE * UP_SIDE, ops.latent_width(k), device=dev)
+    flop = 2.0 * (3 * 128 + 128 * 128 + 128 * k) * rgb_big.shape[0]
+    timing = {}
+    for prec, peak in (("f16", MFMA_F16_PEAK_TFS), ("f32", MFMA_F32_PEAK_TFS)):
+        for _ in range(2):
+            ops.upsample(net, rgb_big, k, precision=prec, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            ops.upsample(net, rgb_big, k, precision=prec, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tfs = flop / (ms * 1e-3) / 1e12
+        timing[prec] = {"ms": ms, "texels_per_s": rgb_big.shape[0] / (ms * 1e-3), "TFLOP_s": tfs,
+                        "mfma_peak_TFLOP_s": peak, "frac": tfs / peak}
+    log("upsampling 4096^2 texels: " + ", ".join(
+        f"{p} {v['ms']:.3f} ms ({v['TFLOP_s']:.0f} TFLOP/s)" for p, v in timing.items()))
+
+    # the frame shaded with upsampled texture codes
+    rgb_tex, _ = training_pairs(E, T, refl, n)
+    ops.upsample(net, rgb_tex, k, precision="f16", out=codes)
+    ops.encode(E, illum, n=n, out=lcodes)
+    ops.shade_latent(P, codes, lcodes, k, out=zimg)
+    ops.decode_xyz(D, T, zimg, k, out=xyz_l)
+    frame = colour.frame_difference(xyz_s.cpu().numpy(), xyz_l.cpu().numpy())
+    log(f"frame with upsampled texture codes: CIEDE2000 mean {frame['mean']:.3f}, p95 {frame['p95']:.3f}")
+    return {"fit": {"steps": fit.steps_done, "batch": 1024, "lr": 2e-3, "first_loss": first,
+                    "final_loss": loss, "us_per_step": us},
+            "colour": quality, "throughput_4096sq": timing,
+            "ciede2000_frame_upsampled_texture_vs_spectral": frame}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +268,9 @@ def main():
                          "steps, the fitting recipe's length, are reported as well)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-upsample", action="store_true")
+    ap.add_argument("--upsample-steps", type=int, default=5000,
+                    help="AdamW steps of the upsampling network's fit")
     ap.add_argument("--serve-count", type=int, default=200,
                     help="requests per arrival rate in the serving measurement")
     ap.add_argument("--record-traffic", nargs=4, metavar="CSV",
@@ -340,6 +429,9 @@ def main():
     log(f"CIEDE2000 latent (two-term codec) vs spectral: mean {de_l2['mean']:.3f}, "
         f"p95 {de_l2['p95']:.3f}")
     bounce = multibounce_leg(args, dev, n, k, T, codecs)
+    up = None
+    if not args.no_upsample:
+        up = upsample_leg(args, dev, n, k, T, E, D, refl, illum, P, xyz_s, codes, lcodes, zimg, xyz_l)
 
     serving = None
     if not (args.no_serve or stress):
@@ -385,6 +477,7 @@ def main():
         "ciede2000_latent_vs_spectral_two_term_codec": de_l2,
         "codec_fit": {name: info for name, (_, info) in codecs.items()},
         "multibounce": bounce,
+        "upsample": up,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

@@ -361,6 +361,60 @@ hc_status hc_upsample(const hc_mlp* net, int32_t precision, const float* rgb, in
                       int64_t ld_rgb, float* Z, int64_t ld_z, void* stream);
 
 /*
+ * Training step of the upsampling network (Sec. 5.2).  Parameters are one
+ * packed float32 array of hc_upsample_param_count(k, 128) values: W1 (128 x 3),
+ * b1 (128), W2 (128 x 128), b2 (128), W3 (k x 128), b3 (k), in this order.
+ * On a batch of N samples (colour c_i = rgb row idx[i], target code z_gt row
+ * idx[i] in the blocked layout; rows 0..N-1 when idx is NULL; indices >= rows
+ * are clamped) the loss is
+ *   L = (1/N) sum_i [ |z_i - z_gt,i|^2 / k + w_max max_c |z_ic - z_gt,ic|
+ *                     + w_col DeltaE76(Lab(M z_i), Lab(M z_gt,i)) ],
+ * z_i the network output, M = T D (3 x k, float32: XYZ of a code through the
+ * frozen decoder), Lab against the reference white (Xn, Yn, Zn).  The paper
+ * uses w_max = 0.3 and w_col = 0.05.  The call writes L (device float) and,
+ * if grad is not NULL, dL/dparams (hand-derived backward; at a tie of the
+ * largest |z - z_gt| the first channel takes the max term's gradient).
+ * With opt it then clips the gradient to the global L2 norm max_grad_norm
+ * (factor min(1, max_grad_norm / (norm + 1e-6))), applies decoupled weight
+ * decay (params *= 1 - lr weight_decay) and the Adam update with bias
+ * correction, and increments *opt->step (AdamW with clipping, Sec. 5.2).
+ * Deterministic.  workspace: hc_upsample_train_workspace_size(k, N) bytes,
+ * 256-byte aligned.
+ */
+typedef struct hc_adamw {
+    float* m;           /* first moments, packed like the parameters */
+    float* v;           /* second moments */
+    int64_t* step;      /* device counter */
+    double lr, beta1, beta2, eps, weight_decay, max_grad_norm;
+} hc_adamw;
+
+typedef struct hc_upsample_train_args {
+    int32_t k;
+    int32_t hidden;     /* must be 128 */
+    float* params;      /* updated in place when opt != NULL */
+    const float* rgb;
+    int64_t ld_rgb;     /* >= 3 */
+    const float* z_gt;
+    int64_t ld_z;       /* >= 4 ceil(k/3) */
+    int64_t rows;       /* rows of rgb and z_gt */
+    const uint32_t* idx;  /* nullable */
+    int64_t N;          /* batch size, >= 1 */
+    const float* M;     /* 3 x k */
+    double white[3];
+    double w_max, w_col;
+    float* loss;        /* device scalar */
+    float* grad;        /* nullable */
+    const hc_adamw* opt;  /* host pointer, nullable */
+    void* workspace;
+    size_t workspace_bytes;
+    void* stream;
+} hc_upsample_train_args;
+
+int64_t hc_upsample_param_count(int32_t k, int32_t hidden);
+size_t hc_upsample_train_workspace_size(int32_t k, int64_t N);
+hc_status hc_upsample_train_step(const hc_upsample_train_args* args);
+
+/*
  * Synthetic light-path generator (workload input, not part of the method).
  * Draws come from SplitMix64's output function mix64 applied to
  * key + (counter + 1) * 0x9E3779B97F4A7C15 with key = mix64(mix64(seed) + stream):

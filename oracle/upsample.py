@@ -82,7 +82,8 @@ def upsample_loss(net, rgb, z_gt, M, white, w_max: float = 0.3, w_col: float = 0
     return float((d * d).mean() + w_max * np.abs(d).max(axis=1).mean() + w_col * de.mean())
 
 
-def upsample_loss_and_grad(net, rgb, z_gt, M, white, w_max: float = 0.3, w_col: float = 0.05):
+def upsample_loss_and_grad(net, rgb, z_gt, M, white, w_max: float = 0.3, w_col: float = 0.05,
+                           abs_scale: bool = False):
     """Loss of upsample_loss and its gradient with respect to every weight.
 
     Backward, per sample (then / N): with d = z - z_gt,
@@ -92,7 +93,9 @@ def upsample_loss_and_grad(net, rgb, z_gt, M, white, w_max: float = 0.3, w_col: 
       dW3 = dz h2^T, db3 = dz, dp2 = (W3^T dz) * silu'(p2), dW2 = dp2 h1^T, db2 = dp2,
       dp1 = (W2^T dp2) * silu'(p1), dW1 = dp1 c^T, db1 = dp1,
     silu'(x) = s + x s (1 - s), s = logistic(x).
-    Returns (loss, dict of gradients keyed like net)."""
+    Returns (loss, dict of gradients keyed like net); with abs_scale also a
+    dict of the batch means of |per-sample contribution| of every element
+    (the magnitude that rounding errors of the batch sum scale with)."""
     c = _f64(rgb)
     W1, b1, W2, b2 = (_f64(net[x]) for x in ("W1", "b1", "W2", "b2"))
     W3, b3 = _f64(net["W3"]), _f64(net["b3"])
@@ -124,7 +127,12 @@ def upsample_loss_and_grad(net, rgb, z_gt, M, white, w_max: float = 0.3, w_col: 
     dp2 = (dz @ W3) * dsilu(p2)
     dp1 = (dp2 @ W2) * dsilu(p1)
     grads = dict(W3=dz.T @ h2, b3=dz.sum(0), W2=dp2.T @ h1, b2=dp2.sum(0), W1=dp1.T @ c, b1=dp1.sum(0))
-    return L, grads
+    if not abs_scale:
+        return L, grads
+    a = np.abs
+    scale = dict(W3=a(dz).T @ a(h2), b3=a(dz).sum(0), W2=a(dp2).T @ a(h1), b2=a(dp2).sum(0),
+                 W1=a(dp1).T @ a(c), b1=a(dp1).sum(0))
+    return L, grads, scale
 
 
 class AdamW:

@@ -11,7 +11,7 @@ __all__ = ["HCError", "load", "ops"]
 
 
 def __getattr__(name):
-    if name in ("ops", "autograd", "serve", "codec_fit", "colour", "multibounce"):
+    if name in ("ops", "autograd", "serve", "codec_fit", "colour", "multibounce", "upsample_fit"):
         import importlib
         return importlib.import_module(f".{name}", __name__)
     raise AttributeError(name)

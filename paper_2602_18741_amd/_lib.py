@@ -63,6 +63,19 @@ class Mlp(C.Structure):
                 ("W3", vp), ("b3", vp)]
 
 
+class AdamW(C.Structure):
+    _fields_ = [("m", vp), ("v", vp), ("step", vp), ("lr", f64), ("beta1", f64), ("beta2", f64),
+                ("eps", f64), ("weight_decay", f64), ("max_grad_norm", f64)]
+
+
+class UpsampleTrainArgs(C.Structure):
+    _fields_ = [("k", i32), ("hidden", i32), ("params", vp), ("rgb", vp), ("ld_rgb", i64),
+                ("z_gt", vp), ("ld_z", i64), ("rows", i64), ("idx", vp), ("N", i64), ("M", vp),
+                ("white", f64 * 3), ("w_max", f64), ("w_col", f64), ("loss", vp), ("grad", vp),
+                ("opt", C.POINTER(AdamW)), ("workspace", vp), ("workspace_bytes", sz),
+                ("stream", vp)]
+
+
 class PathGen(C.Structure):
     _fields_ = [("n_pixels", i64), ("spp", i32), ("l_min", i32), ("l_max", i32), ("n_illum", i32),
                 ("n_tex", i64), ("seed", u64)]
@@ -95,6 +108,9 @@ _PROTOS = {
     "hc_codec_step": (i32, [C.POINTER(CodecArgs)]),
     "hc_codec_weights": (i32, [vp, vp, i32, i32, i32, f64, vp, vp, vp]),
     "hc_upsample": (i32, [vp, i32, vp, i64, i64, vp, i64, vp]),
+    "hc_upsample_param_count": (i64, [i32, i32]),
+    "hc_upsample_train_workspace_size": (sz, [i32, i64]),
+    "hc_upsample_train_step": (i32, [vp]),
     "hc_shade_latent_tiles": (i32, [vp, i32, vp, vp, i32, i32, i32, vp]),
     "hc_shade_spectral_tiles": (i32, [vp, i32, vp, vp, i32, i32, vp, i32, vp]),
     "hc_decode_tiles": (i32, [vp, i32, vp, vp, i32, vp, i32, i32, vp, i32, vp]),

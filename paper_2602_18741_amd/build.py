@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libhc.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["hc_api.hip", "k_latent.hip", "k_spectral.hip", "k_records.hip", "k_encode.hip",
-           "k_codec.hip", "k_gen.hip", "k_upsample.hip"]
+           "k_codec.hip", "k_gen.hip", "k_upsample.hip",
+           "k_upsample_train.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code: hipcc then emits

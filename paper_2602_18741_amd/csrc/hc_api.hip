@@ -321,6 +321,53 @@ hc_status hc_upsample(const hc_mlp* net, int32_t precision, const float* rgb, in
     return launch_upsample(*net, precision, rgb, m, ld_rgb, Z, ld_z, as_stream(stream));
 }
 
+int64_t hc_upsample_param_count(int32_t k, int32_t hidden) {
+    if (k < 1 || k > kMaxK || hidden != 128) return -1;
+    return upsample_param_count(k);
+}
+
+size_t hc_upsample_train_workspace_size(int32_t k, int64_t N) {
+    if (k < 1 || k > kMaxK || N < 1) return 0;
+    return upsample_train_workspace_size(k, N);
+}
+
+hc_status hc_upsample_train_step(const hc_upsample_train_args* a) {
+    clear_error();
+    const char* fn = "hc_upsample_train_step";
+    HC_REQUIRE(a != nullptr, HC_EINVAL, "%s: args is NULL", fn);
+    HC_REQUIRE(a->hidden == 128, HC_EUNSUPPORTED, "%s: hidden width %d (only 128 is compiled)", fn,
+               a->hidden);
+    HC_REQUIRE(a->k >= 1 && a->k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, a->k, kMaxK);
+    HC_REQUIRE(a->N >= 1 && a->N < (int64_t(1) << 31), HC_ESHAPE, "%s: N outside [1, 2^31)", fn);
+    HC_REQUIRE(a->ld_rgb >= 3 && a->ld_z >= 4 * ceil_div(a->k, 3), HC_ESHAPE, "%s: row stride too small",
+               fn);
+    HC_REQUIRE(a->params && a->rgb && a->z_gt && a->M && a->loss, HC_EINVAL, "%s: NULL pointer", fn);
+    if (a->idx) HC_REQUIRE(a->rows >= 1, HC_ESHAPE, "%s: rows must be >= 1 with idx", fn);
+    else HC_REQUIRE(a->rows >= a->N, HC_ESHAPE, "%s: rows < N without idx", fn);
+    for (double w : a->white)
+        HC_REQUIRE(w > 0 && w < HUGE_VAL, HC_EINVAL, "%s: the white must be positive and finite", fn);
+    HC_REQUIRE(a->w_max >= 0 && a->w_max < HUGE_VAL && a->w_col >= 0 && a->w_col < HUGE_VAL, HC_EINVAL,
+               "%s: loss weights must be finite and >= 0", fn);
+    HC_REQUIRE(aligned4(a->params) && aligned4(a->rgb) && aligned4(a->z_gt) && aligned4(a->M) &&
+                   aligned4(a->loss) && (!a->grad || aligned4(a->grad)),
+               HC_EALIGN, "%s: arrays must be 4-byte aligned", fn);
+    if (a->opt) {
+        const hc_adamw* o = a->opt;
+        HC_REQUIRE(o->m && o->v && o->step, HC_EINVAL, "%s: optimizer state has a NULL pointer", fn);
+        HC_REQUIRE(aligned4(o->m) && aligned4(o->v) && aligned8(o->step), HC_EALIGN,
+                   "%s: optimizer state misaligned", fn);
+        HC_REQUIRE(o->lr > 0 && o->beta1 >= 0 && o->beta1 < 1 && o->beta2 >= 0 && o->beta2 < 1 &&
+                       o->eps > 0 && o->weight_decay >= 0 && o->max_grad_norm > 0,
+                   HC_EINVAL, "%s: optimizer hyper-parameters out of range", fn);
+    }
+    const size_t need = upsample_train_workspace_size(a->k, a->N);
+    HC_REQUIRE(a->workspace != nullptr && a->workspace_bytes >= need &&
+                   (reinterpret_cast<uintptr_t>(a->workspace) & 255u) == 0,
+               HC_ENOMEM, "%s: workspace needs %zu bytes (256-byte aligned), got %zu", fn, need,
+               a->workspace_bytes);
+    return launch_upsample_train(*a);
+}
+
 hc_status hc_codec_weights(const void* Wt_E, const void* Wt_D, int32_t k, int32_t n, int32_t dtype,
                            double beta, float* E, float* D, void* stream) {
     clear_error();

@@ -254,6 +254,66 @@ def upsample(net: dict, rgb: torch.Tensor, k: int | None = None, precision: str 
     return out
 
 
+MLP_HIDDEN = 128
+
+
+def upsample_param_count(k: int) -> int:
+    return int(load().hc_upsample_param_count(k, MLP_HIDDEN))
+
+
+def unpack_mlp(params: torch.Tensor, k: int) -> dict:
+    """Views W1, b1, W2, b2, W3, b3 of a packed parameter vector (the layout
+    hc_upsample_train_step uses)."""
+    h = MLP_HIDDEN
+    sizes = [("W1", (h, 3)), ("b1", (h,)), ("W2", (h, h)), ("b2", (h,)), ("W3", (k, h)), ("b3", (k,))]
+    out, o = {}, 0
+    for name, shape in sizes:
+        n = 1
+        for d in shape:
+            n *= d
+        out[name] = params[o:o + n].view(*shape)
+        o += n
+    if o != params.numel():
+        raise ValueError(f"packed parameters hold {params.numel()} values, expected {o}")
+    return out
+
+
+class UpsampleWorkspace:
+    def __init__(self, k: int, N: int, device):
+        self.bytes = int(load().hc_upsample_train_workspace_size(k, N))
+        self.buf = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        self.ptr = self.buf.data_ptr() + off
+
+
+def upsample_train_step(params: torch.Tensor, rgb: torch.Tensor, z_gt: torch.Tensor, M: torch.Tensor,
+                        white, k: int, N: int, idx=None, w_max: float = 0.3, w_col: float = 0.05,
+                        loss=None, grad=None, opt: dict | None = None,
+                        workspace: UpsampleWorkspace | None = None):
+    """One loss/gradient (and optional AdamW) evaluation of the upsampling
+    network's training objective (Sec. 5.2) on the GPU.  params: packed
+    float32 vector; rgb (rows, >= 3) and z_gt (rows, blocked layout) float32;
+    M (3 x k) = T D; opt: dict with m, v, step (int64 device tensor), lr,
+    beta1, beta2, eps, weight_decay, max_grad_norm.  Returns the loss tensor."""
+    _dev(params, rgb, z_gt, M, idx, grad)
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float32, device=params.device)
+    workspace = workspace or UpsampleWorkspace(k, N, params.device)
+    o = None
+    if opt is not None:
+        o = _lib.AdamW(opt["m"].data_ptr(), opt["v"].data_ptr(), opt["step"].data_ptr(),
+                       opt.get("lr", 2e-3), opt.get("beta1", 0.9), opt.get("beta2", 0.999),
+                       opt.get("eps", 1e-8), opt.get("weight_decay", 1e-5),
+                       opt.get("max_grad_norm", 1.0))
+    a = _lib.UpsampleTrainArgs(
+        k, MLP_HIDDEN, params.data_ptr(), rgb.data_ptr(), rgb.stride(0), z_gt.data_ptr(),
+        z_gt.stride(0), rgb.shape[0], _ptr(idx), N, M.contiguous().data_ptr(),
+        (C.c_double * 3)(*[float(w) for w in white]), w_max, w_col, loss.data_ptr(), _ptr(grad),
+        C.pointer(o) if o is not None else None, workspace.ptr, workspace.bytes, _stream())
+    check(load().hc_upsample_train_step(C.byref(a)), "hc_upsample_train_step")
+    return loss
+
+
 def gen_paths(n_pixels: int, spp: int, l_min: int, l_max: int, n_tex: int, n_illum: int, seed: int,
               device="cuda") -> Paths:
     """Generate a frame's records on the GPU (same draws as synth.gen_paths)."""

@@ -1,0 +1,93 @@
+"""Fitting the RGB-to-latent upsampling network on the GPU (Sec. 5.2).
+
+Each step draws a batch of (RGB, target code) rows by index from
+device-resident tables with the counter-based index generator (the counter
+base is the optimizer's step counter, so a captured graph draws a fresh
+batch on every replay) and runs hc_upsample_train_step with the fused
+clipping and AdamW update.  The codec is frozen: the targets are codes of
+the training spectra and M = T D maps a code to XYZ for the colour term.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import ops
+
+
+def default_init(k: int, seed: int) -> np.ndarray:
+    """Packed parameters with torch.nn.Linear's default initialisation:
+    weights and biases uniform in +-1/sqrt(fan_in)."""
+    rng = np.random.default_rng(seed)
+    h = ops.MLP_HIDDEN
+    parts = []
+    for fan_in, shape in ((3, (h, 3)), (3, (h,)), (h, (h, h)), (h, (h,)), (h, (k, h)), (h, (k,))):
+        b = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, shape).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def training_pairs(E: torch.Tensor, T: torch.Tensor, spectra: torch.Tensor, n: int):
+    """Linear RGB (rows of 4 floats, the 4th 0) and codes (blocked layout) of
+    spectra (rows padded to a multiple of 4 floats), both computed by the
+    encode kernel: the codes with the codec's encoder, the colours with the
+    3 x n matrix XYZ->linear-sRGB times T (the linear RGB of Sec. 5.2)."""
+    import synth
+    to_rgb = torch.from_numpy((synth.XYZ_TO_LINEAR_SRGB @ T.cpu().double().numpy()).astype(np.float32))
+    rgb = ops.encode(to_rgb.to(spectra.device), spectra, n=n)
+    z = ops.encode(E, spectra, n=n)
+    return rgb, z
+
+
+class UpsampleFit:
+    def __init__(self, rgb: torch.Tensor, z_gt: torch.Tensor, M: torch.Tensor, white, k: int,
+                 batch: int = 1024, lr: float = 2e-3, weight_decay: float = 1e-5,
+                 max_grad_norm: float = 1.0, w_max: float = 0.3, w_col: float = 0.05, seed: int = 0,
+                 init_seed: int = 0):
+        dev = rgb.device
+        self.k, self.N, self.seed = k, batch, seed
+        self.rgb, self.z_gt, self.M = rgb, z_gt, M.contiguous()
+        self.white = tuple(float(w) for w in white)
+        self.w_max, self.w_col = w_max, w_col
+        self.params = torch.from_numpy(default_init(k, init_seed)).to(dev)
+        self.opt = dict(m=torch.zeros_like(self.params), v=torch.zeros_like(self.params),
+                        step=torch.zeros(1, dtype=torch.int64, device=dev), lr=lr, beta1=0.9,
+                        beta2=0.999, eps=1e-8, weight_decay=weight_decay,
+                        max_grad_norm=max_grad_norm)
+        self.idx = torch.empty(batch, dtype=torch.int32, device=dev)
+        self.loss = torch.zeros((), dtype=torch.float32, device=dev)
+        self.ws = ops.UpsampleWorkspace(k, batch, dev)
+        self.graph = None
+
+    def _step(self):
+        ops.gen_indices(2 * self.seed + 7, self.N, self.rgb.shape[0], step=self.opt["step"],
+                        out=self.idx)
+        ops.upsample_train_step(self.params, self.rgb, self.z_gt, self.M, self.white, self.k, self.N,
+                                idx=self.idx, w_max=self.w_max, w_col=self.w_col, loss=self.loss,
+                                opt=self.opt, workspace=self.ws)
+
+    def capture(self):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self._step()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+
+    def run(self, steps: int):
+        for _ in range(steps):
+            if self.graph is not None:
+                self.graph.replay()
+            else:
+                self._step()
+        return self.loss
+
+    @property
+    def steps_done(self) -> int:
+        return int(self.opt["step"].item())
+
+    def net(self) -> dict:
+        """W1, b1, W2, b2, W3, b3 views of the packed parameters (for ops.upsample)."""
+        return {name: v.contiguous() for name, v in ops.unpack_mlp(self.params, self.k).items()}

@@ -25,6 +25,7 @@ from .spectra import (  # noqa: F401
     illuminant_table,
     codec_uniform,
     codec_init,
+    XYZ_TO_LINEAR_SRGB,
 )
 from .texture import perlin_texture, perlin_weights  # noqa: F401
 from .paths import (  # noqa: F401

@@ -136,3 +136,9 @@ def codec_init(rng: np.random.Generator, k: int, n: int, std: float = 0.1):
     we = rng.normal(0.0, std, size=(k, n)).astype(np.float32)
     wd = rng.normal(0.0, std, size=(n, k)).astype(np.float32)
     return we, wd
+
+
+# XYZ -> linear sRGB primaries (IEC 61966-2-1, the published 4-decimal matrix).
+XYZ_TO_LINEAR_SRGB = np.array([[3.2406, -1.5372, -0.4986],
+                               [-0.9689, 1.8758, 0.0415],
+                               [0.0557, -0.2040, 1.0570]])

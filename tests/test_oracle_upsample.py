@@ -180,3 +180,17 @@ def test_adamw_with_clipping_matches_torch():
     assert 0 < clipped < 30
     for w, p in zip(ws, tp):
         assert np.allclose(w, p.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_abs_scale_bounds_the_gradient():
+    """The batch mean of |per-sample contribution| bounds |gradient| element
+    by element (triangle inequality), with equality for one sample."""
+    k = 9
+    net = _net(k, seed=60)
+    rgb, zg, M, white = _batch(k, 40, 61)
+    _, g, sc = ou.upsample_loss_and_grad(net, rgb, zg, M, white, abs_scale=True)
+    for key in g:
+        assert (np.abs(g[key]) <= sc[key] * (1 + 1e-12) + 1e-300).all()
+    _, g1, sc1 = ou.upsample_loss_and_grad(net, rgb[:1], zg[:1], M, white, abs_scale=True)
+    for key in g1:
+        assert np.allclose(np.abs(g1[key]), sc1[key], rtol=1e-12, atol=0)
