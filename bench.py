@@ -138,6 +138,30 @@ def measured_traffic(bytes_alg):
 MB_CHAINS = 1 << 18
 
 
+def codec_only(args):
+    """--codec-steps graph-replayed codec steps of each objective (n = 31,
+    k = args.k, batch 65,536, pools of 2^20): the step time alone."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2602_18741_amd.codec_fit import CodecFit
+    n, k = 31, args.k
+    pa, pb = synth.workloads.codec_pools(n, 1 << 20)
+    pa, pb = torch.from_numpy(pa).cuda(), torch.from_numpy(pb).cuda()
+    we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
+    for objective in ("eq8", "l2"):
+        fit = CodecFit(we0, wd0, pa, pb, batch=65536, seed=2, objective=objective,
+                       T=synth.cmf_matrix(n))
+        fit.run(1)
+        fit.capture()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = float(fit.run(args.codec_steps))
+        torch.cuda.synchronize()
+        log(f"codec {objective}: {(time.perf_counter() - t0) * 1e6 / args.codec_steps:.1f} us/step, "
+            f"loss {loss:.4g}")
+
+
 def multibounce_leg(args, dev, n, k, T, codecs):
     """Multi-bounce chains (Eq. 10): both forms on MB_CHAINS held-out chains
     of 3 bounces for each fitted codec; GPU time of one evaluation (encode,
@@ -269,6 +293,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-upsample", action="store_true")
+    ap.add_argument("--saturation-frames", type=int, default=8,
+                    help="frames in the burst of the stress workload's serving run")
     ap.add_argument("--upsample-steps", type=int, default=5000,
                     help="AdamW steps of the upsampling network's fit")
     ap.add_argument("--serve-count", type=int, default=200,
@@ -277,9 +303,10 @@ def main():
                     help="fetch, write, copy-fetch, copy-write counter CSVs -> traffic record")
     ap.add_argument("--stress", action="store_true",
                     help="the 4K / 64 spp / n=81 / k=9 stress frame instead of the default frame")
-    ap.add_argument("--only", choices=["latent", "spectral", "copy"],
-                    help="run only the timed steps of one form (or a 1 GiB device copy), "
-                         "for profilers; prints no JSON")
+    ap.add_argument("--only", choices=["latent", "spectral", "copy", "codec"],
+                    help="run only the timed steps of one form (or a 1 GiB device copy, or "
+                         "--codec-steps graph-replayed codec steps of each objective), for "
+                         "profilers; prints no JSON")
     args = ap.parse_args()
     if args.record_traffic:
         record_traffic(*args.record_traffic)
@@ -293,6 +320,9 @@ def main():
     import numpy as np
     import synth
 
+    if args.only == "codec":
+        codec_only(args)
+        return
     if args.only == "copy":
         import torch
         x = torch.ones(1 << 28, device="cuda:0")
@@ -434,6 +464,18 @@ def main():
         up = upsample_leg(args, dev, n, k, T, E, D, refl, illum, P, xyz_s, codes, lcodes, zimg, xyz_l)
 
     serving = None
+    if stress and not args.no_serve:
+        from paper_2602_18741_amd.serve import bench_saturation
+        host_tex = refl.cpu().pin_memory()
+        del P, zimg, codes, refl
+        torch.cuda.empty_cache()
+        t0 = time.time()
+        serving = bench_saturation(dev, host_tex, torch.from_numpy(w["illum"]), T.cpu(), E.cpu(), D.cpu(),
+                                   frames=args.saturation_frames)
+        log(f"serving at saturation measured in {time.time() - t0:.1f} s: " + ", ".join(
+            f"{form} {v['frames_per_s']:.2f} frames/s ({v['path_vertices_per_s'] / 1e9:.1f} G path-vertices/s), "
+            f"p50 {v['p50_ms']:.0f} ms, max {v['p99_ms']:.0f} ms" for form in ("latent", "spectral")
+            for v in [serving[form]]))
     if not (args.no_serve or stress):
         from paper_2602_18741_amd.serve import bench_serving
         del P, zimg

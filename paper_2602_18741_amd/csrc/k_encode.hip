@@ -77,8 +77,9 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncodeArgs a) {
 // Persistent launch over an encode job table (rows [begin, end) of one
 // spectra array each); block b takes jobs b, b + grid, ...
 template <int NB>
-__global__ __launch_bounds__(kThreads) void encode_jobs_kernel(const hc_encode_job* jobs,
-                                                               const int32_t* n_jobs_dev, int max_jobs,
+__global__ __launch_bounds__(kThreads) void encode_jobs_kernel(const hc_encode_job* __restrict__ jobs,
+                                                               const int32_t* __restrict__ n_jobs_dev,
+                                                               int max_jobs,
                                                                const float* E, int k, int n, int rows) {
     extern __shared__ float smem[];
     const int nq = (n + 3) / 4;
@@ -171,9 +172,11 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
 // Persistent launch over a tile table: each tile's pixels of frames[f].image
 // are decoded to frames[f].xyz.
 template <int NB>
-__global__ __launch_bounds__(kThreads) void decode_tiles_kernel(const hc_frame* frames, int n_frames,
-                                                                const hc_tile* tiles,
-                                                                const int32_t* n_tiles_dev, int max_tiles,
+__global__ __launch_bounds__(kThreads) void decode_tiles_kernel(const hc_frame* __restrict__ frames,
+                                                                int n_frames,
+                                                                const hc_tile* __restrict__ tiles,
+                                                                const int32_t* __restrict__ n_tiles_dev,
+                                                                int max_tiles,
                                                                 const float* D, int n, int k,
                                                                 const float* T) {
     __shared__ float s_M[3 * kMaxK];

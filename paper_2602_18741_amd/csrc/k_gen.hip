@@ -40,21 +40,46 @@ __device__ __forceinline__ uint32_t path_length(const GenArgs& g, uint64_t p) {
     return uint32_t(g.l_min) + range32(rand64(g.key_path, p), uint64_t(g.l_span));
 }
 
-// hdr of every path, and each pixel's vertex count into pix_first
-__global__ __launch_bounds__(kThreads) void gen_headers_kernel(GenArgs g, uint32_t* hdr,
+// Lane-per-path mapping shared by the two record kernels: a pixel's paths are
+// `seg` consecutive lanes (spp rounded up to a power of two, at most 64; more
+// samples loop over rounds of seg paths), `pw` pixels per wavefront.
+struct Seg {
+    int seg, pw, rounds;
+};
+
+Seg seg_of(int spp) {
+    Seg s;
+    s.seg = 1;
+    while (s.seg < spp && s.seg < kWave) s.seg <<= 1;
+    s.pw = kWave / s.seg;
+    s.rounds = int(ceil_div(spp, s.seg));
+    return s;
+}
+
+// hdr of every path (stores coalesced across the lanes), and each pixel's
+// vertex count into pix_first (sum over the pixel's lanes by xor shuffles)
+__global__ __launch_bounds__(kThreads) void gen_headers_kernel(GenArgs g, Seg s, uint32_t* hdr,
                                                                uint32_t* counts) {
-    const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (q >= g.n_pixels) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (int64_t(blockIdx.x) * kThreads + threadIdx.x) / kWave;
+    if (wave * s.pw >= g.n_pixels) return;  // whole wavefront
+    const int j0 = lane % s.seg;
+    const int64_t q = wave * s.pw + lane / s.seg;
+    const bool pix_ok = q < g.n_pixels;
     uint32_t sum = 0;
-    for (int j = 0; j < g.spp; ++j) {
-        const uint64_t p = uint64_t(q) * g.spp + j;
-        const uint64_t r = rand64(g.key_path, p);
-        const uint32_t len = uint32_t(g.l_min) + range32(r, uint64_t(g.l_span));
-        const uint32_t light = static_cast<uint32_t>(((r >> 32) * g.n_illum) >> 32);
-        hdr[p] = light | (len << 24);
-        sum += len;
+    for (int r = 0; r < s.rounds; ++r) {
+        const int j = j0 + r * s.seg;
+        if (pix_ok && j < g.spp) {
+            const uint64_t p = uint64_t(q) * g.spp + j;
+            const uint64_t rr = rand64(g.key_path, p);
+            const uint32_t len = uint32_t(g.l_min) + range32(rr, uint64_t(g.l_span));
+            const uint32_t light = static_cast<uint32_t>(((rr >> 32) * g.n_illum) >> 32);
+            hdr[p] = light | (len << 24);
+            sum += len;
+        }
     }
-    counts[q] = sum;
+    for (int m = 1; m < s.seg; m <<= 1) sum += __shfl_xor(sum, m, kWave);
+    if (pix_ok && j0 == 0) counts[q] = sum;
 }
 
 // Exclusive scan of the per-pixel counts (reduce, scan of block sums, scan).
@@ -122,24 +147,39 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(uint32_t* counts, 
     }
 }
 
-// one thread per path; a path's first record is its pixel's first record plus
-// the lengths of the pixel's earlier paths (recomputed from the generator)
-__global__ __launch_bounds__(kThreads) void gen_vertices_kernel(GenArgs g, const uint32_t* pix_first,
+// lane per path; a path's first record is its pixel's first record plus the
+// lengths of the pixel's earlier paths (exclusive scan over the pixel's lanes)
+__global__ __launch_bounds__(kThreads) void gen_vertices_kernel(GenArgs g, Seg s, const uint32_t* pix_first,
                                                                 uint32_t* vtx, uint64_t n_vertices) {
-    const int64_t p = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (p >= g.n_pixels * g.spp) return;
-    const int64_t q = p / g.spp;
-    const int j = int(p - q * g.spp);
-    uint64_t first = pix_first[q];
-    for (int jj = 0; jj < j; ++jj) first += path_length(g, uint64_t(q) * g.spp + jj);
-    const uint32_t len = path_length(g, uint64_t(p));
-    for (uint32_t v = 0; v < len; ++v) {
-        const uint64_t jv = first + v;
-        if (jv >= n_vertices) break;
-        const uint64_t r = rand64(g.key_vtx, uint64_t(p) * 256u + v);
-        const uint32_t texel = range32(r, g.n_tex);
-        const float w = float(uint32_t(r >> 40)) * (1.0f / 16777216.0f);
-        reinterpret_cast<uint2*>(vtx)[jv] = make_uint2(texel, __float_as_uint(w));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (int64_t(blockIdx.x) * kThreads + threadIdx.x) / kWave;
+    if (wave * s.pw >= g.n_pixels) return;  // whole wavefront
+    const int j0 = lane % s.seg;
+    const int64_t q = wave * s.pw + lane / s.seg;
+    const bool pix_ok = q < g.n_pixels;
+    const int last = (lane / s.seg) * s.seg + s.seg - 1;  // the segment's last lane
+    uint64_t next = pix_ok ? pix_first[q] : 0;
+    for (int r = 0; r < s.rounds; ++r) {
+        const int j = j0 + r * s.seg;
+        const bool live = pix_ok && j < g.spp;
+        const uint64_t p = uint64_t(q) * g.spp + j;
+        const uint32_t len = live ? path_length(g, p) : 0u;
+        uint32_t incl = len;
+        for (int d = 1; d < s.seg; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, kWave);
+            if (j0 >= d) incl += y;
+        }
+        const uint32_t total = __shfl(incl, last, kWave);
+        const uint64_t first = next + (incl - len);
+        next += total;
+        for (uint32_t v = 0; v < len; ++v) {
+            const uint64_t jv = first + v;
+            if (jv >= n_vertices) break;
+            const uint64_t rr = rand64(g.key_vtx, p * 256u + v);
+            const uint32_t texel = range32(rr, g.n_tex);
+            const float w = float(uint32_t(rr >> 40)) * (1.0f / 16777216.0f);
+            reinterpret_cast<uint2*>(vtx)[jv] = make_uint2(texel, __float_as_uint(w));
+        }
     }
 }
 
@@ -177,8 +217,10 @@ hc_status launch_gen_headers(const hc_path_gen& g, uint32_t* hdr, uint32_t* pix_
     uint64_t* block_sums = static_cast<uint64_t*>(ws);
     const int64_t nb = ceil_div(g.n_pixels, kScanTile);
     if (g.n_pixels > 0) {
-        hipLaunchKernelGGL(gen_headers_kernel, dim3(uint32_t(ceil_div(g.n_pixels, kThreads))),
-                           dim3(kThreads), 0, st, a, hdr, pix_first);
+        const Seg sg = seg_of(g.spp);
+        const int64_t waves = ceil_div(g.n_pixels, sg.pw);
+        hipLaunchKernelGGL(gen_headers_kernel, dim3(uint32_t(ceil_div(waves, kThreads / kWave))),
+                           dim3(kThreads), 0, st, a, sg, hdr, pix_first);
         hc_status s = launch_status("hc_gen_path_headers");
         if (s != HC_OK) return s;
         hipLaunchKernelGGL(scan_reduce_kernel, dim3(uint32_t(nb)), dim3(kThreads), 0, st, pix_first,
@@ -198,9 +240,11 @@ hc_status launch_gen_headers(const hc_path_gen& g, uint32_t* hdr, uint32_t* pix_
 hc_status launch_gen_vertices(const hc_path_gen& g, const uint32_t* pix_first, uint32_t* vtx,
                               int64_t n_vertices, hipStream_t st) {
     const GenArgs a = make_args(g);
-    const int64_t n_paths = g.n_pixels * g.spp;
-    hipLaunchKernelGGL(gen_vertices_kernel, dim3(uint32_t(ceil_div(n_paths, kThreads))), dim3(kThreads),
-                       0, st, a, pix_first, vtx, uint64_t(n_vertices));
+    if (g.n_pixels == 0) return HC_OK;
+    const Seg sg = seg_of(g.spp);
+    const int64_t waves = ceil_div(g.n_pixels, sg.pw);
+    hipLaunchKernelGGL(gen_vertices_kernel, dim3(uint32_t(ceil_div(waves, kThreads / kWave))),
+                       dim3(kThreads), 0, st, a, sg, pix_first, vtx, uint64_t(n_vertices));
     return launch_status("hc_gen_path_vertices");
 }
 

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentFrame f, int
         stage_lights<NB>(f, s_light);
         __syncthreads();
     }
-    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
     const int64_t q0 = wave * f.P.pw;
     if (q0 >= f.P.n_pixels) return;  // whole wave leaves together; no barrier follows
     if (lights_in_lds)
@@ -151,14 +151,21 @@ __global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentFrame f, int
 // Persistent launch over a tile table: block b takes tiles b, b + grid, ...
 // and its waves split each tile's pixel groups.  Light codes are staged per
 // tile when they fit in the LDS budget.
+// Occupancy floor for the tile kernel, per code width: the frame kernel's
+// occupancy less one wave where that fits the registers without spills (wider
+// codes keep the compiler's choice).  Without it the persistent loop's longer
+// live ranges cost one or two waves per SIMD.
+constexpr int tile_waves(int nb) { return nb <= 1 ? 8 : (nb == 2 ? 6 : 1); }
+
 template <int NB>
-__global__ __launch_bounds__(kBlock) void shade_latent_tiles_kernel(const hc_frame* frames, int n_frames,
-                                                                    const hc_tile* tiles,
-                                                                    const int32_t* n_tiles_dev,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(tile_waves(NB)))) void shade_latent_tiles_kernel(const hc_frame* __restrict__ frames,
+                                                                    int n_frames,
+                                                                    const hc_tile* __restrict__ tiles,
+                                                                    const int32_t* __restrict__ n_tiles_dev,
                                                                     int max_tiles) {
     extern __shared__ float4 s_light[];
     const int n_tiles = min(*n_tiles_dev, max_tiles);
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_in_block();
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         int64_t begin, end;
         const hc_tile tile = tiles[t];
@@ -181,10 +188,11 @@ __global__ __launch_bounds__(kBlock) void shade_latent_tiles_kernel(const hc_fra
         if (lds) stage_lights<NB>(f, s_light);
         __syncthreads();
         const int64_t groups = (end - begin + f.P.pw - 1) / f.P.pw;
-        for (int64_t g = wave; g < groups; g += kWavesPerBlock) {
-            if (lds)
+        if (lds) {
+            for (int64_t g = wave; g < groups; g += kWavesPerBlock)
                 latent_group<NB, true>(f, begin + g * f.P.pw, end, s_light);
-            else
+        } else {
+            for (int64_t g = wave; g < groups; g += kWavesPerBlock)
                 latent_group<NB, false>(f, begin + g * f.P.pw, end, s_light);
         }
     }

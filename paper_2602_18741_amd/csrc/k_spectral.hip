@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralFrame f,
         stage_lights(f, s_light);
         __syncthreads();
     }
-    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
     const int64_t q0 = wave * f.P.pw;
     if (q0 >= f.P.n_pixels) return;
     if (lights_in_lds)
@@ -175,13 +175,15 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralFrame f,
 
 // Persistent launch over a tile table (see the latent form).
 template <int G, int Q>
-__global__ __launch_bounds__(kBlock) void shade_spectral_tiles_kernel(const hc_frame* frames, int n_frames,
-                                                                      const hc_tile* tiles,
-                                                                      const int32_t* n_tiles_dev,
-                                                                      int max_tiles, int n, const float* T) {
+__global__ __launch_bounds__(kBlock) void shade_spectral_tiles_kernel(const hc_frame* __restrict__ frames,
+                                                                      int n_frames,
+                                                                      const hc_tile* __restrict__ tiles,
+                                                                      const int32_t* __restrict__ n_tiles_dev,
+                                                                      int max_tiles, int n,
+                                                                      const float* __restrict__ T) {
     extern __shared__ float4 s_light[];
     const int n_tiles = min(*n_tiles_dev, max_tiles);
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_in_block();
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         int64_t begin, end;
         const hc_tile tile = tiles[t];

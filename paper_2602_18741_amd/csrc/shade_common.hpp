@@ -72,6 +72,13 @@ __device__ __forceinline__ uint32_t segment_scan(uint32_t len, int j0, int seg, 
     return incl - len;
 }
 
+// The wavefront's index in its workgroup, as a value the compiler knows to be
+// uniform across the wavefront (kept in a scalar register, so everything
+// derived from it - pixel ranges, loop bounds - stays scalar too).
+__device__ __forceinline__ int wave_in_block() {
+    return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+}
+
 // Tile-table launches: a fixed grid walks the tiles; a tile's entries are
 // checked against the table sizes so a bad entry is skipped, not followed.
 __device__ __forceinline__ bool tile_range(const hc_tile& t, const hc_frame* frames, int n_frames,

@@ -514,6 +514,15 @@ class GpuBackend:
     def synchronize(self):
         self.stream.synchronize()
 
+    def prewarm(self, nbytes: float):
+        """Fill the caching allocator's pool of the backend's stream with one
+        block of nbytes, which later frame buffers are carved from, so frames
+        do not pay for first-touch device allocations."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            block = torch.empty(int(nbytes), dtype=torch.uint8, device=self.dev)
+            del block
+
 
 # ------------------------------------------------------------------ workload and driver
 
@@ -603,14 +612,13 @@ def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=
     if E is None:
         E, D = (torch.from_numpy(x) for x in synth.codec_uniform(np.random.default_rng([3, 3]), 6, n))
     assets = assets if assets is not None else make_assets(32, n)
-    # size the caching allocator once, so no run pays first-touch hipMalloc
-    torch.empty(int(24e9), dtype=torch.uint8, device=device)
     out = {"rates_fps": list(rates), "requests_per_rate": count,
            "start": "each (form, rate) run starts with no asset resident"}
     for form in ("latent", "spectral"):
         res = {}
         for rate in rates:
             be = GpuBackend(assets, lights, T, E, D, form=form, device=device)
+            be.prewarm(24e9)   # no run pays first-touch allocations
             reqs = make_requests(rate, count, len(assets), seed=int(rate))
             sched = Scheduler(be)
             wall = run_stream(sched, reqs)
@@ -619,5 +627,42 @@ def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=
             s["iterations"] = sched.iterations
             res[str(rate)] = s
             del be, sched
+            torch.cuda.empty_cache()   # the next run's stream cannot reuse this pool
         out[form] = res
+    return out
+
+
+def bench_saturation(device, asset, lights, T, E, D, frames: int = 8, width: int = 3840,
+                     height: int = 2160, spp: int = 64, l_range=(1, 8), mem_budget: float = 150e9,
+                     iter_vertices: float = 400e6, grid: int = 2048, target_tiles: int = 4096,
+                     max_tiles: int = 8192, forms=("latent", "spectral")) -> dict:
+    """Serving at saturation: a burst of `frames` identical-shape requests
+    (default 4K, 64 spp, path length 1..8) on one asset, all arriving at once,
+    after a small warm-up request has brought the asset in (and encoded it).
+    Reports throughput and per-frame latency for both forms.  asset: pinned
+    host float32 (texels, ld) spectral texture."""
+    import torch
+
+    out = {"frames": frames, "width": width, "height": height, "spp": spp, "path_length": list(l_range),
+           "mem_budget_bytes": mem_budget, "iteration_vertices": iter_vertices, "grid": grid,
+           "target_tiles": target_tiles}
+    for form in forms:
+        be = GpuBackend([asset], lights, T, E, D, form=form, device=device, asset_budget=64e9,
+                        grid=grid, max_tiles=max_tiles)
+        be.prewarm(mem_budget)
+        sched = Scheduler(be, mem_budget=mem_budget, iter_vertices=iter_vertices,
+                          target_tiles=target_tiles, max_tiles=max_tiles)
+        warm = Request(rid=10_000, asset=0, width=256, height=256, spp=1, l_min=1, l_max=1, seed=1)
+        run_stream(sched, [warm])
+        be.synchronize()
+        reqs = [Request(rid=i, asset=0, width=width, height=height, spp=spp, l_min=l_range[0],
+                        l_max=l_range[1], seed=20_000 + i, arrival=0.0) for i in range(frames)]
+        it0 = sched.iterations
+        wall = run_stream(sched, reqs, time_limit=600.0)
+        be.synchronize()
+        s = summarize(reqs, wall)
+        s["iterations"] = sched.iterations - it0
+        out[form] = s
+        del be, sched
+        torch.cuda.empty_cache()
     return out

@@ -252,10 +252,13 @@ def test_malformed_records_stay_in_bounds(ops, cfg0):
     assert torch.isfinite(xyz).all() and torch.isfinite(z).all()
 
 
-def test_device_generator_matches_synth(ops):
-    spec = synth.PathSpec(n_pixels=777, spp=16, l_min=1, l_max=8, n_tex=1 << 20, n_illum=256, seed=77)
+@pytest.mark.parametrize("n_pixels,spp,l_min,l_max", [(777, 16, 1, 8), (1000, 1, 1, 4), (333, 3, 0, 2),
+                                                      (129, 64, 1, 8), (65, 100, 0, 5), (40, 130, 2, 2)])
+def test_device_generator_matches_synth(ops, n_pixels, spp, l_min, l_max):
+    spec = synth.PathSpec(n_pixels=n_pixels, spp=spp, l_min=l_min, l_max=l_max, n_tex=1 << 20,
+                          n_illum=256, seed=77 + spp)
     hdr, pf, vtx = synth.gen_paths(spec)
-    P = ops.gen_paths(777, 16, 1, 8, 1 << 20, 256, 77)
+    P = ops.gen_paths(n_pixels, spp, l_min, l_max, 1 << 20, 256, 77 + spp)
     torch.cuda.synchronize()
     assert np.array_equal(to_np(P.hdr).view(np.uint32), hdr)
     assert np.array_equal(to_np(P.pix_first).view(np.uint32), pf)
