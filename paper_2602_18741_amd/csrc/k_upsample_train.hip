@@ -299,8 +299,15 @@ __global__ __launch_bounds__(kThreads) void ustrain_reduce_kernel(ReduceArgs a) 
     const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     double g = 0.0;
     if (e < a.P) {
-        double s = 0.0;
-        for (int r = 0; r < a.rows; ++r) s += double(a.part[r * a.P + e]);
+        // eight interleaved partial sums keep eight row loads in flight
+        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int r = 0;
+        for (; r + 8 <= a.rows; r += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += double(a.part[int64_t(r + u) * a.P + e]);
+        }
+        for (; r < a.rows; ++r) acc[0] += double(a.part[int64_t(r) * a.P + e]);
+        const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         g = s / double(a.N);
         a.grad[e] = float(g);
     }
