@@ -270,8 +270,9 @@ hc_status hc_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int32
  * backward), and optionally applies one Adam step.
  *
  * dtype: 0 = float32 everywhere, 1 = float64 everywhere (parameters, data,
- * T, outputs, Adam state).  Partial sums are accumulated in float64 and
- * reduced in a fixed order, so results are deterministic.
+ * T, outputs, Adam state).  Gradient sums run in that precision over tiles of
+ * at most 64 pairs and in float64 across tiles, in a fixed order, so results
+ * are deterministic.
  * Batch rows: row i of the a-batch is A[idx_a[i]*ld_a ...] when idx_a is
  * not NULL, else A[i*ld_a ...]; likewise b.  Indices must be < rows_a
  * (rows_b); out-of-range indices are clamped.

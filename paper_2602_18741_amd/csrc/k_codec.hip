@@ -10,8 +10,9 @@
 //                r_a = D u - a, r_b = D v - b, r_h = D h - a*b, and the
 //                back-propagated code gradients, staged in LDS; then every
 //                thread contracts over the tile's pairs for its gradient
-//                elements (float64 sums) and writes one partial row per
-//                workgroup.  One kernel per objective: the two-term squared
+//                elements (in the parameters' precision over the tile's at
+//                most 64 pairs, in float64 across tiles) and writes one
+//                partial row per workgroup.  One kernel per objective: the two-term squared
 //                error, or the four-term loss of Eq. 8 (which also needs the
 //                per-pair norms and dot product of the cosine factor, reduced
 //                across the pair's lanes by shuffles, and the code of the
@@ -203,21 +204,19 @@ __global__ __launch_bounds__(kThreads) void codec_partials_kernel(PartialArgs<F>
         // contraction over the tile's pairs; elements [0, kn) are dL/dE
         // (k x n), [kn, 2kn) are dL/dD (n x k), both without the 2/N factor
         for (int e = tid; e < 2 * kn; e += kThreads) {
-            double s = 0.0;
+            F s = 0;
             if (e < kn) {
                 const int j = e / n, i = e % n;
                 for (int p = 0; p < tp; ++p)
-                    s += double(GU[p * k + j]) * double(AA[p * np + i]) +
-                         double(GV[p * k + j]) * double(BB[p * np + i]);
+                    s += GU[p * k + j] * AA[p * np + i] + GV[p * k + j] * BB[p * np + i];
             } else {
                 const int e2 = e - kn;
                 const int i = e2 / k, j = e2 % k;
                 for (int p = 0; p < tp; ++p)
-                    s += double(RA[p * np + i]) * double(U[p * k + j]) +
-                         double(RB[p * np + i]) * double(V[p * k + j]) +
-                         double(RH[p * np + i]) * double(H[p * k + j]);
+                    s += RA[p * np + i] * U[p * k + j] + RB[p * np + i] * V[p * k + j] +
+                         RH[p * np + i] * H[p * k + j];
             }
-            prow[e] = first_tile ? s : prow[e] + s;
+            prow[e] = first_tile ? double(s) : prow[e] + double(s);
         }
         first_tile = false;
     }
@@ -400,22 +399,20 @@ __global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArg
         __syncthreads();
         // contraction over the tile's pairs; [0, kn) is dL/dE, [kn, 2kn) dL/dD
         for (int e = tid; e < 2 * kn; e += kThreads) {
-            double s = 0.0;
+            F s = 0;
             if (e < kn) {
                 const int j = e / n, i = e % n;
                 for (int p = 0; p < tp; ++p)
-                    s += double(GU[p * k + j]) * double(AA[p * np + i]) +
-                         double(GV[p * k + j]) * double(BB[p * np + i]) -
-                         double(DC[p * k + j]) * double(TT[p * np + i]);
+                    s += GU[p * k + j] * AA[p * np + i] + GV[p * k + j] * BB[p * np + i] -
+                         DC[p * k + j] * TT[p * np + i];
             } else {
                 const int e2 = e - kn;
                 const int i = e2 / k, j = e2 % k;
                 for (int p = 0; p < tp; ++p)
-                    s += double(RA[p * np + i]) * double(U[p * k + j]) +
-                         double(RB[p * np + i]) * double(V[p * k + j]) +
-                         double(SG[p * np + i]) * double(H[p * k + j]);
+                    s += RA[p * np + i] * U[p * k + j] + RB[p * np + i] * V[p * k + j] +
+                         SG[p * np + i] * H[p * k + j];
             }
-            prow[e] = first_tile ? s : prow[e] + s;
+            prow[e] = first_tile ? double(s) : prow[e] + double(s);
         }
         first_tile = false;
     }
