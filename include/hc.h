@@ -87,7 +87,7 @@ typedef struct hc_paths {
 
 /* Spectral assets: reflectance rows refl[t*ld + i] (n_texels x n, i < n) and
  * light rows illum[l*ld_illum + i] (n_illum x n).  float32, 16-byte aligned,
- * ld and ld_illum multiples of 4 and >= n. */
+ * ld and ld_illum multiples of 4 and >= n; ld < 2^31. */
 typedef struct hc_spectral_assets {
     const float* refl;
     int64_t n_texels;
@@ -101,7 +101,8 @@ typedef struct hc_spectral_assets {
 } hc_spectral_assets;
 
 /* Latent assets: encoded texels codes[t*ld + ...] and encoded lights
- * illum_codes[l*ld_illum + ...] in the blocked RGBx layout, k channels. */
+ * illum_codes[l*ld_illum + ...] in the blocked RGBx layout, k channels;
+ * ld < 2^31. */
 typedef struct hc_latent_assets {
     const float* codes;
     int64_t n_texels;
@@ -203,7 +204,7 @@ typedef struct hc_frame {
     int32_t n_illum;
     const float* tex;
     int64_t n_texels;
-    int64_t ld_tex;
+    int64_t ld_tex;     /* < 2^31 */
     const float* lights;
     int64_t ld_lights;
     float* image;       /* latent image rows (latent form), stride ld_image */

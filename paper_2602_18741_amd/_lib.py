@@ -132,6 +132,9 @@ def load():
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_2602_18741_amd.build` "
                 "(or __graft_entry__.build()); there is no fallback implementation")
+        # torch first: the process then has one HIP runtime, the one the
+        # caller's streams and tensors belong to, before the library binds it
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in _PROTOS.items():
             fn = getattr(lib, name)

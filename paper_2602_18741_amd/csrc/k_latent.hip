@@ -92,7 +92,7 @@ __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, i
                 float4 row[U][NB];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const float* rp = f.codes + int64_t(tex[u]) * f.ld + 4 * f.block_first;
+                    const float* rp = f.codes + uint64_t(tex[u]) * uint32_t(f.ld) + 4 * f.block_first;  // ld < 2^31
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
                         row[u][b] = (jv + u < end) ? ld4(rp + 4 * b) : make_float4(1.f, 1.f, 1.f, 1.f);

@@ -94,22 +94,28 @@ __device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q
                 uint2 rec[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) rec[u] = ldg_u2(P.vtx + min(jv + u, P.n_vertices - 1u));
+                // rows are loaded unconditionally (no branch per vertex): a
+                // padding slot reads texel 0's row, which stays in cache, and a
+                // lane past the n samples re-reads the row's last chunk; both
+                // are replaced by 1 below
                 uint32_t tex[U];
                 float wt[U];
+                bool ok[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    tex[u] = min(rec[u].x, f.n_tex - 1u);
-                    wt[u] = (jv + u < end) ? __uint_as_float(rec[u].y) : 1.f;
+                    ok[u] = jv + u < end;
+                    tex[u] = ok[u] ? min(rec[u].x, f.n_tex - 1u) : 0u;
+                    wt[u] = ok[u] ? __uint_as_float(rec[u].y) : 1.f;
                 }
                 float4 row[U][Q];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const float* rp = f.refl + int64_t(tex[u]) * f.ld;
+                    const float* rp = f.refl + uint64_t(tex[u]) * uint32_t(f.ld);  // ld < 2^31
 #pragma unroll
                     for (int qq = 0; qq < Q; ++qq) {
                         const int c = qq * G + sub;
-                        row[u][qq] = (jv + u < end && c < f.nq) ? ld4(rp + 4 * c)
-                                                                 : make_float4(1.f, 1.f, 1.f, 1.f);
+                        const float4 v = ld4(rp + 4 * min(c, f.nq - 1));
+                        row[u][qq] = (ok[u] && c < f.nq) ? v : make_float4(1.f, 1.f, 1.f, 1.f);
                     }
                 }
 #pragma unroll
