@@ -124,6 +124,25 @@ def record_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
     print(json.dumps(d))
 
 
+def copy_bandwidth(dev) -> float:
+    """GB/s of a plain 1 GiB device-to-device copy (2 GiB moved per copy),
+    HIP events around 10 back-to-back copies."""
+    import torch
+    x = torch.ones(1 << 28, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 10 * 2 * x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return gbs
+
+
 def measured_traffic(bytes_alg):
     """HBM bytes per shade_latent launch from the committed counter profile,
     if it was taken with the current kernel source; else None."""
@@ -443,6 +462,8 @@ def main():
     log(f"latent step {lat_wall * 1e3:.3f} ms (shade {lat_kern * 1e3:.3f} ms); "
         f"spectral step {spe_wall * 1e3:.3f} ms")
 
+    copy_gbs = copy_bandwidth(dev)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
     bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
     achieved = bytes_lat / lat_kern / 1e9
@@ -508,7 +529,9 @@ def main():
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": bytes_lat,
-                     "kernel_ms": lat_kern * 1e3},
+                     "kernel_ms": lat_kern * 1e3,
+                     "traffic_GBs": None if traffic is None else traffic / lat_kern / 1e9,
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "cpu_baseline": cpu,
         "spectral": {"value": nv / spe_wall, "unit": "path-vertices/s", "ms_per_step": spe_wall * 1e3,
                      "kernel_ms": spe_kern * 1e3, "achieved_GBs": bytes_spe / spe_kern / 1e9,

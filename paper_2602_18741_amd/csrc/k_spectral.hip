@@ -10,9 +10,24 @@ using namespace shade;
 
 // G lanes per path; a lane owns the float4 chunks c = qq*G + sub (qq < Q) of
 // the n samples, so one load instruction covers G consecutive chunks of each
-// path's texel row: one 128-byte line for G = 8.  (2 and 4 lanes per path
-// measured the same at n = 31.)
+// path's texel row: one 128-byte line for G = 8.  (4 lanes per path with two
+// chunks each ran slower at n = 31: fewer wavefronts fit per SIMD.)
 constexpr int kSpecLanes = 8;
+// Pixel groups per wavefront in a frame launch: the per-lane set-up (colour
+// weights, shuffle sources) is shared by that many groups.
+constexpr int kSpecGroupsPerWave = 8;
+
+// A row of ones, as long as the longest spectrum: padding vertex slots read
+// their row from here, so the product needs no select per loaded chunk.
+struct alignas(16) OnesRow {
+    float v[kMaxN];
+};
+constexpr OnesRow make_ones_row() {
+    OnesRow r{};
+    for (int i = 0; i < kMaxN; ++i) r.v[i] = 1.f;
+    return r;
+}
+__device__ const OnesRow kOnesRow = make_ones_row();
 
 struct SpectralFrame {
     PathView P;
@@ -29,6 +44,10 @@ struct SpectralFrame {
     float inv_spp;
 };
 
+// Where a path's light spectrum comes from: global memory, or the light
+// table staged in LDS when it fits the budget.
+enum LightMode { kLightGlobal, kLightLds };
+
 __device__ __forceinline__ void stage_lights(const SpectralFrame& f, float4* s_light) {
     for (uint32_t i = threadIdx.x; i < f.n_illum * uint32_t(f.nq); i += kBlock) {
         const uint32_t l = i / f.nq, c = i % f.nq;
@@ -36,152 +55,228 @@ __device__ __forceinline__ void stage_lights(const SpectralFrame& f, float4* s_l
     }
 }
 
-// The calling wave shades pixels [q0, min(q0 + pw, q_end)).  With LDS the
-// light spectra come from the staged table s_light, else from global memory.
-template <int G, int Q, bool LDS>
-__device__ __forceinline__ void spectral_group(const SpectralFrame& f, int64_t q0, int64_t q_end,
-                                               const float4* s_light) {
-    const PathView& P = f.P;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int sub = lane & (G - 1);
-    const int slot = lane / G;
+// Occupancy floor of the frame kernel: 7 waves per SIMD for one chunk per
+// lane (the compiler's choice is 6 for the global-light variant); wider
+// rows keep the compiler's choice.
+constexpr int spec_frame_waves(int q) { return q <= 1 ? 7 : 1; }
 
-    // colour-matching weights of this lane's samples; zero past n
-    float4 Tr[3][Q];
+constexpr size_t light_lds_bytes(uint32_t n_illum, int nq) { return size_t(n_illum) * nq * sizeof(float4); }
+
+// Sum of v over lanes i and i ^ M of each 32-lane half (M < 32): ds_swizzle in
+// bit-mask mode (and 0x1F, or 0, xor M) needs no address register.
+template <int M>
+__device__ __forceinline__ float xor_add(float v) {
+    static_assert(M > 0 && M < 32, "swizzle reaches within 32 lanes");
+    constexpr int pattern = (M << 10) | 0x1F;
+    return v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
+}
+__device__ __forceinline__ float add_from(float v, int addr) {
+    return v + __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+
+// What a lane needs for every path it shades, given only the sample count:
+// G lanes per path, the lane owning float4 chunks c = qq * G + sub.
+template <int G, int Q>
+struct SpecLane {
+    float4 Tr[3][Q];     // colour-matching weights of the lane's samples, 0 past n
+    bool keep[Q][4];     // the lane's samples below n
+    bool chunk_ok[Q];    // chunk below the n samples' chunk count
+    uint32_t off[Q];     // float offset of chunk qq in a row
+};
+
+template <int G, int Q>
+__device__ __forceinline__ SpecLane<G, Q> spec_lane(const float* T, int n, int nq) {
+    SpecLane<G, Q> L;
+    const int sub = threadIdx.x & (G - 1);
 #pragma unroll
     for (int qq = 0; qq < Q; ++qq) {
         const int c = qq * G + sub;
+        L.chunk_ok[qq] = c < nq;
+        // a lane past the n samples re-reads the last chunk; its sums are
+        // never used
+        L.off[qq] = 4u * uint32_t(min(c, nq - 1));
+        // the products of samples past n are replaced by 0 (not multiplied,
+        // so non-finite row padding cannot leak in)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) L.keep[qq][e] = 4 * c + e < n;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float w[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = 4 * c + e;
-                w[e] = (i < f.n) ? ldg_f32(f.T + ch * f.n + i) : 0.f;
+                const float t = ldg_f32(T + ch * n + min(i, n - 1));
+                w[e] = (i < n) ? t : 0.f;
             }
-            Tr[ch][qq] = make_float4(w[0], w[1], w[2], w[3]);
+            L.Tr[ch][qq] = make_float4(w[0], w[1], w[2], w[3]);
         }
     }
+    return L;
+}
 
-    const int seg = P.spp_pad;  // slots per pixel segment
-    const int j0 = slot % seg;
-    const int64_t q = q0 + slot / seg;
-    const bool pix_ok = q < q_end;
-    uint32_t next = pix_ok ? ldg_u32(P.pix_first + q) : 0u;
-    float ax = 0.f, ay = 0.f, az = 0.f;
+// The calling wave shades the pixel groups g = g_begin, g_begin + g_step, ...
+// below g_end; group g is pixels [q_base + g * pw, ...), cut at q_end.  The
+// light spectra come from global memory or the table s_light staged for mode
+// M.  The lane's shuffle sources are set up once for all groups.
+template <int G, int Q, LightMode M>
+__device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const SpecLane<G, Q>& L,
+                                                int64_t q_base, int64_t q_end, int64_t g_begin,
+                                                int64_t g_end, int64_t g_step, const float4* s_light) {
+    const PathView& P = f.P;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int sub = lane & (G - 1);
+    const int slot = lane / G;
+    const int seg = P.spp_pad;  // slots per pixel segment, a power of two
+    const int seg_log2 = __builtin_ctz(unsigned(seg));
+    const int j0 = slot & (seg - 1);
+    const int pix = slot >> seg_log2;
 
-    for (int r = 0; r < P.rounds; ++r) {
-        const int j = j0 + r * seg;
-        const bool live = pix_ok && j < P.spp;
-        const uint32_t h = live ? ldg_u32(P.hdr + (q * P.spp + j)) : 0u;
-        const uint32_t len = h >> 24;
-        uint32_t total;
-        const uint32_t first = next + segment_scan(len, j0, seg, G, total);
-        next += total;
-        if (live) {
-            float4 prod[Q];
+    // prefix of path lengths over the slots of a pixel segment: source lanes
+    // (byte addresses for ds_bpermute) of the log2(seg) steps, and the lane
+    // of the segment's last slot
+    constexpr int kMaxSteps = 6 - __builtin_ctz(unsigned(G));  // log2(64 / G)
+    int scan_src[kMaxSteps];
 #pragma unroll
-            for (int qq = 0; qq < Q; ++qq) prod[qq] = make_float4(1.f, 1.f, 1.f, 1.f);
-            float wprod = 1.f;
-            const uint32_t end = (first < P.n_vertices) ? min(first + len, P.n_vertices) : first;
-            // U vertices at a time: records, then rows, all in flight before
-            // the first multiply; padding slots multiply by 1
-            constexpr int U = Q <= 2 ? 4 : 2;
-            for (uint32_t jv = first; jv < end; jv += U) {
-                // records first, all U in flight: slots past the path read the
-                // following (in-bounds) records, which the wave fetches anyway;
-                // their weights and rows are replaced by 1 below
-                uint2 rec[U];
+    for (int i = 0; i < kMaxSteps; ++i) scan_src[i] = ((lane - (G << i)) & (kWave - 1)) << 2;
+    const int seg_lanes = seg * G;
+    const int last_src = ((lane & ~(seg_lanes - 1)) + seg_lanes - 1) << 2;
+
+    for (int64_t g = g_begin; g < g_end; g += g_step) {
+        const int64_t q = q_base + g * P.pw + pix;
+        const bool pix_ok = q < q_end;
+        uint32_t next = pix_ok ? ldg_u32(P.pix_first + q) : 0u;
+        float ax = 0.f, ay = 0.f, az = 0.f;
+
+        for (int r = 0; r < P.rounds; ++r) {
+            const int j = j0 + r * seg;
+            const bool live = pix_ok && j < P.spp;
+            const uint32_t h = live ? ldg_u32(P.hdr + (q * P.spp + j)) : 0u;
+            const uint32_t len = h >> 24;
+            // segmented inclusive scan of len, then the segment total
+            uint32_t incl = len;
 #pragma unroll
-                for (int u = 0; u < U; ++u) rec[u] = ldg_u2(P.vtx + min(jv + u, P.n_vertices - 1u));
-                // rows are loaded unconditionally (no branch per vertex): a
-                // padding slot reads texel 0's row, which stays in cache, and a
-                // lane past the n samples re-reads the row's last chunk; both
-                // are replaced by 1 below
-                uint32_t tex[U];
-                float wt[U];
-                bool ok[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    ok[u] = jv + u < end;
-                    tex[u] = ok[u] ? min(rec[u].x, f.n_tex - 1u) : 0u;
-                    wt[u] = ok[u] ? __uint_as_float(rec[u].y) : 1.f;
+            for (int i = 0; i < kMaxSteps; ++i) {
+                if (i < seg_log2) {
+                    const uint32_t y = uint32_t(__builtin_amdgcn_ds_bpermute(scan_src[i], int(incl)));
+                    incl += (j0 >= (1 << i)) ? y : 0u;
                 }
-                float4 row[U][Q];
+            }
+            const uint32_t total = uint32_t(__builtin_amdgcn_ds_bpermute(last_src, int(incl)));
+            const uint32_t first = next + incl - len;
+            next += total;
+            if (live) {
+                float4 prod[Q];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const float* rp = f.refl + uint64_t(tex[u]) * uint32_t(f.ld);  // ld < 2^31
+                for (int qq = 0; qq < Q; ++qq) prod[qq] = make_float4(1.f, 1.f, 1.f, 1.f);
+                float wprod = 1.f;
+                const uint32_t end = (first < P.n_vertices) ? min(first + len, P.n_vertices) : first;
+                // U vertices at a time: records, then rows, all in flight
+                // before the first multiply; padding slots multiply by 1
+                constexpr int U = Q <= 2 ? 4 : 2;
+                for (uint32_t jv = first; jv < end; jv += U) {
+                    // records first, all U in flight: slots past the path read
+                    // the following (in-bounds) records, which the wave fetches
+                    // anyway
+                    uint2 rec[U];
 #pragma unroll
-                    for (int qq = 0; qq < Q; ++qq) {
+                    for (int u = 0; u < U; ++u) rec[u] = ldg_u2(P.vtx + min(jv + u, P.n_vertices - 1u));
+                    // rows are loaded unconditionally (no branch per vertex): a
+                    // padding slot reads the row of ones and weight 1
+                    const float* rp[U];
+                    float wt[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const bool ok = jv + u < end;
+                        const uint32_t tex = min(rec[u].x, f.n_tex - 1u);
+                        const float* tp = f.refl + uint64_t(tex) * uint32_t(f.ld);  // ld < 2^31
+                        rp[u] = ok ? tp : kOnesRow.v;
+                        wt[u] = ok ? __uint_as_float(rec[u].y) : 1.f;
+                    }
+                    float4 row[U][Q];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int qq = 0; qq < Q; ++qq) row[u][qq] = ld4(rp[u] + L.off[qq]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int qq = 0; qq < Q; ++qq) prod[qq] = mul4(prod[qq], row[u][qq]);
+                        wprod *= wt[u];
+                    }
+                }
+                const uint32_t lid = min(h & 0xFFFFFFu, f.n_illum - 1u);
+                float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+                for (int qq = 0; qq < Q; ++qq) {
+                    if (L.chunk_ok[qq]) {
                         const int c = qq * G + sub;
-                        const float4 v = ld4(rp + 4 * min(c, f.nq - 1));
-                        row[u][qq] = (ok[u] && c < f.nq) ? v : make_float4(1.f, 1.f, 1.f, 1.f);
+                        const float4 lt = M == kLightLds ? s_light[lid * f.nq + c]
+                                                         : ld4(f.illum + int64_t(lid) * f.ld_l + 4 * c);
+                        const float4 m = mul4(lt, prod[qq]);
+                        const float s0 = L.keep[qq][0] ? m.x : 0.f;
+                        const float s1 = L.keep[qq][1] ? m.y : 0.f;
+                        const float s2 = L.keep[qq][2] ? m.z : 0.f;
+                        const float s3 = L.keep[qq][3] ? m.w : 0.f;
+                        const float4* Tr = L.Tr[0] + qq;
+                        sx += Tr[0].x * s0 + Tr[0].y * s1 + Tr[0].z * s2 + Tr[0].w * s3;
+                        sy += Tr[Q].x * s0 + Tr[Q].y * s1 + Tr[Q].z * s2 + Tr[Q].w * s3;
+                        sz += Tr[2 * Q].x * s0 + Tr[2 * Q].y * s1 + Tr[2 * Q].z * s2 + Tr[2 * Q].w * s3;
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-#pragma unroll
-                    for (int qq = 0; qq < Q; ++qq) prod[qq] = mul4(prod[qq], row[u][qq]);
-                    wprod *= wt[u];
-                }
-            }
-            const uint32_t lid = min(h & 0xFFFFFFu, f.n_illum - 1u);
-#pragma unroll
-            for (int qq = 0; qq < Q; ++qq) {
-                const int c = qq * G + sub;
-                if (c < f.nq) {
-                    const float4 lt = LDS ? s_light[lid * f.nq + c]
-                                          : ld4(f.illum + int64_t(lid) * f.ld_l + 4 * c);
-                    float4 s = mul4(scale4(lt, wprod), prod[qq]);
-                    // samples past n carry no colour weight; drop them so
-                    // non-finite row padding cannot leak in
-                    if (4 * c + 3 >= f.n) {
-                        if (4 * c + 0 >= f.n) s.x = 0.f;
-                        if (4 * c + 1 >= f.n) s.y = 0.f;
-                        if (4 * c + 2 >= f.n) s.z = 0.f;
-                        if (4 * c + 3 >= f.n) s.w = 0.f;
-                    }
-                    ax += Tr[0][qq].x * s.x + Tr[0][qq].y * s.y + Tr[0][qq].z * s.z + Tr[0][qq].w * s.w;
-                    ay += Tr[1][qq].x * s.x + Tr[1][qq].y * s.y + Tr[1][qq].z * s.z + Tr[1][qq].w * s.w;
-                    az += Tr[2][qq].x * s.x + Tr[2][qq].y * s.y + Tr[2][qq].z * s.z + Tr[2][qq].w * s.w;
-                }
+                // the vertex weights multiply the whole spectrum
+                ax += wprod * sx;
+                ay += wprod * sy;
+                az += wprod * sz;
             }
         }
-    }
-    // reduce over the G sample lanes, then over the pixel's slots
-    const int span = G * seg;
-    for (int m = 1; m < span; m <<= 1) {
-        ax += shfl_xor(ax, m);
-        ay += shfl_xor(ay, m);
-        az += shfl_xor(az, m);
-    }
-    if (pix_ok && sub == 0 && j0 == 0) {
-        float* out = f.xyz + q * 3;
-        stg_f32(out + 0, ax * f.inv_spp);
-        stg_f32(out + 1, ay * f.inv_spp);
-        stg_f32(out + 2, az * f.inv_spp);
+        // reduce over the G sample lanes, then over the pixel's slots: the
+        // span is G * seg lanes, at least G = 8
+        static_assert(G == 8, "the reduction starts at 8 lanes");
+        ax = xor_add<1>(ax); ay = xor_add<1>(ay); az = xor_add<1>(az);
+        ax = xor_add<2>(ax); ay = xor_add<2>(ay); az = xor_add<2>(az);
+        ax = xor_add<4>(ax); ay = xor_add<4>(ay); az = xor_add<4>(az);
+        if (seg_lanes > 8) { ax = xor_add<8>(ax); ay = xor_add<8>(ay); az = xor_add<8>(az); }
+        if (seg_lanes > 16) { ax = xor_add<16>(ax); ay = xor_add<16>(ay); az = xor_add<16>(az); }
+        if (seg_lanes > 32) {
+            const int src = (lane ^ 32) << 2;
+            ax = add_from(ax, src);
+            ay = add_from(ay, src);
+            az = add_from(az, src);
+        }
+        if (pix_ok && sub == 0 && j0 == 0) {
+            float* out = f.xyz + q * 3;
+            stg_f32(out + 0, ax * f.inv_spp);
+            stg_f32(out + 1, ay * f.inv_spp);
+            stg_f32(out + 2, az * f.inv_spp);
+        }
     }
 }
 
-template <int G, int Q>
-__global__ __launch_bounds__(kBlock) void shade_spectral_kernel(SpectralFrame f, int lights_in_lds) {
+template <int G, int Q, LightMode M>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spec_frame_waves(Q)))) void shade_spectral_kernel(SpectralFrame f) {
     extern __shared__ float4 s_light[];
-    if (lights_in_lds) {
+    if constexpr (M == kLightLds) {
         stage_lights(f, s_light);
         __syncthreads();
     }
+    // each wave takes kSpecGroupsPerWave consecutive pixel groups
     const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
-    const int64_t q0 = wave * f.P.pw;
-    if (q0 >= f.P.n_pixels) return;
-    if (lights_in_lds)
-        spectral_group<G, Q, true>(f, q0, f.P.n_pixels, s_light);
-    else
-        spectral_group<G, Q, false>(f, q0, f.P.n_pixels, s_light);
+    const int64_t groups = (f.P.n_pixels + f.P.pw - 1) / f.P.pw;
+    const int64_t g0 = wave * kSpecGroupsPerWave;
+    if (g0 >= groups) return;
+    const int64_t g1 = min(g0 + kSpecGroupsPerWave, groups);
+    const SpecLane<G, Q> L = spec_lane<G, Q>(f.T, f.n, f.nq);
+    spectral_groups<G, Q, M>(f, L, 0, f.P.n_pixels, g0, g1, 1, s_light);
 }
+
+// Occupancy floor for the tile kernel: 6 waves per SIMD for one chunk per
+// lane (80 registers, no spills; the compiler's choice is 5).
+constexpr int spec_tile_waves(int q) { return q <= 1 ? 6 : 1; }
 
 // Persistent launch over a tile table (see the latent form).
 template <int G, int Q>
-__global__ __launch_bounds__(kBlock) void shade_spectral_tiles_kernel(const hc_frame* __restrict__ frames,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spec_tile_waves(Q)))) void shade_spectral_tiles_kernel(const hc_frame* __restrict__ frames,
                                                                       int n_frames,
                                                                       const hc_tile* __restrict__ tiles,
                                                                       const int32_t* __restrict__ n_tiles_dev,
@@ -190,6 +285,7 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_tiles_kernel(const hc_f
     extern __shared__ float4 s_light[];
     const int n_tiles = min(*n_tiles_dev, max_tiles);
     const int wave = wave_in_block();
+    const SpecLane<G, Q> L = spec_lane<G, Q>(T, n, (n + 3) / 4);
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         int64_t begin, end;
         const hc_tile tile = tiles[t];
@@ -208,25 +304,27 @@ __global__ __launch_bounds__(kBlock) void shade_spectral_tiles_kernel(const hc_f
         f.T = T;
         f.xyz = fr.xyz;
         f.inv_spp = 1.0f / static_cast<float>(fr.spp);
-        const bool lds = size_t(f.n_illum) * f.nq * sizeof(float4) <= kLightLdsBytes;
+        const bool lds = light_lds_bytes(f.n_illum, f.nq) <= kLightLdsBytes;
         __syncthreads();
         if (lds) stage_lights(f, s_light);
         __syncthreads();
         const int64_t groups = (end - begin + f.P.pw - 1) / f.P.pw;
-        for (int64_t g = wave; g < groups; g += kWavesPerBlock) {
-            if (lds)
-                spectral_group<G, Q, true>(f, begin + g * f.P.pw, end, s_light);
-            else
-                spectral_group<G, Q, false>(f, begin + g * f.P.pw, end, s_light);
-        }
+        if (lds)
+            spectral_groups<G, Q, kLightLds>(f, L, begin, end, wave, groups, kWavesPerBlock, s_light);
+        else
+            spectral_groups<G, Q, kLightGlobal>(f, L, begin, end, wave, groups, kWavesPerBlock, s_light);
     }
 }
 
 template <int G, int Q>
-hc_status launch_spectral_gq(const SpectralFrame& f, int lights_in_lds, int64_t blocks, size_t lds,
-                             hipStream_t st) {
-    hipLaunchKernelGGL((shade_spectral_kernel<G, Q>), dim3(uint32_t(blocks)), dim3(kBlock), lds, st, f,
-                       lights_in_lds);
+hc_status launch_spectral_gq(const SpectralFrame& f, int64_t blocks, hipStream_t st) {
+    // the light table in LDS if it fits the budget
+    const dim3 grid(static_cast<uint32_t>(blocks)), block(kBlock);
+    const size_t lds = light_lds_bytes(f.n_illum, f.nq);
+    if (lds <= kLightLdsBytes)
+        hipLaunchKernelGGL((shade_spectral_kernel<G, Q, kLightLds>), grid, block, lds, st, f);
+    else
+        hipLaunchKernelGGL((shade_spectral_kernel<G, Q, kLightGlobal>), grid, block, 0, st, f);
     return launch_status("hc_shade_spectral");
 }
 
@@ -256,20 +354,17 @@ hc_status launch_shade_spectral(const hc_paths& P, const hc_spectral_assets& A, 
     f.T = T;
     f.xyz = xyz;
     f.inv_spp = 1.0f / static_cast<float>(P.spp);
-    const size_t lds_need = size_t(A.n_illum) * f.nq * sizeof(float4);
-    const int lights_in_lds = lds_need <= kLightLdsBytes;
-    const size_t lds = lights_in_lds ? lds_need : 0;
-    const int64_t waves = ceil_div(P.n_pixels, f.P.pw);
+    const int64_t waves = ceil_div(ceil_div(P.n_pixels, f.P.pw), kSpecGroupsPerWave);
     const int64_t blocks = ceil_div(waves, kWavesPerBlock);
     if (blocks > 0x7FFFFFFF) {
         set_error("hc_shade_spectral: frame too large for one launch");
         return HC_ESHAPE;
     }
     switch (ceil_div(f.nq, kSpecLanes)) {
-        case 1: return launch_spectral_gq<kSpecLanes, 1>(f, lights_in_lds, blocks, lds, st);
-        case 2: return launch_spectral_gq<kSpecLanes, 2>(f, lights_in_lds, blocks, lds, st);
-        case 3: return launch_spectral_gq<kSpecLanes, 3>(f, lights_in_lds, blocks, lds, st);
-        case 4: return launch_spectral_gq<kSpecLanes, 4>(f, lights_in_lds, blocks, lds, st);
+        case 1: return launch_spectral_gq<kSpecLanes, 1>(f, blocks, st);
+        case 2: return launch_spectral_gq<kSpecLanes, 2>(f, blocks, st);
+        case 3: return launch_spectral_gq<kSpecLanes, 3>(f, blocks, st);
+        case 4: return launch_spectral_gq<kSpecLanes, 4>(f, blocks, st);
         default:
             set_error("hc_shade_spectral: n=%d unsupported", A.n);
             return HC_EUNSUPPORTED;

@@ -182,6 +182,41 @@ def test_large_light_table_read_from_global(ops):
                      REL, FLOOR) <= 1
 
 
+def _padded(a, ld, fill):
+    """numpy (m, n) -> device float32 rows of stride ld, padding set to fill."""
+    a = np.asarray(a, dtype=np.float32)
+    out = np.full((a.shape[0], ld), fill, dtype=np.float32)
+    out[:, :a.shape[1]] = a
+    return torch.from_numpy(out).cuda()
+
+
+# Light counts that put the light table in each place the spectral kernel can
+# read it from: colour-weighted in LDS (3 float4 per light and chunk), plain in
+# LDS, and global memory (LDS budget 16 KiB).
+@pytest.mark.parametrize("n,n_illum", [(31, 8), (31, 60), (31, 600), (81, 5), (81, 40), (81, 300),
+                                       (128, 8), (128, 20), (128, 100), (5, 3)])
+def test_spectral_light_tables_and_nonfinite_padding(ops, n, n_illum):
+    """Row padding past n (reflectance and light rows, strides beyond the
+    padded width) holds NaN and inf; the result must not see it."""
+    spec = synth.PathSpec(n_pixels=1500, spp=8, l_min=0, l_max=5, n_tex=200, n_illum=n_illum,
+                          seed=n * 1000 + n_illum)
+    hdr, pf, vtx = synth.gen_paths(spec)
+    rng = np.random.default_rng(n + n_illum)
+    refl = synth.reflectances(rng, n, 200)
+    illum = synth.illuminant_table(rng, n, n_illum // 2, n_illum - n_illum // 2)
+    T = synth.cmf_matrix(n)
+    ld = 4 * ((n + 3) // 4) + 8
+    P = _paths(ops, hdr, pf, vtx, 8)
+    ref = osh.shade_spectral(hdr, pf, vtx, 8, refl, illum, T)
+    for fill in (float("nan"), float("inf")):
+        xyz = ops.shade_spectral(P, _padded(refl, ld, fill), _padded(illum, ld, fill),
+                                 torch.from_numpy(T).cuda(), n)
+        torch.cuda.synchronize()
+        out = to_np(xyz)
+        assert np.isfinite(out).all()
+        assert xyz_close(out, ref, REL, FLOOR) <= 1.0
+
+
 def test_identity_codec_latent_equals_spectral(ops, cfg0):
     """k = n = 31 (padded to 33) with E = D = I: the latent XYZ equals the
     spectral oracle's XYZ within the tolerance."""
