@@ -502,7 +502,7 @@ def main():
         del P, zimg
         torch.cuda.empty_cache()
         t0 = time.time()
-        serving = bench_serving(dev, count=args.serve_count, E=E.cpu(), D=D.cpu())
+        serving = bench_serving(dev, count=args.serve_count, E=E.cpu(), D=D.cpu(), progress=log)
         log(f"serving measured in {time.time() - t0:.1f} s: " + ", ".join(
             f"{form} {r} fps p50 {v['p50_ms']:.2f} p99 {v['p99_ms']:.2f} ms"
             for form in ("latent", "spectral") for r, v in serving[form].items()))

@@ -599,9 +599,10 @@ def make_assets(n_assets: int = 32, n: int = 31, seed: int = 3):
     return out
 
 
-def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=None, assets=None):
+def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=None, assets=None,
+                  progress=None):
     """p50 / p99 frame latency and throughput of latent and spectral serving of
-    the same request streams."""
+    the same request streams.  progress(str), if given, gets a line per run."""
     import torch
 
     import synth
@@ -626,6 +627,9 @@ def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=
             s = summarize(reqs, wall)
             s["iterations"] = sched.iterations
             res[str(rate)] = s
+            if progress is not None:
+                progress(f"serving {form} {rate} fps: {s['completed']}/{count} requests, "
+                         f"p50 {s['p50_ms']:.2f} ms, p99 {s['p99_ms']:.2f} ms")
             del be, sched
             torch.cuda.empty_cache()   # the next run's stream cannot reuse this pool
         out[form] = res

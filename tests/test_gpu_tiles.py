@@ -1,0 +1,135 @@
+"""Tile-table launches (the serving kernels) against the single-frame calls.
+
+hc_shade_spectral_tiles / hc_shade_latent_tiles / hc_decode_tiles walk a
+device table of frames and pixel-range tiles with a fixed grid.  Each pixel's
+samples are reduced inside one wavefront in the same order as in
+hc_shade_spectral / hc_shade_latent, so the results must be equal bit for bit.
+The cases cover every spectral chunk count (n = 31, 81, 128), light tables in
+LDS and in global memory, latent widths of 1, 2, 3 and 16 blocks, frames of
+1 to 100 samples per pixel, ragged tiles, a tile past its frame's end (clipped)
+and tiles naming no frame (skipped).
+"""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_util import dev_f32, to_np
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(3001, 1), (777, 16), (53, 100)]   # (pixels, spp) of the frames of one launch
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_18741_amd import ops as o
+    return o
+
+
+def _device_bytes(structs):
+    raw = bytes(structs)
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
+
+
+def _tiles(rng, sizes):
+    """Ragged tiles covering each frame, one tile overrunning its frame, two
+    naming no frame; shuffled."""
+    from paper_2602_18741_amd._lib import Tile
+    out = []
+    for f, npx in enumerate(sizes):
+        b = 0
+        while b < npx:
+            e = min(npx, b + int(rng.integers(1, 700)))
+            out.append((f, b, e if e < npx else npx + 50))
+            b = e
+    out += [(len(sizes), 0, 100), (-1, 0, 100)]
+    order = rng.permutation(len(out))
+    arr = (Tile * len(out))()
+    for i, j in enumerate(order):
+        arr[i].frame, arr[i].begin, arr[i].end = out[j]
+    return arr, len(out)
+
+
+def _frames(ops, n_illum, n_tex, seed):
+    out = []
+    for i, (npx, spp) in enumerate(SHAPES):
+        spec = synth.PathSpec(n_pixels=npx, spp=spp, l_min=0, l_max=6, n_tex=n_tex, n_illum=n_illum,
+                              seed=seed + i)
+        out.append(ops.Paths.from_numpy(*synth.gen_paths(spec), spp))
+    return out
+
+
+def _table(paths, tex, lights, images, xyzs):
+    from paper_2602_18741_amd._lib import Frame
+    arr = (Frame * len(paths))()
+    for i, P in enumerate(paths):
+        f = arr[i]
+        f.hdr, f.pix_first, f.vtx = P.hdr.data_ptr(), P.pix_first.data_ptr(), P.vtx.data_ptr()
+        f.n_pixels, f.n_vertices, f.spp = P.n_pixels, P.n_vertices, P.spp
+        f.n_illum, f.tex, f.n_texels, f.ld_tex = lights.shape[0], tex.data_ptr(), tex.shape[0], tex.stride(0)
+        f.lights, f.ld_lights = lights.data_ptr(), lights.stride(0)
+        if images is not None:
+            f.image, f.ld_image = images[i].data_ptr(), images[i].stride(0)
+        f.xyz = xyzs[i].data_ptr()
+    return arr
+
+
+@pytest.mark.parametrize("n,n_illum", [(31, 12), (31, 600), (81, 20), (81, 300), (128, 8), (128, 100)])
+def test_spectral_tiles_equal_single_frame_calls(ops, n, n_illum):
+    from paper_2602_18741_amd._lib import check, load
+    rng = np.random.default_rng(n * 7 + n_illum)
+    refl = dev_f32(synth.reflectances(rng, n, 400))
+    lights = dev_f32(synth.illuminant_table(rng, n, n_illum // 2, n_illum - n_illum // 2))
+    T = torch.from_numpy(synth.cmf_matrix(n)).cuda()
+    paths = _frames(ops, n_illum, 400, seed=n + n_illum)
+    xyzs = [torch.full((P.n_pixels, 3), float("nan"), device="cuda") for P in paths]
+    frames = _device_bytes(_table(paths, refl, lights, None, xyzs))
+    tiles, nt = _tiles(rng, [P.n_pixels for P in paths])
+    d_tiles = _device_bytes(tiles)
+    cnt = torch.tensor([nt], dtype=torch.int32, device="cuda")
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    check(load().hc_shade_spectral_tiles(frames.data_ptr(), len(paths), d_tiles.data_ptr(), cnt.data_ptr(),
+                                         nt, n, T.data_ptr(), 64, st), "hc_shade_spectral_tiles")
+    for P, xyz in zip(paths, xyzs):
+        ref = ops.shade_spectral(P, refl, lights, T, n)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(xyz), to_np(ref))
+
+
+@pytest.mark.parametrize("k,n_illum", [(3, 12), (6, 12), (9, 300), (48, 20)])
+def test_latent_tiles_equal_single_frame_calls(ops, k, n_illum):
+    from paper_2602_18741_amd._lib import check, load
+    n = 31
+    rng = np.random.default_rng(k * 11 + n_illum)
+    E = torch.from_numpy(rng.uniform(size=(k, n)).astype(np.float32)).cuda()
+    D = torch.from_numpy(rng.uniform(size=(n, k)).astype(np.float32)).cuda()
+    T = torch.from_numpy(synth.cmf_matrix(n)).cuda()
+    codes = ops.encode(E, dev_f32(synth.reflectances(rng, n, 400)), n=n)
+    lcodes = ops.encode(E, dev_f32(synth.illuminant_table(rng, n, n_illum // 2, n_illum - n_illum // 2)), n=n)
+    paths = _frames(ops, n_illum, 400, seed=k + n_illum)
+    w = ops.latent_width(k)
+    images = [torch.full((P.n_pixels, w), float("nan"), device="cuda") for P in paths]
+    xyzs = [torch.full((P.n_pixels, 3), float("nan"), device="cuda") for P in paths]
+    frames = _device_bytes(_table(paths, codes, lcodes, images, xyzs))
+    tiles, nt = _tiles(rng, [P.n_pixels for P in paths])
+    d_tiles = _device_bytes(tiles)
+    cnt = torch.tensor([nt], dtype=torch.int32, device="cuda")
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    lib = load()
+    check(lib.hc_shade_latent_tiles(frames.data_ptr(), len(paths), d_tiles.data_ptr(), cnt.data_ptr(), nt,
+                                    k, 64, st), "hc_shade_latent_tiles")
+    check(lib.hc_decode_tiles(frames.data_ptr(), len(paths), d_tiles.data_ptr(), cnt.data_ptr(), nt,
+                              D.data_ptr(), n, k, T.data_ptr(), 64, st), "hc_decode_tiles")
+    for P, img, xyz in zip(paths, images, xyzs):
+        ref_img = ops.shade_latent(P, codes, lcodes, k)
+        ref_xyz = ops.decode_xyz(D, T, ref_img, k)
+        torch.cuda.synchronize()
+        # whole blocked rows: each slot's 4th float is written 0 as well
+        assert np.array_equal(to_np(img), to_np(ref_img))
+        assert np.array_equal(to_np(xyz), to_np(ref_xyz))
