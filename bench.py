@@ -352,12 +352,14 @@ def main():
         log("copied 1 GiB", args.warmup + args.steps, "times")
         return
 
+    from paper_2602_18741_amd.layout import latent_width, line_stride
     stress = args.stress
     wid, k, n = (4, 9, 81) if stress else (1, args.k, 31)
-    # row strides that keep every texel row inside whole 128-byte lines:
-    # 81 samples -> 96 floats (3 lines), 9 channels -> 16 floats (64 B)
-    ld_tex = 96 if stress else 32
-    ld_z = 16 if stress else None
+    # row strides that keep every texel row inside as few 128-byte lines as
+    # its length allows: 31 samples -> 32 floats, 81 -> 96 (3 lines); codes
+    # k = 6 -> 8 floats, k = 9 -> 16 (64 B)
+    ld_tex = line_stride(n)
+    ld_z = line_stride(latent_width(k))
     t_setup = time.time()
     w = synth.workload(wid, k=k, ld_tex=ld_tex)
     spec = w["paths"]
@@ -415,9 +417,8 @@ def main():
     (E, D), _ = codecs["eq8"]
     del pa, pb
 
-    lw = ld_z or ops.latent_width(k)
-    codes = torch.empty(spec.n_tex, lw, device=dev)
-    lcodes = torch.empty(spec.n_illum, lw, device=dev)
+    codes = torch.empty(spec.n_tex, ld_z, device=dev)
+    lcodes = torch.empty(spec.n_illum, ld_z, device=dev)
     zimg = torch.zeros(npx, ops.latent_width(k), device=dev)
     xyz_l = torch.empty(npx, 3, device=dev)
     xyz_s = torch.empty(npx, 3, device=dev)

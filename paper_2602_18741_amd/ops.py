@@ -30,14 +30,7 @@ def _dev(*ts):
             raise ValueError("tensors must live on the GPU")
 
 
-def blocks(k: int) -> int:
-    """Number of RGB-style passes B for a k-channel code (k padded to 3B)."""
-    return (k + 2) // 3
-
-
-def latent_width(k: int) -> int:
-    """Floats per latent row in the blocked RGBx layout."""
-    return 4 * blocks(k)
+from .layout import blocks, latent_width, line_stride  # noqa: E402,F401
 
 
 def to_blocked(z: torch.Tensor, k: int | None = None) -> torch.Tensor:

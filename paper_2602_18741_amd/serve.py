@@ -362,12 +362,13 @@ class GpuBackend:
     # -------------------------------------------------------------- scheduler hooks
     def request_bytes(self, req) -> float:
         paths = req.n_pixels * req.spp * (4 + 8 * req.l_max) + 4 * req.n_pixels
-        out = req.n_pixels * (12 + (16 * self.ops.blocks(self.k) if self.form == "latent" else 0))
+        out = req.n_pixels * (12 + (4 * self.ops.latent_width(self.k) if self.form == "latent" else 0))
         return float(paths + out + 4096)
 
     def _asset_tensor_bytes(self, host):
         texels = host.shape[0]
-        return texels * (16 * self.ops.blocks(self.k) if self.form == "latent" else host.shape[1] * 4)
+        return texels * 4 * (self.ops.line_stride(self.ops.latent_width(self.k)) if self.form == "latent"
+                             else host.shape[1])
 
     def prepare(self, req):
         torch, ops = self.torch, self.ops
@@ -381,7 +382,9 @@ class GpuBackend:
             spectral.record_stream(self.stream)
             if self.form == "latent":
                 with torch.cuda.stream(self.stream):
-                    tex = torch.empty(host.shape[0], ops.latent_width(self.k), device=self.dev)
+                    # line-aligned rows: a code never straddles two 128-byte lines
+                    tex = torch.empty(host.shape[0], ops.line_stride(ops.latent_width(self.k)),
+                                      device=self.dev)
             else:
                 tex = spectral
             self.resident[req.asset] = dict(state="pending", event=ev, spectral=spectral, tex=tex)
@@ -582,9 +585,10 @@ def make_assets(n_assets: int = 32, n: int = 31, seed: int = 3):
     import torch
 
     import synth
+    from .layout import line_stride
     w512 = synth.perlin_weights(3001, 512)
     rng = np.random.default_rng([3, 1, seed])
-    ld = 4 * ((n + 3) // 4)
+    ld = line_stride(n)
     out = []
     for a in range(n_assets):
         side = (512, 1024, 2048)[a % 3]
