@@ -14,8 +14,90 @@ using namespace shade;
 // chunks each ran slower at n = 31: fewer wavefronts fit per SIMD.)
 constexpr int kSpecLanes = 8;
 // Pixel groups per wavefront in a frame launch: the per-lane set-up (colour
-// weights, shuffle sources) is shared by that many groups.
+// weights, chunk offsets, scan constants) is shared by that many groups.
 constexpr int kSpecGroupsPerWave = 8;
+
+// Where a path's light spectrum comes from: global memory, or the light
+// table staged in LDS when it fits the budget.
+enum LightMode { kLightGlobal, kLightLds };
+
+// v plus its value in lane i ^ M (M < 32, inside each 32-lane half):
+// ds_swizzle in bit-mask mode (and 0x1F, or 0, xor M), no address register.
+template <int M>
+__device__ __forceinline__ float xor_add(float v) {
+    static_assert(M > 0 && M < 32, "swizzle reaches within 32 lanes");
+    constexpr int pattern = (M << 10) | 0x1F;
+    return v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
+}
+
+// v plus its value in the lane whose ds_bpermute byte address is addr.
+__device__ __forceinline__ float add_from(float v, int addr) {
+    return v + __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+
+// Sums of x, y and z over each aligned group of `span` lanes (a power of two
+// <= 64), as xor butterflies in the order 1, 2, 4, ...; every lane of the
+// group gets the sums.  The three are interleaved step by step so their
+// shuffles overlap.  KNOWN is a lower bound on span fixed at compile time:
+// the steps below it need no test.
+template <int KNOWN = 1>
+__device__ __forceinline__ void xor_sum3(float& x, float& y, float& z, int span) {
+#define HC_XOR_STEP(M)                                        \
+    if (KNOWN > (M) || span > (M)) {                          \
+        x = xor_add<(M)>(x);                                  \
+        y = xor_add<(M)>(y);                                  \
+        z = xor_add<(M)>(z);                                  \
+    }
+    HC_XOR_STEP(1)
+    HC_XOR_STEP(2)
+    HC_XOR_STEP(4)
+    HC_XOR_STEP(8)
+    HC_XOR_STEP(16)
+#undef HC_XOR_STEP
+    if (span > 32) {
+        const int src = (int(threadIdx.x & (kWave - 1)) ^ 32) << 2;
+        x = add_from(x, src);
+        y = add_from(y, src);
+        z = add_from(z, src);
+    }
+}
+
+// Segmented prefix sum of path lengths over the slots of pixel segments, with
+// the per-lane set-up done once: `seg` slots per segment (a power of two), `G`
+// lanes per slot, the lane in slot j0 of its segment.  The steps are unrolled
+// (at most log2(64 / G)).
+template <int G>
+struct SegScan {
+    static constexpr int kMaxSteps = 6 - __builtin_ctz(unsigned(G));  // log2(64 / G)
+    int src[kMaxSteps];  // ds_bpermute byte address of the lane G << i below
+    int last;            // byte address of the segment's last slot
+    int steps;           // log2(seg)
+    int j0;
+
+    __device__ __forceinline__ SegScan(int lane, int seg, int j0_) : j0(j0_) {
+        steps = __builtin_ctz(unsigned(seg));
+        // (wrapping below lane 0; such a value is used only outside the segment)
+#pragma unroll
+        for (int i = 0; i < kMaxSteps; ++i) src[i] = ((lane - (G << i)) & (kWave - 1)) << 2;
+        const int seg_lanes = seg * G;
+        last = ((lane & ~(seg_lanes - 1)) + seg_lanes - 1) << 2;
+    }
+
+    // Exclusive prefix of len over the slots of the segment; total gets the
+    // segment's sum.
+    __device__ __forceinline__ uint32_t exclusive(uint32_t len, uint32_t& total) const {
+        uint32_t incl = len;
+#pragma unroll
+        for (int i = 0; i < kMaxSteps; ++i) {
+            if (i < steps) {
+                const uint32_t y = uint32_t(__builtin_amdgcn_ds_bpermute(src[i], int(incl)));
+                incl += (j0 >= (1 << i)) ? y : 0u;
+            }
+        }
+        total = uint32_t(__builtin_amdgcn_ds_bpermute(last, int(incl)));
+        return incl - len;
+    }
+};
 
 // A row of ones, as long as the longest spectrum: padding vertex slots read
 // their row from here, so the product needs no select per loaded chunk.
@@ -44,10 +126,6 @@ struct SpectralFrame {
     float inv_spp;
 };
 
-// Where a path's light spectrum comes from: global memory, or the light
-// table staged in LDS when it fits the budget.
-enum LightMode { kLightGlobal, kLightLds };
-
 __device__ __forceinline__ void stage_lights(const SpectralFrame& f, float4* s_light) {
     for (uint32_t i = threadIdx.x; i < f.n_illum * uint32_t(f.nq); i += kBlock) {
         const uint32_t l = i / f.nq, c = i % f.nq;
@@ -61,18 +139,6 @@ __device__ __forceinline__ void stage_lights(const SpectralFrame& f, float4* s_l
 constexpr int spec_frame_waves(int q) { return q <= 1 ? 7 : 1; }
 
 constexpr size_t light_lds_bytes(uint32_t n_illum, int nq) { return size_t(n_illum) * nq * sizeof(float4); }
-
-// Sum of v over lanes i and i ^ M of each 32-lane half (M < 32): ds_swizzle in
-// bit-mask mode (and 0x1F, or 0, xor M) needs no address register.
-template <int M>
-__device__ __forceinline__ float xor_add(float v) {
-    static_assert(M > 0 && M < 32, "swizzle reaches within 32 lanes");
-    constexpr int pattern = (M << 10) | 0x1F;
-    return v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
-}
-__device__ __forceinline__ float add_from(float v, int addr) {
-    return v + __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
-}
 
 // What a lane needs for every path it shades, given only the sample count:
 // G lanes per path, the lane owning float4 chunks c = qq * G + sub.
@@ -117,7 +183,7 @@ __device__ __forceinline__ SpecLane<G, Q> spec_lane(const float* T, int n, int n
 // The calling wave shades the pixel groups g = g_begin, g_begin + g_step, ...
 // below g_end; group g is pixels [q_base + g * pw, ...), cut at q_end.  The
 // light spectra come from global memory or the table s_light staged for mode
-// M.  The lane's shuffle sources are set up once for all groups.
+// M.  The lane's scan sources are set up once for all groups.
 template <int G, int Q, LightMode M>
 __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const SpecLane<G, Q>& L,
                                                 int64_t q_base, int64_t q_end, int64_t g_begin,
@@ -127,19 +193,9 @@ __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const Sp
     const int sub = lane & (G - 1);
     const int slot = lane / G;
     const int seg = P.spp_pad;  // slots per pixel segment, a power of two
-    const int seg_log2 = __builtin_ctz(unsigned(seg));
     const int j0 = slot & (seg - 1);
-    const int pix = slot >> seg_log2;
-
-    // prefix of path lengths over the slots of a pixel segment: source lanes
-    // (byte addresses for ds_bpermute) of the log2(seg) steps, and the lane
-    // of the segment's last slot
-    constexpr int kMaxSteps = 6 - __builtin_ctz(unsigned(G));  // log2(64 / G)
-    int scan_src[kMaxSteps];
-#pragma unroll
-    for (int i = 0; i < kMaxSteps; ++i) scan_src[i] = ((lane - (G << i)) & (kWave - 1)) << 2;
-    const int seg_lanes = seg * G;
-    const int last_src = ((lane & ~(seg_lanes - 1)) + seg_lanes - 1) << 2;
+    const int pix = slot >> __builtin_ctz(unsigned(seg));
+    const SegScan<G> scan(lane, seg, j0);
 
     for (int64_t g = g_begin; g < g_end; g += g_step) {
         const int64_t q = q_base + g * P.pw + pix;
@@ -152,17 +208,8 @@ __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const Sp
             const bool live = pix_ok && j < P.spp;
             const uint32_t h = live ? ldg_u32(P.hdr + (q * P.spp + j)) : 0u;
             const uint32_t len = h >> 24;
-            // segmented inclusive scan of len, then the segment total
-            uint32_t incl = len;
-#pragma unroll
-            for (int i = 0; i < kMaxSteps; ++i) {
-                if (i < seg_log2) {
-                    const uint32_t y = uint32_t(__builtin_amdgcn_ds_bpermute(scan_src[i], int(incl)));
-                    incl += (j0 >= (1 << i)) ? y : 0u;
-                }
-            }
-            const uint32_t total = uint32_t(__builtin_amdgcn_ds_bpermute(last_src, int(incl)));
-            const uint32_t first = next + incl - len;
+            uint32_t total;
+            const uint32_t first = next + scan.exclusive(len, total);
             next += total;
             if (live) {
                 float4 prod[Q];
@@ -230,20 +277,8 @@ __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const Sp
                 az += wprod * sz;
             }
         }
-        // reduce over the G sample lanes, then over the pixel's slots: the
-        // span is G * seg lanes, at least G = 8
-        static_assert(G == 8, "the reduction starts at 8 lanes");
-        ax = xor_add<1>(ax); ay = xor_add<1>(ay); az = xor_add<1>(az);
-        ax = xor_add<2>(ax); ay = xor_add<2>(ay); az = xor_add<2>(az);
-        ax = xor_add<4>(ax); ay = xor_add<4>(ay); az = xor_add<4>(az);
-        if (seg_lanes > 8) { ax = xor_add<8>(ax); ay = xor_add<8>(ay); az = xor_add<8>(az); }
-        if (seg_lanes > 16) { ax = xor_add<16>(ax); ay = xor_add<16>(ay); az = xor_add<16>(az); }
-        if (seg_lanes > 32) {
-            const int src = (lane ^ 32) << 2;
-            ax = add_from(ax, src);
-            ay = add_from(ay, src);
-            az = add_from(az, src);
-        }
+        // reduce over the G sample lanes, then over the pixel's slots
+        xor_sum3<G>(ax, ay, az, G * seg);
         if (pix_ok && sub == 0 && j0 == 0) {
             float* out = f.xyz + q * 3;
             stg_f32(out + 0, ax * f.inv_spp);
