@@ -87,7 +87,8 @@ typedef struct hc_paths {
 
 /* Spectral assets: reflectance rows refl[t*ld + i] (n_texels x n, i < n) and
  * light rows illum[l*ld_illum + i] (n_illum x n).  float32, 16-byte aligned,
- * ld and ld_illum multiples of 4 and >= n; ld < 2^31. */
+ * ld and ld_illum multiples of 4 and >= n; ld < 2^30 (a row stride below
+ * 4 GiB). */
 typedef struct hc_spectral_assets {
     const float* refl;
     int64_t n_texels;
@@ -204,7 +205,7 @@ typedef struct hc_frame {
     int32_t n_illum;
     const float* tex;
     int64_t n_texels;
-    int64_t ld_tex;     /* < 2^31 */
+    int64_t ld_tex;     /* < 2^31 for codes, < 2^30 for spectral rows */
     const float* lights;
     int64_t ld_lights;
     float* image;       /* latent image rows (latent form), stride ld_image */

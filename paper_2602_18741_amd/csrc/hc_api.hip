@@ -114,7 +114,7 @@ hc_status hc_shade_spectral(const hc_paths* paths, const hc_spectral_assets* A, 
     HC_REQUIRE(A->n >= 1 && A->n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, A->n, kMaxN);
     HC_REQUIRE(A->ld >= A->n && A->ld % 4 == 0 && A->ld_illum >= A->n && A->ld_illum % 4 == 0,
                HC_ESHAPE, "%s: ld/ld_illum must be >= n and multiples of 4", fn);
-    HC_REQUIRE(A->ld < (int64_t(1) << 31), HC_ESHAPE, "%s: ld must be < 2^31", fn);
+    HC_REQUIRE(A->ld < (int64_t(1) << 30), HC_ESHAPE, "%s: ld must be < 2^30", fn);
     HC_REQUIRE(A->n_texels >= 1 && A->n_texels < (int64_t(1) << 32), HC_ESHAPE,
                "%s: n_texels outside [1, 2^32)", fn);
     HC_REQUIRE(A->n_illum >= 1 && A->n_illum <= (1 << 24), HC_ESHAPE, "%s: n_illum outside [1, 2^24]",

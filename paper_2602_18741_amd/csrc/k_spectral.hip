@@ -196,6 +196,14 @@ __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const Sp
     const int j0 = slot & (seg - 1);
     const int pix = slot >> __builtin_ctz(unsigned(seg));
     const SegScan<G> scan(lane, seg, j0);
+    // byte addresses of the lane's first chunk in texel row 0 and in the row
+    // of ones, and of its other chunks relative to the first
+    const char* lane_refl = reinterpret_cast<const char*>(f.refl + L.off[0]);
+    const char* lane_ones = reinterpret_cast<const char*>(kOnesRow.v + L.off[0]);
+    const uint32_t row_bytes = uint32_t(f.ld) * 4u;  // ld < 2^30
+    uint32_t dq[Q];
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq) dq[qq] = 4u * (L.off[qq] - L.off[0]);
 
     for (int64_t g = g_begin; g < g_end; g += g_step) {
         const int64_t q = q_base + g * P.pw + pix;
@@ -228,22 +236,25 @@ __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const Sp
 #pragma unroll
                     for (int u = 0; u < U; ++u) rec[u] = ldg_u2(P.vtx + min(jv + u, P.n_vertices - 1u));
                     // rows are loaded unconditionally (no branch per vertex): a
-                    // padding slot reads the row of ones and weight 1
-                    const float* rp[U];
+                    // padding slot reads the row of ones and weight 1.  rp is
+                    // the address of the lane's first chunk: one multiply-add
+                    // from the lane's base (row bytes < 2^32)
+                    const char* rp[U];
                     float wt[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const bool ok = jv + u < end;
                         const uint32_t tex = min(rec[u].x, f.n_tex - 1u);
-                        const float* tp = f.refl + uint64_t(tex) * uint32_t(f.ld);  // ld < 2^31
-                        rp[u] = ok ? tp : kOnesRow.v;
+                        const char* tp = lane_refl + uint64_t(tex) * row_bytes;
+                        rp[u] = ok ? tp : lane_ones;
                         wt[u] = ok ? __uint_as_float(rec[u].y) : 1.f;
                     }
                     float4 row[U][Q];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
 #pragma unroll
-                        for (int qq = 0; qq < Q; ++qq) row[u][qq] = ld4(rp[u] + L.off[qq]);
+                        for (int qq = 0; qq < Q; ++qq)
+                            row[u][qq] = ld4(reinterpret_cast<const float*>(rp[u] + dq[qq]));
                     }
 #pragma unroll
                     for (int u = 0; u < U; ++u) {

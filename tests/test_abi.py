@@ -77,6 +77,11 @@ def test_shade_rejects_bad_records(lib):
     assert s == _lib.HC_ESHAPE and "blocks" in msg
     P = _lib.Paths(0, 4, 0, None, None, None, 0)
     assert lib.hc_shade_latent(C.byref(P), C.byref(L), 0, 2, None, 8, None) == _lib.HC_OK
+    # spectral row strides must stay below 2^30 floats (4 GiB per row)
+    P = _lib.Paths(10, 4, 0, 0x1000, 0x1000, 0x1000, 5)
+    A = _lib.SpectralAssets(0x1000, 1, 31, 0, 1 << 30, 0x1000, 1, 0, 32)
+    s, msg = _err(lib.hc_shade_spectral(C.byref(P), C.byref(A), C.c_void_p(0x1000), C.c_void_p(0x1000), None))
+    assert s == _lib.HC_ESHAPE and "2^30" in msg
 
 
 def test_codec_step_rejects_small_workspace(lib):
