@@ -134,11 +134,31 @@ __device__ __forceinline__ void stage_lights(const SpectralFrame& f, float4* s_l
 }
 
 // Occupancy floor of the frame kernel: 7 waves per SIMD for one chunk per
-// lane (the compiler's choice is 6 for the global-light variant); wider
-// rows keep the compiler's choice.
-constexpr int spec_frame_waves(int q) { return q <= 1 ? 7 : 1; }
+// lane (the compiler's choice is 6 for the global-light variant), 6 for two
+// (80 registers); wider rows keep the compiler's choice.  None spills.
+constexpr int spec_frame_waves(int q) { return q <= 1 ? 7 : (q == 2 ? 6 : 1); }
 
 constexpr size_t light_lds_bytes(uint32_t n_illum, int nq) { return size_t(n_illum) * nq * sizeof(float4); }
+
+// With two or more chunks per lane the colour-matching weights (3 float4 per
+// chunk) would hold 24 or more registers for the whole kernel; they are read
+// from an LDS copy instead, staged once per block at the start of the shared
+// memory (room for n up to 128), the light table after it.
+constexpr bool t_in_lds(int q) { return q >= 2; }
+constexpr int kTLdsFloat4 = 3 * (kMaxN / 4);
+
+__device__ __forceinline__ void stage_T(const float* T, int n, int nq, float4* s_T) {
+    for (int i = threadIdx.x; i < 3 * nq; i += kBlock) {
+        const int ch = i / nq, c = i % nq;
+        float w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * c + e;
+            w[e] = k < n ? ldg_f32(T + ch * n + k) : 0.f;
+        }
+        s_T[i] = make_float4(w[0], w[1], w[2], w[3]);
+    }
+}
 
 // What a lane needs for every path it shades, given only the sample count:
 // G lanes per path, the lane owning float4 chunks c = qq * G + sub.
@@ -152,6 +172,7 @@ struct SpecLane {
 
 template <int G, int Q>
 __device__ __forceinline__ SpecLane<G, Q> spec_lane(const float* T, int n, int nq) {
+    constexpr bool kWithT = !t_in_lds(Q);
     SpecLane<G, Q> L;
     const int sub = threadIdx.x & (G - 1);
 #pragma unroll
@@ -171,7 +192,7 @@ __device__ __forceinline__ SpecLane<G, Q> spec_lane(const float* T, int n, int n
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = 4 * c + e;
-                const float t = ldg_f32(T + ch * n + min(i, n - 1));
+                const float t = kWithT ? ldg_f32(T + ch * n + min(i, n - 1)) : 0.f;
                 w[e] = (i < n) ? t : 0.f;
             }
             L.Tr[ch][qq] = make_float4(w[0], w[1], w[2], w[3]);
@@ -187,7 +208,8 @@ __device__ __forceinline__ SpecLane<G, Q> spec_lane(const float* T, int n, int n
 template <int G, int Q, LightMode M>
 __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const SpecLane<G, Q>& L,
                                                 int64_t q_base, int64_t q_end, int64_t g_begin,
-                                                int64_t g_end, int64_t g_step, const float4* s_light) {
+                                                int64_t g_end, int64_t g_step, const float4* s_light,
+                                                const float4* s_T) {
     const PathView& P = f.P;
     const int lane = threadIdx.x & (kWave - 1);
     const int sub = lane & (G - 1);
@@ -276,10 +298,19 @@ __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const Sp
                         const float s1 = L.keep[qq][1] ? m.y : 0.f;
                         const float s2 = L.keep[qq][2] ? m.z : 0.f;
                         const float s3 = L.keep[qq][3] ? m.w : 0.f;
-                        const float4* Tr = L.Tr[0] + qq;
-                        sx += Tr[0].x * s0 + Tr[0].y * s1 + Tr[0].z * s2 + Tr[0].w * s3;
-                        sy += Tr[Q].x * s0 + Tr[Q].y * s1 + Tr[Q].z * s2 + Tr[Q].w * s3;
-                        sz += Tr[2 * Q].x * s0 + Tr[2 * Q].y * s1 + Tr[2 * Q].z * s2 + Tr[2 * Q].w * s3;
+                        float4 tx, ty, tz;
+                        if constexpr (t_in_lds(Q)) {
+                            tx = s_T[c];
+                            ty = s_T[f.nq + c];
+                            tz = s_T[2 * f.nq + c];
+                        } else {
+                            tx = L.Tr[0][qq];
+                            ty = L.Tr[1][qq];
+                            tz = L.Tr[2][qq];
+                        }
+                        sx += tx.x * s0 + tx.y * s1 + tx.z * s2 + tx.w * s3;
+                        sy += ty.x * s0 + ty.y * s1 + ty.z * s2 + ty.w * s3;
+                        sz += tz.x * s0 + tz.y * s1 + tz.z * s2 + tz.w * s3;
                     }
                 }
                 // the vertex weights multiply the whole spectrum
@@ -301,11 +332,12 @@ __device__ __forceinline__ void spectral_groups(const SpectralFrame& f, const Sp
 
 template <int G, int Q, LightMode M>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spec_frame_waves(Q)))) void shade_spectral_kernel(SpectralFrame f) {
-    extern __shared__ float4 s_light[];
-    if constexpr (M == kLightLds) {
-        stage_lights(f, s_light);
-        __syncthreads();
-    }
+    extern __shared__ float4 s_mem[];
+    float4* s_T = s_mem;
+    float4* s_light = s_mem + (t_in_lds(Q) ? kTLdsFloat4 : 0);
+    if constexpr (t_in_lds(Q)) stage_T(f.T, f.n, f.nq, s_T);
+    if constexpr (M == kLightLds) stage_lights(f, s_light);
+    if constexpr (t_in_lds(Q) || M == kLightLds) __syncthreads();
     // each wave takes kSpecGroupsPerWave consecutive pixel groups
     const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
     const int64_t groups = (f.P.n_pixels + f.P.pw - 1) / f.P.pw;
@@ -313,7 +345,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spec_fra
     if (g0 >= groups) return;
     const int64_t g1 = min(g0 + kSpecGroupsPerWave, groups);
     const SpecLane<G, Q> L = spec_lane<G, Q>(f.T, f.n, f.nq);
-    spectral_groups<G, Q, M>(f, L, 0, f.P.n_pixels, g0, g1, 1, s_light);
+    spectral_groups<G, Q, M>(f, L, 0, f.P.n_pixels, g0, g1, 1, s_light, s_T);
 }
 
 // Occupancy floor for the tile kernel: 6 waves per SIMD for one chunk per
@@ -328,10 +360,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spec_til
                                                                       const int32_t* __restrict__ n_tiles_dev,
                                                                       int max_tiles, int n,
                                                                       const float* __restrict__ T) {
-    extern __shared__ float4 s_light[];
+    extern __shared__ float4 s_mem[];
+    float4* s_T = s_mem;
+    float4* s_light = s_mem + (t_in_lds(Q) ? kTLdsFloat4 : 0);
     const int n_tiles = min(*n_tiles_dev, max_tiles);
     const int wave = wave_in_block();
     const SpecLane<G, Q> L = spec_lane<G, Q>(T, n, (n + 3) / 4);
+    // read after the first tile's barriers below
+    if constexpr (t_in_lds(Q)) stage_T(T, n, (n + 3) / 4, s_T);
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         int64_t begin, end;
         const hc_tile tile = tiles[t];
@@ -356,9 +392,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spec_til
         __syncthreads();
         const int64_t groups = (end - begin + f.P.pw - 1) / f.P.pw;
         if (lds)
-            spectral_groups<G, Q, kLightLds>(f, L, begin, end, wave, groups, kWavesPerBlock, s_light);
+            spectral_groups<G, Q, kLightLds>(f, L, begin, end, wave, groups, kWavesPerBlock, s_light, s_T);
         else
-            spectral_groups<G, Q, kLightGlobal>(f, L, begin, end, wave, groups, kWavesPerBlock, s_light);
+            spectral_groups<G, Q, kLightGlobal>(f, L, begin, end, wave, groups, kWavesPerBlock, s_light, s_T);
     }
 }
 
@@ -366,11 +402,12 @@ template <int G, int Q>
 hc_status launch_spectral_gq(const SpectralFrame& f, int64_t blocks, hipStream_t st) {
     // the light table in LDS if it fits the budget
     const dim3 grid(static_cast<uint32_t>(blocks)), block(kBlock);
-    const size_t lds = light_lds_bytes(f.n_illum, f.nq);
-    if (lds <= kLightLdsBytes)
-        hipLaunchKernelGGL((shade_spectral_kernel<G, Q, kLightLds>), grid, block, lds, st, f);
+    const size_t lights = light_lds_bytes(f.n_illum, f.nq);
+    const size_t t_bytes = t_in_lds(Q) ? kTLdsFloat4 * sizeof(float4) : 0;
+    if (lights <= kLightLdsBytes)
+        hipLaunchKernelGGL((shade_spectral_kernel<G, Q, kLightLds>), grid, block, t_bytes + lights, st, f);
     else
-        hipLaunchKernelGGL((shade_spectral_kernel<G, Q, kLightGlobal>), grid, block, 0, st, f);
+        hipLaunchKernelGGL((shade_spectral_kernel<G, Q, kLightGlobal>), grid, block, t_bytes, st, f);
     return launch_status("hc_shade_spectral");
 }
 
@@ -378,8 +415,9 @@ template <int G, int Q>
 hc_status launch_spectral_tiles_gq(const hc_frame* frames, int n_frames, const hc_tile* tiles,
                                    const int32_t* n_tiles, int max_tiles, int n, const float* T, int grid,
                                    hipStream_t st) {
-    hipLaunchKernelGGL((shade_spectral_tiles_kernel<G, Q>), dim3(grid), dim3(kBlock), kLightLdsBytes, st,
-                       frames, n_frames, tiles, n_tiles, max_tiles, n, T);
+    const size_t t_bytes = t_in_lds(Q) ? kTLdsFloat4 * sizeof(float4) : 0;
+    hipLaunchKernelGGL((shade_spectral_tiles_kernel<G, Q>), dim3(grid), dim3(kBlock), t_bytes + kLightLdsBytes,
+                       st, frames, n_frames, tiles, n_tiles, max_tiles, n, T);
     return launch_status("hc_shade_spectral_tiles");
 }
 

@@ -78,6 +78,25 @@ def test_upsample_matches_oracle_within_derived_bound(ops, precision, k, m):
     assert (z[:, cols] == 0).all()
 
 
+@pytest.mark.parametrize("precision", ["f16", "f32"])
+def test_upsample_full_texture_sampled_rows(ops, precision):
+    """The 4096^2-texel RGBA texture of the throughput measurement, in the
+    same launch: 8192 sampled rows (and the first and last) against the
+    oracle within the derived bound."""
+    k, side = 6, 4096
+    net = _net(k, seed=11)
+    rng = np.random.default_rng(12)
+    rgba = rng.uniform(0, 1, (side * side, 4)).astype(np.float32)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()  # noqa: E731
+    out = torch.empty(side * side, 8, device="cuda")
+    ops.upsample({key: t(v) for key, v in net.items()}, t(rgba), k, precision=precision, out=out)
+    rows = np.concatenate([[0, side * side - 1], rng.choice(side * side, 8192, replace=False)])
+    z = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+    rgb = rgba[rows, :3]
+    bound = _bound(net, rgb, U16 if precision == "f16" else 0.0)
+    assert (np.abs(_blocked_to_k(z, k).astype(np.float64) - ou.upsample(net, rgb)) <= bound).all()
+
+
 def test_upsample_strided_input_and_wide_output(ops):
     """rgb rows with stride 4 (RGBA) and an output stride wider than needed."""
     k, m = 6, 1000
