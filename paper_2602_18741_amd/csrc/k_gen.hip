@@ -147,17 +147,48 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(uint32_t* counts, 
     }
 }
 
-// lane per path; a path's first record is its pixel's first record plus the
-// lengths of the pixel's earlier paths (exclusive scan over the pixel's lanes)
+// One vertex record of path p: texel and weight from the vertex's own draw.
+__device__ __forceinline__ uint2 vertex_record(const GenArgs& g, uint64_t p, uint32_t v) {
+    const uint64_t rr = rand64(g.key_vtx, p * 256u + v);
+    const uint32_t texel = range32(rr, g.n_tex);
+    const float w = float(uint32_t(rr >> 40)) * (1.0f / 16777216.0f);
+    return make_uint2(texel, __float_as_uint(w));
+}
+
+// Vertex records the flat path of a round may hold per wavefront (one byte
+// of lane id each in LDS); rounds with more take the lane-per-path path.
+constexpr int kOwnerCap = 2048;
+
+// LDS written by other lanes of the same wavefront is read below: wait for
+// the LDS operations in flight (lgkmcnt 0, other counters untouched) and keep
+// the compiler from moving memory operations across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
+// A round's paths (one per lane) own consecutive record ranges: a path's
+// first record is its pixel's first record plus the lengths of the pixel's
+// earlier paths (exclusive scan over the pixel's lanes), and the pixels of a
+// wavefront follow each other.  Records are made lane-per-record over that
+// flat range, so the stores of a wavefront are contiguous: each lane marks
+// its records with its lane id in LDS, then lane i makes records i, i + 64, ...
 __global__ __launch_bounds__(kThreads) void gen_vertices_kernel(GenArgs g, Seg s, const uint32_t* pix_first,
                                                                 uint32_t* vtx, uint64_t n_vertices) {
+    __shared__ uint8_t s_owner[kThreads / kWave][kOwnerCap];
+    __shared__ uint32_t s_off[kThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
     const int64_t wave = (int64_t(blockIdx.x) * kThreads + threadIdx.x) / kWave;
     if (wave * s.pw >= g.n_pixels) return;  // whole wavefront
-    const int j0 = lane % s.seg;
-    const int64_t q = wave * s.pw + lane / s.seg;
+    const int seg_log2 = __builtin_ctz(unsigned(s.seg));
+    const int j0 = lane & (s.seg - 1);
+    const int64_t q = wave * s.pw + (lane >> seg_log2);
     const bool pix_ok = q < g.n_pixels;
-    const int last = (lane / s.seg) * s.seg + s.seg - 1;  // the segment's last lane
+    const int last = (lane & ~(s.seg - 1)) + s.seg - 1;  // the segment's last lane
+    uint2* out = reinterpret_cast<uint2*>(vtx);
     uint64_t next = pix_ok ? pix_first[q] : 0;
     for (int r = 0; r < s.rounds; ++r) {
         const int j = j0 + r * s.seg;
@@ -172,13 +203,32 @@ __global__ __launch_bounds__(kThreads) void gen_vertices_kernel(GenArgs g, Seg s
         const uint32_t total = __shfl(incl, last, kWave);
         const uint64_t first = next + (incl - len);
         next += total;
-        for (uint32_t v = 0; v < len; ++v) {
-            const uint64_t jv = first + v;
-            if (jv >= n_vertices) break;
-            const uint64_t rr = rand64(g.key_vtx, p * 256u + v);
-            const uint32_t texel = range32(rr, g.n_tex);
-            const float w = float(uint32_t(rr >> 40)) * (1.0f / 16777216.0f);
-            reinterpret_cast<uint2*>(vtx)[jv] = make_uint2(texel, __float_as_uint(w));
+        // the round's flat range starts at lane 0's first record (lane 0 is
+        // always a live path) and ends at the largest end over the lanes
+        const uint64_t base = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(first >> 32))) << 32) |
+                              __builtin_amdgcn_readfirstlane(uint32_t(first));
+        const uint32_t off = pix_ok ? uint32_t(first - base) : 0u;  // past the frame: no records
+        uint32_t span = off + len;
+        for (int m = 1; m < kWave; m <<= 1) span = max(span, uint32_t(__shfl_xor(int(span), m, kWave)));
+        if (span <= uint32_t(kOwnerCap)) {
+            s_off[wv][lane] = off;
+            for (uint32_t v = 0; v < len; ++v) s_owner[wv][off + v] = uint8_t(lane);
+            wave_lds_sync();
+            for (uint32_t i = lane; i < span; i += kWave) {
+                const int pl = s_owner[wv][i];
+                const uint32_t v = i - s_off[wv][pl];
+                const uint64_t pq = uint64_t(wave * s.pw + (pl >> seg_log2));
+                const uint64_t pp = pq * g.spp + ((pl & (s.seg - 1)) + r * s.seg);
+                const uint64_t jv = base + i;
+                if (jv < n_vertices) out[jv] = vertex_record(g, pp, v);
+            }
+            wave_lds_sync();  // the next round overwrites the maps
+        } else {
+            for (uint32_t v = 0; v < len; ++v) {
+                const uint64_t jv = first + v;
+                if (jv >= n_vertices) break;
+                out[jv] = vertex_record(g, p, v);
+            }
         }
     }
 }

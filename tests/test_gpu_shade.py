@@ -287,8 +287,11 @@ def test_malformed_records_stay_in_bounds(ops, cfg0):
     assert torch.isfinite(xyz).all() and torch.isfinite(z).all()
 
 
+# The last three put more records in a wavefront's round than its LDS map
+# holds (2048) in some or all rounds, so both ways of making records run.
 @pytest.mark.parametrize("n_pixels,spp,l_min,l_max", [(777, 16, 1, 8), (1000, 1, 1, 4), (333, 3, 0, 2),
-                                                      (129, 64, 1, 8), (65, 100, 0, 5), (40, 130, 2, 2)])
+                                                      (129, 64, 1, 8), (65, 100, 0, 5), (40, 130, 2, 2),
+                                                      (50, 64, 30, 60), (300, 8, 20, 40), (90, 130, 0, 40)])
 def test_device_generator_matches_synth(ops, n_pixels, spp, l_min, l_max):
     spec = synth.PathSpec(n_pixels=n_pixels, spp=spp, l_min=l_min, l_max=l_max, n_tex=1 << 20,
                           n_illum=256, seed=77 + spp)
