@@ -155,6 +155,15 @@ __device__ __forceinline__ uint2 vertex_record(const GenArgs& g, uint64_t p, uin
     return make_uint2(texel, __float_as_uint(w));
 }
 
+// Lane 0's value of a 64-bit integer.  readfirstlane returns a signed int:
+// each half goes through uint32_t before widening, so a low half of 2^31 or
+// more is not sign-extended into the high half.
+__device__ __forceinline__ uint64_t first_lane_u64(uint64_t v) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
+    return (uint64_t(hi) << 32) | lo;
+}
+
 // Vertex records the flat path of a round may hold per wavefront (one byte
 // of lane id each in LDS); rounds with more take the lane-per-path path.
 constexpr int kOwnerCap = 2048;
@@ -205,8 +214,7 @@ __global__ __launch_bounds__(kThreads) void gen_vertices_kernel(GenArgs g, Seg s
         next += total;
         // the round's flat range starts at lane 0's first record (lane 0 is
         // always a live path) and ends at the largest end over the lanes
-        const uint64_t base = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(first >> 32))) << 32) |
-                              __builtin_amdgcn_readfirstlane(uint32_t(first));
+        const uint64_t base = first_lane_u64(first);
         const uint32_t off = pix_ok ? uint32_t(first - base) : 0u;  // past the frame: no records
         uint32_t span = off + len;
         for (int m = 1; m < kWave; m <<= 1) span = max(span, uint32_t(__shfl_xor(int(span), m, kWave)));

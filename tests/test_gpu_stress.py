@@ -32,6 +32,18 @@ def test_stress_frame_sampled_pixels():
     xyz_l = ops.decode_xyz(D, T, ops.shade_latent(P, codes, lc, k), k)
     torch.cuda.synchronize()
     xs, xl = xyz_s.cpu().numpy(), xyz_l.cpu().numpy()
+    # the device records of sampled pixels, among them the frame's last ones
+    # (record indices past 2^31), equal the host generator's
+    gpix = np.concatenate([np.sort(np.random.default_rng(5).choice(spec.n_pixels - 256, 256, replace=False)),
+                           np.arange(spec.n_pixels - 256, spec.n_pixels)])
+    gh, gpf, gv = synth.records_of_pixels(spec, gpix)
+    pf_dev = P.pix_first[torch.from_numpy(gpix).cuda()].cpu().numpy().view(np.uint32).astype(np.int64)
+    assert pf_dev[-1] > 2 ** 31
+    counts = (gh >> 24).astype(np.int64).reshape(-1, spec.spp).sum(axis=1)
+    rows = np.concatenate([np.arange(f, f + c) for f, c in zip(pf_dev, counts)])
+    hdr_rows = (gpix[:, None] * spec.spp + np.arange(spec.spp)[None, :]).ravel()
+    assert np.array_equal(P.hdr[torch.from_numpy(hdr_rows).cuda()].cpu().numpy().view(np.uint32), gh)
+    assert np.array_equal(P.vtx[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint32), gv)
     del P, refl, codes, xyz_s, xyz_l
     torch.cuda.empty_cache()
     pix = np.sort(np.random.default_rng(4).choice(spec.n_pixels, 4096, replace=False))
