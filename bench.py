@@ -545,6 +545,13 @@ def main():
         "multibounce": bounce,
         "upsample": up,
         "serving": serving,
+        "env": {"device": torch.cuda.get_device_name(dev),
+                "arch": getattr(torch.cuda.get_device_properties(dev), "gcnArchName", None),
+                "hip": torch.version.hip,
+                "torch": torch.__version__, "host_cores": os.cpu_count(),
+                "seeds": {"paths": spec.seed, "texture": "perlin 1001 / 4001 (workloads 1 / 4)",
+                          "codec_init": [2, 3]},
+                "row_strides_floats": {"spectral": ld_tex, "codes": ld_z}},
     }
     print(json.dumps(out), flush=True)
 

@@ -270,6 +270,30 @@ class Scheduler:
 
 # ------------------------------------------------------------------ GPU backend
 
+class _Range:
+    """A named range on the host timeline (roctx through torch.cuda.nvtx) for
+    profiler marker traces; does nothing when torch has no marker support."""
+
+    def __init__(self, torch, name: str):
+        nvtx = getattr(torch.cuda, "nvtx", None)
+        self.push = getattr(nvtx, "range_push", None)
+        self.pop = getattr(nvtx, "range_pop", None)
+        self.name = name
+
+    def __enter__(self):
+        if self.push is not None:
+            try:
+                self.push(self.name)
+            except RuntimeError:
+                self.push = self.pop = None
+        return self
+
+    def __exit__(self, *exc):
+        if self.pop is not None:
+            self.pop()
+        return False
+
+
 class GpuBackend:
     """Executes plans with the table-driven libhc launches, one captured
     graph per form.  form: "latent" (encode -> shade -> decode) or
@@ -371,6 +395,10 @@ class GpuBackend:
                              else host.shape[1])
 
     def prepare(self, req):
+        with _Range(self.torch, f"prepare {req.width}x{req.height}x{req.spp}"):
+            self._prepare(req)
+
+    def _prepare(self, req):
         torch, ops = self.torch, self.ops
         if req.asset not in self.resident:
             self._make_room()
@@ -444,6 +472,10 @@ class GpuBackend:
                 return  # everything resident is in use; go over budget rather than stall
 
     def launch(self, plan):
+        with _Range(self.torch, "launch iteration"):
+            return self._launch(plan)
+
+    def _launch(self, plan):
         torch = self.torch
         h = self.h_tables[self.flip]
         if self.h_events[self.flip] is not None:
