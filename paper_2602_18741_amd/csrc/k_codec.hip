@@ -457,15 +457,22 @@ __global__ __launch_bounds__(kThreads) void codec_finish_kernel(FinishArgs<F> a)
     const int e = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
     if (e > 2 * kn) return;
     const int64_t stride = 2 * kn + 1;
-    // four interleaved partial sums per lane keep four row loads in flight
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    int r = lane;
-    for (; r + 3 * kWave < a.rows; r += 4 * kWave) {
+    // eight interleaved partial sums per lane keep eight row loads in flight
+    // (the rows of one element are a column: every load is its own line)
+    constexpr int kIlp = 8;
+    double acc[kIlp];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += a.part[int64_t(r + u * kWave) * stride + e];
+    for (int u = 0; u < kIlp; ++u) acc[u] = 0.0;
+    int r = lane;
+    for (; r + (kIlp - 1) * kWave < a.rows; r += kIlp * kWave) {
+        double v[kIlp];
+#pragma unroll
+        for (int u = 0; u < kIlp; ++u) v[u] = a.part[int64_t(r + u * kWave) * stride + e];
+#pragma unroll
+        for (int u = 0; u < kIlp; ++u) acc[u] += v[u];
     }
     for (; r < a.rows; r += kWave) acc[0] += a.part[int64_t(r) * stride + e];
-    double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     for (int m = kWave / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, kWave);
     if (lane != 0) return;
     if (e == 2 * kn) {
