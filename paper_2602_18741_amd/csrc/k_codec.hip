@@ -1,10 +1,12 @@
 // Codec fitting: loss, hand-written gradient and Adam for the non-negative
 // linear codec E = softplus(Wt_E), D = softplus(Wt_D).
 //
-// Three kernels per step, all deterministic (fixed summation orders, no
-// floating-point atomics):
+// Up to three kernels per step, all deterministic (fixed summation orders,
+// no floating-point atomics):
 //   1. weights : E, D = softplus_beta(Wt) into the workspace; bumps the Adam
-//                step counter.
+//                step counter.  Only when E and D do not fit the partials
+//                kernel's LDS; otherwise that kernel stages softplus(Wt)
+//                itself and its block 0 bumps the counter.
 //   2. partials: each workgroup takes tiles of TP pairs; `lpp` lanes per pair
 //                compute u = E a, v = E b, h = u*v, the residuals
 //                r_a = D u - a, r_b = D v - b, r_h = D h - a*b, and the
@@ -93,10 +95,33 @@ struct PartialArgs {
     int64_t N, n_tiles;
     double* part;  // gridDim.x rows of 2kn + 1
     int ed_in_lds;
+    // with E and D staged in LDS the kernel makes them itself from the raw
+    // parameters (softplus), and block 0 bumps the Adam step counter: the
+    // weights kernel is then not launched
+    const F* we;
+    const F* wd;
+    F beta;
+    int64_t* step;
+    int64_t* ws_step;
     // Eq. 8 objective
     const F* T;  // 3 x n
     double w_e2e, w_rec, w_code, w_col, eps;
 };
+
+// E = softplus(Wt_E) and D = softplus(Wt_D) into LDS (the values the weights
+// kernel would write), and the step counter bump.
+template <typename F>
+__device__ __forceinline__ void stage_weights(const PartialArgs<F>& a, F* sm, int kn) {
+    for (int i = threadIdx.x; i < kn; i += kThreads) {
+        sm[i] = softplus(a.we[i], a.beta);
+        sm[kn + i] = softplus(a.wd[i], a.beta);
+    }
+    if (a.step && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t t = *a.step + 1;
+        *a.ws_step = t;
+        *a.step = t;
+    }
+}
 
 template <typename F>
 __global__ __launch_bounds__(kThreads) void codec_partials_kernel(PartialArgs<F> a) {
@@ -109,10 +134,7 @@ __global__ __launch_bounds__(kThreads) void codec_partials_kernel(PartialArgs<F>
     const F* Dp = a.D;
     F* base = sm;
     if (a.ed_in_lds) {
-        for (int i = tid; i < kn; i += kThreads) {
-            sm[i] = a.E[i];
-            sm[kn + i] = a.D[i];
-        }
+        stage_weights(a, sm, kn);
         Ep = sm;
         Dp = sm + kn;
         base = sm + 2 * kn;
@@ -255,10 +277,7 @@ __global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArg
     const F* Dp = a.D;
     F* base = sm;
     if (a.ed_in_lds) {
-        for (int i = tid; i < kn; i += kThreads) {
-            sm[i] = a.E[i];
-            sm[kn + i] = a.D[i];
-        }
+        stage_weights(a, sm, kn);
         Ep = sm;
         Dp = sm + kn;
         base = sm + 2 * kn;
@@ -557,13 +576,17 @@ hc_status run(const hc_codec_args& a) {
     const bool eq8 = a.objective == HC_CODEC_EQ8;
     const Plan pl = plan(k, n, a.N, sizeof(F), a.objective);
     Workspace ws = carve(a.workspace, k, n, pl.grid, sizeof(F));
-    const int g0 = int(ceil_div(kn, kThreads));
-    hipLaunchKernelGGL(codec_weights_kernel<F>, dim3(g0), dim3(kThreads), 0, st,
-                       static_cast<const F*>(a.Wt_E), static_cast<const F*>(a.Wt_D), kn,
-                       F(a.beta), static_cast<F*>(ws.E), static_cast<F*>(ws.D),
-                       a.adam ? a.adam->step : nullptr, ws.step);
-    hc_status s = launch_status("hc_codec_step");
-    if (s != HC_OK) return s;
+    int64_t* adam_step = a.adam ? a.adam->step : nullptr;
+    hc_status s = HC_OK;
+    if (!pl.ed_in_lds) {
+        // the partials kernel reads E and D from the workspace
+        const int g0 = int(ceil_div(kn, kThreads));
+        hipLaunchKernelGGL(codec_weights_kernel<F>, dim3(g0), dim3(kThreads), 0, st,
+                           static_cast<const F*>(a.Wt_E), static_cast<const F*>(a.Wt_D), kn,
+                           F(a.beta), static_cast<F*>(ws.E), static_cast<F*>(ws.D), adam_step, ws.step);
+        s = launch_status("hc_codec_step");
+        if (s != HC_OK) return s;
+    }
 
     PartialArgs<F> p;
     p.k = k;
@@ -586,6 +609,11 @@ hc_status run(const hc_codec_args& a) {
     p.n_tiles = pl.n_tiles;
     p.part = ws.part;
     p.ed_in_lds = pl.ed_in_lds;
+    p.we = static_cast<const F*>(a.Wt_E);
+    p.wd = static_cast<const F*>(a.Wt_D);
+    p.beta = F(a.beta);
+    p.step = pl.ed_in_lds ? adam_step : nullptr;
+    p.ws_step = ws.step;
     p.T = static_cast<const F*>(a.T);
     p.w_e2e = a.w_e2e;
     p.w_rec = a.w_rec;
