@@ -188,7 +188,9 @@ hc_status hc_check_paths(const hc_paths* paths, int64_t n_texels, int32_t n_illu
  * output.  A tile names a frame and a pixel range [begin, end).  The tables
  * and the tile / job counts live in device memory, so a captured HIP graph
  * can replay the same launches with new contents; each launch runs a fixed
- * grid of `grid` workgroups that walk the table.  Tile entries whose frame
+ * grid of `grid` workgroups that walk the table (grid <= 65536; grid <= 0
+ * lets the library take twice the number of the kernel's workgroups the
+ * device holds at once).  Tile entries whose frame
  * index is out of [0, n_frames) are skipped and pixel ranges are clipped to
  * the frame; the frame entries themselves must satisfy the preconditions of
  * hc_shade_latent / hc_shade_spectral (they are not checked on the device).

@@ -184,7 +184,7 @@ static hc_status check_tables(const void* frames, int32_t n_frames, const void* 
                "%s: tables must be 8-byte aligned", fn);
     HC_REQUIRE(n_frames >= 1 && max_tiles >= 1, HC_ESHAPE, "%s: n_frames and max_tiles must be >= 1",
                fn);
-    HC_REQUIRE(grid >= 1 && grid <= 65536, HC_ESHAPE, "%s: grid must be in [1, 65536]", fn);
+    HC_REQUIRE(grid <= 65536, HC_ESHAPE, "%s: grid must be <= 65536 (<= 0: chosen by the library)", fn);
     return HC_OK;
 }
 
@@ -234,7 +234,7 @@ hc_status hc_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int32
     HC_REQUIRE(aligned8(jobs) && aligned4(n_jobs) && aligned4(E), HC_EALIGN, "%s: misaligned table",
                fn);
     HC_REQUIRE(k >= 1 && k <= kMaxK && n >= 1 && n <= kMaxN, HC_ESHAPE, "%s: bad k or n", fn);
-    HC_REQUIRE(max_jobs >= 1 && grid >= 1 && grid <= 65536, HC_ESHAPE, "%s: bad max_jobs or grid", fn);
+    HC_REQUIRE(max_jobs >= 1 && grid <= 65536, HC_ESHAPE, "%s: bad max_jobs or grid", fn);
     return launch_encode_jobs(jobs, n_jobs, max_jobs, E, k, n, grid, as_stream(stream));
 }
 

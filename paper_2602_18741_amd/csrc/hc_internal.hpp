@@ -19,6 +19,26 @@ void clear_error();
 // Checks the launch that was just enqueued.
 hc_status launch_status(const char* what);
 
+// Grid of a persistent tile-table launch that the caller left to the library
+// (grid <= 0): twice the number of workgroups of `kernel` (`threads` threads,
+// `lds` bytes of dynamic LDS) the current device holds at once, so the grid
+// is a whole number of rounds of resident workgroups and none of a partly
+// filled second round finishes after the rest.  A grid > 0 is kept.  Returns
+// 0 (with the error set) if the device cannot be queried.
+template <typename K>
+int tile_grid(int grid, K kernel, int threads, size_t lds, const char* what) {
+    if (grid > 0) return grid;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+        cus <= 0 || per_cu <= 0) {
+        set_error("%s: occupancy query failed", what);
+        return 0;
+    }
+    return 2 * cus * per_cu;
+}
+
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 inline bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 inline bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }

@@ -272,10 +272,13 @@ hc_status launch_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, i
     const size_t lds = (size_t(rows) * (4 * nq + 1) + size_t(3 * nb) * n) * sizeof(float);
     switch (nb) {
 #define HC_ENCJ(NB)                                                                                  \
-    case NB:                                                                                         \
-        hipLaunchKernelGGL(encode_jobs_kernel<NB>, dim3(grid), dim3(kThreads), lds, st, jobs, n_jobs, \
+    case NB: {                                                                                       \
+        const int g = tile_grid(grid, encode_jobs_kernel<NB>, kThreads, lds, "hc_encode_jobs");      \
+        if (g <= 0) return HC_EDEVICE;                                                               \
+        hipLaunchKernelGGL(encode_jobs_kernel<NB>, dim3(g), dim3(kThreads), lds, st, jobs, n_jobs,   \
                            max_jobs, E, k, n, rows);                                                 \
-        break;
+        break;                                                                                       \
+    }
         HC_NB_CASES(HC_ENCJ)
 #undef HC_ENCJ
         default:
@@ -290,10 +293,13 @@ hc_status launch_decode_tiles(const hc_frame* frames, int n_frames, const hc_til
                               const float* T, int grid, hipStream_t st) {
     switch ((k + 2) / 3) {
 #define HC_DECT(NB)                                                                                  \
-    case NB:                                                                                         \
-        hipLaunchKernelGGL(decode_tiles_kernel<NB>, dim3(grid), dim3(kThreads), 0, st, frames, n_frames, \
+    case NB: {                                                                                       \
+        const int g = tile_grid(grid, decode_tiles_kernel<NB>, kThreads, 0, "hc_decode_tiles");      \
+        if (g <= 0) return HC_EDEVICE;                                                               \
+        hipLaunchKernelGGL(decode_tiles_kernel<NB>, dim3(g), dim3(kThreads), 0, st, frames, n_frames, \
                            tiles, n_tiles, max_tiles, D, n, k, T);                                   \
-        break;
+        break;                                                                                       \
+    }
         HC_NB_CASES(HC_DECT)
 #undef HC_DECT
         default:

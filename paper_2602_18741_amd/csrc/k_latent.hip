@@ -247,11 +247,15 @@ hc_status launch_shade_latent_tiles(const hc_frame* frames, int n_frames, const 
     const int nb = int(ceil_div(k, 3));
     const size_t lds = kLightLdsBytes;
     switch (nb) {
-#define HC_CASE(NB)                                                                               \
-    case NB:                                                                                      \
-        hipLaunchKernelGGL(shade_latent_tiles_kernel<NB>, dim3(grid), dim3(kBlock), lds, st, frames, \
-                           n_frames, tiles, n_tiles, max_tiles);                                  \
-        break;
+#define HC_CASE(NB)                                                                                  \
+    case NB: {                                                                                       \
+        const int g = tile_grid(grid, shade_latent_tiles_kernel<NB>, kBlock, lds,                    \
+                                "hc_shade_latent_tiles");                                            \
+        if (g <= 0) return HC_EDEVICE;                                                               \
+        hipLaunchKernelGGL(shade_latent_tiles_kernel<NB>, dim3(g), dim3(kBlock), lds, st, frames,    \
+                           n_frames, tiles, n_tiles, max_tiles);                                     \
+        break;                                                                                       \
+    }
         HC_NB_CASES(HC_CASE)
 #undef HC_CASE
         default:

@@ -415,9 +415,11 @@ template <int G, int Q>
 hc_status launch_spectral_tiles_gq(const hc_frame* frames, int n_frames, const hc_tile* tiles,
                                    const int32_t* n_tiles, int max_tiles, int n, const float* T, int grid,
                                    hipStream_t st) {
-    const size_t t_bytes = t_in_lds(Q) ? kTLdsFloat4 * sizeof(float4) : 0;
-    hipLaunchKernelGGL((shade_spectral_tiles_kernel<G, Q>), dim3(grid), dim3(kBlock), t_bytes + kLightLdsBytes,
-                       st, frames, n_frames, tiles, n_tiles, max_tiles, n, T);
+    const size_t lds = (t_in_lds(Q) ? kTLdsFloat4 * sizeof(float4) : 0) + kLightLdsBytes;
+    const int g = tile_grid(grid, shade_spectral_tiles_kernel<G, Q>, kBlock, lds, "hc_shade_spectral_tiles");
+    if (g <= 0) return HC_EDEVICE;
+    hipLaunchKernelGGL((shade_spectral_tiles_kernel<G, Q>), dim3(g), dim3(kBlock), lds, st, frames, n_frames,
+                       tiles, n_tiles, max_tiles, n, T);
     return launch_status("hc_shade_spectral_tiles");
 }
 

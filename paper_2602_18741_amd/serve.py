@@ -300,7 +300,7 @@ class GpuBackend:
     "spectral" (shade straight to XYZ)."""
 
     def __init__(self, assets, lights, T, E=None, D=None, form: str = "latent", max_frames: int = 64,
-                 max_tiles: int = 8192, max_jobs: int = 4096, grid: int = 2048, device="cuda",
+                 max_tiles: int = 8192, max_jobs: int = 4096, grid: int = 0, device="cuda",
                  use_graph: bool = True, asset_budget: float = 16e9):
         import torch
 
@@ -674,7 +674,7 @@ def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=
 
 def bench_saturation(device, asset, lights, T, E, D, frames: int = 8, width: int = 3840,
                      height: int = 2160, spp: int = 64, l_range=(1, 8), mem_budget: float = 150e9,
-                     iter_vertices: float = 400e6, grid: int = 2048, target_tiles: int = 4096,
+                     iter_vertices: float = 400e6, grid: int = 0, target_tiles: int = 4096,
                      max_tiles: int = 8192, forms=("latent", "spectral")) -> dict:
     """Serving at saturation: a burst of `frames` identical-shape requests
     (default 4K, 64 spp, path length 1..8) on one asset, all arriving at once,

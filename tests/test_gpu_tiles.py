@@ -7,7 +7,8 @@ hc_shade_spectral / hc_shade_latent, so the results must be equal bit for bit.
 The cases cover every spectral chunk count (n = 31, 81, 128), light tables in
 LDS and in global memory, latent widths of 1, 2, 3 and 16 blocks, frames of
 1 to 100 samples per pixel, ragged tiles, a tile past its frame's end (clipped)
-and tiles naming no frame (skipped).
+and tiles naming no frame (skipped); with a fixed grid and the grid left to the
+library (grid 0).
 """
 
 import ctypes as C
@@ -80,8 +81,9 @@ def _table(paths, tex, lights, images, xyzs):
     return arr
 
 
+@pytest.mark.parametrize("grid", [64, 0])
 @pytest.mark.parametrize("n,n_illum", [(31, 12), (31, 600), (81, 20), (81, 300), (128, 8), (128, 100)])
-def test_spectral_tiles_equal_single_frame_calls(ops, n, n_illum):
+def test_spectral_tiles_equal_single_frame_calls(ops, n, n_illum, grid):
     from paper_2602_18741_amd._lib import check, load
     rng = np.random.default_rng(n * 7 + n_illum)
     refl = dev_f32(synth.reflectances(rng, n, 400))
@@ -95,15 +97,16 @@ def test_spectral_tiles_equal_single_frame_calls(ops, n, n_illum):
     cnt = torch.tensor([nt], dtype=torch.int32, device="cuda")
     st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     check(load().hc_shade_spectral_tiles(frames.data_ptr(), len(paths), d_tiles.data_ptr(), cnt.data_ptr(),
-                                         nt, n, T.data_ptr(), 64, st), "hc_shade_spectral_tiles")
+                                         nt, n, T.data_ptr(), grid, st), "hc_shade_spectral_tiles")
     for P, xyz in zip(paths, xyzs):
         ref = ops.shade_spectral(P, refl, lights, T, n)
         torch.cuda.synchronize()
         assert np.array_equal(to_np(xyz), to_np(ref))
 
 
+@pytest.mark.parametrize("grid", [64, 0])
 @pytest.mark.parametrize("k,n_illum", [(3, 12), (6, 12), (9, 300), (48, 20)])
-def test_latent_tiles_equal_single_frame_calls(ops, k, n_illum):
+def test_latent_tiles_equal_single_frame_calls(ops, k, n_illum, grid):
     from paper_2602_18741_amd._lib import check, load
     n = 31
     rng = np.random.default_rng(k * 11 + n_illum)
@@ -123,9 +126,9 @@ def test_latent_tiles_equal_single_frame_calls(ops, k, n_illum):
     st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     lib = load()
     check(lib.hc_shade_latent_tiles(frames.data_ptr(), len(paths), d_tiles.data_ptr(), cnt.data_ptr(), nt,
-                                    k, 64, st), "hc_shade_latent_tiles")
+                                    k, grid, st), "hc_shade_latent_tiles")
     check(lib.hc_decode_tiles(frames.data_ptr(), len(paths), d_tiles.data_ptr(), cnt.data_ptr(), nt,
-                              D.data_ptr(), n, k, T.data_ptr(), 64, st), "hc_decode_tiles")
+                              D.data_ptr(), n, k, T.data_ptr(), grid, st), "hc_decode_tiles")
     for P, img, xyz in zip(paths, images, xyzs):
         ref_img = ops.shade_latent(P, codes, lcodes, k)
         ref_xyz = ops.decode_xyz(D, T, ref_img, k)
