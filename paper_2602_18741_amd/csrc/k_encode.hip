@@ -157,16 +157,22 @@ __device__ __forceinline__ void decode_pixel(const float* s_M, const float* s_D,
     }
 }
 
-// One thread per pixel.
+// kDecodePixels pixels per thread (consecutive blocks of kThreads pixels), so
+// a workgroup's set-up of M is shared by that many pixels.
+constexpr int kDecodePixels = 8;
+
 template <int NB>
 __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
     __shared__ float s_M[3 * kMaxK];
     extern __shared__ float s_D[];  // n x k, only when spectra are requested
     stage_decoder<NB>(a.D, a.T, a.n, a.k, s_M, a.spectra ? s_D : nullptr);
     __syncthreads();
-    const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (q >= a.n_pixels) return;
-    decode_pixel<NB>(s_M, s_D, a.n, a.k, a.zimg, a.ld_z, a.xyz, a.spectra, a.ld_s, q);
+    const int64_t q0 = int64_t(blockIdx.x) * kThreads * kDecodePixels + threadIdx.x;
+    for (int i = 0; i < kDecodePixels; ++i) {
+        const int64_t q = q0 + int64_t(i) * kThreads;
+        if (q >= a.n_pixels) return;
+        decode_pixel<NB>(s_M, s_D, a.n, a.k, a.zimg, a.ld_z, a.xyz, a.spectra, a.ld_s, q);
+    }
 }
 
 // Persistent launch over a tile table: each tile's pixels of frames[f].image
@@ -245,7 +251,7 @@ hc_status launch_decode(const float* D, int n, int k, const float* T, const floa
     a.spectra = spectra;
     a.ld_s = ld_spectra;
     const size_t lds = spectra ? size_t(n) * k * sizeof(float) : 0;
-    const int64_t blocks = ceil_div(n_pixels, kThreads);
+    const int64_t blocks = ceil_div(n_pixels, int64_t(kThreads) * kDecodePixels);
     if (blocks > 0x7FFFFFFF) {
         set_error("hc_decode_xyz: too many pixels for one launch");
         return HC_ESHAPE;
