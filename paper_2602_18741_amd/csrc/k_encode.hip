@@ -20,42 +20,58 @@ struct EncodeArgs {
     int rows;        // rows per block (256 / 128 / 64)
 };
 
-// Stage E (zero rows past k) into LDS.
+// Stage E into LDS as 3NB rows of nq float4 chunks, zero past k rows and
+// past n samples, so a product reads a chunk of four samples at once.
 template <int NB>
-__device__ __forceinline__ void stage_encoder(const float* E, int k, int n, float* s_E) {
-    for (int i = threadIdx.x; i < 3 * NB * n; i += kThreads) s_E[i] = (i < k * n) ? E[i] : 0.f;
+__device__ __forceinline__ void stage_encoder(const float* E, int k, int n, int nq, float4* s_E) {
+    for (int i = threadIdx.x; i < 3 * NB * nq; i += kThreads) {
+        const int c = i / nq, j = i % nq;
+        float w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = (c < k && 4 * j + e < n) ? E[c * n + 4 * j + e] : 0.f;
+        s_E[i] = make_float4(w[0], w[1], w[2], w[3]);
+    }
 }
 
 // Encode rows [r0, r0 + nrows) (nrows <= rows per block): stage the spectra
 // with coalesced float4 loads, then one thread per row accumulates the codes
 // over the n samples in order.  Starts and ends with a block barrier.
 template <int NB>
-__device__ __forceinline__ void encode_rows(const float* s_E, float* s_rows, int n, int nq,
+__device__ __forceinline__ void encode_rows(const float4* s_E, float4* s_rows, int n, int nq,
                                             const float* S, int64_t ld_s, float* Z, int64_t ld_z,
                                             int64_t r0, int nrows) {
-    const int stride = 4 * nq + 1;  // odd stride: a thread's row reads hit distinct banks
+    const int stride = nq + 1;  // float4 chunks; odd: a thread's row reads spread over banks
     const int tid = threadIdx.x;
     __syncthreads();
     for (int i = tid; i < nrows * nq; i += kThreads) {
         const int r = i / nq, c = i % nq;
-        const float4 v = ld4(S + (r0 + r) * ld_s + 4 * c);
-        float* d = s_rows + r * stride + 4 * c;
-        d[0] = v.x;
-        d[1] = v.y;
-        d[2] = v.z;
-        d[3] = v.w;
+        float4 v = ld4(S + (r0 + r) * ld_s + 4 * c);
+        // samples past n (row padding) are not used: E is zero there, but
+        // non-finite padding times zero would not be
+        if (4 * c + 3 >= n) {
+            if (4 * c + 1 >= n) v.y = 0.f;
+            if (4 * c + 2 >= n) v.z = 0.f;
+            v.w = 0.f;
+        }
+        s_rows[r * stride + c] = v;
     }
     __syncthreads();
     if (tid < nrows) {
-        const float* s = s_rows + tid * stride;
+        const float4* s = s_rows + tid * stride;
         // channels past k read zero rows of E (staged that way), so they stay 0
         float z[3 * NB];
 #pragma unroll
         for (int c = 0; c < 3 * NB; ++c) z[c] = 0.f;
-        for (int i = 0; i < n; ++i) {
-            const float si = s[i];
+        for (int j = 0; j < nq; ++j) {
+            const float4 sj = s[j];
 #pragma unroll
-            for (int c = 0; c < 3 * NB; ++c) z[c] += s_E[c * n + i] * si;
+            for (int c = 0; c < 3 * NB; ++c) {
+                const float4 e = s_E[c * nq + j];
+                z[c] += e.x * sj.x;
+                z[c] += e.y * sj.y;
+                z[c] += e.z * sj.z;
+                z[c] += e.w * sj.w;
+            }
         }
         float* out = Z + (r0 + tid) * ld_z;
 #pragma unroll
@@ -66,9 +82,9 @@ __device__ __forceinline__ void encode_rows(const float* s_E, float* s_rows, int
 
 template <int NB>
 __global__ __launch_bounds__(kThreads) void encode_kernel(EncodeArgs a) {
-    extern __shared__ float smem[];
-    float* s_E = smem + a.rows * (4 * a.nq + 1);
-    stage_encoder<NB>(a.E, a.k, a.n, s_E);
+    extern __shared__ float4 smem[];
+    float4* s_E = smem + a.rows * (a.nq + 1);
+    stage_encoder<NB>(a.E, a.k, a.n, a.nq, s_E);
     const int64_t r0 = int64_t(blockIdx.x) * a.rows;
     const int nrows = int(min<int64_t>(a.rows, a.m - r0));
     encode_rows<NB>(s_E, smem, a.n, a.nq, a.S, a.ld_s, a.Z, a.ld_z, r0, nrows);
@@ -81,10 +97,10 @@ __global__ __launch_bounds__(kThreads) void encode_jobs_kernel(const hc_encode_j
                                                                const int32_t* __restrict__ n_jobs_dev,
                                                                int max_jobs,
                                                                const float* E, int k, int n, int rows) {
-    extern __shared__ float smem[];
+    extern __shared__ float4 smem[];
     const int nq = (n + 3) / 4;
-    float* s_E = smem + rows * (4 * nq + 1);
-    stage_encoder<NB>(E, k, n, s_E);
+    float4* s_E = smem + rows * (nq + 1);
+    stage_encoder<NB>(E, k, n, nq, s_E);
     const int n_jobs = min(*n_jobs_dev, max_jobs);
     for (int j = blockIdx.x; j < n_jobs; j += gridDim.x) {
         const hc_encode_job job = jobs[j];
@@ -221,7 +237,7 @@ hc_status launch_encode(const float* E, int k, int n, const float* S, int64_t m,
     a.ld_z = ld_z;
     a.rows = rows_per_block(a.nq);
     const int nb = (k + 2) / 3;
-    const size_t lds = (size_t(a.rows) * (4 * a.nq + 1) + size_t(3 * nb) * n) * sizeof(float);
+    const size_t lds = (size_t(a.rows) * (a.nq + 1) + size_t(3 * nb) * a.nq) * sizeof(float4);
     const uint32_t blocks = uint32_t(ceil_div(m, a.rows));
     switch (nb) {
 #define HC_ENC(NB) \
@@ -275,7 +291,7 @@ hc_status launch_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, i
     const int nq = (n + 3) / 4;
     const int rows = rows_per_block(nq);
     const int nb = (k + 2) / 3;
-    const size_t lds = (size_t(rows) * (4 * nq + 1) + size_t(3 * nb) * n) * sizeof(float);
+    const size_t lds = (size_t(rows) * (nq + 1) + size_t(3 * nb) * nq) * sizeof(float4);
     switch (nb) {
 #define HC_ENCJ(NB)                                                                                  \
     case NB: {                                                                                       \
