@@ -82,7 +82,7 @@ __device__ __forceinline__ void layer1(const float4* w1b, float r, float gg, flo
 // ------------------------------------------------------------------ F16
 
 template <int NT, int MC3>
-__global__ __launch_bounds__(kThreads) void upsample_f16_kernel(UpArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT > 1 ? 3 : 1))) void upsample_f16_kernel(UpArgs a) {
     __shared__ hc_h8 sW2[8 * 4 * kWave];    // [mo][c][lane]
     __shared__ hc_h8 sW3[MC3 * 4 * kWave];  // [m3][c][lane]
     __shared__ float4 sW1[kHidden];          // (w_r, w_g, w_b, b1)
@@ -297,11 +297,14 @@ __global__ __launch_bounds__(kThreads) void upsample_f32_kernel(UpArgs a) {
     }
 }
 
-constexpr int kNT16 = 1;  // tiles per wave per step: more raise registers past 4 waves/SIMD
+// 16-texel tiles per wave per step.  F16 with k <= 16: two tiles share each
+// weight fragment read from LDS (167 registers, 3 waves per SIMD: 1.56 against
+// 1.64 ms for 4096^2 texels at one tile and 4 waves); wider outputs would spill
+// at two tiles and keep one, as does F32.
+constexpr int kNT16 = 2;
 constexpr int kNT32 = 1;
 constexpr int kMaxGrid = 2048;
 
-template <int NT>
 int64_t grid_for(const UpArgs& a) {
     return std::min<int64_t>(ceil_div(a.n_groups, kWaves), kMaxGrid);
 }
@@ -327,16 +330,17 @@ hc_status launch_upsample(const hc_mlp& net, int precision, const float* rgb, in
     const int mc3 = int(ceil_div(net.k, 16));
     const int64_t tiles = ceil_div(m, 16);
     if (precision == HC_MLP_F16) {
-        a.n_groups = ceil_div(tiles, kNT16);
-        const dim3 grid(uint32_t(grid_for<kNT16>(a)));
+        const int nt = mc3 == 1 ? kNT16 : 1;
+        a.n_groups = ceil_div(tiles, nt);
+        const dim3 grid(uint32_t(grid_for(a)));
         switch (mc3) {
             case 1: hipLaunchKernelGGL((upsample_f16_kernel<kNT16, 1>), grid, dim3(kThreads), 0, st, a); break;
-            case 2: hipLaunchKernelGGL((upsample_f16_kernel<kNT16, 2>), grid, dim3(kThreads), 0, st, a); break;
-            default: hipLaunchKernelGGL((upsample_f16_kernel<kNT16, 3>), grid, dim3(kThreads), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((upsample_f16_kernel<1, 2>), grid, dim3(kThreads), 0, st, a); break;
+            default: hipLaunchKernelGGL((upsample_f16_kernel<1, 3>), grid, dim3(kThreads), 0, st, a); break;
         }
     } else {
         a.n_groups = ceil_div(tiles, kNT32);
-        const dim3 grid(uint32_t(grid_for<kNT32>(a)));
+        const dim3 grid(uint32_t(grid_for(a)));
         switch (mc3) {
             case 1: hipLaunchKernelGGL((upsample_f32_kernel<kNT32, 1>), grid, dim3(kThreads), 0, st, a); break;
             case 2: hipLaunchKernelGGL((upsample_f32_kernel<kNT32, 2>), grid, dim3(kThreads), 0, st, a); break;

@@ -194,7 +194,7 @@ def _padded(a, ld, fill):
 # read it from: colour-weighted in LDS (3 float4 per light and chunk), plain in
 # LDS, and global memory (LDS budget 16 KiB).
 @pytest.mark.parametrize("n,n_illum", [(31, 8), (31, 60), (31, 600), (81, 5), (81, 40), (81, 300),
-                                       (128, 8), (128, 20), (128, 100), (5, 3)])
+                                       (128, 8), (128, 20), (128, 100), (5, 3), (50, 30), (50, 200)])
 def test_spectral_light_tables_and_nonfinite_padding(ops, n, n_illum):
     """Row padding past n (reflectance and light rows, strides beyond the
     padded width) holds NaN and inf; the result must not see it."""

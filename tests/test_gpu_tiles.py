@@ -4,7 +4,7 @@ hc_shade_spectral_tiles / hc_shade_latent_tiles / hc_decode_tiles walk a
 device table of frames and pixel-range tiles with a fixed grid.  Each pixel's
 samples are reduced inside one wavefront in the same order as in
 hc_shade_spectral / hc_shade_latent, so the results must be equal bit for bit.
-The cases cover every spectral chunk count (n = 31, 81, 128), light tables in
+The cases cover every spectral chunk count (n = 31, 50, 81, 128), light tables in
 LDS and in global memory, latent widths of 1, 2, 3 and 16 blocks, frames of
 1 to 100 samples per pixel, ragged tiles, a tile past its frame's end (clipped)
 and tiles naming no frame (skipped); with a fixed grid and the grid left to the
@@ -82,7 +82,8 @@ def _table(paths, tex, lights, images, xyzs):
 
 
 @pytest.mark.parametrize("grid", [64, 0])
-@pytest.mark.parametrize("n,n_illum", [(31, 12), (31, 600), (81, 20), (81, 300), (128, 8), (128, 100)])
+@pytest.mark.parametrize("n,n_illum", [(31, 12), (31, 600), (50, 30), (50, 200), (81, 20), (81, 300),
+                                       (128, 8), (128, 100)])
 def test_spectral_tiles_equal_single_frame_calls(ops, n, n_illum, grid):
     from paper_2602_18741_amd._lib import check, load
     rng = np.random.default_rng(n * 7 + n_illum)
