@@ -155,6 +155,7 @@ def measured_traffic(bytes_alg):
 
 
 MB_CHAINS = 1 << 18
+CODEC_STEPS_PER_GRAPH = 8   # codec fit steps recorded in one HIP graph
 
 
 def codec_only(args):
@@ -172,7 +173,7 @@ def codec_only(args):
         fit = CodecFit(we0, wd0, pa, pb, batch=65536, seed=2, objective=objective,
                        T=synth.cmf_matrix(n))
         fit.run(1)
-        fit.capture()
+        fit.capture(CODEC_STEPS_PER_GRAPH)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         loss = float(fit.run(args.codec_steps))
@@ -398,7 +399,7 @@ def main():
                        objective=objective, T=w["T"])
         recipe_steps = min(2000, codec_steps)
         fit.run(1)
-        fit.capture()
+        fit.capture(CODEC_STEPS_PER_GRAPH)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         loss_recipe = float(fit.run(recipe_steps - 1))

@@ -276,10 +276,18 @@ hc_status hc_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int32
  * dtype: 0 = float32 everywhere, 1 = float64 everywhere (parameters, data,
  * T, outputs, Adam state).  Gradient sums run in that precision over tiles of
  * at most 64 pairs and in float64 across tiles, in a fixed order, so results
- * are deterministic.
+ * are deterministic.  (float32 with n = 31 and k = 6 or 9 runs one pair per
+ * lane and sums each wavefront's pairs on the fp32 matrix cores: 64 pairs per
+ * 256-pair chunk of the batch, one chunk per wavefront up to N = 262,144.)
  * Batch rows: row i of the a-batch is A[idx_a[i]*ld_a ...] when idx_a is
  * not NULL, else A[i*ld_a ...]; likewise b.  Indices must be < rows_a
- * (rows_b); out-of-range indices are clamped.
+ * (rows_b); out-of-range indices are clamped.  With draw not NULL the rows
+ * are drawn on the device instead (idx_a and idx_b must then be NULL): row i
+ * of the a-batch is the index hc_gen_indices(draw->seed_a, draw->ctr0,
+ * draw->ctr_scale_dev, N, rows_a, ...) writes at position i, likewise b with
+ * seed_b, so a fitting loop needs no index arrays and no extra launches.
+ * When ctr_scale_dev is the Adam step counter, the draw sees its value from
+ * before the call (the counter is incremented by the call's last kernel).
  */
 #define HC_CODEC_L2 0
 #define HC_CODEC_EQ8 1
@@ -292,6 +300,12 @@ typedef struct hc_adam {
     int64_t* step;      /* device counter: steps taken; incremented by the call */
     double lr, beta1, beta2, eps;
 } hc_adam;
+
+typedef struct hc_pair_draw {
+    uint64_t seed_a, seed_b;
+    uint64_t ctr0;
+    const int64_t* ctr_scale_dev;  /* device counter, nullable */
+} hc_pair_draw;
 
 typedef struct hc_codec_args {
     int32_t k, n;
@@ -319,6 +333,7 @@ typedef struct hc_codec_args {
     const void* T;      /* 3 x n, row-major */
     double w_e2e, w_rec, w_code, w_col;  /* finite, >= 0 */
     double cos_eps;     /* > 0; 1e-8 is customary */
+    const hc_pair_draw* draw;  /* host pointer, nullable: batch rows drawn on the device */
 } hc_codec_args;
 
 /* Bytes of workspace hc_codec_step needs for this shape, for either

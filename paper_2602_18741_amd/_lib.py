@@ -48,6 +48,10 @@ class Adam(C.Structure):
                 ("lr", f64), ("beta1", f64), ("beta2", f64), ("eps", f64)]
 
 
+class PairDraw(C.Structure):
+    _fields_ = [("seed_a", u64), ("seed_b", u64), ("ctr0", u64), ("ctr_scale_dev", vp)]
+
+
 class CodecArgs(C.Structure):
     _fields_ = [("k", i32), ("n", i32), ("dtype", i32), ("objective", i32),
                 ("beta", f64), ("lam", f64), ("Wt_E", vp), ("Wt_D", vp), ("A", vp), ("B", vp),
@@ -55,7 +59,7 @@ class CodecArgs(C.Structure):
                 ("idx_a", vp), ("idx_b", vp), ("N", i64), ("loss", vp), ("grad_E", vp),
                 ("grad_D", vp), ("adam", C.POINTER(Adam)), ("workspace", vp),
                 ("workspace_bytes", sz), ("stream", vp), ("T", vp), ("w_e2e", f64), ("w_rec", f64),
-                ("w_code", f64), ("w_col", f64), ("cos_eps", f64)]
+                ("w_code", f64), ("w_col", f64), ("cos_eps", f64), ("draw", C.POINTER(PairDraw))]
 
 
 class Mlp(C.Structure):

@@ -2,8 +2,8 @@
 
 Each step draws N (reflectance, light) pairs by index from device-resident
 pools with the counter-based index generator (the counter base is the Adam
-step counter, so a captured graph draws fresh pairs on every replay), then
-runs hc_codec_step with the fused Adam update.  The step can be captured
+step counter, so a captured graph draws fresh pairs on every replay) inside
+hc_codec_step, which also applies the fused Adam update.  The step can be captured
 once in a HIP graph and replayed.  State (parameters, Adam moments, step)
 round-trips through .npz checkpoints.
 """
@@ -37,40 +37,43 @@ class CodecFit:
                          m_D=torch.zeros_like(self.Wt_D), v_D=torch.zeros_like(self.Wt_D),
                          step=torch.zeros(1, dtype=torch.int64, device=dev), lr=lr,
                          beta1=0.9, beta2=0.999, eps=1e-8)
-        self.idx_a = torch.empty(batch, dtype=torch.int32, device=dev)
-        self.idx_b = torch.empty(batch, dtype=torch.int32, device=dev)
         self.loss = torch.zeros((), dtype=dtype, device=dev)
         self.ws = ops.CodecWorkspace(self.k, self.n, batch, dev)
-        self.graph = None
+        self.graph, self.graph_steps = None, 1
 
     def _step(self):
-        # indices for step t use counters [t*N, (t+1)*N) of two seeded streams
-        ops.gen_indices(2 * self.seed + 1, self.N, self.pool_a.shape[0], step=self.adam["step"],
-                        out=self.idx_a)
-        ops.gen_indices(2 * self.seed + 2, self.N, self.pool_b.shape[0], step=self.adam["step"],
-                        out=self.idx_b)
+        # rows for step t: counters [t*N, (t+1)*N) of two seeded index streams
+        # (the indices ops.gen_indices would write), drawn inside the step
+        draw = dict(seed_a=2 * self.seed + 1, seed_b=2 * self.seed + 2, step=self.adam["step"])
         ops.codec_step(self.Wt_E, self.Wt_D, self.pool_a, self.pool_b, self.N, lam=self.lam,
-                       beta=self.beta, idx_a=self.idx_a, idx_b=self.idx_b, loss=self.loss,
+                       beta=self.beta, draw=draw, loss=self.loss,
                        adam=self.adam, workspace=self.ws, objective=self.objective, T=self.T,
                        weights=self.eq8_weights)
 
-    def capture(self):
-        """Record one step in a HIP graph (warm-up step first, as graph capture
-        needs the kernels loaded).  Later run() calls replay it."""
+    def capture(self, steps: int = 1):
+        """Record `steps` consecutive steps in one HIP graph (run a warm-up step
+        first, as graph capture needs the kernels loaded).  Later run() calls
+        replay it as often as it fits and take any remaining steps one by one;
+        each captured step reads the device step counter when it runs, so every
+        replay draws new pairs."""
+        if steps < 1:
+            raise ValueError("steps must be >= 1")
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
-            self._step()
+            for _ in range(steps):
+                self._step()
         torch.cuda.current_stream().wait_stream(s)
-        self.graph = g
+        self.graph, self.graph_steps = g, steps
 
     def run(self, steps: int):
-        for _ in range(steps):
-            if self.graph is not None:
+        if self.graph is not None:
+            for _ in range(steps // self.graph_steps):
                 self.graph.replay()
-            else:
-                self._step()
+            steps %= self.graph_steps
+        for _ in range(steps):
+            self._step()
         return self.loss
 
     @property

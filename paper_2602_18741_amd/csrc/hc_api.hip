@@ -274,10 +274,19 @@ hc_status hc_codec_step(const hc_codec_args* a) {
     HC_REQUIRE(a->beta > 0, HC_EINVAL, "%s: beta must be > 0", fn);
     HC_REQUIRE(a->ld_a >= a->n && a->ld_b >= a->n, HC_ESHAPE, "%s: ld_a/ld_b < n", fn);
     HC_REQUIRE(a->Wt_E && a->Wt_D && a->A && a->B && a->loss, HC_EINVAL, "%s: NULL pointer", fn);
-    if (a->idx_a) HC_REQUIRE(a->rows_a >= 1, HC_ESHAPE, "%s: rows_a must be >= 1 with idx_a", fn);
-    if (a->idx_b) HC_REQUIRE(a->rows_b >= 1, HC_ESHAPE, "%s: rows_b must be >= 1 with idx_b", fn);
-    if (!a->idx_a) HC_REQUIRE(a->rows_a >= a->N, HC_ESHAPE, "%s: rows_a < N without idx_a", fn);
-    if (!a->idx_b) HC_REQUIRE(a->rows_b >= a->N, HC_ESHAPE, "%s: rows_b < N without idx_b", fn);
+    if (a->draw) {
+        HC_REQUIRE(!a->idx_a && !a->idx_b, HC_EINVAL, "%s: draw excludes idx_a / idx_b", fn);
+        HC_REQUIRE(a->rows_a >= 1 && a->rows_a < (int64_t(1) << 32) && a->rows_b >= 1 &&
+                       a->rows_b < (int64_t(1) << 32),
+                   HC_ESHAPE, "%s: drawn rows need rows_a, rows_b in [1, 2^32)", fn);
+        HC_REQUIRE(!a->draw->ctr_scale_dev || aligned8(a->draw->ctr_scale_dev), HC_EALIGN,
+                   "%s: draw counter misaligned", fn);
+    } else {
+        if (a->idx_a) HC_REQUIRE(a->rows_a >= 1, HC_ESHAPE, "%s: rows_a must be >= 1 with idx_a", fn);
+        if (a->idx_b) HC_REQUIRE(a->rows_b >= 1, HC_ESHAPE, "%s: rows_b must be >= 1 with idx_b", fn);
+        if (!a->idx_a) HC_REQUIRE(a->rows_a >= a->N, HC_ESHAPE, "%s: rows_a < N without idx_a", fn);
+        if (!a->idx_b) HC_REQUIRE(a->rows_b >= a->N, HC_ESHAPE, "%s: rows_b < N without idx_b", fn);
+    }
     const size_t esz = a->dtype ? 8 : 4;
     auto al = [&](const void* p) { return (reinterpret_cast<uintptr_t>(p) % esz) == 0; };
     HC_REQUIRE(al(a->Wt_E) && al(a->Wt_D) && al(a->A) && al(a->B) && al(a->loss) &&

@@ -25,6 +25,9 @@
 //                applies the softplus slope logistic(beta Wt) and optionally
 //                the Adam update.
 
+#include <type_traits>
+
+#include "counter_rng.hpp"
 #include "hc_internal.hpp"
 
 namespace hc {
@@ -62,11 +65,7 @@ __global__ __launch_bounds__(kThreads) void codec_weights_kernel(const F* we, co
         E[e] = softplus(we[e], beta);
         D[e] = softplus(wd[e], beta);
     }
-    if (step && blockIdx.x == 0 && threadIdx.x == 0) {
-        const int64_t t = *step + 1;
-        *ws_step = t;
-        *step = t;
-    }
+    if (step && blockIdx.x == 0 && threadIdx.x == 0) *ws_step = *step + 1;
 }
 
 template <typename F>
@@ -92,12 +91,16 @@ struct PartialArgs {
     int64_t ld_a, ld_b, rows_a, rows_b;
     const uint32_t* idx_a;
     const uint32_t* idx_b;
+    // rows drawn on the device: counter base draw_ctr0 (+ *draw_scale * N)
+    int draw;
+    uint64_t key_a, key_b, draw_ctr0;
+    const int64_t* draw_scale;
     int64_t N, n_tiles;
     double* part;  // gridDim.x rows of 2kn + 1
     int ed_in_lds;
     // with E and D staged in LDS the kernel makes them itself from the raw
-    // parameters (softplus), and block 0 bumps the Adam step counter: the
-    // weights kernel is then not launched
+    // parameters (softplus), and block 0 writes the incremented Adam step to
+    // the workspace: the weights kernel is then not launched
     const F* we;
     const F* wd;
     F beta;
@@ -109,17 +112,35 @@ struct PartialArgs {
 };
 
 // E = softplus(Wt_E) and D = softplus(Wt_D) into LDS (the values the weights
-// kernel would write), and the step counter bump.
+// kernel would write), and the incremented step into the workspace (the
+// finish kernel stores it to the counter, after every read of the counter
+// by this step's pair draw).
 template <typename F>
 __device__ __forceinline__ void stage_weights(const PartialArgs<F>& a, F* sm, int kn) {
     for (int i = threadIdx.x; i < kn; i += kThreads) {
         sm[i] = softplus(a.we[i], a.beta);
         sm[kn + i] = softplus(a.wd[i], a.beta);
     }
-    if (a.step && blockIdx.x == 0 && threadIdx.x == 0) {
-        const int64_t t = *a.step + 1;
-        *a.ws_step = t;
-        *a.step = t;
+    if (a.step && blockIdx.x == 0 && threadIdx.x == 0) *a.ws_step = *a.step + 1;
+}
+
+// Counter base of the pair draw for this call.
+template <typename F>
+__device__ __forceinline__ uint64_t draw_base(const PartialArgs<F>& a) {
+    return a.draw_ctr0 + (a.draw_scale ? uint64_t(*a.draw_scale) * uint64_t(a.N) : 0ull);
+}
+
+// Batch rows of pair gi: drawn (the indices hc_gen_indices would write),
+// gathered by index (clamped) or the identity.
+template <typename F>
+__device__ __forceinline__ void batch_rows(const PartialArgs<F>& a, uint64_t base, int64_t gi, int64_t& ra,
+                                           int64_t& rb) {
+    if (a.draw) {
+        ra = range32(rand64(a.key_a, base + uint64_t(gi)), uint64_t(a.rows_a));
+        rb = range32(rand64(a.key_b, base + uint64_t(gi)), uint64_t(a.rows_b));
+    } else {
+        ra = a.idx_a ? min<int64_t>(a.idx_a[gi], a.rows_a - 1) : gi;
+        rb = a.idx_b ? min<int64_t>(a.idx_b[gi], a.rows_b - 1) : gi;
     }
 }
 
@@ -152,6 +173,7 @@ __global__ __launch_bounds__(kThreads) void codec_partials_kernel(PartialArgs<F>
 
     const int pair = tid / lpp;
     const int part = tid % lpp;
+    const uint64_t ctr_base = a.draw ? draw_base(a) : 0ull;
     double loss_acc = 0.0;
     double* prow = a.part + int64_t(blockIdx.x) * (2 * kn + 1);
     bool first_tile = true;
@@ -162,10 +184,7 @@ __global__ __launch_bounds__(kThreads) void codec_partials_kernel(PartialArgs<F>
         __syncthreads();  // the previous tile's contraction has finished with LDS
         if (pair < tp) {
             int64_t ra = 0, rb = 0;
-            if (valid) {
-                ra = a.idx_a ? min<int64_t>(a.idx_a[gi], a.rows_a - 1) : gi;
-                rb = a.idx_b ? min<int64_t>(a.idx_b[gi], a.rows_b - 1) : gi;
-            }
+            if (valid) batch_rows(a, ctr_base, gi, ra, rb);
             for (int i = part; i < n; i += lpp) {
                 AA[pair * np + i] = valid ? a.A[ra * a.ld_a + i] : F(0);
                 BB[pair * np + i] = valid ? a.B[rb * a.ld_b + i] : F(0);
@@ -297,6 +316,7 @@ __global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArg
 
     const int pair = tid / lpp;
     const int part = tid % lpp;
+    const uint64_t ctr_base = a.draw ? draw_base(a) : 0ull;
     const double inv_n = 1.0 / n;
     double loss_acc = 0.0;
     double* prow = a.part + int64_t(blockIdx.x) * (2 * kn + 1);
@@ -308,10 +328,7 @@ __global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArg
         __syncthreads();  // the previous tile's contraction has finished with LDS
         {
             int64_t ra = 0, rb = 0;
-            if (valid) {
-                ra = a.idx_a ? min<int64_t>(a.idx_a[gi], a.rows_a - 1) : gi;
-                rb = a.idx_b ? min<int64_t>(a.idx_b[gi], a.rows_b - 1) : gi;
-            }
+            if (valid) batch_rows(a, ctr_base, gi, ra, rb);
             for (int i = part; i < n; i += lpp) {
                 const F ai = valid ? a.A[ra * a.ld_a + i] : F(0);
                 const F bi = valid ? a.B[rb * a.ld_b + i] : F(0);
@@ -446,6 +463,363 @@ __global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArg
     }
 }
 
+// ------------------------------------------------------------------ kernel 2, lane-per-pair form
+//
+// float32 with n = 31 (400-700 nm at 10 nm) and k = 6 or 9.  A lane owns one
+// pair: a and b, the residuals and the codes stay in registers, every loop
+// has compile-time bounds, and E, D and T are read from LDS at one address
+// for the whole wavefront (a broadcast).  The sums over pairs of outer
+// products,
+//   dD = sum_p r_a' u^T + r_b' v^T + g_3 h^T,   dE = sum_p g_u a^T + g_v b^T + c_3 t^T
+// (g_3 = g_S and c_3 = -w_code (2/k) d for Eq. 8; g_3 = lambda r_h and no third
+// dE term for the two-term loss), are contractions over the pairs and run on
+// the fp32 matrix cores (v_mfma_f32_16x16x4_f32, K = pairs).  For one term and
+// 16 samples a lane writes its pair's values down its column of the wave's
+// [16 rows][64 pairs] LDS block; lane (g, m) then reads row m, pairs
+// 16g .. 16g+15, as four 16-byte loads feeding 16 matrix steps (step s takes
+// pairs s, 16 + s, 32 + s, 48 + s).  Rows are 68 floats apart, so the column
+// writes of a row and each 8-lane group of row reads fall on distinct banks,
+// and every access is one base register plus a constant offset.  The
+// wavefronts of a workgroup are summed in a fixed order into one partial row.
+
+constexpr int kLaneN = 31;
+constexpr int kLanePad = 32;
+constexpr int kLaneWaves = kThreads / kWave;
+constexpr int kRow = kWave + 4;  // LDS row stride of the contraction blocks
+
+typedef float hc_mf4 __attribute__((ext_vector_type(4)));
+
+// Orders a wavefront's LDS writes before its later reads of other lanes'
+// values (LDS executes one wavefront's instructions in order; this keeps the
+// compiler from moving accesses across the point).
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A compiler-level memory clobber: table reads from LDS after it are issued
+// again instead of reusing (and keeping live) the values read before it.
+__device__ __forceinline__ void reread_tables() { __asm__ volatile("" ::: "memory"); }
+
+// x, opaque to the compiler: a product of it is recomputed where it is needed
+// rather than kept in a register, and a finished sum is computed here rather
+// than sunk towards a late use (which would keep its inputs live).
+__device__ __forceinline__ float fresh(float x) {
+    __asm__ volatile("" : "+v"(x));
+    return x;
+}
+
+// c += sum over the wave's 64 pairs of L[row m][pair] R[row m'][pair] for the
+// 16 x 16 tile (m, m'); lrow / rrow point at pair 16g of the lane's rows.
+__device__ __forceinline__ hc_mf4 contract64(const float* lrow, const float* rrow, hc_mf4 c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const hc_mf4 x = *reinterpret_cast<const hc_mf4*>(lrow + 4 * q);
+        const hc_mf4 y = *reinterpret_cast<const hc_mf4*>(rrow + 4 * q);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[0], y[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[1], y[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[2], y[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[3], y[3], c, 0, 0, 0);
+    }
+    return c;
+}
+
+template <bool EQ8, int K>
+__global__ __launch_bounds__(kThreads) void codec_lanes_kernel(PartialArgs<float> a) {
+    constexpr int N = kLaneN, NP = kLanePad, K4 = (K + 3) & ~3;
+    constexpr int TERMS_E = EQ8 ? 3 : 2;
+    __shared__ __align__(16) float sE[K * NP];   // E, rows padded with 0
+    __shared__ __align__(16) float sDt[K * NP];  // D^T, rows padded with 0
+    __shared__ __align__(16) float sD[NP * K4];  // D, rows padded with 0
+    __shared__ __align__(16) float sT[3 * NP];
+    __shared__ __align__(16) float sZero[kWave];
+    __shared__ __align__(16) float sX[kLaneWaves][16 * kRow];     // samples x pairs
+    __shared__ __align__(16) float sY[kLaneWaves][3 * K * kRow];  // codes x pairs, 3 terms
+    __shared__ double s_loss[kLaneWaves];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
+    // the pair rows of a chunk of 64 pairs (row 0 for lanes past the batch);
+    // the first chunk's loads are in flight while the tables are staged
+    const uint64_t ctr_base = a.draw ? draw_base(a) : 0ull;
+    float av[N], bv[N];
+    auto load_rows = [&](int64_t ch) {
+        const int64_t pi = ch * kWave + lane;
+        int64_t ra = 0, rb = 0;
+        if (pi < a.N) batch_rows(a, ctr_base, pi, ra, rb);
+        const float* pa = a.A + ra * a.ld_a;
+        const float* pb = a.B + rb * a.ld_b;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            av[i] = pa[i];
+            bv[i] = pb[i];
+        }
+    };
+    const int64_t ch0 = int64_t(blockIdx.x) * kLaneWaves + wave;
+    if (ch0 * kWave < a.N) load_rows(ch0);
+    for (int e = tid; e < K * NP; e += kThreads) {
+        const int j = e / NP, i = e % NP;
+        sE[e] = i < N ? softplus(a.we[j * N + i], a.beta) : 0.f;
+        sDt[e] = i < N ? softplus(a.wd[i * K + j], a.beta) : 0.f;
+    }
+    for (int e = tid; e < NP * K4; e += kThreads) {
+        const int i = e / K4, j = e % K4;
+        sD[e] = (i < N && j < K) ? softplus(a.wd[i * K + j], a.beta) : 0.f;
+    }
+    if (EQ8)
+        for (int e = tid; e < 3 * NP; e += kThreads) sT[e] = e % NP < N ? a.T[(e / NP) * N + e % NP] : 0.f;
+    if (tid < kWave) sZero[tid] = 0.f;
+    if (a.step && blockIdx.x == 0 && tid == 0) *a.ws_step = *a.step + 1;
+    __syncthreads();
+
+    const int g = lane >> 4, m = lane & 15;
+    float* X = sX[wave];
+    float* Y = sY[wave];
+    float* xcol = X + lane;  // the lane's column: row s at xcol[s * kRow]
+    float* ycol = Y + lane;
+    const float* xrow = X + m * kRow + 16 * g;
+    // rows of the code blocks past k read zeros
+    const float* yrow[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) yrow[t] = m < K ? Y + (t * K + m) * kRow + 16 * g : sZero + 16 * g;
+
+    hc_mf4 gd[2], ge[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) gd[c] = ge[c] = hc_mf4{0.f, 0.f, 0.f, 0.f};
+    double loss_acc = 0.0;
+    const float lam = a.lam;
+    const float wr = EQ8 ? float(a.w_rec * 2.0 / N) : 1.f;
+    const float wk = EQ8 ? float(a.w_code * 2.0 / K) : 0.f;
+
+    for (int64_t ch = ch0; ch * kWave < a.N; ch += int64_t(gridDim.x) * kLaneWaves) {
+        // keeps the reads of E, D and T from LDS inside the loop: hoisted out
+        // of it, all of them would stay live in registers
+        reread_tables();
+        if (ch != ch0) load_rows(ch);
+        const bool valid = ch * kWave + lane < a.N;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            av[i] = valid ? av[i] : 0.f;
+            bv[i] = valid ? bv[i] : 0.f;
+        }
+
+        // codes u = E a, v = E b, h = u v (Eq. 4, Eq. 6); Eq. 8: d = h - E t
+        float u[K], v[K], h[K], dc[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            float su = 0.f, sv = 0.f, sw = 0.f;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const float e = sE[j * NP + i];
+                su = fmaf(e, av[i], su);
+                sv = fmaf(e, bv[i], sv);
+                if (EQ8) sw = fmaf(e, fresh(av[i]) * bv[i], sw);
+            }
+            u[j] = fresh(su);
+            v[j] = fresh(sv);
+            h[j] = su * sv;
+            dc[j] = EQ8 ? fresh(h[j] - sw) : 0.f;
+        }
+        wave_lds_order();  // the previous chunk's reads of the code block are done
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            ycol[j * kRow] = u[j];
+            ycol[(K + j) * kRow] = v[j];
+            ycol[(2 * K + j) * kRow] = h[j];
+        }
+
+        // reconstructions D u, D v, D h, 16 samples at a time: the per-pair
+        // sums, D^T r_a' and D^T r_b' accumulated as the residuals appear,
+        // and their dD terms on the matrix cores
+        reread_tables();
+        float S[N];
+        float gu[K], gv[K], gs[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) gu[j] = gv[j] = gs[j] = 0.f;
+        float s_rr = 0.f, s_rh = 0.f, s_st = 0.f, s_ss = 0.f, s_tt = 0.f, s_c0 = 0.f, s_c1 = 0.f, s_c2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            float xa[16], xb[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int i = 16 * c + s;
+                xa[s] = xb[s] = 0.f;
+                if (i >= N) continue;
+                float du = 0.f, dv = 0.f, dh = 0.f;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const float d = sD[i * K4 + j];
+                    du = fmaf(d, u[j], du);
+                    dv = fmaf(d, v[j], dv);
+                    dh = fmaf(d, h[j], dh);
+                }
+                const float ti = fresh(av[i]) * bv[i];
+                const float rai = du - av[i], rbi = dv - bv[i], rh = dh - ti;
+                S[i] = dh;
+                s_rr = fmaf(rai, rai, fmaf(rbi, rbi, s_rr));
+                s_rh = fmaf(rh, rh, s_rh);
+                if (EQ8) {
+                    s_st = fmaf(dh, ti, s_st);
+                    s_ss = fmaf(dh, dh, s_ss);
+                    s_tt = fmaf(ti, ti, s_tt);
+                    s_c0 = fmaf(sT[i], rh, s_c0);
+                    s_c1 = fmaf(sT[NP + i], rh, s_c1);
+                    s_c2 = fmaf(sT[2 * NP + i], rh, s_c2);
+                }
+                const float rap = valid ? wr * rai : 0.f, rbp = valid ? wr * rbi : 0.f;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const float d = sD[i * K4 + j];
+                    gu[j] = fmaf(d, rap, gu[j]);
+                    gv[j] = fmaf(d, rbp, gv[j]);
+                }
+                xa[s] = rap;
+                xb[s] = rbp;
+            }
+            wave_lds_order();
+#pragma unroll
+            for (int s = 0; s < 16; ++s) xcol[s * kRow] = xa[s];
+            wave_lds_order();
+            gd[c] = contract64(xrow, yrow[0], gd[c]);
+            wave_lds_order();
+#pragma unroll
+            for (int s = 0; s < 16; ++s) xcol[s * kRow] = xb[s];
+            wave_lds_order();
+            gd[c] = contract64(xrow, yrow[1], gd[c]);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            gu[j] = fresh(gu[j]);
+            gv[j] = fresh(gv[j]);
+        }
+        s_rr = fresh(s_rr);
+        s_rh = fresh(s_rh);
+        if (EQ8) {
+            s_st = fresh(s_st);
+            s_ss = fresh(s_ss);
+            s_tt = fresh(s_tt);
+            s_c0 = fresh(s_c0);
+            s_c1 = fresh(s_c1);
+            s_c2 = fresh(s_c2);
+        }
+
+        // per-pair factors of the third term: g_3 = g_S (Eq. 8) or lambda r_h
+        reread_tables();
+        float al, bt, bs, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+        if (EQ8) {
+            float s_dd = 0.f;
+#pragma unroll
+            for (int j = 0; j < K; ++j) s_dd = fmaf(dc[j], dc[j], s_dd);
+            const double M = double(s_rh) / N;
+            const double sn = sqrt(double(s_ss));
+            const double ns = sn > a.eps ? sn : a.eps;
+            const double tn = sqrt(double(s_tt));
+            const double nt = tn > a.eps ? tn : a.eps;
+            const double cs = double(s_st) / (ns * nt);
+            if (valid)
+                loss_acc += a.w_e2e * M * (2.0 - cs) + a.w_rec * double(s_rr) / N + a.w_code * double(s_dd) / K +
+                            a.w_col * (double(s_c0) * s_c0 + double(s_c1) * s_c1 + double(s_c2) * s_c2) / 3.0;
+            // g_S = al r_h - bt t + bs S + T^T gc
+            al = float(a.w_e2e * (2.0 - cs) * 2.0 / N);
+            bt = float(a.w_e2e * M / (ns * nt));
+            bs = float(sn > a.eps ? a.w_e2e * M * cs / double(s_ss) : 0.0);
+            g0 = float(a.w_col * (2.0 / 3.0) * s_c0);
+            g1 = float(a.w_col * (2.0 / 3.0) * s_c1);
+            g2 = float(a.w_col * (2.0 / 3.0) * s_c2);
+        } else {
+            if (valid) loss_acc += double(s_rr) + double(lam) * double(s_rh);
+            al = lam;
+            bt = 0.f;
+            bs = 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            float xg[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int i = 16 * c + s;
+                xg[s] = 0.f;
+                if (i >= N) continue;
+                const float ti = fresh(av[i]) * bv[i];
+                float g3 = al * (S[i] - ti) - bt * ti + bs * S[i];
+                if (EQ8) g3 += g0 * sT[i] + g1 * sT[NP + i] + g2 * sT[2 * NP + i];
+                g3 = valid ? g3 : 0.f;
+#pragma unroll
+                for (int j = 0; j < K; ++j) gs[j] = fmaf(sD[i * K4 + j], g3, gs[j]);
+                xg[s] = g3;
+            }
+            wave_lds_order();
+#pragma unroll
+            for (int s = 0; s < 16; ++s) xcol[s * kRow] = xg[s];
+            wave_lds_order();
+            gd[c] = contract64(xrow, yrow[2], gd[c]);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) gs[j] = fresh(gs[j]);
+
+        // code-space gradients g_u = D^T r_a' + g_h v, g_v = D^T r_b' + g_h u,
+        // g_h = D^T g_3 (+ w_code (2/k) d for Eq. 8), then dE on the matrix
+        // cores: rows = codes, columns = samples
+        wave_lds_order();
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const float dcp = (EQ8 && valid) ? wk * dc[j] : 0.f;
+            const float gh = gs[j] + dcp;
+            ycol[j * kRow] = gu[j] + gh * v[j];
+            ycol[(K + j) * kRow] = gv[j] + gh * u[j];
+            if (EQ8) ycol[(2 * K + j) * kRow] = -dcp;
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int t = 0; t < TERMS_E; ++t) {
+                wave_lds_order();
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const int i = 16 * c + s;
+                    float x = 0.f;
+                    if (i < N) x = t == 0 ? av[i] : (t == 1 ? bv[i] : fresh(av[i]) * bv[i]);
+                    xcol[s * kRow] = x;
+                }
+                wave_lds_order();
+                ge[c] = contract64(yrow[t], xrow, ge[c]);
+            }
+        }
+    }
+
+    // the wavefronts' tiles, then their fixed-order sum into the partial row;
+    // [0, kn) is dL/dE (k x n), [kn, 2kn) dL/dD (n x k)
+    constexpr int kn = K * N;
+    static_assert(2 * kn <= 16 * kRow, "partial tile fits the sample block");
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * c + 4 * g + r, j = m;  // dD element of the tile
+            if (i < N && j < K) X[kn + i * K + j] = gd[c][r];
+            const int j2 = 4 * g + r, i2 = 16 * c + m;  // dE element
+            if (i2 < N && j2 < K) X[j2 * N + i2] = ge[c][r];
+        }
+    }
+    for (int mm = kWave / 2; mm >= 1; mm >>= 1) loss_acc += __shfl_xor(loss_acc, mm, kWave);
+    if (lane == 0) s_loss[wave] = loss_acc;
+    __syncthreads();
+    double* prow = a.part + int64_t(blockIdx.x) * (2 * kn + 1);
+    for (int e = tid; e < 2 * kn; e += kThreads) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kLaneWaves; ++w) t += double(sX[w][e]);
+        prow[e] = t;
+    }
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kLaneWaves; ++w) t += s_loss[w];
+        prow[2 * kn] = t;
+    }
+}
+
 // ------------------------------------------------------------------ kernel 3
 
 template <typename F>
@@ -465,6 +839,7 @@ struct FinishArgs {
     F* m_d;
     F* v_d;
     const int64_t* ws_step;
+    int64_t* step;  // Adam step counter: receives *ws_step
     double lr, beta1, beta2, eps;
     int adam;
 };
@@ -474,23 +849,28 @@ __global__ __launch_bounds__(kThreads) void codec_finish_kernel(FinishArgs<F> a)
     const int kn = a.k * a.n;
     const int lane = threadIdx.x & (kWave - 1);
     const int e = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    // the incremented step reaches the counter only now, after the pair draw
+    // of this step has read it
+    if (a.adam && e == 0 && lane == 0) *a.step = *a.ws_step;
     if (e > 2 * kn) return;
     const int64_t stride = 2 * kn + 1;
     // eight interleaved partial sums per lane keep eight row loads in flight
-    // (the rows of one element are a column: every load is its own line)
+    // (the rows of one element are a column: every load is its own line);
+    // rows past the table add 0
     constexpr int kIlp = 8;
     double acc[kIlp];
 #pragma unroll
     for (int u = 0; u < kIlp; ++u) acc[u] = 0.0;
-    int r = lane;
-    for (; r + (kIlp - 1) * kWave < a.rows; r += kIlp * kWave) {
+    for (int r0 = lane; r0 < a.rows; r0 += kIlp * kWave) {
         double v[kIlp];
 #pragma unroll
-        for (int u = 0; u < kIlp; ++u) v[u] = a.part[int64_t(r + u * kWave) * stride + e];
+        for (int u = 0; u < kIlp; ++u) {
+            const int r = r0 + u * kWave;
+            v[u] = r < a.rows ? a.part[int64_t(r) * stride + e] : 0.0;
+        }
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) acc[u] += v[u];
     }
-    for (; r < a.rows; r += kWave) acc[0] += a.part[int64_t(r) * stride + e];
     double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     for (int m = kWave / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, kWave);
     if (lane != 0) return;
@@ -569,16 +949,33 @@ Workspace carve(void* ws, int k, int n, int64_t rows, size_t esz) {
     return w;
 }
 
+inline void launch_lanes(const PartialArgs<double>&, bool, int, int64_t, hipStream_t) {}
+
+inline void launch_lanes(const PartialArgs<float>& p, bool eq8, int k, int64_t rows, hipStream_t st) {
+    const dim3 grid(static_cast<uint32_t>(rows)), block(kThreads);
+    if (k == 6) {
+        if (eq8) hipLaunchKernelGGL((codec_lanes_kernel<true, 6>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((codec_lanes_kernel<false, 6>), grid, block, 0, st, p);
+    } else {
+        if (eq8) hipLaunchKernelGGL((codec_lanes_kernel<true, 9>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((codec_lanes_kernel<false, 9>), grid, block, 0, st, p);
+    }
+}
+
 template <typename F>
 hc_status run(const hc_codec_args& a) {
     const int k = a.k, n = a.n, kn = k * n;
     hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
     const bool eq8 = a.objective == HC_CODEC_EQ8;
     const Plan pl = plan(k, n, a.N, sizeof(F), a.objective);
-    Workspace ws = carve(a.workspace, k, n, pl.grid, sizeof(F));
+    // float32 at n = 31 with k = 6 or 9 takes the lane-per-pair kernel (one
+    // partial row per 256 pairs), which stages softplus(Wt) itself
+    const bool lanes = std::is_same<F, float>::value && n == kLaneN && (k == 6 || k == 9);
+    const int64_t rows = lanes ? std::min<int64_t>(ceil_div(a.N, kThreads), kMaxRows) : pl.grid;
+    Workspace ws = carve(a.workspace, k, n, rows, sizeof(F));
     int64_t* adam_step = a.adam ? a.adam->step : nullptr;
     hc_status s = HC_OK;
-    if (!pl.ed_in_lds) {
+    if (!lanes && !pl.ed_in_lds) {
         // the partials kernel reads E and D from the workspace
         const int g0 = int(ceil_div(kn, kThreads));
         hipLaunchKernelGGL(codec_weights_kernel<F>, dim3(g0), dim3(kThreads), 0, st,
@@ -605,6 +1002,11 @@ hc_status run(const hc_codec_args& a) {
     p.rows_b = a.rows_b;
     p.idx_a = a.idx_a;
     p.idx_b = a.idx_b;
+    p.draw = a.draw != nullptr;
+    p.key_a = a.draw ? stream_key(a.draw->seed_a, kIndexStream) : 0;
+    p.key_b = a.draw ? stream_key(a.draw->seed_b, kIndexStream) : 0;
+    p.draw_ctr0 = a.draw ? a.draw->ctr0 : 0;
+    p.draw_scale = a.draw ? a.draw->ctr_scale_dev : nullptr;
     p.N = a.N;
     p.n_tiles = pl.n_tiles;
     p.part = ws.part;
@@ -612,7 +1014,7 @@ hc_status run(const hc_codec_args& a) {
     p.we = static_cast<const F*>(a.Wt_E);
     p.wd = static_cast<const F*>(a.Wt_D);
     p.beta = F(a.beta);
-    p.step = pl.ed_in_lds ? adam_step : nullptr;
+    p.step = (lanes || pl.ed_in_lds) ? adam_step : nullptr;
     p.ws_step = ws.step;
     p.T = static_cast<const F*>(a.T);
     p.w_e2e = a.w_e2e;
@@ -620,7 +1022,9 @@ hc_status run(const hc_codec_args& a) {
     p.w_code = a.w_code;
     p.w_col = a.w_col;
     p.eps = a.cos_eps;
-    if (eq8)
+    if (lanes)
+        launch_lanes(p, eq8, k, rows, st);
+    else if (eq8)
         hipLaunchKernelGGL(codec_partials_eq8_kernel<F>, dim3(uint32_t(pl.grid)), dim3(kThreads), pl.lds,
                            st, p);
     else
@@ -636,7 +1040,7 @@ hc_status run(const hc_codec_args& a) {
     f.inv_n = 1.0 / double(a.N);
     f.gscale = (eq8 ? 1.0 : 2.0) / double(a.N);
     f.part = ws.part;
-    f.rows = int(pl.grid);
+    f.rows = int(rows);
     f.we = static_cast<F*>(a.Wt_E);
     f.wd = static_cast<F*>(a.Wt_D);
     f.loss = static_cast<F*>(a.loss);
@@ -657,6 +1061,7 @@ hc_status run(const hc_codec_args& a) {
         f.lr = f.beta1 = f.beta2 = f.eps = 0.0;
     }
     f.ws_step = ws.step;
+    f.step = adam_step;
     const int g2 = int(ceil_div(2 * kn + 1, kThreads / kWave));
     hipLaunchKernelGGL(codec_finish_kernel<F>, dim3(g2), dim3(kThreads), 0, st, f);
     return launch_status("hc_codec_step");

@@ -3,6 +3,7 @@
 // 2014) applied to key + (counter + 1) * 0x9E3779B97F4A7C15, with
 // key = mix64(mix64(seed) + stream).  Any path is reproducible on its own.
 
+#include "counter_rng.hpp"
 #include "hc_internal.hpp"
 
 namespace hc {
@@ -11,22 +12,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kScanItems = 4;                      // items per thread in the scan
 constexpr int kScanTile = kThreads * kScanItems;   // pixels per scan block
-constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
-
-__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-__host__ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t stream) {
-    return mix64(mix64(seed) + stream);
-}
-__device__ __forceinline__ uint64_t rand64(uint64_t key, uint64_t ctr) {
-    return mix64(key + (ctr + 1) * kGolden);
-}
-__device__ __forceinline__ uint32_t range32(uint64_t r, uint64_t n) {
-    return static_cast<uint32_t>(((r & 0xFFFFFFFFull) * n) >> 32);
-}
 
 struct GenArgs {
     int64_t n_pixels;
@@ -309,7 +294,7 @@ hc_status launch_gen_vertices(const hc_path_gen& g, const uint32_t* pix_first, u
 hc_status launch_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* scale, int64_t count,
                              int64_t n, uint32_t* out, hipStream_t st) {
     hipLaunchKernelGGL(gen_indices_kernel, dim3(uint32_t(ceil_div(count, kThreads))), dim3(kThreads), 0,
-                       st, stream_key(seed, 3), ctr0, scale, count, uint64_t(n), out);
+                       st, stream_key(seed, kIndexStream), ctr0, scale, count, uint64_t(n), out);
     return launch_status("hc_gen_indices");
 }
 

@@ -181,11 +181,14 @@ EQ8_WEIGHTS = (0.5, 0.75, 1.0, 0.5)   # w_e2e, w_rec, w_code, w_col of Eq. 8 (Se
 def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a=None, idx_b=None,
                loss=None, grad_e=None, grad_d=None, adam: dict | None = None,
                workspace: CodecWorkspace | None = None, objective: str = "l2", T=None,
-               weights=EQ8_WEIGHTS, cos_eps: float = 1e-8):
+               weights=EQ8_WEIGHTS, cos_eps: float = 1e-8, draw: dict | None = None):
     """One loss/gradient (and optional Adam) evaluation on the GPU.
 
     A, B: (rows, n) tensors of the parameters' dtype; with idx_a/idx_b the
-    batch rows are gathered by index.  adam: dict with m_E, v_E, m_D, v_D,
+    batch rows are gathered by index; with draw = dict(seed_a, seed_b, ctr0=0,
+    step=None) they are drawn on the device: row i of the a-batch is what
+    gen_indices(seed_a, N, rows of A, ctr0, step)[i] would be (likewise b),
+    with no index arrays.  adam: dict with m_E, v_E, m_D, v_D,
     step (int64 device tensor), lr, beta1, beta2, eps.  objective "l2" is the
     two-term squared error weighted by lam; "eq8" the four-term loss of
     Eq. 8 with `weights` (w_e2e, w_rec, w_code, w_col) and the 3 x n
@@ -210,6 +213,14 @@ def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a
                        adam["v_D"].data_ptr(), adam["step"].data_ptr(), adam.get("lr", 1e-3),
                        adam.get("beta1", 0.9), adam.get("beta2", 0.999), adam.get("eps", 1e-8))
     w = tuple(float(x) for x in weights) if eq8 else (0.0, 0.0, 0.0, 0.0)
+    dr = None
+    if draw is not None:
+        if idx_a is not None or idx_b is not None:
+            raise ValueError("draw excludes idx_a / idx_b")
+        step = draw.get("step")
+        if step is not None:
+            _dev(step)
+        dr = _lib.PairDraw(int(draw["seed_a"]), int(draw["seed_b"]), int(draw.get("ctr0", 0)), _ptr(step))
     args = _lib.CodecArgs(
         k, n, dt, _lib.HC_CODEC_EQ8 if eq8 else _lib.HC_CODEC_L2, beta, lam, we.data_ptr(),
         wd.data_ptr(), A.data_ptr(), B.data_ptr(),
@@ -218,7 +229,8 @@ def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a
         N, loss.data_ptr(), None if grad_e is None else grad_e.data_ptr(),
         None if grad_d is None else grad_d.data_ptr(), C.pointer(ad) if ad is not None else None,
         workspace.buf.data_ptr(), workspace.bytes, torch.cuda.current_stream().cuda_stream,
-        T.data_ptr() if eq8 else None, *w, cos_eps if eq8 else 0.0)
+        T.data_ptr() if eq8 else None, *w, cos_eps if eq8 else 0.0,
+        C.pointer(dr) if dr is not None else None)
     check(load().hc_codec_step(C.byref(args)), "hc_codec_step")
     return loss
 

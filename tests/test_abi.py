@@ -35,6 +35,8 @@ def test_struct_sizes_match_header():
     assert C.sizeof(_lib.LatentAssets) == 56
     assert C.sizeof(_lib.Adam) == 72
     assert C.sizeof(_lib.PathGen) == 40
+    assert C.sizeof(_lib.PairDraw) == 32
+    assert C.sizeof(_lib.CodecArgs) == 232
 
 
 def _err(status):
@@ -94,6 +96,27 @@ def test_codec_step_rejects_small_workspace(lib):
     assert s == _lib.HC_ENOMEM and str(need) in msg
     args.dtype = 2
     assert lib.hc_codec_step(C.byref(args)) == _lib.HC_EINVAL
+
+
+def test_codec_step_validates_the_pair_draw(lib):
+    need = lib.hc_codec_workspace_size(6, 31, 65536)
+    args = _lib.CodecArgs(6, 31, 0, 0, 10.0, 1.0, 0x1000, 0x1000, 0x1000, 0x1000, 31, 31,
+                          1 << 20, 1 << 20, 0x1000, None, 65536, 0x1000, None, None, None,
+                          0x1000, need, None)
+    dr = _lib.PairDraw(1, 2, 0, None)
+    args.draw = C.pointer(dr)
+    s, msg = _err(lib.hc_codec_step(C.byref(args)))
+    assert s == _lib.HC_EINVAL and "draw excludes" in msg
+    args.idx_a = None
+    args.rows_b = 1 << 32
+    s, msg = _err(lib.hc_codec_step(C.byref(args)))
+    assert s == _lib.HC_ESHAPE and "2^32" in msg
+    args.rows_b = 0
+    assert lib.hc_codec_step(C.byref(args)) == _lib.HC_ESHAPE
+    args.rows_b = 1 << 20
+    dr.ctr_scale_dev = 0x1004
+    s, msg = _err(lib.hc_codec_step(C.byref(args)))
+    assert s == _lib.HC_EALIGN and "counter" in msg
 
 
 def test_codec_step_validates_the_eq8_objective(lib):

@@ -100,6 +100,49 @@ def test_gather_by_index_equals_explicit_batch(ops):
     assert torch.equal(l1, l2) and torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])
 
 
+@pytest.mark.parametrize("objective", ["l2", "eq8"])
+@pytest.mark.parametrize("n,k,dtype", [(31, 6, torch.float32), (31, 9, torch.float32), (81, 9, torch.float32),
+                                       (31, 7, torch.float32), (31, 6, torch.float64)])
+def test_drawn_rows_equal_generated_indices(ops, objective, n, k, dtype):
+    """Rows drawn inside the step are the rows hc_gen_indices writes for the
+    same seeds and counters: loss and gradients equal bit for bit, over three
+    Adam steps whose draws take their counter base from the step counter (the
+    draw must see each step's counter before the step increments it).  The
+    cases cover the lane-per-pair kernel (float32, n = 31, k = 6 or 9) and the
+    tiled kernels."""
+    N, rows = 3001, 20000
+    rng = np.random.default_rng(n + k)
+    we, wd = synth.codec_init(rng, k, n)
+    pa, pb = _pairs(n, rows, 11)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(np.asarray(x, npdt))).cuda()  # noqa: E731
+    T = t(synth.cmf_matrix(n)) if objective == "eq8" else None
+    A, B = t(pa), t(pb)
+    runs = []
+    for use_draw in (False, True):
+        Wt_E, Wt_D = t(we), t(wd)
+        st = dict(m_E=torch.zeros_like(Wt_E), v_E=torch.zeros_like(Wt_E), m_D=torch.zeros_like(Wt_D),
+                  v_D=torch.zeros_like(Wt_D), step=torch.full((1,), 5, dtype=torch.int64, device="cuda"),
+                  lr=1e-3)
+        out = []
+        for _ in range(3):
+            ge = torch.empty(k, n, dtype=dtype, device="cuda")
+            gd = torch.empty(n, k, dtype=dtype, device="cuda")
+            kw = dict(grad_e=ge, grad_d=gd, adam=st, objective=objective, T=T)
+            if use_draw:
+                loss = ops.codec_step(Wt_E, Wt_D, A, B, N, draw=dict(seed_a=7, seed_b=8, ctr0=3, step=st["step"]),
+                                      **kw)
+            else:
+                ia = ops.gen_indices(7, N, rows, ctr0=3, step=st["step"])
+                ib = ops.gen_indices(8, N, rows, ctr0=3, step=st["step"])
+                loss = ops.codec_step(Wt_E, Wt_D, A, B, N, idx_a=ia, idx_b=ib, **kw)
+            out += [loss.clone(), ge, gd]
+        torch.cuda.synchronize()
+        assert int(st["step"].item()) == 8
+        runs.append(out + [Wt_E, Wt_D])
+    assert all(torch.equal(x, y) for x, y in zip(*runs))
+
+
 def test_step_is_deterministic(ops):
     n, k, N = 81, 9, 65536
     rng = np.random.default_rng(6)

@@ -33,19 +33,22 @@ def _same(a, b):
         all(torch.equal(a.adam[x], b.adam[x]) for x in ("m_E", "v_E", "m_D", "v_D", "step"))
 
 
-def test_graph_replay_equals_eager_steps(fitcls, pools):
+@pytest.mark.parametrize("per_graph", [1, 4])
+def test_graph_replay_equals_eager_steps(fitcls, pools, per_graph):
+    """Graphs of one step and of four steps (each step drawing its pairs from
+    the device counter at replay time) equal eager steps bit for bit."""
     eager = _fit(fitcls, pools)
-    eager.run(12)
+    eager.run(16)
     graphed = _fit(fitcls, pools)
     graphed.run(1)
-    graphed.capture()
+    graphed.capture(per_graph)
     for _ in range(3):           # replays separated by host work and syncs
-        graphed.run(1)
+        graphed.run(per_graph)
         torch.cuda.synchronize()
         _ = float(graphed.loss)
-    graphed.run(8)
+    graphed.run(15 - 3 * per_graph)   # whole replays, then single steps
     torch.cuda.synchronize()
-    assert graphed.steps_done == eager.steps_done == 12
+    assert graphed.steps_done == eager.steps_done == 16
     assert _same(eager, graphed) and torch.equal(eager.loss, graphed.loss)
 
 
