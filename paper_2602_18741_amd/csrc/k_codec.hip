@@ -25,6 +25,7 @@
 //                applies the softplus slope logistic(beta Wt) and optionally
 //                the Adam update.
 
+#include <cmath>
 #include <type_traits>
 
 #include "counter_rng.hpp"
@@ -463,29 +464,35 @@ __global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArg
     }
 }
 
-// ------------------------------------------------------------------ kernel 2, lane-per-pair form
+// ------------------------------------------------------------------ kernel 2, two lanes per pair
 //
-// float32 with n = 31 (400-700 nm at 10 nm) and k = 6 or 9.  A lane owns one
-// pair: a and b, the residuals and the codes stay in registers, every loop
-// has compile-time bounds, and E, D and T are read from LDS at one address
-// for the whole wavefront (a broadcast).  The sums over pairs of outer
+// float32 with n = 31 (400-700 nm at 10 nm) and k = 6 or 9.  Lanes 2p and
+// 2p + 1 of a wavefront own pair p of its 32: each holds one half of the
+// samples (0-15, 16-30) of a and b in registers, and every loop has
+// compile-time bounds.  Sums over the samples (the codes E a, E b, E t, the
+// per-pair norms, D^T r) are taken per half and completed with one DPP add
+// of the partner lane, so both lanes hold the same values.  E, D and T are
+// read from LDS at the two halves' addresses.  The sums over pairs of outer
 // products,
 //   dD = sum_p r_a' u^T + r_b' v^T + g_3 h^T,   dE = sum_p g_u a^T + g_v b^T + c_3 t^T
 // (g_3 = g_S and c_3 = -w_code (2/k) d for Eq. 8; g_3 = lambda r_h and no third
 // dE term for the two-term loss), are contractions over the pairs and run on
-// the fp32 matrix cores (v_mfma_f32_16x16x4_f32, K = pairs).  For one term and
-// 16 samples a lane writes its pair's values down its column of the wave's
-// [16 rows][64 pairs] LDS block; lane (g, m) then reads row m, pairs
-// 16g .. 16g+15, as four 16-byte loads feeding 16 matrix steps (step s takes
-// pairs s, 16 + s, 32 + s, 48 + s).  Rows are 68 floats apart, so the column
-// writes of a row and each 8-lane group of row reads fall on distinct banks,
-// and every access is one base register plus a constant offset.  The
-// wavefronts of a workgroup are summed in a fixed order into one partial row.
+// the fp32 matrix cores (v_mfma_f32_16x16x4_f32, K = pairs).  For one term
+// each lane writes its 16 samples down its pair's column of the wave's
+// [2 halves][16 samples][32 pairs] LDS block; for the 16-sample tile of half
+// c, lane (g, m) reads row m, pairs 8g .. 8g+7, as two 16-byte loads feeding
+// 8 matrix steps (step s takes pairs s, 8 + s, 16 + s, 24 + s).  Rows are 36
+// floats apart and the two halves 32 banks apart, so the column writes and
+// each 8-lane group of row reads fall on distinct banks.  The wavefronts of
+// a workgroup are summed in a fixed order into one partial row.
 
 constexpr int kLaneN = 31;
 constexpr int kLanePad = 32;
-constexpr int kLaneWaves = kThreads / kWave;
-constexpr int kRow = kWave + 4;  // LDS row stride of the contraction blocks
+constexpr int kLaneThreads = 512;
+constexpr int kLaneWaves = kLaneThreads / kWave;
+constexpr int kWavePairs = kWave / 2;                 // pairs per wavefront
+constexpr int kRow = kWavePairs + 4;                  // LDS row stride of the contraction blocks
+constexpr int kHalfStride = 16 * kRow + 32;           // second half's block, 32 banks over
 
 typedef float hc_mf4 __attribute__((ext_vector_type(4)));
 
@@ -510,11 +517,17 @@ __device__ __forceinline__ float fresh(float x) {
     return x;
 }
 
-// c += sum over the wave's 64 pairs of L[row m][pair] R[row m'][pair] for the
-// 16 x 16 tile (m, m'); lrow / rrow point at pair 16g of the lane's rows.
-__device__ __forceinline__ hc_mf4 contract64(const float* lrow, const float* rrow, hc_mf4 c) {
+// x plus the partner lane's x (lanes 2p, 2p + 1): the same value on both.
+__device__ __forceinline__ float pair_sum(float x) {
+    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    return fresh(x + __int_as_float(y));
+}
+
+// c += sum over the wave's 32 pairs of L[row m][pair] R[row m'][pair] for the
+// 16 x 16 tile (m, m'); lrow / rrow point at pair 8g of the lane's rows.
+__device__ __forceinline__ hc_mf4 contract32(const float* lrow, const float* rrow, hc_mf4 c) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 2; ++q) {
         const hc_mf4 x = *reinterpret_cast<const hc_mf4*>(lrow + 4 * q);
         const hc_mf4 y = *reinterpret_cast<const hc_mf4*>(rrow + 4 * q);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[0], y[0], c, 0, 0, 0);
@@ -526,63 +539,50 @@ __device__ __forceinline__ hc_mf4 contract64(const float* lrow, const float* rro
 }
 
 template <bool EQ8, int K>
-__global__ __launch_bounds__(kThreads) void codec_lanes_kernel(PartialArgs<float> a) {
+__global__ __launch_bounds__(kLaneThreads) void codec_lanes_kernel(PartialArgs<float> a) {
     constexpr int N = kLaneN, NP = kLanePad, K4 = (K + 3) & ~3;
     constexpr int TERMS_E = EQ8 ? 3 : 2;
     __shared__ __align__(16) float sE[K * NP];   // E, rows padded with 0
     __shared__ __align__(16) float sDt[K * NP];  // D^T, rows padded with 0
-    __shared__ __align__(16) float sD[NP * K4];  // D, rows padded with 0
+    __shared__ __align__(16) float sD[NP * K4];  // D, rows padded with 0 (row 31 too)
     __shared__ __align__(16) float sT[3 * NP];
-    __shared__ __align__(16) float sZero[kWave];
-    __shared__ __align__(16) float sX[kLaneWaves][16 * kRow];     // samples x pairs
-    __shared__ __align__(16) float sY[kLaneWaves][3 * K * kRow];  // codes x pairs, 3 terms
+    __shared__ __align__(16) float sZero[kWavePairs];
+    __shared__ __align__(16) float sX[kLaneWaves][2 * kHalfStride];  // [half][sample][pair]
+    __shared__ __align__(16) float sY[kLaneWaves][3 * K * kRow];     // [term][code][pair]
     __shared__ double s_loss[kLaneWaves];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave;
-    // the pair rows of a chunk of 64 pairs (row 0 for lanes past the batch);
-    // the first chunk's loads are in flight while the tables are staged
+    const int pr = lane >> 1, hf = lane & 1;  // pair in the wave, half of the samples
+    const int i0 = 16 * hf;
     const uint64_t ctr_base = a.draw ? draw_base(a) : 0ull;
-    float av[N], bv[N];
-    auto load_rows = [&](int64_t ch) {
-        const int64_t pi = ch * kWave + lane;
-        int64_t ra = 0, rb = 0;
-        if (pi < a.N) batch_rows(a, ctr_base, pi, ra, rb);
-        const float* pa = a.A + ra * a.ld_a;
-        const float* pb = a.B + rb * a.ld_b;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            av[i] = pa[i];
-            bv[i] = pb[i];
-        }
-    };
-    const int64_t ch0 = int64_t(blockIdx.x) * kLaneWaves + wave;
-    if (ch0 * kWave < a.N) load_rows(ch0);
-    for (int e = tid; e < K * NP; e += kThreads) {
+
+    for (int e = tid; e < K * NP; e += kLaneThreads) {
         const int j = e / NP, i = e % NP;
         sE[e] = i < N ? softplus(a.we[j * N + i], a.beta) : 0.f;
         sDt[e] = i < N ? softplus(a.wd[i * K + j], a.beta) : 0.f;
     }
-    for (int e = tid; e < NP * K4; e += kThreads) {
+    for (int e = tid; e < NP * K4; e += kLaneThreads) {
         const int i = e / K4, j = e % K4;
         sD[e] = (i < N && j < K) ? softplus(a.wd[i * K + j], a.beta) : 0.f;
     }
     if (EQ8)
-        for (int e = tid; e < 3 * NP; e += kThreads) sT[e] = e % NP < N ? a.T[(e / NP) * N + e % NP] : 0.f;
-    if (tid < kWave) sZero[tid] = 0.f;
+        for (int e = tid; e < 3 * NP; e += kLaneThreads)
+            sT[e] = e % NP < N ? a.T[(e / NP) * N + e % NP] : 0.f;
+    if (tid < kWavePairs) sZero[tid] = 0.f;
     if (a.step && blockIdx.x == 0 && tid == 0) *a.ws_step = *a.step + 1;
     __syncthreads();
 
     const int g = lane >> 4, m = lane & 15;
     float* X = sX[wave];
     float* Y = sY[wave];
-    float* xcol = X + lane;  // the lane's column: row s at xcol[s * kRow]
-    float* ycol = Y + lane;
-    const float* xrow = X + m * kRow + 16 * g;
+    float* xcol = X + hf * kHalfStride + pr;  // the lane's column: sample s at xcol[s * kRow]
+    float* ycol = Y + pr;
+    const float* xrow[2] = {X + m * kRow + 8 * g, X + kHalfStride + m * kRow + 8 * g};
     // rows of the code blocks past k read zeros
     const float* yrow[3];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) yrow[t] = m < K ? Y + (t * K + m) * kRow + 16 * g : sZero + 16 * g;
+    for (int t = 0; t < 3; ++t) yrow[t] = m < K ? Y + (t * K + m) * kRow + 8 * g : sZero + 8 * g;
 
     hc_mf4 gd[2], ge[2];
 #pragma unroll
@@ -592,16 +592,30 @@ __global__ __launch_bounds__(kThreads) void codec_lanes_kernel(PartialArgs<float
     const float wr = EQ8 ? float(a.w_rec * 2.0 / N) : 1.f;
     const float wk = EQ8 ? float(a.w_code * 2.0 / K) : 0.f;
 
-    for (int64_t ch = ch0; ch * kWave < a.N; ch += int64_t(gridDim.x) * kLaneWaves) {
+    for (int64_t ch = int64_t(blockIdx.x) * kLaneWaves + wave; ch * kWavePairs < a.N;
+         ch += int64_t(gridDim.x) * kLaneWaves) {
         // keeps the reads of E, D and T from LDS inside the loop: hoisted out
         // of it, all of them would stay live in registers
         reread_tables();
-        if (ch != ch0) load_rows(ch);
-        const bool valid = ch * kWave + lane < a.N;
+        const int64_t pi = ch * kWavePairs + pr;
+        const bool valid = pi < a.N;
+        int64_t ra = 0, rb = 0;
+        if (valid) batch_rows(a, ctr_base, pi, ra, rb);
+        const float* pa = a.A + ra * a.ld_a + i0;
+        const float* pb = a.B + rb * a.ld_b + i0;
+        // the half's samples; sample 31 (past n) reads sample 30 and is zeroed
+        float av[16], bv[16];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            av[i] = valid ? av[i] : 0.f;
-            bv[i] = valid ? bv[i] : 0.f;
+        for (int s = 0; s < 16; ++s) {
+            const int o = s < 15 ? s : 15 - hf;
+            av[s] = pa[o];
+            bv[s] = pb[o];
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const bool in = valid && (s < 15 || hf == 0);
+            av[s] = in ? av[s] : 0.f;
+            bv[s] = in ? bv[s] : 0.f;
         }
 
         // codes u = E a, v = E b, h = u v (Eq. 4, Eq. 6); Eq. 8: d = h - E t
@@ -610,98 +624,96 @@ __global__ __launch_bounds__(kThreads) void codec_lanes_kernel(PartialArgs<float
         for (int j = 0; j < K; ++j) {
             float su = 0.f, sv = 0.f, sw = 0.f;
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const float e = sE[j * NP + i];
-                su = fmaf(e, av[i], su);
-                sv = fmaf(e, bv[i], sv);
-                if (EQ8) sw = fmaf(e, fresh(av[i]) * bv[i], sw);
+            for (int s = 0; s < 16; ++s) {
+                const float e = sE[j * NP + i0 + s];
+                su = fmaf(e, av[s], su);
+                sv = fmaf(e, bv[s], sv);
+                if (EQ8) sw = fmaf(e, fresh(av[s]) * bv[s], sw);
             }
-            u[j] = fresh(su);
-            v[j] = fresh(sv);
-            h[j] = su * sv;
-            dc[j] = EQ8 ? fresh(h[j] - sw) : 0.f;
+            u[j] = pair_sum(su);
+            v[j] = pair_sum(sv);
+            h[j] = u[j] * v[j];
+            dc[j] = EQ8 ? fresh(h[j] - pair_sum(sw)) : 0.f;
         }
         wave_lds_order();  // the previous chunk's reads of the code block are done
+        if (hf == 0) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            ycol[j * kRow] = u[j];
-            ycol[(K + j) * kRow] = v[j];
-            ycol[(2 * K + j) * kRow] = h[j];
+            for (int j = 0; j < K; ++j) {
+                ycol[j * kRow] = u[j];
+                ycol[(K + j) * kRow] = v[j];
+                ycol[(2 * K + j) * kRow] = h[j];
+            }
         }
 
-        // reconstructions D u, D v, D h, 16 samples at a time: the per-pair
-        // sums, D^T r_a' and D^T r_b' accumulated as the residuals appear,
-        // and their dD terms on the matrix cores
+        // reconstructions D u, D v, D h of the half's samples: the per-pair
+        // sums, D^T r_a' and D^T r_b' accumulated as the residuals appear
         reread_tables();
-        float S[N];
+        float S[16], xa[16], xb[16];
         float gu[K], gv[K], gs[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) gu[j] = gv[j] = gs[j] = 0.f;
         float s_rr = 0.f, s_rh = 0.f, s_st = 0.f, s_ss = 0.f, s_tt = 0.f, s_c0 = 0.f, s_c1 = 0.f, s_c2 = 0.f;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            float xa[16], xb[16];
+        for (int s = 0; s < 16; ++s) {
+            const int i = i0 + s;  // row 31 of D and T is zero
+            float du = 0.f, dv = 0.f, dh = 0.f;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int i = 16 * c + s;
-                xa[s] = xb[s] = 0.f;
-                if (i >= N) continue;
-                float du = 0.f, dv = 0.f, dh = 0.f;
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const float d = sD[i * K4 + j];
-                    du = fmaf(d, u[j], du);
-                    dv = fmaf(d, v[j], dv);
-                    dh = fmaf(d, h[j], dh);
-                }
-                const float ti = fresh(av[i]) * bv[i];
-                const float rai = du - av[i], rbi = dv - bv[i], rh = dh - ti;
-                S[i] = dh;
-                s_rr = fmaf(rai, rai, fmaf(rbi, rbi, s_rr));
-                s_rh = fmaf(rh, rh, s_rh);
-                if (EQ8) {
-                    s_st = fmaf(dh, ti, s_st);
-                    s_ss = fmaf(dh, dh, s_ss);
-                    s_tt = fmaf(ti, ti, s_tt);
-                    s_c0 = fmaf(sT[i], rh, s_c0);
-                    s_c1 = fmaf(sT[NP + i], rh, s_c1);
-                    s_c2 = fmaf(sT[2 * NP + i], rh, s_c2);
-                }
-                const float rap = valid ? wr * rai : 0.f, rbp = valid ? wr * rbi : 0.f;
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const float d = sD[i * K4 + j];
-                    gu[j] = fmaf(d, rap, gu[j]);
-                    gv[j] = fmaf(d, rbp, gv[j]);
-                }
-                xa[s] = rap;
-                xb[s] = rbp;
+            for (int j = 0; j < K; ++j) {
+                const float d = sD[i * K4 + j];
+                du = fmaf(d, u[j], du);
+                dv = fmaf(d, v[j], dv);
+                dh = fmaf(d, h[j], dh);
             }
-            wave_lds_order();
+            const float ti = fresh(av[s]) * bv[s];
+            const float rai = du - av[s], rbi = dv - bv[s], rh = dh - ti;
+            S[s] = dh;
+            s_rr = fmaf(rai, rai, fmaf(rbi, rbi, s_rr));
+            s_rh = fmaf(rh, rh, s_rh);
+            if (EQ8) {
+                s_st = fmaf(dh, ti, s_st);
+                s_ss = fmaf(dh, dh, s_ss);
+                s_tt = fmaf(ti, ti, s_tt);
+                s_c0 = fmaf(sT[i], rh, s_c0);
+                s_c1 = fmaf(sT[NP + i], rh, s_c1);
+                s_c2 = fmaf(sT[2 * NP + i], rh, s_c2);
+            }
+            const float rap = valid ? wr * rai : 0.f, rbp = valid ? wr * rbi : 0.f;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) xcol[s * kRow] = xa[s];
-            wave_lds_order();
-            gd[c] = contract64(xrow, yrow[0], gd[c]);
-            wave_lds_order();
-#pragma unroll
-            for (int s = 0; s < 16; ++s) xcol[s * kRow] = xb[s];
-            wave_lds_order();
-            gd[c] = contract64(xrow, yrow[1], gd[c]);
+            for (int j = 0; j < K; ++j) {
+                const float d = sD[i * K4 + j];
+                gu[j] = fmaf(d, rap, gu[j]);
+                gv[j] = fmaf(d, rbp, gv[j]);
+            }
+            xa[s] = rap;
+            xb[s] = rbp;
         }
+        // dD terms r_a' u^T and r_b' v^T: rows = samples, columns = codes
+        wave_lds_order();
+#pragma unroll
+        for (int s = 0; s < 16; ++s) xcol[s * kRow] = xa[s];
+        wave_lds_order();
+        gd[0] = contract32(xrow[0], yrow[0], gd[0]);
+        gd[1] = contract32(xrow[1], yrow[0], gd[1]);
+        wave_lds_order();
+#pragma unroll
+        for (int s = 0; s < 16; ++s) xcol[s * kRow] = xb[s];
+        wave_lds_order();
+        gd[0] = contract32(xrow[0], yrow[1], gd[0]);
+        gd[1] = contract32(xrow[1], yrow[1], gd[1]);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            gu[j] = fresh(gu[j]);
-            gv[j] = fresh(gv[j]);
+            gu[j] = pair_sum(gu[j]);
+            gv[j] = pair_sum(gv[j]);
         }
-        s_rr = fresh(s_rr);
-        s_rh = fresh(s_rh);
+        s_rr = pair_sum(s_rr);
+        s_rh = pair_sum(s_rh);
         if (EQ8) {
-            s_st = fresh(s_st);
-            s_ss = fresh(s_ss);
-            s_tt = fresh(s_tt);
-            s_c0 = fresh(s_c0);
-            s_c1 = fresh(s_c1);
-            s_c2 = fresh(s_c2);
+            s_st = pair_sum(s_st);
+            s_ss = pair_sum(s_ss);
+            s_tt = pair_sum(s_tt);
+            s_c0 = pair_sum(s_c0);
+            s_c1 = pair_sum(s_c1);
+            s_c2 = pair_sum(s_c2);
         }
 
         // per-pair factors of the third term: g_3 = g_S (Eq. 8) or lambda r_h
@@ -717,7 +729,7 @@ __global__ __launch_bounds__(kThreads) void codec_lanes_kernel(PartialArgs<float
             const double tn = sqrt(double(s_tt));
             const double nt = tn > a.eps ? tn : a.eps;
             const double cs = double(s_st) / (ns * nt);
-            if (valid)
+            if (valid && hf == 0)
                 loss_acc += a.w_e2e * M * (2.0 - cs) + a.w_rec * double(s_rr) / N + a.w_code * double(s_dd) / K +
                             a.w_col * (double(s_c0) * s_c0 + double(s_c1) * s_c1 + double(s_c2) * s_c2) / 3.0;
             // g_S = al r_h - bt t + bs S + T^T gc
@@ -728,70 +740,63 @@ __global__ __launch_bounds__(kThreads) void codec_lanes_kernel(PartialArgs<float
             g1 = float(a.w_col * (2.0 / 3.0) * s_c1);
             g2 = float(a.w_col * (2.0 / 3.0) * s_c2);
         } else {
-            if (valid) loss_acc += double(s_rr) + double(lam) * double(s_rh);
+            if (valid && hf == 0) loss_acc += double(s_rr) + double(lam) * double(s_rh);
             al = lam;
             bt = 0.f;
             bs = 0.f;
         }
+        float xg[16];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            float xg[16];
+        for (int s = 0; s < 16; ++s) {
+            const int i = i0 + s;
+            const float ti = fresh(av[s]) * bv[s];
+            float g3 = al * (S[s] - ti) - bt * ti + bs * S[s];
+            if (EQ8) g3 += g0 * sT[i] + g1 * sT[NP + i] + g2 * sT[2 * NP + i];
+            g3 = valid ? g3 : 0.f;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int i = 16 * c + s;
-                xg[s] = 0.f;
-                if (i >= N) continue;
-                const float ti = fresh(av[i]) * bv[i];
-                float g3 = al * (S[i] - ti) - bt * ti + bs * S[i];
-                if (EQ8) g3 += g0 * sT[i] + g1 * sT[NP + i] + g2 * sT[2 * NP + i];
-                g3 = valid ? g3 : 0.f;
-#pragma unroll
-                for (int j = 0; j < K; ++j) gs[j] = fmaf(sD[i * K4 + j], g3, gs[j]);
-                xg[s] = g3;
-            }
-            wave_lds_order();
-#pragma unroll
-            for (int s = 0; s < 16; ++s) xcol[s * kRow] = xg[s];
-            wave_lds_order();
-            gd[c] = contract64(xrow, yrow[2], gd[c]);
+            for (int j = 0; j < K; ++j) gs[j] = fmaf(sD[i * K4 + j], g3, gs[j]);
+            xg[s] = g3;
         }
+        // dD term g_3 h^T
+        wave_lds_order();
 #pragma unroll
-        for (int j = 0; j < K; ++j) gs[j] = fresh(gs[j]);
+        for (int s = 0; s < 16; ++s) xcol[s * kRow] = xg[s];
+        wave_lds_order();
+        gd[0] = contract32(xrow[0], yrow[2], gd[0]);
+        gd[1] = contract32(xrow[1], yrow[2], gd[1]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) gs[j] = pair_sum(gs[j]);
 
         // code-space gradients g_u = D^T r_a' + g_h v, g_v = D^T r_b' + g_h u,
         // g_h = D^T g_3 (+ w_code (2/k) d for Eq. 8), then dE on the matrix
         // cores: rows = codes, columns = samples
         wave_lds_order();
+        if (hf == 0) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const float dcp = (EQ8 && valid) ? wk * dc[j] : 0.f;
-            const float gh = gs[j] + dcp;
-            ycol[j * kRow] = gu[j] + gh * v[j];
-            ycol[(K + j) * kRow] = gv[j] + gh * u[j];
-            if (EQ8) ycol[(2 * K + j) * kRow] = -dcp;
+            for (int j = 0; j < K; ++j) {
+                const float dcp = (EQ8 && valid) ? wk * dc[j] : 0.f;
+                const float gh = gs[j] + dcp;
+                ycol[j * kRow] = gu[j] + gh * v[j];
+                ycol[(K + j) * kRow] = gv[j] + gh * u[j];
+                if (EQ8) ycol[(2 * K + j) * kRow] = -dcp;
+            }
         }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int t = 0; t < TERMS_E; ++t) {
+            wave_lds_order();
 #pragma unroll
-            for (int t = 0; t < TERMS_E; ++t) {
-                wave_lds_order();
-#pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    const int i = 16 * c + s;
-                    float x = 0.f;
-                    if (i < N) x = t == 0 ? av[i] : (t == 1 ? bv[i] : fresh(av[i]) * bv[i]);
-                    xcol[s * kRow] = x;
-                }
-                wave_lds_order();
-                ge[c] = contract64(yrow[t], xrow, ge[c]);
-            }
+            for (int s = 0; s < 16; ++s)
+                xcol[s * kRow] = t == 0 ? av[s] : (t == 1 ? bv[s] : fresh(av[s]) * bv[s]);
+            wave_lds_order();
+            ge[0] = contract32(yrow[t], xrow[0], ge[0]);
+            ge[1] = contract32(yrow[t], xrow[1], ge[1]);
         }
     }
 
     // the wavefronts' tiles, then their fixed-order sum into the partial row;
     // [0, kn) is dL/dE (k x n), [kn, 2kn) dL/dD (n x k)
     constexpr int kn = K * N;
-    static_assert(2 * kn <= 16 * kRow, "partial tile fits the sample block");
+    static_assert(2 * kn <= 2 * kHalfStride, "partial tile fits the sample block");
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -807,7 +812,7 @@ __global__ __launch_bounds__(kThreads) void codec_lanes_kernel(PartialArgs<float
     if (lane == 0) s_loss[wave] = loss_acc;
     __syncthreads();
     double* prow = a.part + int64_t(blockIdx.x) * (2 * kn + 1);
-    for (int e = tid; e < 2 * kn; e += kThreads) {
+    for (int e = tid; e < 2 * kn; e += kLaneThreads) {
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < kLaneWaves; ++w) t += double(sX[w][e]);
@@ -841,6 +846,7 @@ struct FinishArgs {
     const int64_t* ws_step;
     int64_t* step;  // Adam step counter: receives *ws_step
     double lr, beta1, beta2, eps;
+    double ln_beta1, ln_beta2;
     int adam;
 };
 
@@ -854,6 +860,22 @@ __global__ __launch_bounds__(kThreads) void codec_finish_kernel(FinishArgs<F> a)
     if (a.adam && e == 0 && lane == 0) *a.step = *a.ws_step;
     if (e > 2 * kn) return;
     const int64_t stride = 2 * kn + 1;
+    const bool isE = e < kn;
+    const int idx = isE ? e : e - kn;
+    F* w = isE ? a.we : a.wd;
+    F* m = isE ? a.m_e : a.m_d;
+    F* v = isE ? a.v_e : a.v_d;
+    // lane 0's parameter, Adam state and step are fetched with the partial
+    // rows, so their latency overlaps that of the sums
+    double wt = 0.0, m0 = 0.0, v0 = 0.0, t = 0.0;
+    if (lane == 0 && e < 2 * kn) {
+        wt = double(w[idx]);
+        if (a.adam) {
+            m0 = double(m[idx]);
+            v0 = double(v[idx]);
+            t = double(*a.ws_step);
+        }
+    }
     // eight interleaved partial sums per lane keep eight row loads in flight
     // (the rows of one element are a column: every load is its own line);
     // rows past the table add 0
@@ -862,37 +884,31 @@ __global__ __launch_bounds__(kThreads) void codec_finish_kernel(FinishArgs<F> a)
 #pragma unroll
     for (int u = 0; u < kIlp; ++u) acc[u] = 0.0;
     for (int r0 = lane; r0 < a.rows; r0 += kIlp * kWave) {
-        double v[kIlp];
+        double x[kIlp];
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) {
             const int r = r0 + u * kWave;
-            v[u] = r < a.rows ? a.part[int64_t(r) * stride + e] : 0.0;
+            x[u] = r < a.rows ? a.part[int64_t(r) * stride + e] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kIlp; ++u) acc[u] += v[u];
+        for (int u = 0; u < kIlp; ++u) acc[u] += x[u];
     }
     double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    for (int m = kWave / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, kWave);
+    for (int mm = kWave / 2; mm >= 1; mm >>= 1) s += __shfl_xor(s, mm, kWave);
     if (lane != 0) return;
     if (e == 2 * kn) {
         *a.loss = F(s * a.inv_n);
         return;
     }
-    const bool isE = e < kn;
-    const int idx = isE ? e : e - kn;
-    F* w = isE ? a.we : a.wd;
-    const double wt = double(w[idx]);
     const double g = s * a.gscale * slope(wt, a.beta);
     F* gout = isE ? a.grad_e : a.grad_d;
     if (gout) gout[idx] = F(g);
     if (a.adam) {
-        F* m = isE ? a.m_e : a.m_d;
-        F* v = isE ? a.v_e : a.v_d;
-        const double t = double(*a.ws_step);
-        const double mm = a.beta1 * double(m[idx]) + (1.0 - a.beta1) * g;
-        const double vv = a.beta2 * double(v[idx]) + (1.0 - a.beta2) * g * g;
-        const double bc1 = 1.0 - pow(a.beta1, t);
-        const double bc2 = 1.0 - pow(a.beta2, t);
+        const double mm = a.beta1 * m0 + (1.0 - a.beta1) * g;
+        const double vv = a.beta2 * v0 + (1.0 - a.beta2) * g * g;
+        // beta^t = exp(t ln beta), ln beta from the host
+        const double bc1 = 1.0 - exp(t * a.ln_beta1);
+        const double bc2 = 1.0 - exp(t * a.ln_beta2);
         const double denom = sqrt(vv) / sqrt(bc2) + a.eps;
         m[idx] = F(mm);
         v[idx] = F(vv);
@@ -952,7 +968,7 @@ Workspace carve(void* ws, int k, int n, int64_t rows, size_t esz) {
 inline void launch_lanes(const PartialArgs<double>&, bool, int, int64_t, hipStream_t) {}
 
 inline void launch_lanes(const PartialArgs<float>& p, bool eq8, int k, int64_t rows, hipStream_t st) {
-    const dim3 grid(static_cast<uint32_t>(rows)), block(kThreads);
+    const dim3 grid(static_cast<uint32_t>(rows)), block(kLaneThreads);
     if (k == 6) {
         if (eq8) hipLaunchKernelGGL((codec_lanes_kernel<true, 6>), grid, block, 0, st, p);
         else hipLaunchKernelGGL((codec_lanes_kernel<false, 6>), grid, block, 0, st, p);
@@ -968,10 +984,10 @@ hc_status run(const hc_codec_args& a) {
     hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
     const bool eq8 = a.objective == HC_CODEC_EQ8;
     const Plan pl = plan(k, n, a.N, sizeof(F), a.objective);
-    // float32 at n = 31 with k = 6 or 9 takes the lane-per-pair kernel (one
-    // partial row per 256 pairs), which stages softplus(Wt) itself
+    // float32 at n = 31 with k = 6 or 9 takes the two-lanes-per-pair kernel
+    // (one partial row per 256 pairs), which stages softplus(Wt) itself
     const bool lanes = std::is_same<F, float>::value && n == kLaneN && (k == 6 || k == 9);
-    const int64_t rows = lanes ? std::min<int64_t>(ceil_div(a.N, kThreads), kMaxRows) : pl.grid;
+    const int64_t rows = lanes ? std::min<int64_t>(ceil_div(a.N, kLaneWaves * kWavePairs), kMaxRows) : pl.grid;
     Workspace ws = carve(a.workspace, k, n, rows, sizeof(F));
     int64_t* adam_step = a.adam ? a.adam->step : nullptr;
     hc_status s = HC_OK;
@@ -1056,9 +1072,13 @@ hc_status run(const hc_codec_args& a) {
         f.beta1 = a.adam->beta1;
         f.beta2 = a.adam->beta2;
         f.eps = a.adam->eps;
+        // beta = 0 gives exp(t * -inf) = 0 for every step t >= 1
+        f.ln_beta1 = std::log(a.adam->beta1);
+        f.ln_beta2 = std::log(a.adam->beta2);
     } else {
         f.m_e = f.v_e = f.m_d = f.v_d = nullptr;
         f.lr = f.beta1 = f.beta2 = f.eps = 0.0;
+        f.ln_beta1 = f.ln_beta2 = 0.0;
     }
     f.ws_step = ws.step;
     f.step = adam_step;
