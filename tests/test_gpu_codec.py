@@ -101,6 +101,30 @@ def test_gather_by_index_equals_explicit_batch(ops):
 
 
 @pytest.mark.parametrize("objective", ["l2", "eq8"])
+def test_batch_past_one_chunk_per_wavefront(ops, objective):
+    """N = 300,001 at n = 31, k = 6 in float32: the two-lanes-per-pair kernel
+    runs out of workgroups (1,024 partial rows of 256 pairs) and every
+    wavefront takes two or more 32-pair chunks, the last one ragged."""
+    n, k, N = 31, 6, 300001
+    rng = np.random.default_rng(41)
+    we, wd = synth.codec_init(rng, k, n)
+    A, B = _pairs(n, N, 42)
+    T = synth.cmf_matrix(n)
+    ge = torch.empty(k, n, device="cuda")
+    gd = torch.empty(n, k, device="cuda")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()  # noqa: E731
+    kw = dict(objective="eq8", T=t(T)) if objective == "eq8" else {}
+    loss = ops.codec_step(t(we), t(wd), t(A), t(B), N, grad_e=ge, grad_d=gd, **kw)
+    torch.cuda.synchronize()
+    if objective == "eq8":
+        L, rge, rgd = oc.loss_eq8_and_grad(we, wd, A, B, T)
+    else:
+        L, rge, rgd = oc.loss_and_grad(we, wd, A, B, 1.0, 10.0)
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert _grad_ok(to_np(ge), rge) and _grad_ok(to_np(gd), rgd)
+
+
+@pytest.mark.parametrize("objective", ["l2", "eq8"])
 @pytest.mark.parametrize("n,k,dtype", [(31, 6, torch.float32), (31, 9, torch.float32), (81, 9, torch.float32),
                                        (31, 7, torch.float32), (31, 6, torch.float64)])
 def test_drawn_rows_equal_generated_indices(ops, objective, n, k, dtype):
