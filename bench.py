@@ -155,7 +155,7 @@ def measured_traffic(bytes_alg):
 
 
 MB_CHAINS = 1 << 18
-CODEC_STEPS_PER_GRAPH = 8   # codec fit steps recorded in one HIP graph
+CODEC_STEPS_PER_GRAPH = 8   # fit steps (codec, upsampler) recorded in one HIP graph
 
 
 def codec_only(args):
@@ -239,7 +239,7 @@ def upsample_leg(args, dev, n, k, T, E, D, refl, illum, P, xyz_s, codes, lcodes,
     rgb_pool, z_pool = training_pairs(E, T, pool, n)
     fit = UpsampleFit(rgb_pool, z_pool, M, white, k, batch=1024, seed=4)
     first = float(fit.run(1))
-    fit.capture()
+    fit.capture(CODEC_STEPS_PER_GRAPH)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     loss = float(fit.run(args.upsample_steps - 1))

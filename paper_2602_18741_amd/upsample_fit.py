@@ -58,7 +58,7 @@ class UpsampleFit:
         self.idx = torch.empty(batch, dtype=torch.int32, device=dev)
         self.loss = torch.zeros((), dtype=torch.float32, device=dev)
         self.ws = ops.UpsampleWorkspace(k, batch, dev)
-        self.graph = None
+        self.graph, self.graph_steps = None, 1
 
     def _step(self):
         ops.gen_indices(2 * self.seed + 7, self.N, self.rgb.shape[0], step=self.opt["step"],
@@ -67,21 +67,30 @@ class UpsampleFit:
                                 idx=self.idx, w_max=self.w_max, w_col=self.w_col, loss=self.loss,
                                 opt=self.opt, workspace=self.ws)
 
-    def capture(self):
+    def capture(self, steps: int = 1):
+        """Record `steps` consecutive steps in one HIP graph (run a warm-up step
+        first, as graph capture needs the kernels loaded).  Later run() calls
+        replay it as often as it fits and take any remaining steps one by one;
+        each captured step reads the device step counter when it runs, so every
+        replay draws a new batch."""
+        if steps < 1:
+            raise ValueError("steps must be >= 1")
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
-            self._step()
+            for _ in range(steps):
+                self._step()
         torch.cuda.current_stream().wait_stream(s)
-        self.graph = g
+        self.graph, self.graph_steps = g, steps
 
     def run(self, steps: int):
-        for _ in range(steps):
-            if self.graph is not None:
+        if self.graph is not None:
+            for _ in range(steps // self.graph_steps):
                 self.graph.replay()
-            else:
-                self._step()
+            steps %= self.graph_steps
+        for _ in range(steps):
+            self._step()
         return self.loss
 
     @property

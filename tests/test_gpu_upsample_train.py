@@ -170,3 +170,30 @@ def test_short_fit_reduces_the_loss(ops):
     fit.capture()
     last = float(fit.run(300))
     assert last < 0.3 * first
+
+
+def test_multi_step_graph_replay_equals_eager_steps(ops):
+    """Four steps per graph replay (each drawing its batch from the device
+    counter at replay time), then single steps: parameters and optimizer
+    state equal eager steps bit for bit."""
+    from paper_2602_18741_amd.upsample_fit import UpsampleFit
+    k = 6
+    rng = np.random.default_rng(17)
+    rgb = rng.uniform(0, 1, (1 << 13, 3)).astype(np.float32)
+    zg = (rgb @ rng.uniform(0, 1, (k, 3)).T).astype(np.float32)
+    M = rng.uniform(0.05, 0.5, (3, k)).astype(np.float32)
+
+    def make():
+        return UpsampleFit(torch.from_numpy(rgb).cuda(), torch.from_numpy(_blocked(zg, k)).cuda(),
+                           torch.from_numpy(M).cuda(), WHITE, k, batch=512, seed=2)
+    eager = make()
+    eager.run(15)
+    graphed = make()
+    graphed.run(1)
+    graphed.capture(4)
+    graphed.run(14)          # three replays, then two single steps
+    torch.cuda.synchronize()
+    assert graphed.steps_done == eager.steps_done == 15
+    for name in ("m", "v", "step"):
+        assert torch.equal(eager.opt[name], graphed.opt[name])
+    assert torch.equal(eager.params, graphed.params) and torch.equal(eager.loss, graphed.loss)
