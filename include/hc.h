@@ -276,9 +276,11 @@ hc_status hc_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int32
  * dtype: 0 = float32 everywhere, 1 = float64 everywhere (parameters, data,
  * T, outputs, Adam state).  Gradient sums run in that precision over tiles of
  * at most 64 pairs and in float64 across tiles, in a fixed order, so results
- * are deterministic.  (float32 with n = 31 and k = 6 or 9 runs one pair per
- * lane and sums each wavefront's pairs on the fp32 matrix cores: 64 pairs per
- * 256-pair chunk of the batch, one chunk per wavefront up to N = 262,144.)
+ * are deterministic.  (float32 with n = 31 or 81 and k = 6 or 9 spreads each
+ * pair over 2 or 8 lanes and sums each wavefront's pairs on the fp32 matrix
+ * cores: 32 or 8 pairs per wavefront and chunk, in float32 over the chunks a
+ * wavefront takes - one each up to N = 262,144 (n = 31) or 65,536 (n = 81) -
+ * and in float64 across wavefronts.)
  * Batch rows: row i of the a-batch is A[idx_a[i]*ld_a ...] when idx_a is
  * not NULL, else A[i*ld_a ...]; likewise b.  Indices must be < rows_a
  * (rows_b); out-of-range indices are clamped.  With draw not NULL the rows

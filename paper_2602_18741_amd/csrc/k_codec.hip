@@ -464,35 +464,63 @@ __global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArg
     }
 }
 
-// ------------------------------------------------------------------ kernel 2, two lanes per pair
+// ------------------------------------------------------------------ kernel 2, a few lanes per pair
 //
-// float32 with n = 31 (400-700 nm at 10 nm) and k = 6 or 9.  Lanes 2p and
-// 2p + 1 of a wavefront own pair p of its 32: each holds one half of the
-// samples (0-15, 16-30) of a and b in registers, and every loop has
-// compile-time bounds.  Sums over the samples (the codes E a, E b, E t, the
-// per-pair norms, D^T r) are taken per half and completed with one DPP add
-// of the partner lane, so both lanes hold the same values.  E, D and T are
-// read from LDS at the two halves' addresses.  The sums over pairs of outer
-// products,
+// float32 with n = 31 (400-700 nm at 10 nm) or n = 81 (380-780 nm at 5 nm) and
+// k = 6 or 9.  LPP consecutive lanes of a wavefront own one pair (two at
+// n = 31, eight at n = 81): lane q of the group holds samples
+// [q SPL, (q + 1) SPL) of a and b in registers (samples past n are zero
+// padding up to whole 16-sample tiles), and every loop has compile-time
+// bounds.  Sums over the samples (the codes E a, E b, E t, the per-pair norms,
+// D^T r) are taken per lane and completed with DPP adds inside the group, in
+// an order that leaves the same value on each of its lanes.  E, D and T are
+// read from LDS, one address per lane of a group.  The sums over pairs of
+// outer products,
 //   dD = sum_p r_a' u^T + r_b' v^T + g_3 h^T,   dE = sum_p g_u a^T + g_v b^T + c_3 t^T
 // (g_3 = g_S and c_3 = -w_code (2/k) d for Eq. 8; g_3 = lambda r_h and no third
 // dE term for the two-term loss), are contractions over the pairs and run on
 // the fp32 matrix cores (v_mfma_f32_16x16x4_f32, K = pairs).  For one term
-// each lane writes its 16 samples down its pair's column of the wave's
-// [2 halves][16 samples][32 pairs] LDS block; for the 16-sample tile of half
-// c, lane (g, m) reads row m, pairs 8g .. 8g+7, as two 16-byte loads feeding
-// 8 matrix steps (step s takes pairs s, 8 + s, 16 + s, 24 + s).  Rows are 36
-// floats apart and the two halves 32 banks apart, so the column writes and
-// each 8-lane group of row reads fall on distinct banks.  The wavefronts of
-// a workgroup are summed in a fixed order into one partial row.
+// each lane writes its samples, as they are computed, down its pair's column
+// of a per-wavefront [samples][pairs] LDS block; for the tile of samples
+// 16c .. 16c+15, lane (g, m) reads row m, PPW/4 consecutive pairs (16- or
+// 8-byte loads), one matrix step per pair.  Rows are PPW + 4 floats apart and
+// the lane groups' row ranges start PPW banks apart, so the column writes fall
+// on distinct banks, and so do the row reads of a lane group's rows.  The wavefronts of a
+// workgroup are summed in a fixed order into one partial row.
 
-constexpr int kLaneN = 31;
-constexpr int kLanePad = 32;
-constexpr int kLaneThreads = 512;
-constexpr int kLaneWaves = kLaneThreads / kWave;
-constexpr int kWavePairs = kWave / 2;                 // pairs per wavefront
-constexpr int kRow = kWavePairs + 4;                  // LDS row stride of the contraction blocks
-constexpr int kHalfStride = 16 * kRow + 32;           // second half's block, 32 banks over
+template <int N>
+struct LaneShape;
+template <>
+struct LaneShape<31> {
+    static constexpr int NP = 32;       // samples padded to whole 16-sample tiles
+    static constexpr int LPP = 2;       // lanes per pair
+    static constexpr int THREADS = 512;
+    static constexpr int XBLOCKS = 1;   // sample blocks per wavefront (1 or 2)
+};
+template <>
+struct LaneShape<81> {
+    static constexpr int NP = 96;
+    static constexpr int LPP = 8;       // 12 samples per lane: registers for 4 waves per SIMD
+    static constexpr int THREADS = 512;
+    static constexpr int XBLOCKS = 1;
+};
+
+template <int N>
+struct LaneDims : LaneShape<N> {
+    using S = LaneShape<N>;
+    static constexpr int SPL = S::NP / S::LPP;               // samples per lane
+    static constexpr int PPW = kWave / S::LPP;               // pairs per wavefront
+    static constexpr int WAVES = S::THREADS / kWave;
+    static constexpr int PAIRS = WAVES * PPW;                // pairs per workgroup and chunk
+    static constexpr int ROW = PPW + 4;                      // LDS row stride of the sample blocks
+    // extra offset between consecutive lane groups' row ranges, so that they
+    // start PPW banks apart
+    static constexpr int QP = (((PPW - SPL * ROW) % 64) + 64) % 64;
+    static constexpr int XSIZE = S::NP * ROW + (S::LPP - 1) * QP;
+    static constexpr int NC = S::NP / 16;                    // 16-sample tiles
+    static constexpr int STEPS = PPW / 4;                    // matrix steps per tile and term
+    static_assert(S::NP % S::LPP == 0 && (STEPS == 2 || STEPS % 4 == 0), "lane shape");
+};
 
 typedef float hc_mf4 __attribute__((ext_vector_type(4)));
 
@@ -517,19 +545,38 @@ __device__ __forceinline__ float fresh(float x) {
     return x;
 }
 
-// x plus the partner lane's x (lanes 2p, 2p + 1): the same value on both.
-__device__ __forceinline__ float pair_sum(float x) {
-    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
-    return fresh(x + __int_as_float(y));
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
-// c += sum over the wave's 32 pairs of L[row m][pair] R[row m'][pair] for the
-// 16 x 16 tile (m, m'); lrow / rrow point at pair 8g of the lane's rows.
-__device__ __forceinline__ hc_mf4 contract32(const float* lrow, const float* rrow, hc_mf4 c) {
+// Sum over the pair's LPP lanes (2, 4 or 8): pairwise, then pairs of pairs,
+// then halves; every lane of the group ends with the same value.
+template <int LPP>
+__device__ __forceinline__ float pair_sum(float x) {
+    x = x + dpp<0xB1>(x);                    // quad_perm 1,0,3,2: the xor-1 partner
+    if (LPP >= 4) x = x + dpp<0x4E>(x);      // quad_perm 2,3,0,1: the xor-2 partner
+    if (LPP == 8) x = x + dpp<0x141>(x);     // row_half_mirror: lane 7 - i of the eight
+    return fresh(x);
+}
+
+// c += sum over the wave's PPW pairs of L[row m][pair] R[row m'][pair] for the
+// 16 x 16 tile (m, m'); lrow / rrow point at pair STEPS g of the lane's rows.
+typedef float hc_mf2 __attribute__((ext_vector_type(2)));
+
+template <int STEPS>
+__device__ __forceinline__ hc_mf4 contract(const float* lrow, const float* rrow, hc_mf4 c) {
+    if (STEPS == 2) {
+        const hc_mf2 x = *reinterpret_cast<const hc_mf2*>(lrow);
+        const hc_mf2 y = *reinterpret_cast<const hc_mf2*>(rrow);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[0], y[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[1], y[1], c, 0, 0, 0);
+        return c;
+    }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const hc_mf4 x = *reinterpret_cast<const hc_mf4*>(lrow + 4 * q);
-        const hc_mf4 y = *reinterpret_cast<const hc_mf4*>(rrow + 4 * q);
+    for (int v = 0; v < STEPS / 4; ++v) {
+        const hc_mf4 x = *reinterpret_cast<const hc_mf4*>(lrow + 4 * v);
+        const hc_mf4 y = *reinterpret_cast<const hc_mf4*>(rrow + 4 * v);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[0], y[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[1], y[1], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[2], y[2], c, 0, 0, 0);
@@ -538,82 +585,92 @@ __device__ __forceinline__ hc_mf4 contract32(const float* lrow, const float* rro
     return c;
 }
 
-template <bool EQ8, int K>
-__global__ __launch_bounds__(kLaneThreads) void codec_lanes_kernel(PartialArgs<float> a) {
-    constexpr int N = kLaneN, NP = kLanePad, K4 = (K + 3) & ~3;
+template <bool EQ8, int K, int N>
+__global__ __launch_bounds__(LaneShape<N>::THREADS) void codec_lanes_kernel(PartialArgs<float> a) {
+    using L = LaneDims<N>;
+    constexpr int NP = L::NP, LPP = L::LPP, SPL = L::SPL, PPW = L::PPW, ROW = L::ROW, QP = L::QP;
+    constexpr int NC = L::NC, STEPS = L::STEPS, WAVES = L::WAVES, THREADS = L::THREADS;
+    // D rows K4 + 2 floats apart: the rows SPL apart that a pair's lanes read
+    // at once fall on different banks
+    constexpr int DS = ((K + 3) & ~3) + 2;
     constexpr int TERMS_E = EQ8 ? 3 : 2;
     __shared__ __align__(16) float sE[K * NP];   // E, rows padded with 0
-    __shared__ __align__(16) float sDt[K * NP];  // D^T, rows padded with 0
-    __shared__ __align__(16) float sD[NP * K4];  // D, rows padded with 0 (row 31 too)
+    __shared__ __align__(16) float sD[NP * DS];  // D, rows past n zero
     __shared__ __align__(16) float sT[3 * NP];
-    __shared__ __align__(16) float sZero[kWavePairs];
-    __shared__ __align__(16) float sX[kLaneWaves][2 * kHalfStride];  // [half][sample][pair]
-    __shared__ __align__(16) float sY[kLaneWaves][3 * K * kRow];     // [term][code][pair]
-    __shared__ double s_loss[kLaneWaves];
+    __shared__ __align__(16) float sZero[PPW];
+    __shared__ __align__(16) float sX[WAVES][L::XBLOCKS][L::XSIZE];  // [sample][pair]
+    __shared__ __align__(16) float sY[WAVES][3 * K * ROW];          // [term][code][pair]
+    __shared__ double s_loss[WAVES];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave;
-    const int pr = lane >> 1, hf = lane & 1;  // pair in the wave, half of the samples
-    const int i0 = 16 * hf;
+    const int pr = lane / LPP, q = lane % LPP;  // pair in the wave, lane in the pair
+    const int i0 = SPL * q;                     // the lane's first sample
     const uint64_t ctr_base = a.draw ? draw_base(a) : 0ull;
 
-    for (int e = tid; e < K * NP; e += kLaneThreads) {
+    for (int e = tid; e < K * NP; e += THREADS) {
         const int j = e / NP, i = e % NP;
         sE[e] = i < N ? softplus(a.we[j * N + i], a.beta) : 0.f;
-        sDt[e] = i < N ? softplus(a.wd[i * K + j], a.beta) : 0.f;
     }
-    for (int e = tid; e < NP * K4; e += kLaneThreads) {
-        const int i = e / K4, j = e % K4;
+    for (int e = tid; e < NP * DS; e += THREADS) {
+        const int i = e / DS, j = e % DS;
         sD[e] = (i < N && j < K) ? softplus(a.wd[i * K + j], a.beta) : 0.f;
     }
     if (EQ8)
-        for (int e = tid; e < 3 * NP; e += kLaneThreads)
-            sT[e] = e % NP < N ? a.T[(e / NP) * N + e % NP] : 0.f;
-    if (tid < kWavePairs) sZero[tid] = 0.f;
+        for (int e = tid; e < 3 * NP; e += THREADS) sT[e] = e % NP < N ? a.T[(e / NP) * N + e % NP] : 0.f;
+    if (tid < PPW) sZero[tid] = 0.f;
     if (a.step && blockIdx.x == 0 && tid == 0) *a.ws_step = *a.step + 1;
     __syncthreads();
 
     const int g = lane >> 4, m = lane & 15;
-    float* X = sX[wave];
+    float* X0 = sX[wave][0];
+    float* X1 = sX[wave][L::XBLOCKS - 1];
     float* Y = sY[wave];
-    float* xcol = X + hf * kHalfStride + pr;  // the lane's column: sample s at xcol[s * kRow]
+    // the lane's columns: its sample s at xcol[s * ROW]
+    const int col = i0 * ROW + q * QP + pr;
+    float* xcol0 = X0 + col;
+    float* xcol1 = X1 + col;
     float* ycol = Y + pr;
-    const float* xrow[2] = {X + m * kRow + 8 * g, X + kHalfStride + m * kRow + 8 * g};
+    // lane (g, m)'s row of the tile of samples 16c .. 16c+15
+    auto xrow = [&](const float* X, int c) {
+        const int i = 16 * c + m;
+        return X + i * ROW + (i / SPL) * QP + STEPS * g;
+    };
     // rows of the code blocks past k read zeros
     const float* yrow[3];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) yrow[t] = m < K ? Y + (t * K + m) * kRow + 8 * g : sZero + 8 * g;
+    for (int t = 0; t < 3; ++t) yrow[t] = m < K ? Y + (t * K + m) * ROW + STEPS * g : sZero + STEPS * g;
 
-    hc_mf4 gd[2], ge[2];
+    hc_mf4 gd[NC], ge[NC];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) gd[c] = ge[c] = hc_mf4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < NC; ++c) gd[c] = ge[c] = hc_mf4{0.f, 0.f, 0.f, 0.f};
     double loss_acc = 0.0;
     const float lam = a.lam;
     const float wr = EQ8 ? float(a.w_rec * 2.0 / N) : 1.f;
     const float wk = EQ8 ? float(a.w_code * 2.0 / K) : 0.f;
+    const int last = N - 1 - i0;  // the lane's last sample below n, relative to i0
 
-    for (int64_t ch = int64_t(blockIdx.x) * kLaneWaves + wave; ch * kWavePairs < a.N;
-         ch += int64_t(gridDim.x) * kLaneWaves) {
+    for (int64_t ch = int64_t(blockIdx.x) * WAVES + wave; ch * PPW < a.N; ch += int64_t(gridDim.x) * WAVES) {
         // keeps the reads of E, D and T from LDS inside the loop: hoisted out
         // of it, all of them would stay live in registers
         reread_tables();
-        const int64_t pi = ch * kWavePairs + pr;
+        const int64_t pi = ch * PPW + pr;
         const bool valid = pi < a.N;
         int64_t ra = 0, rb = 0;
         if (valid) batch_rows(a, ctr_base, pi, ra, rb);
         const float* pa = a.A + ra * a.ld_a + i0;
         const float* pb = a.B + rb * a.ld_b + i0;
-        // the half's samples; sample 31 (past n) reads sample 30 and is zeroed
-        float av[16], bv[16];
+        // the lane's samples; samples past n re-read the last one and are zeroed
+        float av[SPL], bv[SPL];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int o = s < 15 ? s : 15 - hf;
+        for (int s = 0; s < SPL; ++s) {
+            const int o = s < last ? s : last;
             av[s] = pa[o];
             bv[s] = pb[o];
         }
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const bool in = valid && (s < 15 || hf == 0);
+        for (int s = 0; s < SPL; ++s) {
+            const bool in = valid && s <= last;
             av[s] = in ? av[s] : 0.f;
             bv[s] = in ? bv[s] : 0.f;
         }
@@ -624,42 +681,42 @@ __global__ __launch_bounds__(kLaneThreads) void codec_lanes_kernel(PartialArgs<f
         for (int j = 0; j < K; ++j) {
             float su = 0.f, sv = 0.f, sw = 0.f;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
+            for (int s = 0; s < SPL; ++s) {
                 const float e = sE[j * NP + i0 + s];
                 su = fmaf(e, av[s], su);
                 sv = fmaf(e, bv[s], sv);
                 if (EQ8) sw = fmaf(e, fresh(av[s]) * bv[s], sw);
             }
-            u[j] = pair_sum(su);
-            v[j] = pair_sum(sv);
+            u[j] = pair_sum<LPP>(su);
+            v[j] = pair_sum<LPP>(sv);
             h[j] = u[j] * v[j];
-            dc[j] = EQ8 ? fresh(h[j] - pair_sum(sw)) : 0.f;
+            dc[j] = EQ8 ? fresh(h[j] - pair_sum<LPP>(sw)) : 0.f;
         }
-        wave_lds_order();  // the previous chunk's reads of the code block are done
-        if (hf == 0) {
+        wave_lds_order();  // the previous chunk's reads of the blocks are done
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                ycol[j * kRow] = u[j];
-                ycol[(K + j) * kRow] = v[j];
-                ycol[(2 * K + j) * kRow] = h[j];
+        for (int t = 0; t < 3; ++t) {
+            if (q == t % LPP) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) ycol[(t * K + j) * ROW] = t == 0 ? u[j] : (t == 1 ? v[j] : h[j]);
             }
         }
 
-        // reconstructions D u, D v, D h of the half's samples: the per-pair
-        // sums, D^T r_a' and D^T r_b' accumulated as the residuals appear
+        // reconstructions D u, D v, D h of the lane's samples: the per-pair
+        // sums, D^T r_a' and D^T r_b' accumulated as the residuals appear;
+        // r_a' (and with two blocks r_b') written to the sample blocks
         reread_tables();
-        float S[16], xa[16], xb[16];
+        float S[SPL], xb[L::XBLOCKS == 2 ? 1 : SPL];
         float gu[K], gv[K], gs[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) gu[j] = gv[j] = gs[j] = 0.f;
         float s_rr = 0.f, s_rh = 0.f, s_st = 0.f, s_ss = 0.f, s_tt = 0.f, s_c0 = 0.f, s_c1 = 0.f, s_c2 = 0.f;
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int i = i0 + s;  // row 31 of D and T is zero
+        for (int s = 0; s < SPL; ++s) {
+            const int i = i0 + s;  // rows of D and T past n are zero
             float du = 0.f, dv = 0.f, dh = 0.f;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const float d = sD[i * K4 + j];
+                const float d = sD[i * DS + j];
                 du = fmaf(d, u[j], du);
                 dv = fmaf(d, v[j], dv);
                 dh = fmaf(d, h[j], dh);
@@ -680,40 +737,42 @@ __global__ __launch_bounds__(kLaneThreads) void codec_lanes_kernel(PartialArgs<f
             const float rap = valid ? wr * rai : 0.f, rbp = valid ? wr * rbi : 0.f;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const float d = sD[i * K4 + j];
+                const float d = sD[i * DS + j];
                 gu[j] = fmaf(d, rap, gu[j]);
                 gv[j] = fmaf(d, rbp, gv[j]);
             }
-            xa[s] = rap;
-            xb[s] = rbp;
+            xcol0[s * ROW] = rap;
+            if (L::XBLOCKS == 2)
+                xcol1[s * ROW] = rbp;
+            else
+                xb[s] = rbp;
         }
         // dD terms r_a' u^T and r_b' v^T: rows = samples, columns = codes
         wave_lds_order();
 #pragma unroll
-        for (int s = 0; s < 16; ++s) xcol[s * kRow] = xa[s];
-        wave_lds_order();
-        gd[0] = contract32(xrow[0], yrow[0], gd[0]);
-        gd[1] = contract32(xrow[1], yrow[0], gd[1]);
-        wave_lds_order();
+        for (int c = 0; c < NC; ++c) gd[c] = contract<STEPS>(xrow(X0, c), yrow[0], gd[c]);
+        if (L::XBLOCKS == 1) {
+            wave_lds_order();
 #pragma unroll
-        for (int s = 0; s < 16; ++s) xcol[s * kRow] = xb[s];
-        wave_lds_order();
-        gd[0] = contract32(xrow[0], yrow[1], gd[0]);
-        gd[1] = contract32(xrow[1], yrow[1], gd[1]);
+            for (int s = 0; s < SPL; ++s) xcol0[s * ROW] = xb[(L::XBLOCKS == 2) ? 0 : s];
+            wave_lds_order();
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gd[c] = contract<STEPS>(xrow(X1, c), yrow[1], gd[c]);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            gu[j] = pair_sum(gu[j]);
-            gv[j] = pair_sum(gv[j]);
+            gu[j] = pair_sum<LPP>(gu[j]);
+            gv[j] = pair_sum<LPP>(gv[j]);
         }
-        s_rr = pair_sum(s_rr);
-        s_rh = pair_sum(s_rh);
+        s_rr = pair_sum<LPP>(s_rr);
+        s_rh = pair_sum<LPP>(s_rh);
         if (EQ8) {
-            s_st = pair_sum(s_st);
-            s_ss = pair_sum(s_ss);
-            s_tt = pair_sum(s_tt);
-            s_c0 = pair_sum(s_c0);
-            s_c1 = pair_sum(s_c1);
-            s_c2 = pair_sum(s_c2);
+            s_st = pair_sum<LPP>(s_st);
+            s_ss = pair_sum<LPP>(s_ss);
+            s_tt = pair_sum<LPP>(s_tt);
+            s_c0 = pair_sum<LPP>(s_c0);
+            s_c1 = pair_sum<LPP>(s_c1);
+            s_c2 = pair_sum<LPP>(s_c2);
         }
 
         // per-pair factors of the third term: g_3 = g_S (Eq. 8) or lambda r_h
@@ -729,7 +788,7 @@ __global__ __launch_bounds__(kLaneThreads) void codec_lanes_kernel(PartialArgs<f
             const double tn = sqrt(double(s_tt));
             const double nt = tn > a.eps ? tn : a.eps;
             const double cs = double(s_st) / (ns * nt);
-            if (valid && hf == 0)
+            if (valid && q == 0)
                 loss_acc += a.w_e2e * M * (2.0 - cs) + a.w_rec * double(s_rr) / N + a.w_code * double(s_dd) / K +
                             a.w_col * (double(s_c0) * s_c0 + double(s_c1) * s_c1 + double(s_c2) * s_c2) / 3.0;
             // g_S = al r_h - bt t + bs S + T^T gc
@@ -740,87 +799,91 @@ __global__ __launch_bounds__(kLaneThreads) void codec_lanes_kernel(PartialArgs<f
             g1 = float(a.w_col * (2.0 / 3.0) * s_c1);
             g2 = float(a.w_col * (2.0 / 3.0) * s_c2);
         } else {
-            if (valid && hf == 0) loss_acc += double(s_rr) + double(lam) * double(s_rh);
+            if (valid && q == 0) loss_acc += double(s_rr) + double(lam) * double(s_rh);
             al = lam;
             bt = 0.f;
             bs = 0.f;
         }
-        float xg[16];
+        wave_lds_order();  // the r_a' (r_b') tiles have been read
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
+        for (int s = 0; s < SPL; ++s) {
             const int i = i0 + s;
             const float ti = fresh(av[s]) * bv[s];
             float g3 = al * (S[s] - ti) - bt * ti + bs * S[s];
             if (EQ8) g3 += g0 * sT[i] + g1 * sT[NP + i] + g2 * sT[2 * NP + i];
             g3 = valid ? g3 : 0.f;
 #pragma unroll
-            for (int j = 0; j < K; ++j) gs[j] = fmaf(sD[i * K4 + j], g3, gs[j]);
-            xg[s] = g3;
+            for (int j = 0; j < K; ++j) gs[j] = fmaf(sD[i * DS + j], g3, gs[j]);
+            xcol0[s * ROW] = g3;
         }
         // dD term g_3 h^T
         wave_lds_order();
 #pragma unroll
-        for (int s = 0; s < 16; ++s) xcol[s * kRow] = xg[s];
-        wave_lds_order();
-        gd[0] = contract32(xrow[0], yrow[2], gd[0]);
-        gd[1] = contract32(xrow[1], yrow[2], gd[1]);
+        for (int c = 0; c < NC; ++c) gd[c] = contract<STEPS>(xrow(X0, c), yrow[2], gd[c]);
 #pragma unroll
-        for (int j = 0; j < K; ++j) gs[j] = pair_sum(gs[j]);
+        for (int j = 0; j < K; ++j) gs[j] = pair_sum<LPP>(gs[j]);
 
         // code-space gradients g_u = D^T r_a' + g_h v, g_v = D^T r_b' + g_h u,
         // g_h = D^T g_3 (+ w_code (2/k) d for Eq. 8), then dE on the matrix
         // cores: rows = codes, columns = samples
         wave_lds_order();
-        if (hf == 0) {
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const float dcp = (EQ8 && valid) ? wk * dc[j] : 0.f;
-                const float gh = gs[j] + dcp;
-                ycol[j * kRow] = gu[j] + gh * v[j];
-                ycol[(K + j) * kRow] = gv[j] + gh * u[j];
-                if (EQ8) ycol[(2 * K + j) * kRow] = -dcp;
+        for (int t = 0; t < TERMS_E; ++t) {
+            if (q == t % LPP) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const float dcp = (EQ8 && valid) ? wk * dc[j] : 0.f;
+                    const float gh = gs[j] + dcp;
+                    ycol[(t * K + j) * ROW] = t == 0 ? gu[j] + gh * v[j] : (t == 1 ? gv[j] + gh * u[j] : -dcp);
+                }
             }
         }
 #pragma unroll
-        for (int t = 0; t < TERMS_E; ++t) {
+        for (int t = 0; t < TERMS_E; t += L::XBLOCKS) {
+            if (t > 0) wave_lds_order();
+#pragma unroll
+            for (int s = 0; s < SPL; ++s) {
+                xcol0[s * ROW] = t == 0 ? av[s] : (t == 1 ? bv[s] : fresh(av[s]) * bv[s]);
+                if (L::XBLOCKS == 2 && t + 1 < TERMS_E) xcol1[s * ROW] = t == 0 ? bv[s] : fresh(av[s]) * bv[s];
+            }
             wave_lds_order();
 #pragma unroll
-            for (int s = 0; s < 16; ++s)
-                xcol[s * kRow] = t == 0 ? av[s] : (t == 1 ? bv[s] : fresh(av[s]) * bv[s]);
-            wave_lds_order();
-            ge[0] = contract32(yrow[t], xrow[0], ge[0]);
-            ge[1] = contract32(yrow[t], xrow[1], ge[1]);
+            for (int c = 0; c < NC; ++c) ge[c] = contract<STEPS>(yrow[t], xrow(X0, c), ge[c]);
+            if (L::XBLOCKS == 2 && t + 1 < TERMS_E) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) ge[c] = contract<STEPS>(yrow[t + 1], xrow(X1, c), ge[c]);
+            }
         }
     }
 
     // the wavefronts' tiles, then their fixed-order sum into the partial row;
     // [0, kn) is dL/dE (k x n), [kn, 2kn) dL/dD (n x k)
     constexpr int kn = K * N;
-    static_assert(2 * kn <= 2 * kHalfStride, "partial tile fits the sample block");
+    static_assert(2 * kn <= L::XSIZE, "partial tile fits a sample block");
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < NC; ++c) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = 16 * c + 4 * g + r, j = m;  // dD element of the tile
-            if (i < N && j < K) X[kn + i * K + j] = gd[c][r];
+            if (i < N && j < K) X0[kn + i * K + j] = gd[c][r];
             const int j2 = 4 * g + r, i2 = 16 * c + m;  // dE element
-            if (i2 < N && j2 < K) X[j2 * N + i2] = ge[c][r];
+            if (i2 < N && j2 < K) X0[j2 * N + i2] = ge[c][r];
         }
     }
     for (int mm = kWave / 2; mm >= 1; mm >>= 1) loss_acc += __shfl_xor(loss_acc, mm, kWave);
     if (lane == 0) s_loss[wave] = loss_acc;
     __syncthreads();
     double* prow = a.part + int64_t(blockIdx.x) * (2 * kn + 1);
-    for (int e = tid; e < 2 * kn; e += kLaneThreads) {
+    for (int e = tid; e < 2 * kn; e += THREADS) {
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < kLaneWaves; ++w) t += double(sX[w][e]);
+        for (int w = 0; w < WAVES; ++w) t += double(sX[w][0][e]);
         prow[e] = t;
     }
     if (tid == 0) {
         double t = 0.0;
-        for (int w = 0; w < kLaneWaves; ++w) t += s_loss[w];
+        for (int w = 0; w < WAVES; ++w) t += s_loss[w];
         prow[2 * kn] = t;
     }
 }
@@ -965,18 +1028,29 @@ Workspace carve(void* ws, int k, int n, int64_t rows, size_t esz) {
     return w;
 }
 
-inline void launch_lanes(const PartialArgs<double>&, bool, int, int64_t, hipStream_t) {}
+inline void launch_lanes(const PartialArgs<double>&, bool, int, int, int64_t, hipStream_t) {}
 
-inline void launch_lanes(const PartialArgs<float>& p, bool eq8, int k, int64_t rows, hipStream_t st) {
-    const dim3 grid(static_cast<uint32_t>(rows)), block(kLaneThreads);
+template <int N>
+void launch_lanes_n(const PartialArgs<float>& p, bool eq8, int k, int64_t rows, hipStream_t st) {
+    const dim3 grid(static_cast<uint32_t>(rows)), block(LaneShape<N>::THREADS);
     if (k == 6) {
-        if (eq8) hipLaunchKernelGGL((codec_lanes_kernel<true, 6>), grid, block, 0, st, p);
-        else hipLaunchKernelGGL((codec_lanes_kernel<false, 6>), grid, block, 0, st, p);
+        if (eq8) hipLaunchKernelGGL((codec_lanes_kernel<true, 6, N>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((codec_lanes_kernel<false, 6, N>), grid, block, 0, st, p);
     } else {
-        if (eq8) hipLaunchKernelGGL((codec_lanes_kernel<true, 9>), grid, block, 0, st, p);
-        else hipLaunchKernelGGL((codec_lanes_kernel<false, 9>), grid, block, 0, st, p);
+        if (eq8) hipLaunchKernelGGL((codec_lanes_kernel<true, 9, N>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((codec_lanes_kernel<false, 9, N>), grid, block, 0, st, p);
     }
 }
+
+inline void launch_lanes(const PartialArgs<float>& p, bool eq8, int k, int n, int64_t rows, hipStream_t st) {
+    if (n == 31)
+        launch_lanes_n<31>(p, eq8, k, rows, st);
+    else
+        launch_lanes_n<81>(p, eq8, k, rows, st);
+}
+
+// Pairs per workgroup of the few-lanes-per-pair kernel for n (31 or 81).
+inline int64_t lane_pairs(int n) { return n == 31 ? LaneDims<31>::PAIRS : LaneDims<81>::PAIRS; }
 
 template <typename F>
 hc_status run(const hc_codec_args& a) {
@@ -984,10 +1058,11 @@ hc_status run(const hc_codec_args& a) {
     hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
     const bool eq8 = a.objective == HC_CODEC_EQ8;
     const Plan pl = plan(k, n, a.N, sizeof(F), a.objective);
-    // float32 at n = 31 with k = 6 or 9 takes the two-lanes-per-pair kernel
-    // (one partial row per 256 pairs), which stages softplus(Wt) itself
-    const bool lanes = std::is_same<F, float>::value && n == kLaneN && (k == 6 || k == 9);
-    const int64_t rows = lanes ? std::min<int64_t>(ceil_div(a.N, kLaneWaves * kWavePairs), kMaxRows) : pl.grid;
+    // float32 at n = 31 or 81 with k = 6 or 9 takes the few-lanes-per-pair
+    // kernel (one partial row per 256 or 64 pairs), which stages softplus(Wt)
+    // itself
+    const bool lanes = std::is_same<F, float>::value && (n == 31 || n == 81) && (k == 6 || k == 9);
+    const int64_t rows = lanes ? std::min<int64_t>(ceil_div(a.N, lane_pairs(n)), kMaxRows) : pl.grid;
     Workspace ws = carve(a.workspace, k, n, rows, sizeof(F));
     int64_t* adam_step = a.adam ? a.adam->step : nullptr;
     hc_status s = HC_OK;
@@ -1039,7 +1114,7 @@ hc_status run(const hc_codec_args& a) {
     p.w_col = a.w_col;
     p.eps = a.cos_eps;
     if (lanes)
-        launch_lanes(p, eq8, k, rows, st);
+        launch_lanes(p, eq8, k, n, rows, st);
     else if (eq8)
         hipLaunchKernelGGL(codec_partials_eq8_kernel<F>, dim3(uint32_t(pl.grid)), dim3(kThreads), pl.lds,
                            st, p);
