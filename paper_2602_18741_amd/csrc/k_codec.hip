@@ -500,7 +500,7 @@ struct LaneShape<31> {
 template <>
 struct LaneShape<81> {
     static constexpr int NP = 96;
-    static constexpr int LPP = 8;       // 12 samples per lane: registers for 4 waves per SIMD
+    static constexpr int LPP = 8;       // 12 samples per lane (at 4 lanes, 24 samples: one wave per SIMD)
     static constexpr int THREADS = 512;
     static constexpr int XBLOCKS = 1;
 };
