@@ -205,7 +205,7 @@ def test_eq8_autograd_backward_matches_oracle(ops):
     loss = codec_loss_eq8(we, wd, _t(A), _t(B), _t(T))
     (2.5 * loss).backward()
     L, ge, gd = oc.loss_eq8_and_grad(we0, wd0, A, B, T)
-    assert abs(float(loss) - L) <= 1e-5 * L
+    assert abs(float(loss.detach()) - L) <= 1e-5 * L
     assert _grad_ok(to_np(we.grad), 2.5 * ge) and _grad_ok(to_np(wd.grad), 2.5 * gd)
 
 
@@ -231,3 +231,47 @@ def test_eq8_degenerate_pairs(ops):
     assert np.isfinite(float(loss)) and abs(float(loss) - L) <= 1e-12 * L
     assert np.allclose(to_np(ge), rge, rtol=1e-10, atol=1e-13 * np.abs(rge).max())
     assert np.allclose(to_np(gd), rgd, rtol=1e-10, atol=1e-13 * np.abs(rgd).max())
+
+
+@pytest.mark.parametrize("n,k", [(31, 6), (81, 9)])
+@pytest.mark.parametrize("N", [1, 31, 33])
+def test_eq8_tiny_batches_fp32(ops, n, k, N):
+    """Batches smaller than one wavefront's pairs (the lanes past the batch
+    carry zero pairs) on the few-lanes-per-pair kernels."""
+    rng = np.random.default_rng(N + n)
+    we, wd = synth.codec_init(rng, k, n)
+    A, B = _pairs(n, max(N, 2), 50 + N)
+    A, B = A[:N], B[:N]
+    T = synth.cmf_matrix(n)
+    ge = torch.empty(k, n, device="cuda")
+    gd = torch.empty(n, k, device="cuda")
+    loss = ops.codec_step(_t(we), _t(wd), _t(A), _t(B), N, grad_e=ge, grad_d=gd, objective="eq8",
+                          T=_t(T), weights=W)
+    torch.cuda.synchronize()
+    L, rge, rgd = oc.loss_eq8_and_grad(we, wd, A, B, T, W)
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert _grad_ok(to_np(ge), rge) and _grad_ok(to_np(gd), rgd)
+
+
+@pytest.mark.parametrize("n,k", [(31, 6), (81, 9)])
+def test_eq8_degenerate_pairs_fp32(ops, n, k):
+    """The degenerate pairs of the float64 test (products that vanish, an
+    all-zero spectrum) on the float32 few-lanes-per-pair kernels: finite, and
+    equal to the oracle within the float32 bounds."""
+    N = 64
+    rng = np.random.default_rng(33)
+    we, wd = synth.codec_init(rng, k, n)
+    A, B = _pairs(n, N, 34)
+    h = n // 2
+    A[:8, h:] = 0.0
+    B[:8, :h] = 0.0                      # t = 0 on the first 8 pairs
+    A[8:12] = 0.0                        # a = 0: u = 0, S_hat = 0
+    T = synth.cmf_matrix(n)
+    ge = torch.empty(k, n, device="cuda")
+    gd = torch.empty(n, k, device="cuda")
+    loss = ops.codec_step(_t(we), _t(wd), _t(A), _t(B), N, grad_e=ge, grad_d=gd, objective="eq8", T=_t(T))
+    torch.cuda.synchronize()
+    L, rge, rgd = oc.loss_eq8_and_grad(we, wd, A.astype(np.float32), B.astype(np.float32), T.astype(np.float32))
+    assert np.isfinite(float(loss)) and abs(float(loss) - L) <= 1e-5 * L
+    assert np.isfinite(to_np(ge)).all() and np.isfinite(to_np(gd)).all()
+    assert _grad_ok(to_np(ge), rge) and _grad_ok(to_np(gd), rgd)
