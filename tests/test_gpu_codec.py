@@ -246,5 +246,5 @@ def test_autograd_backward_matches_oracle(ops):
     loss = codec_loss(we, wd, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), 0.5)
     (3.0 * loss).backward()
     L, ge, gd = oc.loss_and_grad(we0, wd0, A, B, 0.5)
-    assert abs(float(loss) - L) <= 1e-5 * L
+    assert abs(float(loss.detach()) - L) <= 1e-5 * L
     assert _grad_ok(to_np(we.grad), 3.0 * ge) and _grad_ok(to_np(wd.grad), 3.0 * gd)
