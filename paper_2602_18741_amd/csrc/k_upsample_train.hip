@@ -3,7 +3,7 @@
 // (RGB, code) pairs drawn by index.  Deterministic: fixed summation orders,
 // no floating-point atomics.
 //
-//   1. partials: a workgroup takes two samples at a time, one per half
+//   1. partials: a workgroup takes four samples at a time, one per quarter
 //                (128 threads, one per hidden unit).  Forward through the
 //                three layers, the per-sample loss terms and dL/dz, then
 //                backward to the hidden pre-activations, with W2 and W3 in LDS
@@ -19,6 +19,8 @@
 //                min(1, max_norm / (norm + 1e-6)), then per parameter the
 //                decoupled weight decay and the Adam update.
 
+#include <cmath>
+
 #include "hc_internal.hpp"
 
 namespace hc {
@@ -26,17 +28,21 @@ namespace {
 
 constexpr int kH = 128;            // hidden width
 constexpr int kThreads = 256;
+constexpr int kSamples = 4;        // samples a partials workgroup takes at once
+constexpr int kPThreads = kSamples * kH;
 constexpr int kRS = kH + 1;        // LDS row stride of W2 and W3
-constexpr int kMaxRows = 128;      // partial rows (workgroups of kernel 1)
-constexpr int kW3PerThread = kMaxK / 2;
+constexpr int kMaxRows = 256;      // partial rows (workgroups of kernel 1): one per CU
+static_assert(kMaxRows <= kThreads, "one workgroup sums the per-row losses");
+constexpr int kW3PerThread = kMaxK / kSamples;
+constexpr int kW2PerThread = kH / kSamples;
 
 // packed parameter offsets (floats): W1 (128 x 3), b1, W2 (128 x 128), b2, W3 (k x 128), b3
 constexpr int64_t kOffB1 = 3 * kH;
 constexpr int64_t kOffW2 = kOffB1 + kH;
 constexpr int64_t kOffB2 = kOffW2 + kH * kH;
 constexpr int64_t kOffW3 = kOffB2 + kH;
-__host__ __device__ inline int64_t off_b3(int k) { return kOffW3 + int64_t(k) * kH; }
-__host__ __device__ inline int64_t param_count(int k) { return off_b3(k) + k; }
+__host__ __device__ constexpr int64_t off_b3(int k) { return kOffW3 + int64_t(k) * kH; }
+__host__ __device__ constexpr int64_t param_count(int k) { return off_b3(k) + k; }
 
 struct TrainArgs {
     int k;
@@ -74,7 +80,7 @@ __device__ __forceinline__ void lab_f(float t, float& f, float& fp) {
     }
 }
 
-__global__ __launch_bounds__(kThreads) void ustrain_partials_kernel(TrainArgs a) {
+__global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a) {
     extern __shared__ __align__(16) float sm[];
     const int k = a.k;
     float* sW2 = sm;                    // 128 x kRS
@@ -83,25 +89,25 @@ __global__ __launch_bounds__(kThreads) void ustrain_partials_kernel(TrainArgs a)
     float* sB2 = sW1 + 4 * kH;
     float* sB3 = sB2 + kH;              // k
     float* sM = sB3 + kMaxK;            // 3 x k
-    float* sS = sM + 3 * kMaxK;         // per half: p1, h1, p2, h2, dp2, dp1 (128 each), z, d, dz (48 each), misc 8
-    constexpr int kHalf = 6 * kH + 3 * kMaxK + 8;
+    float* sS = sM + 3 * kMaxK;         // per sample: p1, h1, p2, h2, dp2, dp1 (128 each), z, d, dz (48 each), misc 8
+    constexpr int kPer = 6 * kH + 3 * kMaxK + 8;
 
     const int tid = threadIdx.x;
     const float* P = a.params;
-    for (int e = tid; e < kH * kH; e += kThreads) sW2[(e / kH) * kRS + e % kH] = P[kOffW2 + e];
-    for (int e = tid; e < k * kH; e += kThreads) sW3[(e / kH) * kRS + e % kH] = P[kOffW3 + e];
-    for (int j = tid; j < kH; j += kThreads) {
+    for (int e = tid; e < kH * kH; e += kPThreads) sW2[(e / kH) * kRS + e % kH] = P[kOffW2 + e];
+    for (int e = tid; e < k * kH; e += kPThreads) sW3[(e / kH) * kRS + e % kH] = P[kOffW3 + e];
+    for (int j = tid; j < kH; j += kPThreads) {
         sW1[4 * j + 0] = P[3 * j];
         sW1[4 * j + 1] = P[3 * j + 1];
         sW1[4 * j + 2] = P[3 * j + 2];
         sW1[4 * j + 3] = P[kOffB1 + j];
         sB2[j] = P[kOffB2 + j];
     }
-    for (int c = tid; c < k; c += kThreads) sB3[c] = P[off_b3(k) + c];
-    for (int e = tid; e < 3 * k; e += kThreads) sM[e] = a.M[e];
+    for (int c = tid; c < k; c += kPThreads) sB3[c] = P[off_b3(k) + c];
+    for (int e = tid; e < 3 * k; e += kPThreads) sM[e] = a.M[e];
 
-    const int half = tid / kH, j = tid % kH;
-    float* S = sS + half * kHalf;
+    const int smp = tid / kH, j = tid % kH;  // the thread's sample of the four, hidden unit
+    float* S = sS + smp * kPer;
     float* p1 = S;
     float* h1 = p1 + kH;
     float* p2 = h1 + kH;
@@ -112,13 +118,11 @@ __global__ __launch_bounds__(kThreads) void ustrain_partials_kernel(TrainArgs a)
     float* dd = zz + kMaxK;
     float* dz = dd + kMaxK;
     float* misc = dz + kMaxK;  // rgb (3), gX (3)
-    float* SA = sS;            // the two halves' areas for the accumulation phase
-    float* SB = sS + kHalf;
 
     // gradient elements owned by this thread
-    float aW2[64];
+    float aW2[kW2PerThread];
 #pragma unroll
-    for (int q = 0; q < 64; ++q) aW2[q] = 0.f;
+    for (int q = 0; q < kW2PerThread; ++q) aW2[q] = 0.f;
     float aW3[kW3PerThread];
 #pragma unroll
     for (int r = 0; r < kW3PerThread; ++r) aW3[r] = 0.f;
@@ -126,9 +130,9 @@ __global__ __launch_bounds__(kThreads) void ustrain_partials_kernel(TrainArgs a)
     double loss = 0.0;
     __syncthreads();
 
-    const int64_t pairs = (a.N + 1) / 2;
-    for (int64_t pr = blockIdx.x; pr < pairs; pr += gridDim.x) {
-        const int64_t s = 2 * pr + half;
+    const int64_t groups = (a.N + kSamples - 1) / kSamples;
+    for (int64_t pr = blockIdx.x; pr < groups; pr += gridDim.x) {
+        const int64_t s = kSamples * pr + smp;
         const bool valid = s < a.N;
         int64_t row = 0;
         if (valid) row = a.idx ? min<int64_t>(a.idx[s], a.rows - 1) : s;
@@ -225,34 +229,51 @@ __global__ __launch_bounds__(kThreads) void ustrain_partials_kernel(TrainArgs a)
             dp1[j] = v * (sg + x * sg * (1.f - sg));
         }
         __syncthreads();
-        // accumulate both samples into the owned gradient elements
+        // accumulate the four samples, in order, into the owned gradient
+        // elements: W2 rows i = 4q + hi, W3 rows c = 4r + hi, column jj
         {
             const int jj = tid % kH, hi = tid / kH;
-            const float h1a = SA[kH + jj], h1b = SB[kH + jj];
+            float h1[kSamples], h2[kSamples];
 #pragma unroll
-            for (int q = 0; q < 64; ++q) {
-                const int i = 2 * q + hi;
-                aW2[q] = fmaf(SA[4 * kH + i], h1a, fmaf(SB[4 * kH + i], h1b, aW2[q]));
+            for (int u = 0; u < kSamples; ++u) {
+                h1[u] = sS[u * kPer + kH + jj];
+                h2[u] = sS[u * kPer + 3 * kH + jj];
             }
-            const float h2a = SA[3 * kH + jj], h2b = SB[3 * kH + jj];
-            const float* dza = SA + 6 * kH + 2 * kMaxK;
-            const float* dzb = SB + 6 * kH + 2 * kMaxK;
+#pragma unroll
+            for (int q = 0; q < kW2PerThread; ++q) {
+                const int i = kSamples * q + hi;
+                float v = aW2[q];
+#pragma unroll
+                for (int u = 0; u < kSamples; ++u) v = fmaf(sS[u * kPer + 4 * kH + i], h1[u], v);
+                aW2[q] = v;
+            }
 #pragma unroll
             for (int r = 0; r < kW3PerThread; ++r) {
-                const int c = 2 * r + hi;
-                if (c < k) aW3[r] = fmaf(dza[c], h2a, fmaf(dzb[c], h2b, aW3[r]));
+                const int c = kSamples * r + hi;
+                if (c < k) {
+                    float v = aW3[r];
+#pragma unroll
+                    for (int u = 0; u < kSamples; ++u) v = fmaf(sS[u * kPer + 6 * kH + 2 * kMaxK + c], h2[u], v);
+                    aW3[r] = v;
+                }
             }
             if (hi == 0) {
-                aB += SA[4 * kH + jj] + SB[4 * kH + jj];  // b2
-            } else {
-                const float da = SA[5 * kH + jj], db = SB[5 * kH + jj];
-                const float* ma = SA + 6 * kH + 3 * kMaxK;
-                const float* mb = SB + 6 * kH + 3 * kMaxK;
 #pragma unroll
-                for (int x = 0; x < 3; ++x) aW1[x] = fmaf(da, ma[x], fmaf(db, mb[x], aW1[x]));
-                aB += da + db;  // b1
+                for (int u = 0; u < kSamples; ++u) aB += sS[u * kPer + 4 * kH + jj];  // b2
+            } else if (hi == 1) {
+#pragma unroll
+                for (int u = 0; u < kSamples; ++u) {
+                    const float d1 = sS[u * kPer + 5 * kH + jj];
+                    const float* mu = sS + u * kPer + 6 * kH + 3 * kMaxK;
+#pragma unroll
+                    for (int x = 0; x < 3; ++x) aW1[x] = fmaf(d1, mu[x], aW1[x]);
+                    aB += d1;  // b1
+                }
             }
-            if (tid < k) aB3 += dza[tid] + dzb[tid];
+            if (tid < k) {
+#pragma unroll
+                for (int u = 0; u < kSamples; ++u) aB3 += sS[u * kPer + 6 * kH + 2 * kMaxK + tid];
+            }
         }
         __syncthreads();
     }
@@ -261,26 +282,30 @@ __global__ __launch_bounds__(kThreads) void ustrain_partials_kernel(TrainArgs a)
     {
         const int jj = tid % kH, hi = tid / kH;
 #pragma unroll
-        for (int q = 0; q < 64; ++q) prow[kOffW2 + (2 * q + hi) * kH + jj] = aW2[q];
+        for (int q = 0; q < kW2PerThread; ++q) prow[kOffW2 + (kSamples * q + hi) * kH + jj] = aW2[q];
 #pragma unroll
         for (int r = 0; r < kW3PerThread; ++r) {
-            const int c = 2 * r + hi;
+            const int c = kSamples * r + hi;
             if (c < k) prow[kOffW3 + c * kH + jj] = aW3[r];
         }
         if (hi == 0) {
             prow[kOffB2 + jj] = aB;
-        } else {
+        } else if (hi == 1) {
 #pragma unroll
             for (int x = 0; x < 3; ++x) prow[3 * jj + x] = aW1[x];
             prow[kOffB1 + jj] = aB;
         }
         if (tid < k) prow[off_b3(k) + tid] = aB3;
     }
-    // workgroup loss: the two per-sample threads (tid 0 and 128), fixed order
-    __shared__ double s_loss[2];
+    // workgroup loss: the per-sample threads (tid 0, 128, 256, 384), fixed order
+    __shared__ double s_loss[kSamples];
     if (tid % kH == 0) s_loss[tid / kH] = loss;
     __syncthreads();
-    if (tid == 0) a.loss_part[blockIdx.x] = s_loss[0] + s_loss[1];
+    if (tid == 0) {
+        double t = 0.0;
+        for (int u = 0; u < kSamples; ++u) t += s_loss[u];
+        a.loss_part[blockIdx.x] = t;
+    }
 }
 
 struct ReduceArgs {
@@ -295,20 +320,45 @@ struct ReduceArgs {
     int64_t* ws_step;
 };
 
+// Sum of x[0 .. count) (count <= kThreads) by the calling workgroup, in a fixed
+// order: a butterfly inside each wavefront, then the wavefronts in order.  The
+// result is valid in thread 0.
+__device__ double block_sum(const double* x, int count) {
+    __shared__ double s_w[kThreads / kWave];
+    double v = int(threadIdx.x) < count ? x[threadIdx.x] : 0.0;
+    for (int m = kWave / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kThreads / kWave; ++w) t += s_w[w];
+    return t;
+}
+
 __global__ __launch_bounds__(kThreads) void ustrain_reduce_kernel(ReduceArgs a) {
     const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     double g = 0.0;
     if (e < a.P) {
-        // eight interleaved partial sums keep eight row loads in flight
-        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int r = 0;
-        for (; r + 8 <= a.rows; r += 8) {
+        // sixteen interleaved partial sums keep sixteen row loads in flight
+        // (whole batches unguarded: a guarded load becomes a branch per row)
+        constexpr int kIlp = 16;
+        double acc[kIlp];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += double(a.part[int64_t(r + u) * a.P + e]);
+        for (int u = 0; u < kIlp; ++u) acc[u] = 0.0;
+        int r = 0;
+        for (; r + kIlp <= a.rows; r += kIlp) {
+            float x[kIlp];
+#pragma unroll
+            for (int u = 0; u < kIlp; ++u) x[u] = a.part[int64_t(r + u) * a.P + e];
+#pragma unroll
+            for (int u = 0; u < kIlp; ++u) acc[u] += double(x[u]);
         }
         for (; r < a.rows; ++r) acc[0] += double(a.part[int64_t(r) * a.P + e]);
-        const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-        g = s / double(a.N);
+#pragma unroll
+        for (int w = kIlp / 2; w >= 1; w >>= 1)
+#pragma unroll
+            for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
+        g = acc[0] / double(a.N);
         a.grad[e] = float(g);
     }
     double sq = g * g;
@@ -320,9 +370,10 @@ __global__ __launch_bounds__(kThreads) void ustrain_reduce_kernel(ReduceArgs a) 
         double t = 0.0;
         for (int w = 0; w < kThreads / kWave; ++w) t += s_sq[w];
         a.sq_part[blockIdx.x] = t;
-        if (blockIdx.x == 0) {
-            double l = 0.0;
-            for (int r = 0; r < a.rows; ++r) l += a.loss_part[r];
+    }
+    if (blockIdx.x == 0) {
+        const double l = block_sum(a.loss_part, a.rows);  // rows <= kThreads
+        if (threadIdx.x == 0) {
             *a.loss = float(l / double(a.N));
             if (a.step) {
                 const int64_t t1 = *a.step + 1;
@@ -343,14 +394,15 @@ struct AdamWArgs {
     float* v;
     const int64_t* ws_step;
     double lr, beta1, beta2, eps, wd, max_norm;
+    double ln_beta1, ln_beta2;
 };
 
 __global__ __launch_bounds__(kThreads) void ustrain_adamw_kernel(AdamWArgs a) {
     __shared__ double s_scale;
+    // every block forms the same norm from the block sums (nsq <= kThreads)
+    const double t2 = block_sum(a.sq_part, a.nsq);
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int b = 0; b < a.nsq; ++b) t += a.sq_part[b];
-        const double norm = sqrt(t);
+        const double norm = sqrt(t2);
         const double c = a.max_norm / (norm + 1e-6);
         s_scale = c < 1.0 ? c : 1.0;
     }
@@ -362,18 +414,21 @@ __global__ __launch_bounds__(kThreads) void ustrain_adamw_kernel(AdamWArgs a) {
     const double w = double(a.params[e]) * (1.0 - a.lr * a.wd);
     const double mm = a.beta1 * double(a.m[e]) + (1.0 - a.beta1) * g;
     const double vv = a.beta2 * double(a.v[e]) + (1.0 - a.beta2) * g * g;
-    const double bc1 = 1.0 - pow(a.beta1, t);
-    const double bc2 = 1.0 - pow(a.beta2, t);
+    // beta^t = exp(t ln beta), ln beta from the host
+    const double bc1 = 1.0 - exp(t * a.ln_beta1);
+    const double bc2 = 1.0 - exp(t * a.ln_beta2);
     a.m[e] = float(mm);
     a.v[e] = float(vv);
     a.params[e] = float(w - (a.lr / bc1) * mm / (sqrt(vv) / sqrt(bc2) + a.eps));
 }
 
-int64_t grid_rows(int64_t N) { return std::min<int64_t>((N + 1) / 2, kMaxRows); }
+int64_t grid_rows(int64_t N) { return std::min<int64_t>((N + kSamples - 1) / kSamples, kMaxRows); }
+static_assert((param_count(kMaxK) + kThreads - 1) / kThreads <= kThreads,
+              "one workgroup sums the per-block squares");
 
 size_t lds_bytes(int k) {
     return sizeof(float) * (size_t(kH) * kRS + size_t(k) * kRS + 4 * kH + kH + kMaxK + 3 * kMaxK +
-                            2 * (6 * kH + 3 * kMaxK + 8));
+                            kSamples * (6 * kH + 3 * kMaxK + 8));
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -439,7 +494,7 @@ hc_status launch_upsample_train(const hc_upsample_train_args& u) {
     a.w_col = float(u.w_col);
     a.part = ws.part;
     a.loss_part = ws.loss_part;
-    hipLaunchKernelGGL(ustrain_partials_kernel, dim3(uint32_t(rows)), dim3(kThreads), lds_bytes(k), st, a);
+    hipLaunchKernelGGL(ustrain_partials_kernel, dim3(uint32_t(rows)), dim3(kPThreads), lds_bytes(k), st, a);
     hc_status s = launch_status("hc_upsample_train_step");
     if (s != HC_OK) return s;
 
@@ -471,6 +526,9 @@ hc_status launch_upsample_train(const hc_upsample_train_args& u) {
     w.lr = u.opt->lr;
     w.beta1 = u.opt->beta1;
     w.beta2 = u.opt->beta2;
+    // beta = 0 gives exp(t * -inf) = 0 for every step t >= 1
+    w.ln_beta1 = std::log(u.opt->beta1);
+    w.ln_beta2 = std::log(u.opt->beta2);
     w.eps = u.opt->eps;
     w.wd = u.opt->weight_decay;
     w.max_norm = u.opt->max_grad_norm;
