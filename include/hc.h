@@ -401,8 +401,18 @@ hc_status hc_upsample(const hc_mlp* net, int32_t precision, const float* rgb, in
  * decay (params *= 1 - lr weight_decay) and the Adam update with bias
  * correction, and increments *opt->step (AdamW with clipping, Sec. 5.2).
  * Deterministic.  workspace: hc_upsample_train_workspace_size(k, N) bytes,
- * 256-byte aligned.
+ * 256-byte aligned.  Batch rows: idx[i] (clamped below rows) when idx is not
+ * NULL, else i; with draw not NULL they are drawn on the device instead (idx
+ * must then be NULL): sample i is row hc_gen_indices(draw->seed, draw->ctr0,
+ * draw->ctr_scale_dev, N, rows, ...)[i].  When ctr_scale_dev is the
+ * optimizer's step counter, the draw sees its value from before the call.
  */
+typedef struct hc_index_draw {
+    uint64_t seed;
+    uint64_t ctr0;
+    const int64_t* ctr_scale_dev;  /* device counter, nullable */
+} hc_index_draw;
+
 typedef struct hc_adamw {
     float* m;           /* first moments, packed like the parameters */
     float* v;           /* second moments */
@@ -430,6 +440,7 @@ typedef struct hc_upsample_train_args {
     void* workspace;
     size_t workspace_bytes;
     void* stream;
+    const hc_index_draw* draw;  /* host pointer, nullable: batch rows drawn on the device */
 } hc_upsample_train_args;
 
 int64_t hc_upsample_param_count(int32_t k, int32_t hidden);

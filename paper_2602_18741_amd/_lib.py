@@ -72,12 +72,16 @@ class AdamW(C.Structure):
                 ("eps", f64), ("weight_decay", f64), ("max_grad_norm", f64)]
 
 
+class IndexDraw(C.Structure):
+    _fields_ = [("seed", u64), ("ctr0", u64), ("ctr_scale_dev", vp)]
+
+
 class UpsampleTrainArgs(C.Structure):
     _fields_ = [("k", i32), ("hidden", i32), ("params", vp), ("rgb", vp), ("ld_rgb", i64),
                 ("z_gt", vp), ("ld_z", i64), ("rows", i64), ("idx", vp), ("N", i64), ("M", vp),
                 ("white", f64 * 3), ("w_max", f64), ("w_col", f64), ("loss", vp), ("grad", vp),
                 ("opt", C.POINTER(AdamW)), ("workspace", vp), ("workspace_bytes", sz),
-                ("stream", vp)]
+                ("stream", vp), ("draw", C.POINTER(IndexDraw))]
 
 
 class PathGen(C.Structure):

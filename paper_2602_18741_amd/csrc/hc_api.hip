@@ -353,8 +353,17 @@ hc_status hc_upsample_train_step(const hc_upsample_train_args* a) {
     HC_REQUIRE(a->ld_rgb >= 3 && a->ld_z >= 4 * ceil_div(a->k, 3), HC_ESHAPE, "%s: row stride too small",
                fn);
     HC_REQUIRE(a->params && a->rgb && a->z_gt && a->M && a->loss, HC_EINVAL, "%s: NULL pointer", fn);
-    if (a->idx) HC_REQUIRE(a->rows >= 1, HC_ESHAPE, "%s: rows must be >= 1 with idx", fn);
-    else HC_REQUIRE(a->rows >= a->N, HC_ESHAPE, "%s: rows < N without idx", fn);
+    if (a->draw) {
+        HC_REQUIRE(!a->idx, HC_EINVAL, "%s: draw excludes idx", fn);
+        HC_REQUIRE(a->rows >= 1 && a->rows < (int64_t(1) << 32), HC_ESHAPE,
+                   "%s: drawn rows need rows in [1, 2^32)", fn);
+        HC_REQUIRE(!a->draw->ctr_scale_dev || aligned8(a->draw->ctr_scale_dev), HC_EALIGN,
+                   "%s: draw counter misaligned", fn);
+    } else if (a->idx) {
+        HC_REQUIRE(a->rows >= 1, HC_ESHAPE, "%s: rows must be >= 1 with idx", fn);
+    } else {
+        HC_REQUIRE(a->rows >= a->N, HC_ESHAPE, "%s: rows < N without idx", fn);
+    }
     for (double w : a->white)
         HC_REQUIRE(w > 0 && w < HUGE_VAL, HC_EINVAL, "%s: the white must be positive and finite", fn);
     HC_REQUIRE(a->w_max >= 0 && a->w_max < HUGE_VAL && a->w_col >= 0 && a->w_col < HUGE_VAL, HC_EINVAL,

@@ -21,6 +21,7 @@
 
 #include <cmath>
 
+#include "counter_rng.hpp"
 #include "hc_internal.hpp"
 
 namespace hc {
@@ -53,6 +54,10 @@ struct TrainArgs {
     int64_t ld_z;
     int64_t rows;
     const uint32_t* idx;
+    // rows drawn on the device: counter base draw_ctr0 (+ *draw_scale * N)
+    int draw;
+    uint64_t key, draw_ctr0;
+    const int64_t* draw_scale;
     int64_t N;
     const float* M;  // 3 x k
     float wx, wy, wz;  // reference white
@@ -130,12 +135,16 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
     double loss = 0.0;
     __syncthreads();
 
+    const uint64_t ctr_base =
+        a.draw ? a.draw_ctr0 + (a.draw_scale ? uint64_t(*a.draw_scale) * uint64_t(a.N) : 0ull) : 0ull;
     const int64_t groups = (a.N + kSamples - 1) / kSamples;
     for (int64_t pr = blockIdx.x; pr < groups; pr += gridDim.x) {
         const int64_t s = kSamples * pr + smp;
         const bool valid = s < a.N;
         int64_t row = 0;
-        if (valid) row = a.idx ? min<int64_t>(a.idx[s], a.rows - 1) : s;
+        if (valid)
+            row = a.draw ? int64_t(range32(rand64(a.key, ctr_base + uint64_t(s)), uint64_t(a.rows)))
+                         : (a.idx ? min<int64_t>(a.idx[s], a.rows - 1) : s);
         // forward
         const float* cp = a.rgb + row * a.ld_rgb;
         const float cr = valid ? cp[0] : 0.f, cg = valid ? cp[1] : 0.f, cb = valid ? cp[2] : 0.f;
@@ -485,6 +494,10 @@ hc_status launch_upsample_train(const hc_upsample_train_args& u) {
     a.ld_z = u.ld_z;
     a.rows = u.rows;
     a.idx = u.idx;
+    a.draw = u.draw != nullptr;
+    a.key = u.draw ? stream_key(u.draw->seed, kIndexStream) : 0;
+    a.draw_ctr0 = u.draw ? u.draw->ctr0 : 0;
+    a.draw_scale = u.draw ? u.draw->ctr_scale_dev : nullptr;
     a.N = u.N;
     a.M = u.M;
     a.wx = float(u.white[0]);

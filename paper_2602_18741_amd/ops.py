@@ -294,13 +294,21 @@ class UpsampleWorkspace:
 def upsample_train_step(params: torch.Tensor, rgb: torch.Tensor, z_gt: torch.Tensor, M: torch.Tensor,
                         white, k: int, N: int, idx=None, w_max: float = 0.3, w_col: float = 0.05,
                         loss=None, grad=None, opt: dict | None = None,
-                        workspace: UpsampleWorkspace | None = None):
+                        workspace: UpsampleWorkspace | None = None, draw: dict | None = None):
     """One loss/gradient (and optional AdamW) evaluation of the upsampling
     network's training objective (Sec. 5.2) on the GPU.  params: packed
     float32 vector; rgb (rows, >= 3) and z_gt (rows, blocked layout) float32;
     M (3 x k) = T D; opt: dict with m, v, step (int64 device tensor), lr,
-    beta1, beta2, eps, weight_decay, max_grad_norm.  Returns the loss tensor."""
+    beta1, beta2, eps, weight_decay, max_grad_norm.  Batch rows: idx, or with
+    draw = dict(seed, ctr0=0, step=None) the rows gen_indices(seed, N, rows,
+    ctr0, step) would give, drawn inside the step.  Returns the loss tensor."""
     _dev(params, rgb, z_gt, M, idx, grad)
+    dr = None
+    if draw is not None:
+        if idx is not None:
+            raise ValueError("draw excludes idx")
+        _dev(draw.get("step"))
+        dr = _lib.IndexDraw(int(draw["seed"]), int(draw.get("ctr0", 0)), _ptr(draw.get("step")))
     if loss is None:
         loss = torch.empty((), dtype=torch.float32, device=params.device)
     workspace = workspace or UpsampleWorkspace(k, N, params.device)
@@ -314,7 +322,8 @@ def upsample_train_step(params: torch.Tensor, rgb: torch.Tensor, z_gt: torch.Ten
         k, MLP_HIDDEN, params.data_ptr(), rgb.data_ptr(), rgb.stride(0), z_gt.data_ptr(),
         z_gt.stride(0), rgb.shape[0], _ptr(idx), N, M.contiguous().data_ptr(),
         (C.c_double * 3)(*[float(w) for w in white]), w_max, w_col, loss.data_ptr(), _ptr(grad),
-        C.pointer(o) if o is not None else None, workspace.ptr, workspace.bytes, _stream())
+        C.pointer(o) if o is not None else None, workspace.ptr, workspace.bytes, _stream(),
+        C.pointer(dr) if dr is not None else None)
     check(load().hc_upsample_train_step(C.byref(a)), "hc_upsample_train_step")
     return loss
 

@@ -3,8 +3,8 @@
 Each step draws a batch of (RGB, target code) rows by index from
 device-resident tables with the counter-based index generator (the counter
 base is the optimizer's step counter, so a captured graph draws a fresh
-batch on every replay) and runs hc_upsample_train_step with the fused
-clipping and AdamW update.  The codec is frozen: the targets are codes of
+batch on every replay) inside hc_upsample_train_step, which also applies the
+fused clipping and AdamW update.  The codec is frozen: the targets are codes of
 the training spectra and M = T D maps a code to XYZ for the colour term.
 """
 
@@ -55,17 +55,16 @@ class UpsampleFit:
                         step=torch.zeros(1, dtype=torch.int64, device=dev), lr=lr, beta1=0.9,
                         beta2=0.999, eps=1e-8, weight_decay=weight_decay,
                         max_grad_norm=max_grad_norm)
-        self.idx = torch.empty(batch, dtype=torch.int32, device=dev)
         self.loss = torch.zeros((), dtype=torch.float32, device=dev)
         self.ws = ops.UpsampleWorkspace(k, batch, dev)
         self.graph, self.graph_steps = None, 1
 
     def _step(self):
-        ops.gen_indices(2 * self.seed + 7, self.N, self.rgb.shape[0], step=self.opt["step"],
-                        out=self.idx)
+        # rows for step t: counters [t*N, (t+1)*N) of a seeded index stream
+        # (the indices ops.gen_indices would write), drawn inside the step
         ops.upsample_train_step(self.params, self.rgb, self.z_gt, self.M, self.white, self.k, self.N,
-                                idx=self.idx, w_max=self.w_max, w_col=self.w_col, loss=self.loss,
-                                opt=self.opt, workspace=self.ws)
+                                draw=dict(seed=2 * self.seed + 7, step=self.opt["step"]), w_max=self.w_max,
+                                w_col=self.w_col, loss=self.loss, opt=self.opt, workspace=self.ws)
 
     def capture(self, steps: int = 1):
         """Record `steps` consecutive steps in one HIP graph (run a warm-up step

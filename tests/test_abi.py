@@ -37,6 +37,8 @@ def test_struct_sizes_match_header():
     assert C.sizeof(_lib.PathGen) == 40
     assert C.sizeof(_lib.PairDraw) == 32
     assert C.sizeof(_lib.CodecArgs) == 232
+    assert C.sizeof(_lib.IndexDraw) == 24
+    assert C.sizeof(_lib.UpsampleTrainArgs) == 176
 
 
 def _err(status):
@@ -179,3 +181,22 @@ def test_upsample_validates_before_launch(lib):
     assert lib.hc_upsample(C.byref(net), 0, None, 0, 3, None, 8, None) == _lib.HC_OK
     net.W2 = 0x1002
     assert lib.hc_upsample(*args()) == _lib.HC_EALIGN
+
+
+def test_upsample_train_step_validates_the_index_draw(lib):
+    need = lib.hc_upsample_train_workspace_size(6, 1024)
+    args = _lib.UpsampleTrainArgs(6, 128, 0x1000, 0x1000, 4, 0x1000, 8, 1 << 16, 0x1000, 1024, 0x1000,
+                                  (C.c_double * 3)(0.95, 1.0, 1.09), 0.3, 0.05, 0x1000, None, None,
+                                  0x10000, need, None)
+    dr = _lib.IndexDraw(7, 0, None)
+    args.draw = C.pointer(dr)
+    s, msg = _err(lib.hc_upsample_train_step(C.byref(args)))
+    assert s == _lib.HC_EINVAL and "draw excludes idx" in msg
+    args.idx = None
+    args.rows = 1 << 32
+    s, msg = _err(lib.hc_upsample_train_step(C.byref(args)))
+    assert s == _lib.HC_ESHAPE and "2^32" in msg
+    args.rows = 1 << 16
+    dr.ctr_scale_dev = 0x1004
+    s, msg = _err(lib.hc_upsample_train_step(C.byref(args)))
+    assert s == _lib.HC_EALIGN and "counter" in msg

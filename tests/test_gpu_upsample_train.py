@@ -197,3 +197,34 @@ def test_multi_step_graph_replay_equals_eager_steps(ops):
     for name in ("m", "v", "step"):
         assert torch.equal(eager.opt[name], graphed.opt[name])
     assert torch.equal(eager.params, graphed.params) and torch.equal(eager.loss, graphed.loss)
+
+
+def test_drawn_rows_equal_generated_indices(ops):
+    """Rows drawn inside the training step are the rows hc_gen_indices writes
+    for the same seed and counters: loss, gradient-driven parameters and
+    optimizer state equal bit for bit over three AdamW steps whose draws take
+    their counter base from the step counter."""
+    k, N, rows = 6, 1000, 5000
+    rng = np.random.default_rng(23)
+    rgb = torch.from_numpy(rng.uniform(0, 1, (rows, 3)).astype(np.float32)).cuda()
+    z = torch.from_numpy(_blocked(rng.uniform(0, 1, (rows, k)).astype(np.float32), k)).cuda()
+    M = torch.from_numpy(rng.uniform(0.05, 0.5, (3, k)).astype(np.float32)).cuda()
+    from paper_2602_18741_amd.upsample_fit import default_init
+    runs = []
+    for use_draw in (False, True):
+        params = torch.from_numpy(default_init(k, 3)).cuda()
+        opt = dict(m=torch.zeros_like(params), v=torch.zeros_like(params),
+                   step=torch.full((1,), 4, dtype=torch.int64, device="cuda"), lr=2e-3)
+        out = []
+        for _ in range(3):
+            if use_draw:
+                loss = ops.upsample_train_step(params, rgb, z, M, WHITE, k, N, opt=opt,
+                                               draw=dict(seed=11, ctr0=2, step=opt["step"]))
+            else:
+                idx = ops.gen_indices(11, N, rows, ctr0=2, step=opt["step"])
+                loss = ops.upsample_train_step(params, rgb, z, M, WHITE, k, N, idx=idx, opt=opt)
+            out.append(loss.clone())
+        torch.cuda.synchronize()
+        assert int(opt["step"].item()) == 7
+        runs.append(out + [params, opt["m"], opt["v"]])
+    assert all(torch.equal(x, y) for x, y in zip(*runs))
