@@ -1,29 +1,35 @@
 // Codec fitting: loss, hand-written gradient and Adam for the non-negative
 // linear codec E = softplus(Wt_E), D = softplus(Wt_D).
 //
-// Up to three kernels per step, all deterministic (fixed summation orders,
-// no floating-point atomics):
-//   1. weights : E, D = softplus_beta(Wt) into the workspace; bumps the Adam
-//                step counter.  Only when E and D do not fit the partials
-//                kernel's LDS; otherwise that kernel stages softplus(Wt)
-//                itself and its block 0 bumps the counter.
-//   2. partials: each workgroup takes tiles of TP pairs; `lpp` lanes per pair
-//                compute u = E a, v = E b, h = u*v, the residuals
-//                r_a = D u - a, r_b = D v - b, r_h = D h - a*b, and the
-//                back-propagated code gradients, staged in LDS; then every
-//                thread contracts over the tile's pairs for its gradient
-//                elements (in the parameters' precision over the tile's at
-//                most 64 pairs, in float64 across tiles) and writes one
-//                partial row per workgroup.  One kernel per objective: the two-term squared
-//                error, or the four-term loss of Eq. 8 (which also needs the
-//                per-pair norms and dot product of the cosine factor, reduced
-//                across the pair's lanes by shuffles, and the code of the
-//                spectral product for L_code).
+// Two or three kernels per step, all deterministic (fixed summation orders,
+// no floating-point atomics).  The batch rows come from the caller, through
+// index arrays, or from the counter-based generator inside the partials
+// kernel.
+//   1. weights : E, D = softplus_beta(Wt) into the workspace, and the
+//                incremented Adam step into the workspace.  Only when E and D
+//                do not fit the partials kernel's LDS; otherwise that kernel
+//                stages softplus(Wt) itself and its block 0 writes the step.
+//   2. partials, float32 with n = 31 or 81 and k = 6 or 9: a few lanes per
+//                pair with the pair in registers and the sums over pairs of
+//                outer products on the fp32 matrix cores (kernel 2 below,
+//                "a few lanes per pair").  Otherwise each workgroup takes
+//                tiles of TP pairs; `lpp` lanes per pair compute u = E a,
+//                v = E b, h = u*v, the residuals r_a = D u - a, r_b = D v - b,
+//                r_h = D h - a*b, and the back-propagated code gradients,
+//                staged in LDS; then every thread contracts over the tile's
+//                pairs for its gradient elements (in the parameters' precision
+//                over the tile's at most 64 pairs, in float64 across tiles).
+//                Either way one partial row per workgroup.  One kernel per
+//                objective: the two-term squared error, or the four-term loss
+//                of Eq. 8 (which also needs the per-pair norms and dot product
+//                of the cosine factor, reduced across the pair's lanes, and
+//                the code of the spectral product for L_code).
 //   3. finish  : one wavefront per gradient element sums the partial rows
 //                (fixed order, float64), scales by 2/N (two-term) or 1/N
 //                (Eq. 8, whose per-pair terms carry their own factors),
 //                applies the softplus slope logistic(beta Wt) and optionally
-//                the Adam update.
+//                the Adam update, and stores the incremented step counter
+//                (after every read of it by the step's pair draw).
 
 #include <cmath>
 #include <type_traits>
@@ -1028,6 +1034,8 @@ Workspace carve(void* ws, int k, int n, int64_t rows, size_t esz) {
     return w;
 }
 
+// float64 never takes the few-lanes-per-pair kernel (`lanes` is false for it);
+// this overload only lets run<double> compile.
 inline void launch_lanes(const PartialArgs<double>&, bool, int, int, int64_t, hipStream_t) {}
 
 template <int N>
