@@ -182,6 +182,29 @@ def codec_only(args):
             f"loss {loss:.4g}")
 
 
+def codec_step_timing(n, k, steps, dev):
+    """Graph-replayed codec fit steps (batch 65,536, pools of 2^18) of both
+    objectives at one (n, k): microseconds per step."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2602_18741_amd.codec_fit import CodecFit
+    pa, pb = synth.workloads.codec_pools(n, 1 << 18)
+    pa, pb = torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev)
+    we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
+    out = {"n": n, "k": k, "batch": 65536, "steps": steps}
+    for objective in ("eq8", "l2"):
+        fit = CodecFit(we0, wd0, pa, pb, batch=65536, seed=2, objective=objective, T=synth.cmf_matrix(n))
+        fit.run(1)
+        fit.capture(CODEC_STEPS_PER_GRAPH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fit.run(steps)
+        torch.cuda.synchronize()
+        out[f"{objective}_us_per_step"] = (time.perf_counter() - t0) * 1e6 / steps
+    return out
+
+
 def multibounce_leg(args, dev, n, k, T, codecs):
     """Multi-bounce chains (Eq. 10): both forms on MB_CHAINS held-out chains
     of 3 bounces for each fitted codec; GPU time of one evaluation (encode,
@@ -417,6 +440,12 @@ def main():
         codecs["l2"] = fit_codec("l2")
     (E, D), _ = codecs["eq8"]
     del pa, pb
+    # the codec step at the 380-780 nm grid (n = 81) with nine channels
+    codec81 = None
+    if not args.only and not stress and args.codec_steps >= 2000:
+        codec81 = codec_step_timing(81, 9, 2000, dev)
+        log(f"codec step n = 81, k = 9: eq8 {codec81['eq8_us_per_step']:.1f} us, "
+            f"l2 {codec81['l2_us_per_step']:.1f} us")
 
     codes = torch.empty(spec.n_tex, ld_z, device=dev)
     lcodes = torch.empty(spec.n_illum, ld_z, device=dev)
@@ -543,6 +572,7 @@ def main():
         "ciede2000_latent_vs_spectral": de,
         "ciede2000_latent_vs_spectral_two_term_codec": de_l2,
         "codec_fit": {name: info for name, (_, info) in codecs.items()},
+        "codec_step_n81_k9": codec81,
         "multibounce": bounce,
         "upsample": up,
         "serving": serving,
