@@ -681,8 +681,14 @@ __global__ __launch_bounds__(LaneShape<N>::THREADS) void codec_lanes_kernel(Part
             bv[s] = in ? bv[s] : 0.f;
         }
 
-        // codes u = E a, v = E b, h = u v (Eq. 4, Eq. 6); Eq. 8: d = h - E t
+        // codes u = E a, v = E b, h = u v (Eq. 4, Eq. 6); Eq. 8: d = h - E t,
+        // with t = a b formed once per sample for this loop
         float u[K], v[K], h[K], dc[K];
+        float tv[EQ8 ? SPL : 1];
+        if (EQ8) {
+#pragma unroll
+            for (int s = 0; s < SPL; ++s) tv[EQ8 ? s : 0] = fresh(av[s]) * bv[s];
+        }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             float su = 0.f, sv = 0.f, sw = 0.f;
@@ -691,7 +697,7 @@ __global__ __launch_bounds__(LaneShape<N>::THREADS) void codec_lanes_kernel(Part
                 const float e = sE[j * NP + i0 + s];
                 su = fmaf(e, av[s], su);
                 sv = fmaf(e, bv[s], sv);
-                if (EQ8) sw = fmaf(e, fresh(av[s]) * bv[s], sw);
+                if (EQ8) sw = fmaf(e, tv[EQ8 ? s : 0], sw);
             }
             u[j] = pair_sum<LPP>(su);
             v[j] = pair_sum<LPP>(sv);
