@@ -746,7 +746,9 @@ __global__ __launch_bounds__(LaneShape<N>::THREADS) void codec_lanes_kernel(Part
                 s_c1 = fmaf(sT[NP + i], rh, s_c1);
                 s_c2 = fmaf(sT[2 * NP + i], rh, s_c2);
             }
-            const float rap = valid ? wr * rai : 0.f, rbp = valid ? wr * rbi : 0.f;
+            // a pair past the batch has a = b = 0, so its residuals (and g_3
+            // below: both norms clamp to eps, every factor stays finite) are 0
+            const float rap = wr * rai, rbp = wr * rbi;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const float d = sD[i * DS + j];
@@ -823,7 +825,6 @@ __global__ __launch_bounds__(LaneShape<N>::THREADS) void codec_lanes_kernel(Part
             const float ti = fresh(av[s]) * bv[s];
             float g3 = al * (S[s] - ti) - bt * ti + bs * S[s];
             if (EQ8) g3 += g0 * sT[i] + g1 * sT[NP + i] + g2 * sT[2 * NP + i];
-            g3 = valid ? g3 : 0.f;
 #pragma unroll
             for (int j = 0; j < K; ++j) gs[j] = fmaf(sD[i * DS + j], g3, gs[j]);
             xcol0[s * ROW] = g3;
