@@ -614,16 +614,62 @@ __global__ __launch_bounds__(LaneShape<N>::THREADS) void codec_lanes_kernel(Part
     const int i0 = SPL * q;                     // the lane's first sample
     const uint64_t ctr_base = a.draw ? draw_base(a) : 0ull;
 
-    for (int e = tid; e < K * NP; e += THREADS) {
-        const int j = e / NP, i = e % NP;
-        sE[e] = i < N ? softplus(a.we[j * N + i], a.beta) : 0.f;
+    // the raw parameters and T this thread stages are loaded first, then the
+    // first chunk's pair rows: loads complete in order, so the rows are still
+    // in flight while the softplus values are formed and stored
+    constexpr int IE = (K * NP + THREADS - 1) / THREADS, ID = (NP * DS + THREADS - 1) / THREADS;
+    constexpr int IT = (3 * NP + THREADS - 1) / THREADS;
+    // (indices clamped into the arrays, the values past them selected away)
+    float rwe[IE], rwd[ID], rt[IT];
+#pragma unroll
+    for (int u = 0; u < IE; ++u) {
+        const int e = min(tid + u * THREADS, K * NP - 1), j = e / NP, i = min(e % NP, N - 1);
+        rwe[u] = a.we[j * N + i];
     }
-    for (int e = tid; e < NP * DS; e += THREADS) {
-        const int i = e / DS, j = e % DS;
-        sD[e] = (i < N && j < K) ? softplus(a.wd[i * K + j], a.beta) : 0.f;
+#pragma unroll
+    for (int u = 0; u < ID; ++u) {
+        const int e = min(tid + u * THREADS, NP * DS - 1), i = min(e / DS, N - 1), j = min(e % DS, K - 1);
+        rwd[u] = a.wd[i * K + j];
     }
-    if (EQ8)
-        for (int e = tid; e < 3 * NP; e += THREADS) sT[e] = e % NP < N ? a.T[(e / NP) * N + e % NP] : 0.f;
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+        const int e = min(tid + u * THREADS, 3 * NP - 1);
+        rt[u] = EQ8 ? a.T[(e / NP) * N + min(e % NP, N - 1)] : 0.f;
+    }
+    const int last = N - 1 - i0;  // the lane's last sample below n, relative to i0
+    // the lane's samples of a chunk's pair (row 0 for pairs past the batch);
+    // samples past n re-read the last one (and are zeroed in the loop)
+    float av[SPL], bv[SPL];
+    auto load_rows = [&](int64_t ch) {
+        const int64_t pi = ch * PPW + pr;
+        int64_t ra = 0, rb = 0;
+        if (pi < a.N) batch_rows(a, ctr_base, pi, ra, rb);
+        const float* pa = a.A + ra * a.ld_a + i0;
+        const float* pb = a.B + rb * a.ld_b + i0;
+#pragma unroll
+        for (int s = 0; s < SPL; ++s) {
+            const int o = s < last ? s : last;
+            av[s] = pa[o];
+            bv[s] = pb[o];
+        }
+    };
+    const int64_t ch0 = int64_t(blockIdx.x) * WAVES + wave;
+    if (ch0 * PPW < a.N) load_rows(ch0);
+#pragma unroll
+    for (int u = 0; u < IE; ++u) {
+        const int e = tid + u * THREADS, i = e % NP;
+        if (e < K * NP) sE[e] = i < N ? softplus(rwe[u], a.beta) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < ID; ++u) {
+        const int e = tid + u * THREADS, i = e / DS, j = e % DS;
+        if (e < NP * DS) sD[e] = (i < N && j < K) ? softplus(rwd[u], a.beta) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+        const int e = tid + u * THREADS;
+        if (EQ8 && e < 3 * NP) sT[e] = e % NP < N ? rt[u] : 0.f;
+    }
     if (tid < PPW) sZero[tid] = 0.f;
     if (a.step && blockIdx.x == 0 && tid == 0) *a.ws_step = *a.step + 1;
     __syncthreads();
@@ -654,26 +700,13 @@ __global__ __launch_bounds__(LaneShape<N>::THREADS) void codec_lanes_kernel(Part
     const float lam = a.lam;
     const float wr = EQ8 ? float(a.w_rec * 2.0 / N) : 1.f;
     const float wk = EQ8 ? float(a.w_code * 2.0 / K) : 0.f;
-    const int last = N - 1 - i0;  // the lane's last sample below n, relative to i0
 
-    for (int64_t ch = int64_t(blockIdx.x) * WAVES + wave; ch * PPW < a.N; ch += int64_t(gridDim.x) * WAVES) {
+    for (int64_t ch = ch0; ch * PPW < a.N; ch += int64_t(gridDim.x) * WAVES) {
         // keeps the reads of E, D and T from LDS inside the loop: hoisted out
         // of it, all of them would stay live in registers
         reread_tables();
-        const int64_t pi = ch * PPW + pr;
-        const bool valid = pi < a.N;
-        int64_t ra = 0, rb = 0;
-        if (valid) batch_rows(a, ctr_base, pi, ra, rb);
-        const float* pa = a.A + ra * a.ld_a + i0;
-        const float* pb = a.B + rb * a.ld_b + i0;
-        // the lane's samples; samples past n re-read the last one and are zeroed
-        float av[SPL], bv[SPL];
-#pragma unroll
-        for (int s = 0; s < SPL; ++s) {
-            const int o = s < last ? s : last;
-            av[s] = pa[o];
-            bv[s] = pb[o];
-        }
+        if (ch != ch0) load_rows(ch);
+        const bool valid = ch * PPW + pr < a.N;
 #pragma unroll
         for (int s = 0; s < SPL; ++s) {
             const bool in = valid && s <= last;
