@@ -40,6 +40,37 @@ def training_pairs(E: torch.Tensor, T: torch.Tensor, spectra: torch.Tensor, n: i
     return rgb, z
 
 
+class PlateauLR:
+    """Reduce-on-plateau learning-rate rule (the schedule of Sec. 5.2: factor
+    0.5, patience 200, floor 1e-6), in the form of torch's ReduceLROnPlateau
+    with its defaults otherwise: a loss counts as better when it is below the
+    best so far by more than `threshold` relative; after more than `patience`
+    evaluations without one the rate is multiplied by `factor`, not below
+    `min_lr` (changes smaller than `eps` are skipped), and the count restarts."""
+
+    def __init__(self, lr: float, factor: float = 0.5, patience: int = 200, min_lr: float = 1e-6,
+                 threshold: float = 1e-4, eps: float = 1e-8):
+        if not 0.0 < factor < 1.0:
+            raise ValueError("factor must be in (0, 1)")
+        self.lr, self.factor, self.patience = float(lr), float(factor), int(patience)
+        self.min_lr, self.threshold, self.eps = float(min_lr), float(threshold), float(eps)
+        self.best = float("inf")
+        self.bad = 0
+
+    def step(self, loss: float) -> float:
+        loss = float(loss)
+        if loss < self.best * (1.0 - self.threshold):
+            self.best, self.bad = loss, 0
+        else:
+            self.bad += 1
+        if self.bad > self.patience:
+            new = max(self.lr * self.factor, self.min_lr)
+            if self.lr - new > self.eps:
+                self.lr = new
+            self.bad = 0
+        return self.lr
+
+
 class UpsampleFit:
     def __init__(self, rgb: torch.Tensor, z_gt: torch.Tensor, M: torch.Tensor, white, k: int,
                  batch: int = 1024, lr: float = 2e-3, weight_decay: float = 1e-5,
@@ -91,6 +122,23 @@ class UpsampleFit:
         for _ in range(steps):
             self._step()
         return self.loss
+
+    def run_epochs(self, epochs: int, epoch_steps: int, plateau: PlateauLR | None = None):
+        """`epochs` rounds of `epoch_steps` steps; after each, the plateau rule
+        (if any) sees the loss of the round's last batch and may lower the
+        learning rate.  The rate is a launch argument, so a captured graph is
+        recorded again when it changes.  Returns the per-round losses."""
+        losses = []
+        for _ in range(epochs):
+            loss = float(self.run(epoch_steps))
+            losses.append(loss)
+            if plateau is not None:
+                lr = plateau.step(loss)
+                if lr != self.opt["lr"]:
+                    self.opt["lr"] = lr
+                    if self.graph is not None:
+                        self.capture(self.graph_steps)
+        return losses
 
     @property
     def steps_done(self) -> int:

@@ -228,3 +228,36 @@ def test_drawn_rows_equal_generated_indices(ops):
         assert int(opt["step"].item()) == 7
         runs.append(out + [params, opt["m"], opt["v"]])
     assert all(torch.equal(x, y) for x, y in zip(*runs))
+
+
+def test_plateau_schedule_with_graph_recapture_equals_eager(ops):
+    """run_epochs with the plateau rule: every round lowers the rate
+    (threshold 1: no loss counts as better, the first one included), the graph
+    is recorded again
+    after each change, and the result equals the same schedule run eagerly,
+    bit for bit."""
+    from paper_2602_18741_amd.upsample_fit import PlateauLR, UpsampleFit
+    k = 6
+    rng = np.random.default_rng(29)
+    rgb = rng.uniform(0, 1, (1 << 12, 3)).astype(np.float32)
+    zg = (rgb @ rng.uniform(0, 1, (k, 3)).T).astype(np.float32)
+    M = rng.uniform(0.05, 0.5, (3, k)).astype(np.float32)
+
+    def make():
+        return UpsampleFit(torch.from_numpy(rgb).cuda(), torch.from_numpy(_blocked(zg, k)).cuda(),
+                           torch.from_numpy(M).cuda(), WHITE, k, batch=256, seed=5)
+    eager = make()
+    l_e = eager.run_epochs(5, 3, PlateauLR(2e-3, patience=0, threshold=1.0))
+    graphed = make()
+    graphed.run(1)
+    graphed.capture(3)
+    graphed.opt["step"].zero_()
+    graphed.params.copy_(make().params)
+    for name in ("m", "v"):
+        graphed.opt[name].zero_()
+    l_g = graphed.run_epochs(5, 3, PlateauLR(2e-3, patience=0, threshold=1.0))
+    torch.cuda.synchronize()
+    assert eager.opt["lr"] == graphed.opt["lr"] == 2e-3 * 0.5 ** 5
+    assert l_e == l_g
+    assert torch.equal(eager.params, graphed.params)
+    assert all(torch.equal(eager.opt[x], graphed.opt[x]) for x in ("m", "v", "step"))
