@@ -1,10 +1,12 @@
 // Training step of the upsampling network (Sec. 5.2): loss, hand-written
 // backward and AdamW with global-norm gradient clipping, on a batch of
-// (RGB, code) pairs drawn by index.  Deterministic: fixed summation orders,
-// no floating-point atomics.
+// (RGB, code) pairs gathered by index or drawn from the counter-based
+// generator inside kernel 1.  Deterministic: fixed summation orders, no
+// floating-point atomics.
 //
-//   1. partials: a workgroup takes four samples at a time, one per quarter
-//                (128 threads, one per hidden unit).  Forward through the
+//   1. partials: a workgroup (at most one per CU's worth: 256 partial rows)
+//                takes four samples at a time, one per quarter (128 threads,
+//                one per hidden unit).  Forward through the
 //                three layers, the per-sample loss terms and dL/dz, then
 //                backward to the hidden pre-activations, with W2 and W3 in LDS
 //                (odd row stride: row-wise and column-wise reads are both
@@ -12,8 +14,10 @@
 //                elements and accumulates them over the workgroup's samples
 //                in registers; one partial row per workgroup.
 //   2. reduce  : a lane per parameter sums the partial rows in a fixed order
-//                (float64), divides by N, writes the gradient, and each block
-//                writes its sum of squares; block 0 also sums the loss.
+//                (float64, sixteen row loads in flight), divides by N, writes
+//                the gradient, and each block writes its sum of squares;
+//                block 0 also sums the per-row losses (a wavefront butterfly)
+//                and increments the step counter, after kernel 1's draw.
 //   3. adamw   : every block forms the global gradient norm from the block
 //                sums (same order everywhere), the clipping factor
 //                min(1, max_norm / (norm + 1e-6)), then per parameter the
