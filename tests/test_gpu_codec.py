@@ -248,3 +248,29 @@ def test_autograd_backward_matches_oracle(ops):
     L, ge, gd = oc.loss_and_grad(we0, wd0, A, B, 0.5)
     assert abs(float(loss.detach()) - L) <= 1e-5 * L
     assert _grad_ok(to_np(we.grad), 3.0 * ge) and _grad_ok(to_np(wd.grad), 3.0 * gd)
+
+
+@pytest.mark.parametrize("n,k", [(31, 6), (81, 9), (31, 7)])
+def test_drawn_rows_without_a_counter(ops, n, k):
+    """A draw with no counter pointer uses the base ctr0 alone: the rows are
+    gen_indices(seed, N, rows, ctr0) without a step."""
+    N, rows = 2000, 7000
+    rng = np.random.default_rng(n * k)
+    we, wd = synth.codec_init(rng, k, n)
+    pa, pb = _pairs(n, rows, 12)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()  # noqa: E731
+    A, B = t(pa), t(pb)
+    outs = []
+    for use_draw in (False, True):
+        ge = torch.empty(k, n, device="cuda")
+        gd = torch.empty(n, k, device="cuda")
+        if use_draw:
+            loss = ops.codec_step(t(we), t(wd), A, B, N, grad_e=ge, grad_d=gd,
+                                  draw=dict(seed_a=3, seed_b=4, ctr0=123456789))
+        else:
+            ia = ops.gen_indices(3, N, rows, ctr0=123456789)
+            ib = ops.gen_indices(4, N, rows, ctr0=123456789)
+            loss = ops.codec_step(t(we), t(wd), A, B, N, idx_a=ia, idx_b=ib, grad_e=ge, grad_d=gd)
+        outs.append((loss.clone(), ge, gd))
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(*outs))

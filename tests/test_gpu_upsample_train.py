@@ -261,3 +261,21 @@ def test_plateau_schedule_with_graph_recapture_equals_eager(ops):
     assert l_e == l_g
     assert torch.equal(eager.params, graphed.params)
     assert all(torch.equal(eager.opt[x], graphed.opt[x]) for x in ("m", "v", "step"))
+
+
+def test_drawn_rows_without_a_counter(ops):
+    """A training-step draw with no counter pointer uses the base ctr0 alone."""
+    from paper_2602_18741_amd.upsample_fit import default_init
+    k, N, rows = 9, 700, 3000
+    rng = np.random.default_rng(31)
+    rgb = torch.from_numpy(rng.uniform(0, 1, (rows, 3)).astype(np.float32)).cuda()
+    z = torch.from_numpy(_blocked(rng.uniform(0, 1, (rows, k)).astype(np.float32), k)).cuda()
+    M = torch.from_numpy(rng.uniform(0.05, 0.5, (3, k)).astype(np.float32)).cuda()
+    params = torch.from_numpy(default_init(k, 4)).cuda()
+    g1 = torch.empty_like(params)
+    g2 = torch.empty_like(params)
+    l1 = ops.upsample_train_step(params, rgb, z, M, WHITE, k, N, grad=g1, draw=dict(seed=9, ctr0=77))
+    idx = ops.gen_indices(9, N, rows, ctr0=77)
+    l2 = ops.upsample_train_step(params, rgb, z, M, WHITE, k, N, grad=g2, idx=idx)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
