@@ -35,11 +35,15 @@ constexpr int kH = 128;            // hidden width
 constexpr int kThreads = 256;
 constexpr int kSamples = 4;        // samples a partials workgroup takes at once
 constexpr int kPThreads = kSamples * kH;
-constexpr int kRS = kH + 1;        // LDS row stride of W2 and W3
+// LDS row stride of W2 and W3: rows 16-byte aligned for the forward's row
+// reads, 4 banks apart so 16 threads' rows and a row's columns are spread
+constexpr int kRS = kH + 4;
 constexpr int kMaxRows = 256;      // partial rows (workgroups of kernel 1): one per CU
 static_assert(kMaxRows <= kThreads, "one workgroup sums the per-row losses");
 constexpr int kW3PerThread = kMaxK / kSamples;
 constexpr int kW2PerThread = kH / kSamples;
+static_assert(kRS % 4 == 0 && (6 * kH + 3 * kMaxK + 8) % 4 == 0 && kMaxK % 4 == 0,
+              "16-byte aligned rows and per-sample areas in LDS");
 
 // packed parameter offsets (floats): W1 (128 x 3), b1, W2 (128 x 128), b2, W3 (k x 128), b3
 constexpr int64_t kOffB1 = 3 * kH;
@@ -165,14 +169,32 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
         __syncthreads();
         {
             float v = sB2[j];
-            for (int i = 0; i < kH; ++i) v = fmaf(sW2[j * kRS + i], h1[i], v);
+            const float4* wr = reinterpret_cast<const float4*>(sW2 + j * kRS);
+            const float4* hv = reinterpret_cast<const float4*>(h1);
+#pragma unroll 8
+            for (int i = 0; i < kH / 4; ++i) {
+                const float4 w = wr[i], x = hv[i];
+                v = fmaf(w.x, x.x, v);
+                v = fmaf(w.y, x.y, v);
+                v = fmaf(w.z, x.z, v);
+                v = fmaf(w.w, x.w, v);
+            }
             p2[j] = v;
             h2[j] = v * logistic(v);
         }
         __syncthreads();
         if (j < k) {
             float v = sB3[j];
-            for (int i = 0; i < kH; ++i) v = fmaf(sW3[j * kRS + i], h2[i], v);
+            const float4* wr = reinterpret_cast<const float4*>(sW3 + j * kRS);
+            const float4* hv = reinterpret_cast<const float4*>(h2);
+#pragma unroll 8
+            for (int i = 0; i < kH / 4; ++i) {
+                const float4 w = wr[i], x = hv[i];
+                v = fmaf(w.x, x.x, v);
+                v = fmaf(w.y, x.y, v);
+                v = fmaf(w.z, x.z, v);
+                v = fmaf(w.w, x.w, v);
+            }
             const float g = valid ? a.zgt[row * a.ld_z + 4 * (j / 3) + j % 3] : v;
             zz[j] = v;
             dd[j] = v - g;
