@@ -265,7 +265,8 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
         }
         __syncthreads();
         // accumulate the four samples, in order, into the owned gradient
-        // elements: W2 rows i = 4q + hi, W3 rows c = 4r + hi, column jj
+        // elements: W2 rows i = 32 hi + q (contiguous: 16-byte reads of dp2),
+        // W3 rows c = 4r + hi, column jj
         {
             const int jj = tid % kH, hi = tid / kH;
             float h1[kSamples], h2[kSamples];
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
             }
 #pragma unroll
             for (int q = 0; q < kW2PerThread; ++q) {
-                const int i = kSamples * q + hi;
+                const int i = kW2PerThread * hi + q;
                 float v = aW2[q];
 #pragma unroll
                 for (int u = 0; u < kSamples; ++u) v = fmaf(sS[u * kPer + 4 * kH + i], h1[u], v);
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
     {
         const int jj = tid % kH, hi = tid / kH;
 #pragma unroll
-        for (int q = 0; q < kW2PerThread; ++q) prow[kOffW2 + (kSamples * q + hi) * kH + jj] = aW2[q];
+        for (int q = 0; q < kW2PerThread; ++q) prow[kOffW2 + (kW2PerThread * hi + q) * kH + jj] = aW2[q];
 #pragma unroll
         for (int r = 0; r < kW3PerThread; ++r) {
             const int c = kSamples * r + hi;
