@@ -83,8 +83,9 @@ def test_fp64_gradient_matches_oracle_and_finite_differences(ops, seed):
         assert abs(fd - to_np(ge)[idx]) <= 1e-7 * scale
 
 
-def test_gather_by_index_equals_explicit_batch(ops):
-    n, k, N = 31, 6, 5000
+@pytest.mark.parametrize("n,k", [(31, 6), (81, 9), (81, 7)])
+def test_gather_by_index_equals_explicit_batch(ops, n, k):
+    N = 5000
     rng = np.random.default_rng(4)
     we, wd = synth.codec_init(rng, k, n)
     pa, pb = _pairs(n, 20000, 5)
