@@ -54,6 +54,18 @@ __device__ __forceinline__ float silu(float x) {
     return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
+// With u = -log2(e) y: silu(y) = y / (1 + 2^u) = -ln(2) u / (1 + 2^u).  The F16
+// kernel carries s = u / (1 + 2^u) between layers: -log2(e) is folded into the
+// staged layer-1 weights and bias and into the layer-2 bias, the two factors
+// cancel in layer 2 (ln(2) log2(e) = 1), and layer 3 applies -ln(2) with its bias.
+constexpr float kNegLog2e = -1.4426950408889634f;
+constexpr float kNegLn2 = -0.6931471805599453f;
+
+__device__ __forceinline__ float silu_log2(float u) {
+    // 2^u = inf gives s = 0; 2^u = 0 gives s = u, i.e. silu(y) = y
+    return u * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u));
+}
+
 // Feature held by slot i of lane group g in the 32-wide K chunk c (F16 order).
 __device__ __forceinline__ int f16_feature(int c, int g, int i) {
     return 32 * c + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
@@ -85,7 +97,7 @@ template <int NT, int MC3>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT > 1 ? 3 : 1))) void upsample_f16_kernel(UpArgs a) {
     __shared__ hc_h8 sW2[8 * 4 * kWave];    // [mo][c][lane]
     __shared__ hc_h8 sW3[MC3 * 4 * kWave];  // [m3][c][lane]
-    __shared__ float4 sW1[kHidden];          // (w_r, w_g, w_b, b1)
+    __shared__ float sW1[8 * kWave];         // [mo][lane]: A operand of (w_r, w_g, w_b, b1)
     __shared__ __align__(16) float sB2[kHidden];
     __shared__ float sB3[16 * MC3];
 
@@ -107,11 +119,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT > 1
             v[i] = row < a.k ? (_Float16)ldg_f32(a.W3 + row * kHidden + f16_feature(c, g, i)) : (_Float16)0.0f;
         sW3[e] = v;
     }
-    for (int j = tid; j < kHidden; j += kThreads) {
-        sW1[j] = make_float4(ldg_f32(a.W1 + 3 * j), ldg_f32(a.W1 + 3 * j + 1), ldg_f32(a.W1 + 3 * j + 2),
-                             ldg_f32(a.b1 + j));
-        sB2[j] = ldg_f32(a.b2 + j);
+    for (int e = tid; e < 8 * kWave; e += kThreads) {
+        // feature 16 mo + lane % 16, input component lane / 16 (3: the bias)
+        const int lane = e % kWave, j = 16 * (e / kWave) + lane % 16, c = lane / 16;
+        sW1[e] = kNegLog2e * (c < 3 ? ldg_f32(a.W1 + 3 * j + c) : ldg_f32(a.b1 + j));
     }
+    for (int j = tid; j < kHidden; j += kThreads) sB2[j] = kNegLog2e * ldg_f32(a.b2 + j);
     for (int j = tid; j < 16 * MC3; j += kThreads) sB3[j] = j < a.k ? ldg_f32(a.b3 + j) : 0.0f;
     __syncthreads();
 
@@ -122,37 +135,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT > 1
         // keeps the weight reads from LDS inside the loop: hoisted out of it,
         // every fragment would stay live in registers for the whole kernel
         __asm__ volatile("" ::: "memory");
-        // layer 1: B operands of layer 2, two 16-feature chunks per K chunk
+        // layer 1 on the matrix cores, K = 4: lane (g, n) brings component g of
+        // texel n (g = 3: the constant 1 that takes the bias); the 16 x 16 results
+        // land in the layout of layer 2's outputs, two chunks per K chunk of layer 2
         hc_h8 h1[NT][4];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int64_t texel = (grp * NT + t) * 16 + n;
-            float r = 0.f, gg = 0.f, bb = 0.f;
-            if (texel < a.m) {
-                const float* p = a.rgb + texel * a.ld_rgb;
-                r = ldg_f32(p);
-                gg = ldg_f32(p + 1);
-                bb = ldg_f32(p + 2);
-            }
+            float x = g == 3 ? 1.0f : 0.0f;
+            if (g < 3 && texel < a.m) x = ldg_f32(a.rgb + texel * a.ld_rgb + g);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                float lo[4], hi[4];
-                layer1(sW1, r, gg, bb, 2 * c, g, lo);
-                layer1(sW1, r, gg, bb, 2 * c + 1, g, hi);
+            for (int mo = 0; mo < 8; ++mo) {
+                const hc_f4 u = __builtin_amdgcn_mfma_f32_16x16x4f32(sW1[mo * kWave + lane], x,
+                                                                     hc_f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    h1[t][c][i] = (_Float16)lo[i];
-                    h1[t][c][i + 4] = (_Float16)hi[i];
-                }
+                for (int r = 0; r < 4; ++r) h1[t][mo >> 1][(mo & 1) * 4 + r] = (_Float16)silu_log2(u[r]);
             }
         }
-        // layer 2: 8 output chunks of 16 features x 4 K chunks of 32
+        // layer 2: 8 output chunks of 16 features x 4 K chunks of 32; the chain
+        // starts from the (scaled) bias, so u = W2 s1 + b2' comes out of it
         hc_h8 h2[NT][4];
 #pragma unroll
         for (int mo = 0; mo < 8; ++mo) {
+            const float4 b = *reinterpret_cast<const float4*>(sB2 + 16 * mo + 4 * g);
+            const hc_f4 bias = {b.x, b.y, b.z, b.w};
             hc_f4 acc[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = hc_f4{0.f, 0.f, 0.f, 0.f};
+            for (int t = 0; t < NT; ++t) acc[t] = bias;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const hc_h8 w = sW2[(mo * 4 + c) * kWave + lane];
@@ -160,15 +169,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT > 1
                 for (int t = 0; t < NT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w, h1[t][c], acc[t], 0, 0, 0);
             }
-            const float4 bias = *reinterpret_cast<const float4*>(sB2 + 16 * mo + 4 * g);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 // features 16 mo + 4 g + r of texel n: half of K chunk mo / 2
                 const int half = (mo & 1) * 4;
-                h2[t][mo >> 1][half + 0] = (_Float16)silu(acc[t][0] + bias.x);
-                h2[t][mo >> 1][half + 1] = (_Float16)silu(acc[t][1] + bias.y);
-                h2[t][mo >> 1][half + 2] = (_Float16)silu(acc[t][2] + bias.z);
-                h2[t][mo >> 1][half + 3] = (_Float16)silu(acc[t][3] + bias.w);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h2[t][mo >> 1][half + r] = (_Float16)silu_log2(acc[t][r]);
             }
         }
         // layer 3 and output
@@ -192,7 +198,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT > 1
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int ch = 16 * m3 + 4 * g + r;
-                    if (ch < a.k) stg_f32(zrow + 4 * (ch / 3) + ch % 3, acc[t][r] + sB3[ch]);
+                    if (ch < a.k) stg_f32(zrow + 4 * (ch / 3) + ch % 3, fmaf(kNegLn2, acc[t][r], sB3[ch]));
                 }
             }
         }
