@@ -9,7 +9,11 @@ Lipschitz constant 1.1:
     e(p2_j) <= (2 u16 + g + ua) S2_j + g |b2_j|
     e(h2_j) <= 1.1 e(p2_j) + ua |h2_j|
     e(z_c)  <= sum_j |W3_cj| e(h2_j) + (2 u16 + g) sum_j |W3_cj| |h2_j| + g |b3_c|
-The fp32 path has u16 = 0.  Checked element by element against this bound.
+The fp32 path has u16 = 0.  The fp16 kernel carries s = -h / ln 2 between layers
+(-log2 e folded into the layer-1 weights and the biases in fp32, -ln 2 applied in
+the output FMA): each fold is one more fp32 rounding, a few 2^-24 relative, inside
+the slack of g and ua; rounding s to fp16 is the same relative u16 as rounding h.
+Checked element by element against this bound.
 """
 
 import numpy as np
