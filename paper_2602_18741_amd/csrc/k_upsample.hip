@@ -19,7 +19,8 @@
 //        unchanged.
 //   F32: fp32 operands, v_mfma_f32_16x16x4_f32; K chunk (16c + 4g + r) per
 //        lane group g, register r.
-// Layer 1 (K = 3) and the activations run on the vector ALU in fp32.
+// Layer 1 (K = 3 inputs and the bias) is one v_mfma_f32_16x16x4_f32 per 16
+// features in both; the activations run on the vector ALU in fp32.
 
 #include "hc_internal.hpp"
 
@@ -48,14 +49,8 @@ struct UpArgs {
     int64_t n_groups;  // groups of NT tiles of 16 texels
 };
 
-__device__ __forceinline__ float silu(float x) {
-    // x * logistic(x); exp2 of a large argument gives inf and rcp(inf) = 0
-    const float e = __builtin_amdgcn_exp2f(-x * 1.4426950408889634f);
-    return x * __builtin_amdgcn_rcpf(1.0f + e);
-}
-
-// With u = -log2(e) y: silu(y) = y / (1 + 2^u) = -ln(2) u / (1 + 2^u).  The F16
-// kernel carries s = u / (1 + 2^u) between layers: -log2(e) is folded into the
+// With u = -log2(e) y: silu(y) = y / (1 + 2^u) = -ln(2) u / (1 + 2^u).  Both
+// kernels carry s = u / (1 + 2^u) between layers: -log2(e) is folded into the
 // staged layer-1 weights and bias and into the layer-2 bias, the two factors
 // cancel in layer 2 (ln(2) log2(e) = 1), and layer 3 applies -ln(2) with its bias.
 constexpr float kNegLog2e = -1.4426950408889634f;
@@ -78,16 +73,6 @@ __device__ __forceinline__ void write_padding(float* zrow, int k, int64_t ld_z, 
     for (int col = g; col < ld_z; col += 4) {
         const int b = col >> 2, j = col & 3;
         if (j == 3 || b >= nb || 3 * b + j >= k) stg_f32(zrow + col, 0.0f);
-    }
-}
-
-// Layer 1 for the lane's texel: features 16 kc + 4 g + i, i < 4, of chunk kc.
-__device__ __forceinline__ void layer1(const float4* w1b, float r, float gg, float bb, int kc, int g,
-                                       float out[4]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float4 w = w1b[16 * kc + 4 * g + i];  // (w_r, w_g, w_b, bias)
-        out[i] = silu(fmaf(w.x, r, fmaf(w.y, gg, fmaf(w.z, bb, w.w))));
     }
 }
 
@@ -215,7 +200,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT > 1
 template <int NT, int MC3>
 __global__ __launch_bounds__(kThreads) void upsample_f32_kernel(UpArgs a) {
     __shared__ float sW2[8 * 32 * kWave];  // [mo][kc * 4 + r][lane], 64 KiB
-    __shared__ float4 sW1[kHidden];          // (w_r, w_g, w_b, b1)
+    __shared__ float sW1[8 * kWave];        // [mo][lane]: A operand of (w_r, w_g, w_b, b1)
+    __shared__ __align__(16) float sB2[kHidden];
 
     const int tid = threadIdx.x;
     for (int e = tid; e < 8 * 32 * kWave; e += kThreads) {
@@ -223,9 +209,12 @@ __global__ __launch_bounds__(kThreads) void upsample_f32_kernel(UpArgs a) {
         const int kc = ch / 4, r = ch % 4, m = lane % 16, g = lane / 16;
         sW2[e] = ldg_f32(a.W2 + (16 * mo + m) * kHidden + 16 * kc + 4 * g + r);
     }
-    for (int j = tid; j < kHidden; j += kThreads)
-        sW1[j] = make_float4(ldg_f32(a.W1 + 3 * j), ldg_f32(a.W1 + 3 * j + 1), ldg_f32(a.W1 + 3 * j + 2),
-                             ldg_f32(a.b1 + j));
+    for (int e = tid; e < 8 * kWave; e += kThreads) {
+        // as in the F16 kernel: scaled by -log2(e), component lane / 16 (3: the bias)
+        const int lane = e % kWave, j = 16 * (e / kWave) + lane % 16, c = lane / 16;
+        sW1[e] = kNegLog2e * (c < 3 ? ldg_f32(a.W1 + 3 * j + c) : ldg_f32(a.b1 + j));
+    }
+    for (int j = tid; j < kHidden; j += kThreads) sB2[j] = kNegLog2e * ldg_f32(a.b2 + j);
     __syncthreads();
 
     const int lane = tid & (kWave - 1);
@@ -235,26 +224,29 @@ __global__ __launch_bounds__(kThreads) void upsample_f32_kernel(UpArgs a) {
         // keeps the weight reads from LDS inside the loop: hoisted out of it,
         // every fragment would stay live in registers for the whole kernel
         __asm__ volatile("" ::: "memory");
+        // layer 1 on the matrix cores (K = r, g, b, 1), activations s of silu_log2
         float h1[NT][8][4];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int64_t texel = (grp * NT + t) * 16 + n;
-            float r = 0.f, gg = 0.f, bb = 0.f;
-            if (texel < a.m) {
-                const float* p = a.rgb + texel * a.ld_rgb;
-                r = ldg_f32(p);
-                gg = ldg_f32(p + 1);
-                bb = ldg_f32(p + 2);
-            }
+            float x = g == 3 ? 1.0f : 0.0f;
+            if (g < 3 && texel < a.m) x = ldg_f32(a.rgb + texel * a.ld_rgb + g);
 #pragma unroll
-            for (int kc = 0; kc < 8; ++kc) layer1(sW1, r, gg, bb, kc, g, h1[t][kc]);
+            for (int kc = 0; kc < 8; ++kc) {
+                const hc_f4 u = __builtin_amdgcn_mfma_f32_16x16x4f32(sW1[kc * kWave + lane], x,
+                                                                     hc_f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h1[t][kc][r] = silu_log2(u[r]);
+            }
         }
         float h2[NT][8][4];
 #pragma unroll
         for (int mo = 0; mo < 8; ++mo) {
+            const float4 b = *reinterpret_cast<const float4*>(sB2 + 16 * mo + 4 * g);
+            const hc_f4 bias = {b.x, b.y, b.z, b.w};
             hc_f4 acc[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = hc_f4{0.f, 0.f, 0.f, 0.f};
+            for (int t = 0; t < NT; ++t) acc[t] = bias;
 #pragma unroll
             for (int ch = 0; ch < 32; ++ch) {
                 const float w = sW2[(mo * 32 + ch) * kWave + lane];
@@ -265,8 +257,7 @@ __global__ __launch_bounds__(kThreads) void upsample_f32_kernel(UpArgs a) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    h2[t][mo][r] = silu(acc[t][r] + ldg_f32(a.b2 + 16 * mo + 4 * g + r));
+                for (int r = 0; r < 4; ++r) h2[t][mo][r] = silu_log2(acc[t][r]);
             }
         }
 #pragma unroll
@@ -291,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void upsample_f32_kernel(UpArgs a) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int ch = 16 * m3 + 4 * g + r;
-                    if (ch < a.k) stg_f32(zrow + 4 * (ch / 3) + ch % 3, acc[t][r] + ldg_f32(a.b3 + ch));
+                    if (ch < a.k) stg_f32(zrow + 4 * (ch / 3) + ch % 3, fmaf(kNegLn2, acc[t][r], ldg_f32(a.b3 + ch)));
                 }
             }
         }
@@ -304,9 +295,8 @@ __global__ __launch_bounds__(kThreads) void upsample_f32_kernel(UpArgs a) {
 }
 
 // 16-texel tiles per wave per step.  F16 with k <= 16: two tiles share each
-// weight fragment read from LDS (167 registers, 3 waves per SIMD: 1.56 against
-// 1.64 ms for 4096^2 texels at one tile and 4 waves); wider outputs would spill
-// at two tiles and keep one, as does F32.
+// weight fragment read from LDS (112 registers); wider outputs keep one tile,
+// as does F32.
 constexpr int kNT16 = 2;
 constexpr int kNT32 = 1;
 constexpr int kMaxGrid = 2048;
