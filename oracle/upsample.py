@@ -83,16 +83,19 @@ def upsample_loss(net, rgb, z_gt, M, white, w_max: float = 0.3, w_col: float = 0
 
 
 def upsample_loss_and_grad(net, rgb, z_gt, M, white, w_max: float = 0.3, w_col: float = 0.05,
-                           abs_scale: bool = False):
+                           abs_scale: bool = False, cstar=None):
     """Loss of upsample_loss and its gradient with respect to every weight.
 
     Backward, per sample (then / N): with d = z - z_gt,
-      dz = (2/k) d + w_max sign(d_c*) e_c*  (c* the first channel of largest |d|)
+      dz = (2/k) d + w_max sign(d_c*) e_c*  (c* a channel of largest |d|)
            + w_col M^T J^T (Lab_z - Lab_gt) / DeltaE   (0 where DeltaE = 0),
     J the Jacobian of Lab at M z; then through the layers,
       dW3 = dz h2^T, db3 = dz, dp2 = (W3^T dz) * silu'(p2), dW2 = dp2 h1^T, db2 = dp2,
       dp1 = (W2^T dp2) * silu'(p1), dW1 = dp1 c^T, db1 = dp1,
     silu'(x) = s + x s (1 - s), s = logistic(x).
+    The max over channels has one subgradient per channel that attains it;
+    c* defaults to the first such channel, and `cstar` (one channel index per
+    sample) picks another where several tie.
     Returns (loss, dict of gradients keyed like net); with abs_scale also a
     dict of the batch means of |per-sample contribution| of every element
     (the magnitude that rounding errors of the batch sum scale with)."""
@@ -108,7 +111,9 @@ def upsample_loss_and_grad(net, rgb, z_gt, M, white, w_max: float = 0.3, w_col: 
     z = h2 @ W3.T + b3
     d = z - _f64(z_gt)
     ad = np.abs(d)
-    cstar = np.argmax(ad, axis=1)
+    if cstar is None:
+        cstar = np.argmax(ad, axis=1)
+    cstar = np.asarray(cstar, dtype=np.int64)
     lz, lg = lab(z @ M.T, white), lab(_f64(z_gt) @ M.T, white)
     diff = lz - lg
     de = np.linalg.norm(diff, axis=1)

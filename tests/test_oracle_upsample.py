@@ -194,3 +194,50 @@ def test_abs_scale_bounds_the_gradient():
     _, g1, sc1 = ou.upsample_loss_and_grad(net, rgb[:1], zg[:1], M, white, abs_scale=True)
     for key in g1:
         assert np.allclose(np.abs(g1[key]), sc1[key], rtol=1e-12, atol=0)
+
+
+def test_tied_max_channels_give_the_one_sided_derivatives():
+    """At an exact tie of the two largest |z - z_gt| the max-abs term of
+    Sec. 5.2 has a kink: the right-sided derivative along a direction v is the
+    larger of the two tied channels' directional derivatives, the left-sided
+    one the smaller.  The oracle's gradients with either channel taking the
+    term (cstar) must be exactly those two, checked by one-sided differences
+    of the loss; with no tie, cstar = argmax reproduces the default."""
+    k = 6
+    net = _net(k, seed=70)
+    rgb, zg, M, white = _batch(k, 1, 71)
+    z = ou.upsample(net, rgb)[0]
+    a, b, t = 1, 4, 0.9                        # planted tie: d_a = +t, d_b = -t
+    zg = z - 0.01 * np.arange(k)               # other |d| well below t
+    zg[a], zg[b] = z[a] - t, z[b] + t
+    zg = zg[None]
+    ga = ou.upsample_loss_and_grad(net, rgb, zg, M, white, cstar=[a])[1]
+    gb = ou.upsample_loss_and_grad(net, rgb, zg, M, white, cstar=[b])[1]
+    flat = lambda g: np.concatenate([g[x].ravel() for x in sorted(g)])  # noqa: E731
+    fa, fb = flat(ga), flat(gb)
+    assert np.linalg.norm(fa - fb) > 1e-3 * np.linalg.norm(fa)     # the two subgradients differ
+    rng = np.random.default_rng(72)
+    keys = sorted(net)
+    cuts = np.cumsum([net[x].size for x in keys])[:-1]
+
+    def unflat(f):
+        return {x: p.reshape(net[x].shape) for x, p in zip(keys, np.split(f, cuts))}
+    # three random directions and the one that separates the two subgradients
+    dirs = [rng.normal(size=fa.size) for _ in range(3)] + [(fa - fb) / np.linalg.norm(fa - fb)]
+    h = 1e-7
+    l0 = ou.upsample_loss(net, rgb, zg, M, white)
+    for fv in dirs:
+        v = unflat(fv)
+        step = lambda s: {x: net[x] + s * v[x] for x in net}  # noqa: E731
+        right = (ou.upsample_loss(step(h), rgb, zg, M, white) - l0) / h
+        left = (l0 - ou.upsample_loss(step(-h), rgb, zg, M, white)) / h
+        hi, lo = max(fa @ fv, fb @ fv), min(fa @ fv, fb @ fv)
+        tol = 1e-5 * (abs(hi) + abs(lo) + 1)
+        assert abs(right - hi) <= tol and abs(left - lo) <= tol
+    assert hi - lo > 100 * tol                  # the last direction resolves the kink
+    # no tie: the explicit argmax choice is the default
+    rgb2, zg2, M2, _ = _batch(k, 20, 73)
+    d = np.abs(ou.upsample(net, rgb2) - zg2)
+    g0 = ou.upsample_loss_and_grad(net, rgb2, zg2, M2, white)[1]
+    g1 = ou.upsample_loss_and_grad(net, rgb2, zg2, M2, white, cstar=np.argmax(d, axis=1))[1]
+    assert all(np.array_equal(g0[x], g1[x]) for x in g0)
