@@ -1,7 +1,10 @@
 """The stress shape: 3840 x 2160 px, 64 spp, path length 1..8, 4096^2 x 81
 texture, 256 lights, k = 9.  The whole frame is shaded on the GPU in the
-benchmark's layout (rows of 96 floats, codes of 16 floats) and 4,096 seeded
-pixels are checked against the FP64 oracle in both forms."""
+benchmark's layout (rows of 96 floats, codes of 16 floats) and 16,384 seeded
+pixels are checked against the FP64 oracle in both forms.  The oracle is
+given only the texture rows those pixels reach (texel indices renumbered
+into that subset), which leaves every product unchanged and keeps it from
+converting the whole 16.7 M x 81 table to FP64."""
 
 import numpy as np
 import pytest
@@ -46,14 +49,13 @@ def test_stress_frame_sampled_pixels():
     assert np.array_equal(P.vtx[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint32), gv)
     del P, refl, codes, xyz_s, xyz_l
     torch.cuda.empty_cache()
-    pix = np.sort(np.random.default_rng(4).choice(spec.n_pixels, 4096, replace=False))
+    pix = np.sort(np.random.default_rng(4).choice(spec.n_pixels, 16384, replace=False))
     hdr, pf, vtx = synth.records_of_pixels(spec, pix)
-    tex = w["refl"][:, :n]
-    assert xyz_close(xs[pix], osh.shade_spectral(hdr, pf, vtx, spec.spp, tex, w["illum"], w["T"]),
+    used, inv = np.unique(vtx[:, 0], return_inverse=True)
+    vsub = vtx.copy()
+    vsub[:, 0] = inv.astype(vtx.dtype)
+    tex = w["refl"][used, :n]
+    assert xyz_close(xs[pix], osh.shade_spectral(hdr, pf, vsub, spec.spp, tex, w["illum"], w["T"]),
                      2e-5, 1e-7) <= 1.0
-    # the oracle encodes only the texels these pixels reach
-    used = np.unique(vtx[:, 0])
-    codes_o = np.zeros((spec.n_tex, k))
-    codes_o[used] = osh.encode(w["E"], tex[used])
-    z = osh.shade_latent(hdr, pf, vtx, spec.spp, codes_o, osh.encode(w["E"], w["illum"]))
+    z = osh.shade_latent(hdr, pf, vsub, spec.spp, osh.encode(w["E"], tex), osh.encode(w["E"], w["illum"]))
     assert xyz_close(xl[pix], osh.decode(w["D"], w["T"], z)[1], 2e-5, 1e-7) <= 1.0
