@@ -43,23 +43,33 @@ def log(*a):
 _W = None
 
 
-def _oracle_chunk(pixels):
+def _oracle_chunk(job):
     """Oracle latent pipeline (FP64) on a chunk of frame pixels; returns
-    (path-vertices, seconds)."""
+    (path-vertices, seconds).  With `subset` the oracle is handed only the
+    texture rows the chunk's records reach (texel indices renumbered into
+    them), which changes no product and keeps it from converting a
+    multi-gigabyte table to FP64 per chunk."""
+    import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import shade as osh
     from synth import records_of_pixels
+    pixels, subset = job
     w = _W
     hdr, pf, vtx = records_of_pixels(w["paths"], pixels)
+    tex = w["refl"][:, :w["n"]]
+    if subset:
+        used, inv = np.unique(vtx[:, 0], return_inverse=True)
+        vtx = vtx.copy()
+        vtx[:, 0] = inv.astype(vtx.dtype)
+        tex = tex[used]
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        osh.render_latent_xyz(hdr, pf, vtx, w["paths"].spp, w["refl"][:, :w["n"]], w["illum"], w["E"],
-                              w["D"], w["T"])
+        osh.render_latent_xyz(hdr, pf, vtx, w["paths"].spp, tex, w["illum"], w["E"], w["D"], w["T"])
         dt = time.perf_counter() - t0
     return int(vtx.shape[0]), dt
 
 
-def cpu_baseline(w, n_pixels=None, chunk=32768):
+def cpu_baseline(w, n_pixels=None, chunk=32768, subset=False, what="the frame"):
     """Time the oracle on a pixel sample of the frame with a pool of worker
     processes (forked before any GPU use, one BLAS thread each)."""
     import multiprocessing as mp
@@ -71,7 +81,7 @@ def cpu_baseline(w, n_pixels=None, chunk=32768):
         n_pixels = w["paths"].n_pixels
     rng = np.random.default_rng(12)
     pix = np.sort(rng.choice(w["paths"].n_pixels, n_pixels, replace=False))
-    chunks = [pix[i:i + chunk] for i in range(0, n_pixels, chunk)]
+    chunks = [(pix[i:i + chunk], subset) for i in range(0, n_pixels, chunk)]
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
         t0 = time.perf_counter()
@@ -79,9 +89,10 @@ def cpu_baseline(w, n_pixels=None, chunk=32768):
         wall = time.perf_counter() - t0
     verts = sum(r[0] for r in res)
     return {"value": verts / wall, "unit": "path-vertices/s", "cores": workers, "kind": "oracle",
-            "sample": f"{n_pixels} pixels of the frame ({verts} path-vertices), FP64 numpy "
-                      f"latent pipeline (encode, shade, decode) in {len(chunks)} chunks, "
-                      f"{wall:.2f} s wall, {sum(r[1] for r in res):.1f} core-s"}
+            "sample": f"{n_pixels} pixels of {what} ({verts} path-vertices), FP64 numpy "
+                      f"latent pipeline (encode, shade, decode) in {len(chunks)} chunks"
+                      + (" (each given the texture rows its records reach)" if subset else "")
+                      + f", {wall:.2f} s wall, {sum(r[1] for r in res):.1f} core-s"}
 
 
 # ------------------------------------------------------------------ GPU part
@@ -97,29 +108,50 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def _counter_mean(csv_path, kernel_substr, counter):
+def _counter_mean(csv_path, kernel_substr, counter, required=True):
     import csv
     vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
             if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter]
     if not vals:
-        raise SystemExit(f"no {counter} rows for {kernel_substr} in {csv_path}")
+        if required:
+            raise SystemExit(f"no {counter} rows for {kernel_substr} in {csv_path}")
+        return None
     return sum(vals) / len(vals)
 
 
-def record_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
-    """Write the HBM traffic of one latent shading launch from rocprofv3 --pmc
-    CSVs: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the kernel, each
-    scaled by the ratio of the true bytes of a 1 GiB device copy to what the
-    same counter reads for that copy."""
+TRAFFIC_NOTE = ("fetch/write: FETCH_SIZE and WRITE_SIZE of the kernel, each scaled by true bytes / "
+                "counter of a 1 GiB device copy; they count what the L2 asks of the memory side, "
+                "MALL hits included, so above the copy rate they are not HBM bytes. "
+                "ea_read_bytes: L2-to-fabric read requests x their size (all 128 B here). "
+                "dram_read_bytes: TCC_EA0_RDREQ_DRAM x 128 B, the requests the L2 sends towards "
+                "memory; the L2 counters cannot tell a MALL hit from an HBM read.")
+
+
+def record_traffic(d_fetch, d_write, d_copy_fetch, d_copy_write, d_req=None):
+    """Write the traffic record of one latent shading launch from rocprofv3
+    --pmc CSVs (run_counter_collection.csv in each directory): FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) of the kernel scaled by the ratio of the
+    true bytes of a 1 GiB device copy to what the same counter reads for that
+    copy; with d_req also the L2-to-fabric read requests (TCC_EA0_RDREQ,
+    TCC_EA0_RDREQ_128B, TCC_EA0_RDREQ_DRAM)."""
+    csv = lambda d: os.path.join(d, "run_counter_collection.csv")  # noqa: E731
     gib_kib = float(1 << 20)
-    f_scale = gib_kib / _counter_mean(copy_fetch_csv, "copyBuffer", "FETCH_SIZE")
-    w_scale = gib_kib / _counter_mean(copy_write_csv, "copyBuffer", "WRITE_SIZE")
-    fetch = _counter_mean(fetch_csv, "shade_latent_kernel", "FETCH_SIZE") * 1024 * f_scale
-    write = _counter_mean(write_csv, "shade_latent_kernel", "WRITE_SIZE") * 1024 * w_scale
+    kern = "shade_latent_kernel"
+    f_scale = gib_kib / _counter_mean(csv(d_copy_fetch), "copyBuffer", "FETCH_SIZE")
+    w_scale = gib_kib / _counter_mean(csv(d_copy_write), "copyBuffer", "WRITE_SIZE")
+    fetch = _counter_mean(csv(d_fetch), kern, "FETCH_SIZE") * 1024 * f_scale
+    write = _counter_mean(csv(d_write), kern, "WRITE_SIZE") * 1024 * w_scale
     d = {"kernel": "shade_latent_kernel<2>", "workload": WORKLOAD,
          "kernel_source_sha": kernel_source_sha(), "fetch_scale": f_scale, "write_scale": w_scale,
          "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
-         "hbm_bytes_per_launch": fetch + write}
+         "hbm_bytes_per_launch": fetch + write, "note": TRAFFIC_NOTE}
+    if d_req:
+        req = {c: _counter_mean(csv(d_req), kern, c, required=False)
+               for c in ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_DRAM_sum")}
+        d["ea_read_requests"] = req["TCC_EA0_RDREQ_sum"]
+        d["ea_read_bytes"] = None if req["TCC_EA0_RDREQ_128B_sum"] is None else 128 * req["TCC_EA0_RDREQ_128B_sum"]
+        d["dram_read_requests"] = req["TCC_EA0_RDREQ_DRAM_sum"]
+        d["dram_read_bytes"] = None if req["TCC_EA0_RDREQ_DRAM_sum"] is None else 128 * req["TCC_EA0_RDREQ_DRAM_sum"]
     json.dump(d, open(TRAFFIC_JSON, "w"), indent=1)
     print(json.dumps(d))
 
@@ -143,15 +175,171 @@ def copy_bandwidth(dev) -> float:
     return gbs
 
 
-def measured_traffic(bytes_alg):
-    """HBM bytes per shade_latent launch from the committed counter profile,
-    if it was taken with the current kernel source; else None."""
+def measured_traffic():
+    """Traffic record of the latent shading launch from the committed counter
+    profile, if it was taken with the current kernel source; else None."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
     d = json.load(open(TRAFFIC_JSON))
     if d.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return d.get("hbm_bytes_per_launch")
+    d.setdefault("note", TRAFFIC_NOTE)
+    return d
+
+
+def gather_ceiling(vtx, table, row_floats, lanes, dev, reps=3):
+    """The random-gather probe (hc_gather_probe) over these records and this
+    table, for unroll 1..8 and grids of 2, 4 and 8 workgroups per CU: the
+    best vertex (row) rate, HIP events on the launch stream."""
+    import torch
+    from paper_2602_18741_amd import ops
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    nv = int(vtx.shape[0])
+    best = None
+    out = torch.empty(8 * cus * 256, device=dev)
+    for per_cu in (2, 4, 8):
+        for unroll in (1, 2, 4, 8):
+            grid = per_cu * cus
+            ops.gather_probe(vtx, table, row_floats, unroll, lanes, grid, out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                ops.gather_probe(vtx, table, row_floats, unroll, lanes, grid, out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            if best is None or ms < best["ms"]:
+                best = {"ms": ms, "unroll": unroll, "workgroups_per_cu": per_cu}
+    best.update(rows_per_s=nv / (best["ms"] * 1e-3), rows=nv, row_bytes=4 * row_floats,
+                lanes_per_row=lanes, table_bytes=int(table.numel()) * 4)
+    return best
+
+
+def random_records(nv, n_rows, dev, seed=7):
+    """nv records with uniform random texels in [0, n_rows) and weight 1."""
+    import torch
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    vtx = torch.empty(nv, 2, dtype=torch.int32, device=dev)
+    vtx[:, 0] = torch.randint(0, n_rows, (nv,), device=dev, generator=g, dtype=torch.int32)
+    vtx[:, 1] = 0x3F800000
+    return vtx
+
+
+def frame_roofline(kernel, bytes_alg, kern_s, nv, ceiling, copy_gbs, limiter):
+    """Roofline entry of one shading kernel: algorithmic bytes per launch over
+    its time against the 8 TB/s HBM peak, and its vertex rate against the
+    random-gather ceiling of the same records and table."""
+    achieved = bytes_alg / kern_s / 1e9
+    rate = nv / kern_s
+    return {"bound": "hbm", "limiter": limiter, "kernel": kernel, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "algorithmic_bytes": bytes_alg, "kernel_ms": kern_s * 1e3, "path_vertices_per_s": rate,
+            "gather_ceiling_rows_per_s": ceiling["rows_per_s"], "frac_of_gather_ceiling":
+                rate / ceiling["rows_per_s"], "gather_ceiling": ceiling,
+            "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
+
+
+STRESS_CODEC_STEPS = 2000
+
+
+def stress_leg(w, args, dev, copy_gbs, cpu):
+    """Config-4 frame (3840 x 2160, 64 spp, path length 1..8, 4096^2 x 81
+    texture, 256 lights): both forms timed as single frames with the codec
+    fitted at n = 81, k = 9, per-form roofline and gather ceiling (tables of
+    1 GiB and 6.4 GB, past the 256 MB cache), CIEDE2000 of latent against
+    spectral, and the oracle timed on 16,384 pixels (taken before GPU use)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2602_18741_amd import colour, ops
+    from paper_2602_18741_amd.codec_fit import CodecFit
+    from paper_2602_18741_amd.layout import latent_width, line_stride
+    n, k = 81, 9
+    ld_z = line_stride(latent_width(k))
+    spec = w["paths"]
+    t0 = time.time()
+    refl = torch.from_numpy(w["refl"]).to(dev)
+    illum = ops.padded(torch.from_numpy(w["illum"]).to(dev))
+    T = torch.from_numpy(w["T"]).to(dev)
+    P = ops.gen_paths(spec.n_pixels, spec.spp, spec.l_min, spec.l_max, spec.n_tex, spec.n_illum,
+                      spec.seed, device=dev)
+    nv, npath, npx = P.n_vertices, spec.n_paths, spec.n_pixels
+    pa, pb = synth.workloads.codec_pools(n, 1 << 18)
+    pa, pb = torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev)
+    we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
+    fit = CodecFit(we0, wd0, pa, pb, batch=65536, seed=2, objective="eq8", T=w["T"])
+    fit.run(1)
+    fit.capture(CODEC_STEPS_PER_GRAPH)
+    loss = float(fit.run(STRESS_CODEC_STEPS - 1))
+    E, D = fit.weights()
+    del pa, pb, fit
+    log(f"stress frame: {npx} px, {npath} paths, {nv} path-vertices; inputs on the GPU and codec "
+        f"fitted ({STRESS_CODEC_STEPS} steps, loss {loss:.4g}) in {time.time() - t0:.1f} s")
+    codes = torch.empty(spec.n_tex, ld_z, device=dev)
+    lcodes = torch.empty(spec.n_illum, ld_z, device=dev)
+    zimg = torch.empty(npx, latent_width(k), device=dev)
+    xyz_l = torch.empty(npx, 3, device=dev)
+    xyz_s = torch.empty(npx, 3, device=dev)
+
+    def latent_step(ev=None):
+        ops.encode(E, refl, n=n, out=codes)
+        ops.encode(E, illum, n=n, out=lcodes)
+        if ev:
+            ev[0].record()
+        ops.shade_latent(P, codes, lcodes, k, out=zimg)
+        if ev:
+            ev[1].record()
+        ops.decode_xyz(D, T, zimg, k, out=xyz_l)
+
+    def spectral_step(ev=None):
+        if ev:
+            ev[0].record()
+        ops.shade_spectral(P, refl, illum, T, n, out=xyz_s)
+        if ev:
+            ev[1].record()
+
+    res = {}
+    for name, step in (("latent", latent_step), ("spectral", spectral_step)):
+        step()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.stress_steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for e in evs:
+            step(e)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t1) / args.stress_steps
+        kern = sum(a.elapsed_time(b) for a, b in evs) / args.stress_steps / 1e3
+        res[name] = (wall, kern)
+        log(f"stress {name}: step {wall * 1e3:.2f} ms, shade kernel {kern * 1e3:.2f} ms")
+    de = colour.frame_difference(xyz_s.cpu().numpy(), xyz_l.cpu().numpy())
+    log(f"stress CIEDE2000 latent vs spectral: mean {de['mean']:.3f}, p95 {de['p95']:.3f}")
+    del zimg, xyz_l, xyz_s
+    ceil_l = gather_ceiling(P.vtx, codes, 4 * ops.blocks(k), 1, dev, reps=2)
+    ceil_s = gather_ceiling(P.vtx, refl, 4 * ((n + 3) // 4), 8, dev, reps=2)
+    log(f"stress gather ceilings: codes {ceil_l['rows_per_s'] / 1e9:.1f} G rows/s, "
+        f"spectra {ceil_s['rows_per_s'] / 1e9:.1f} G rows/s")
+    bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
+    bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
+    lat = frame_roofline(f"shade_latent_kernel<{ops.blocks(k)}>", bytes_lat, res["latent"][1], nv, ceil_l,
+                         copy_gbs, "random 64-byte code rows from a 1 GiB table in HBM (one 128-byte "
+                         "line each)")
+    spe = frame_roofline("shade_spectral_kernel (n = 81)", bytes_spe, res["spectral"][1], nv, ceil_s, copy_gbs,
+                         "random 384-byte spectral rows from a 6.4 GB table in HBM (three 128-byte "
+                         "lines each)")
+    out = {"workload": STRESS, "pixels": npx, "spp": spec.spp, "paths": npath, "path_vertices": nv,
+           "n": n, "k": k, "codec": {"objective": "eq8", "steps": STRESS_CODEC_STEPS, "loss": loss},
+           "latent": {"value": nv / res["latent"][0], "unit": "path-vertices/s",
+                      "ms_per_step": res["latent"][0] * 1e3, "roofline": lat},
+           "spectral": {"value": nv / res["spectral"][0], "unit": "path-vertices/s",
+                        "ms_per_step": res["spectral"][0] * 1e3, "roofline": spe},
+           "speedup_latent_vs_spectral": res["spectral"][0] / res["latent"][0],
+           "shade_speedup_latent_vs_spectral": res["spectral"][1] / res["latent"][1],
+           "ciede2000_latent_vs_spectral": de, "cpu_baseline": cpu}
+    del P, refl, codes, lcodes, illum
+    torch.cuda.empty_cache()
+    return out
 
 
 MB_CHAINS = 1 << 18
@@ -340,15 +528,21 @@ def main():
                     help="frames in the burst of the stress workload's serving run")
     ap.add_argument("--upsample-steps", type=int, default=5000,
                     help="AdamW steps of the upsampling network's fit")
-    ap.add_argument("--serve-count", type=int, default=200,
+    ap.add_argument("--serve-count", type=int, default=2000,
                     help="requests per arrival rate in the serving measurement")
-    ap.add_argument("--record-traffic", nargs=4, metavar="CSV",
-                    help="fetch, write, copy-fetch, copy-write counter CSVs -> traffic record")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="leave out the 3840x2160 / 64 spp / n=81 / k=9 single-frame leg")
+    ap.add_argument("--stress-steps", type=int, default=3,
+                    help="timed frames per form in the stress leg (one untimed first)")
+    ap.add_argument("--record-traffic", nargs="+", metavar="DIR",
+                    help="rocprofv3 --pmc output directories: fetch, write, copy-fetch, copy-write "
+                         "[, requests] -> traffic record of the latent shading kernel")
     ap.add_argument("--stress", action="store_true",
                     help="the 4K / 64 spp / n=81 / k=9 stress frame instead of the default frame")
-    ap.add_argument("--only", choices=["latent", "spectral", "copy", "codec"],
+    ap.add_argument("--only", choices=["latent", "spectral", "copy", "codec", "gather"],
                     help="run only the timed steps of one form (or a 1 GiB device copy, or "
-                         "--codec-steps graph-replayed codec steps of each objective), for "
+                         "--codec-steps graph-replayed codec steps of each objective, or the "
+                         "random-gather probe over the frame's records and code table), for "
                          "profilers; prints no JSON")
     args = ap.parse_args()
     if args.record_traffic:
@@ -391,6 +585,15 @@ def main():
     cpu = None if (args.no_cpu or args.only or stress) else cpu_baseline(w)
     if cpu:
         log("cpu baseline:", cpu["sample"])
+    w4 = cpu4 = None
+    if not (args.only or stress or args.no_stress):
+        t_setup = time.time()
+        w4 = synth.workload(4, ld_tex=line_stride(81))
+        log(f"stress inputs generated in {time.time() - t_setup:.1f} s")
+        if not args.no_cpu:
+            cpu4 = cpu_baseline(w4, n_pixels=16384, chunk=1024, subset=True,
+                                what="the 3840x2160, 64 spp frame")
+            log("stress cpu baseline:", cpu4["sample"])
 
     import torch
     from paper_2602_18741_amd import colour, ops
@@ -484,6 +687,13 @@ def main():
         kern = sum(a.elapsed_time(b) for a, b in evs) / args.steps / 1e3
         return wall, kern
 
+    if args.only == "gather":
+        latent_step()
+        for _ in range(args.warmup + args.steps):
+            ops.gather_probe(P.vtx, codes, 4 * ops.blocks(k), 4, 1, 4 * 256)
+        torch.cuda.synchronize()
+        log(f"gather probe: {args.warmup + args.steps} launches over {nv} records")
+        return
     if args.only:
         wall, kern = timed(latent_step if args.only == "latent" else spectral_step)
         log(f"{args.only}: step {wall * 1e3:.3f} ms, shade kernel {kern * 1e3:.3f} ms")
@@ -497,8 +707,36 @@ def main():
     log(f"device copy: {copy_gbs:.0f} GB/s")
     bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
     bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
-    achieved = bytes_lat / lat_kern / 1e9
-    traffic = None if stress else measured_traffic(bytes_lat)
+    traffic = None if stress else measured_traffic()
+
+    # the random-gather ceiling of the frame's records: over the code table
+    # and the spectral table the kernels read, and over a 1 GiB table of
+    # 32-byte rows (past the 256 MB cache)
+    ceil_lat = gather_ceiling(P.vtx, codes, 4 * ops.blocks(k), 1, dev)
+    ceil_spe = gather_ceiling(P.vtx, refl, 4 * ((n + 3) // 4), 1 if n <= 16 else 8, dev)
+    big = torch.rand(1 << 25, 8, device=dev)
+    recs = random_records(nv, big.shape[0], dev)
+    ceil_1g = gather_ceiling(recs, big, 8, 1, dev)
+    del big, recs
+    torch.cuda.empty_cache()
+    log(f"gather ceilings: code table {ceil_lat['rows_per_s'] / 1e9:.1f} G rows/s, spectral table "
+        f"{ceil_spe['rows_per_s'] / 1e9:.1f} G rows/s, 1 GiB table of 32-byte rows "
+        f"{ceil_1g['rows_per_s'] / 1e9:.1f} G rows/s")
+    tbl_mb = codes.numel() * 4 / 2 ** 20
+    roof = frame_roofline(f"shade_latent_kernel<{ops.blocks(k)}>", bytes_lat, lat_kern, nv, ceil_lat,
+                          copy_gbs, f"random {4 * ops.blocks(k) * 4}-byte code rows from a "
+                          f"{tbl_mb:.0f} MiB table" + (" resident in the 256 MB MALL" if tbl_mb < 256
+                                                        else " in HBM") + " (one 128-byte line each)")
+    roof["traffic"] = None if traffic is None else traffic["hbm_bytes_per_launch"]
+    if traffic is not None:
+        roof["traffic_note"] = traffic["note"]
+        for key in ("fetch_bytes_per_launch", "write_bytes_per_launch", "ea_read_bytes", "dram_read_bytes"):
+            roof[f"traffic_{key}"] = traffic.get(key)
+        roof["traffic_GBs"] = traffic["hbm_bytes_per_launch"] / lat_kern / 1e9
+    roof["gather_ceiling_1GiB_rows_per_s"] = ceil_1g["rows_per_s"]
+    roof["gather_ceiling_1GiB"] = ceil_1g
+    roof_spe = frame_roofline("shade_spectral_kernel", bytes_spe, spe_kern, nv, ceil_spe, copy_gbs,
+                              "random spectral rows from the texture (one 128-byte line per row at n = 31)")
 
     de = colour.frame_difference(xyz_s.cpu().numpy(), xyz_l.cpu().numpy())
     log(f"CIEDE2000 latent (Eq. 8 codec) vs spectral: mean {de['mean']:.3f}, p95 {de['p95']:.3f}")
@@ -515,6 +753,15 @@ def main():
     if not args.no_upsample:
         up = upsample_leg(args, dev, n, k, T, E, D, refl, illum, P, xyz_s, codes, lcodes, zimg, xyz_l)
 
+    stress_out = None
+    if w4 is not None:
+        del P, zimg
+        torch.cuda.empty_cache()
+        t0 = time.time()
+        stress_out = stress_leg(w4, args, dev, copy_gbs, cpu4)
+        del w4
+        log(f"stress leg measured in {time.time() - t0:.1f} s")
+
     serving = None
     if stress and not args.no_serve:
         from paper_2602_18741_amd.serve import bench_saturation
@@ -530,7 +777,8 @@ def main():
             for v in [serving[form]]))
     if not (args.no_serve or stress):
         from paper_2602_18741_amd.serve import bench_serving
-        del P, zimg
+        if stress_out is None:
+            del P, zimg
         torch.cuda.empty_cache()
         t0 = time.time()
         serving = bench_serving(dev, count=args.serve_count, E=E.cpu(), D=D.cpu(), progress=log)
@@ -556,17 +804,11 @@ def main():
                    "paths": npath,
                    "path_vertices": nv, "k": k, "n": n, "texels": spec.n_tex,
                    "lights": spec.n_illum, "step": "encode texture+lights, shade latent, decode"},
-        "roofline": {"bound": "hbm", "kernel": f"shade_latent_kernel<{ops.blocks(k)}>",
-                     "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes": bytes_lat,
-                     "kernel_ms": lat_kern * 1e3,
-                     "traffic_GBs": None if traffic is None else traffic / lat_kern / 1e9,
-                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "spectral": {"value": nv / spe_wall, "unit": "path-vertices/s", "ms_per_step": spe_wall * 1e3,
                      "kernel_ms": spe_kern * 1e3, "achieved_GBs": bytes_spe / spe_kern / 1e9,
-                     "algorithmic_bytes": bytes_spe},
+                     "algorithmic_bytes": bytes_spe, "roofline": roof_spe},
         "speedup_latent_vs_spectral": spe_wall / lat_wall,
         "shade_speedup_latent_vs_spectral": spe_kern / lat_kern,
         "ciede2000_latent_vs_spectral": de,
@@ -575,6 +817,7 @@ def main():
         "codec_step_n81_k9": codec81,
         "multibounce": bounce,
         "upsample": up,
+        "stress": stress_out,
         "serving": serving,
         "env": {"device": torch.cuda.get_device_name(dev),
                 "arch": getattr(torch.cuda.get_device_properties(dev), "gcnArchName", None),

@@ -480,6 +480,28 @@ hc_status hc_gen_path_vertices(const hc_path_gen* g, const uint32_t* pix_first, 
 hc_status hc_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* ctr_scale_dev,
                          int64_t count, int64_t n, uint32_t* out, void* stream);
 
+/*
+ * Random-gather probe (measurement, not part of the method).  Reads every
+ * vertex record of vtx (uint32 pairs {texel, float bits of the weight}, as
+ * in hc_paths) and the first 4 * ceil(row_floats / 4) floats (whole 16-byte
+ * chunks, as the shading kernels load rows) of row texel of table (row
+ * stride ld floats; texels past n_rows are clamped to the last row), and
+ * adds weight * (sum of those floats) into a per-lane sum; each of the
+ * grid * 256 lanes writes its sum to out[lane].  The shading kernels gather
+ * the same rows for the same records, so this rate, with nothing else done,
+ * bounds theirs: for uniformly random texels each row costs whole cache
+ * lines and the rate is the memory system's random-line rate, not its
+ * streaming bandwidth.
+ *   unroll          1, 2, 4 or 8 vertices in flight per lane (or lane group);
+ *   lanes_per_row   1 (one lane loads the whole row, row_floats <= 16) or
+ *                   8 (the row's 16-byte chunks over 8 lanes, <= 128 floats);
+ *   grid            workgroups of 256 lanes (>= 1); out holds grid * 256 floats.
+ * table, vtx and out need 16-, 8- and 4-byte alignment, ld a multiple of 4.
+ */
+hc_status hc_gather_probe(const uint32_t* vtx, int64_t n_vertices, const float* table, int64_t n_rows,
+                          int64_t ld, int32_t row_floats, int32_t unroll, int32_t lanes_per_row,
+                          int32_t grid, float* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

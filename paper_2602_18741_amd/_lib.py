@@ -11,7 +11,9 @@ import os
 import re
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libhc.so")
+# HC_LIBRARY names another build of the same library to load (the
+# host-sanitized checking build); by default the in-tree libhc.so
+LIB_PATH = os.environ.get("HC_LIBRARY") or os.path.join(_PKG, "libhc.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "hc.h")
 
 HC_OK, HC_EINVAL, HC_ESHAPE, HC_EALIGN, HC_ENOMEM, HC_EDEVICE, HC_EUNSUPPORTED = range(7)
@@ -127,6 +129,7 @@ _PROTOS = {
     "hc_gen_path_headers": (i32, [C.POINTER(PathGen), vp, vp, vp, vp, sz, vp]),
     "hc_gen_path_vertices": (i32, [C.POINTER(PathGen), vp, vp, i64, vp]),
     "hc_gen_indices": (i32, [u64, u64, vp, i64, i64, vp, vp]),
+    "hc_gather_probe": (i32, [vp, i64, vp, i64, i64, i32, i32, i32, i32, vp, vp]),
 }
 
 _lib = None

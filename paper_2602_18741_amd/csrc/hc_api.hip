@@ -254,9 +254,10 @@ size_t hc_codec_workspace_size(int32_t k, int32_t n, int64_t N) {
     return codec_workspace_size(k, n, N);
 }
 
-hc_status hc_codec_step(const hc_codec_args* a) {
-    clear_error();
-    const char* fn = "hc_codec_step";
+namespace {
+
+// Every check of hc_codec_step except the workspace's.
+hc_status check_codec_args(const hc_codec_args* a, const char* fn) {
     HC_REQUIRE(a != nullptr, HC_EINVAL, "%s: args is NULL", fn);
     HC_REQUIRE(a->k >= 1 && a->k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, a->k, kMaxK);
     HC_REQUIRE(a->n >= 1 && a->n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, a->n, kMaxN);
@@ -303,12 +304,23 @@ hc_status hc_codec_step(const hc_codec_args* a) {
                        m->eps > 0,
                    HC_EINVAL, "%s: adam hyper-parameters out of range", fn);
     }
+    return HC_OK;
+}
+
+}  // namespace
+
+hc_status hc_codec_step(const hc_codec_args* a) {
+    clear_error();
+    const char* fn = "hc_codec_step";
+    const hc_status s = check_codec_args(a, fn);
+    if (s != HC_OK) return s;
     const size_t need = codec_workspace_size(a->k, a->n, a->N);
     HC_REQUIRE(a->workspace != nullptr && a->workspace_bytes >= need && aligned8(a->workspace),
                HC_ENOMEM, "%s: workspace needs %zu bytes (8-byte aligned), got %zu", fn, need,
                a->workspace_bytes);
     return launch_codec_step(*a);
 }
+
 
 hc_status hc_upsample(const hc_mlp* net, int32_t precision, const float* rgb, int64_t m,
                       int64_t ld_rgb, float* Z, int64_t ld_z, void* stream) {
@@ -459,6 +471,31 @@ hc_status hc_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* ctr_scale_
     HC_REQUIRE(out && aligned4(out), HC_EINVAL, "%s: out NULL/misaligned", fn);
     HC_REQUIRE(!ctr_scale_dev || aligned8(ctr_scale_dev), HC_EALIGN, "%s: counter misaligned", fn);
     return launch_gen_indices(seed, ctr0, ctr_scale_dev, count, n, out, as_stream(stream));
+}
+
+hc_status hc_gather_probe(const uint32_t* vtx, int64_t n_vertices, const float* table, int64_t n_rows,
+                          int64_t ld, int32_t row_floats, int32_t unroll, int32_t lanes_per_row,
+                          int32_t grid, float* out, void* stream) {
+    clear_error();
+    const char* fn = "hc_gather_probe";
+    HC_REQUIRE(n_vertices >= 0 && n_vertices < (int64_t(1) << 32), HC_ESHAPE,
+               "%s: n_vertices outside [0, 2^32)", fn);
+    HC_REQUIRE(n_rows >= 1 && n_rows < (int64_t(1) << 32), HC_ESHAPE, "%s: n_rows outside [1, 2^32)", fn);
+    HC_REQUIRE(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8, HC_EINVAL,
+               "%s: unroll must be 1, 2, 4 or 8 (got %d)", fn, unroll);
+    HC_REQUIRE(lanes_per_row == 1 || lanes_per_row == 8, HC_EINVAL, "%s: lanes_per_row must be 1 or 8", fn);
+    HC_REQUIRE(row_floats >= 1 && row_floats <= (lanes_per_row == 1 ? 16 : 128), HC_ESHAPE,
+               "%s: row_floats=%d outside [1, %d] for %d lane(s) per row", fn, row_floats,
+               lanes_per_row == 1 ? 16 : 128, lanes_per_row);
+    HC_REQUIRE(ld >= row_floats && ld % 4 == 0 && ld < (int64_t(1) << 31), HC_ESHAPE,
+               "%s: ld must be >= row_floats, a multiple of 4 and < 2^31", fn);
+    HC_REQUIRE(grid >= 1 && grid <= (1 << 20), HC_ESHAPE, "%s: grid outside [1, 2^20]", fn);
+    HC_REQUIRE(table && out && (vtx || n_vertices == 0), HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned16(table) && aligned4(out) && aligned8(vtx), HC_EALIGN,
+               "%s: table/vtx/out need 16/8/4-byte alignment", fn);
+    return launch_gather_probe(reinterpret_cast<const uint2*>(vtx), uint32_t(n_vertices), table,
+                               uint32_t(n_rows), uint32_t(ld), row_floats, unroll, lanes_per_row, out,
+                               grid, as_stream(stream));
 }
 
 }  // extern "C"

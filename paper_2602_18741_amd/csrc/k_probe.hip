@@ -1,0 +1,111 @@
+// Random-gather probe: the memory system's rate for the texel gathers of a
+// vertex-record stream, with none of the shading arithmetic.
+//
+// Both shading forms spend their time gathering one texel row per path
+// vertex at the record's texel index; for uniformly random indices no
+// cache line is reused, so the rate of those gathers, not the byte count,
+// bounds the kernels.  This kernel reads the same records and the same rows
+// and does nothing else with them: per vertex, the weight times the sum of
+// the row's floats is added to a per-lane sum (so no load is dead), and
+// every lane of the grid writes its sum once.  Its vertex rate is the
+// ceiling the shading kernels are compared with.
+//
+// Layout knobs (template parameters), so that the best of several issue
+// shapes can be taken as the ceiling:
+//   U    vertices in flight per lane group (all records, then all rows,
+//        are loaded before the first add);
+//   G    lanes per row: 1 (a lane loads the whole row) or 8 (a row's
+//        16-byte chunks are spread over 8 consecutive lanes);
+//   CPL  16-byte chunks per lane (G * CPL >= chunks of the row).
+// Rows are read in whole 16-byte chunks (row_floats rounded up to a
+// multiple of 4), as the shading kernels read them.
+// Vertices are taken in a grid-stride loop; records of one wave-load are
+// consecutive, as in the shading kernels' pixel-major streams.
+
+#include "hc_internal.hpp"
+
+namespace hc {
+namespace {
+
+constexpr int kProbeBlock = 256;
+
+template <int U, int G, int CPL>
+__global__ __launch_bounds__(kProbeBlock) void gather_probe_kernel(const uint2* __restrict__ vtx,
+                                                                   uint32_t n_vertices,
+                                                                   const float* __restrict__ table,
+                                                                   uint32_t n_rows, uint32_t ld,
+                                                                   int chunks, float* __restrict__ out) {
+    const uint64_t groups = uint64_t(gridDim.x) * (kProbeBlock / G);   // row groups in the grid
+    const uint64_t g0 = uint64_t(blockIdx.x) * (kProbeBlock / G) + threadIdx.x / G;
+    const int sub = threadIdx.x % G;
+    float acc = 0.f;
+    for (uint64_t v = g0; v < n_vertices; v += groups * U) {
+        uint2 rec[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t j = v + uint64_t(u) * groups;
+            rec[u] = j < n_vertices ? ldg_u2(vtx + j) : make_uint2(0u, 0u);   // weight 0 past the end
+        }
+        float4 row[U][CPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float* rp = table + uint64_t(min(rec[u].x, n_rows - 1u)) * ld;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int ch = sub + c * G;
+                row[u][c] = ch < chunks ? ld4(rp + 4 * ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) s += (row[u][c].x + row[u][c].y) + (row[u][c].z + row[u][c].w);
+            acc += __uint_as_float(rec[u].y) * s;
+        }
+    }
+    stg_f32(out + uint64_t(blockIdx.x) * kProbeBlock + threadIdx.x, acc);
+}
+
+template <int U, int G, int CPL>
+hc_status launch_one(const uint2* vtx, uint32_t nv, const float* table, uint32_t n_rows, uint32_t ld,
+                     int chunks, float* out, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((gather_probe_kernel<U, G, CPL>), dim3(grid), dim3(kProbeBlock), 0, st, vtx, nv,
+                       table, n_rows, ld, chunks, out);
+    return launch_status("hc_gather_probe");
+}
+
+template <int G, int CPL>
+hc_status by_unroll(int unroll, const uint2* vtx, uint32_t nv, const float* table, uint32_t n_rows,
+                    uint32_t ld, int chunks, float* out, int grid, hipStream_t st) {
+    switch (unroll) {
+        case 1: return launch_one<1, G, CPL>(vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+        case 2: return launch_one<2, G, CPL>(vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+        case 4: return launch_one<4, G, CPL>(vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+        default: return launch_one<8, G, CPL>(vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+    }
+}
+
+}  // namespace
+
+hc_status launch_gather_probe(const uint2* vtx, uint32_t nv, const float* table, uint32_t n_rows,
+                              uint32_t ld, int row_floats, int unroll, int lanes_per_row, float* out,
+                              int grid, hipStream_t st) {
+    const int chunks = (row_floats + 3) / 4;
+    if (lanes_per_row == 1) {
+        switch (chunks) {
+            case 1: return by_unroll<1, 1>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+            case 2: return by_unroll<1, 2>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+            case 3: return by_unroll<1, 3>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+            default: return by_unroll<1, 4>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+        }
+    }
+    switch ((chunks + 7) / 8) {
+        case 1: return by_unroll<8, 1>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+        case 2: return by_unroll<8, 2>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+        case 3: return by_unroll<8, 3>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+        default: return by_unroll<8, 4>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
+    }
+}
+
+}  // namespace hc

@@ -357,3 +357,18 @@ def gen_indices(seed: int, count: int, n: int, ctr0: int = 0, step: torch.Tensor
     check(load().hc_gen_indices(seed, ctr0, _ptr(step), count, n, _ptr(out), _stream()),
           "hc_gen_indices")
     return out
+
+
+def gather_probe(vtx: torch.Tensor, table: torch.Tensor, row_floats: int, unroll: int = 4,
+                 lanes_per_row: int = 1, grid: int = 2048, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Random-gather probe over a record stream (see hc_gather_probe): the
+    rows the shading kernels gather for these records, read and summed with
+    nothing else done.  vtx is (V, 2) 32-bit records, table (rows, ld) float32.
+    Returns the grid * 256 per-lane sums."""
+    _dev(vtx, table)
+    if out is None:
+        out = torch.empty(grid * 256, dtype=torch.float32, device=table.device)
+    check(load().hc_gather_probe(_ptr(vtx), int(vtx.shape[0]), _ptr(table), int(table.shape[0]),
+                                 int(table.stride(0)), row_floats, unroll, lanes_per_row, grid,
+                                 _ptr(out), _stream()), "hc_gather_probe")
+    return out

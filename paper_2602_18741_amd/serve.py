@@ -93,22 +93,35 @@ def span_tiles(spans):
 
 
 class Scheduler:
-    """Admission, tiling and completion bookkeeping (device independent).
+    """Admission, asset residency, tiling and completion bookkeeping (device
+    independent).
 
-    backend must provide: request_bytes(req); prepare(req) (allocate, make
-    the records, start bringing the asset in); asset_state(asset) ->
-    "pending" (still arriving), "needs_encode" or "ready"; launch(plan) ->
-    handle; poll(handle) -> bool; release(req); finish(req) (fetch results
-    if kept).  A frame is tiled only once its asset has arrived, so uploads
-    overlap the shading of other frames.
+    One memory budget covers both the admitted requests' buffers and the
+    resident assets.  The head of the queue is admitted when its buffers,
+    plus its asset if that is not resident, fit the budget, after evicting
+    least-recently-used assets that no admitted request uses; otherwise it
+    waits (back-pressure) and so does everything behind it (FIFO).  A request
+    that could never fit, even with every asset evicted, is rejected at
+    submission.
+
+    backend must provide: request_bytes(req); asset_bytes(asset, loading)
+    (device bytes of a resident asset, and while it is being brought in);
+    load_asset(asset) (start bringing it in); evict_asset(asset);
+    asset_state(asset) -> "pending" (still arriving), "needs_encode" or
+    "ready"; encode_jobs(asset) (encode-table entries of its encode) and
+    max_jobs; prepare(req) (allocate, make the records); launch(plan) ->
+    handle; poll(handle) -> bool; release(req); finish(req) (fetch results if
+    kept).  A frame is tiled only once its asset has arrived (and is encoded
+    in that iteration or before), so uploads overlap the shading of other
+    frames.  mem_budget None asks the backend (memory_budget()).
     """
 
-    def __init__(self, backend, max_frames: int = 64, mem_budget: float = 32e9,
+    def __init__(self, backend, max_frames: int = 64, mem_budget: float | None = None,
                  tile_pixels: int | None = None, iter_vertices: float = 40e6, max_inflight: int = 2,
                  max_tiles: int = 8192, decode_pixels: int = 65536, target_tiles: int = 4096):
         self.b = backend
         self.max_frames = max_frames
-        self.mem_budget = mem_budget
+        self.mem_budget = float(backend.memory_budget() if mem_budget is None else mem_budget)
         # tile_pixels fixes the tile size; by default each frame's tiles hold
         # about iter_vertices / target_tiles path-vertices, so an iteration
         # carries enough tiles to occupy every workgroup of the launch
@@ -122,46 +135,90 @@ class Scheduler:
         self.active: list[Request] = []
         self.free_slots = list(range(max_frames))[::-1]
         self.mem_used = 0.0
+        self.mem_peak = 0.0
+        # resident assets in least-recently-used order: asset -> [refs, bytes charged]
+        self.assets: collections.OrderedDict[int, list] = collections.OrderedDict()
         self.inflight: collections.deque = collections.deque()
         self.done: list[Request] = []
         self.rejected: list[Request] = []
         self.iterations = 0
+        self.evictions = 0
 
     # -------------------------------------------------------------- intake
     def submit(self, req: Request):
-        need = self.b.request_bytes(req)
+        need = self.b.request_bytes(req) + self.b.asset_bytes(req.asset, True)
         if need > self.mem_budget:
             req.state, req.error = "failed", "request larger than the memory budget"
+            req.t_done = req.arrival
             self.rejected.append(req)
             return
         self.queue.append(req)
+
+    def _charge(self, nbytes: float):
+        self.mem_used += nbytes
+        self.mem_peak = max(self.mem_peak, self.mem_used)
+
+    def _evict_for(self, need: float) -> bool:
+        """Evict assets no admitted request uses, least recently used first,
+        until `need` more bytes fit; True if they do.  An asset still
+        arriving is not evicted; one waiting for its encode with no request
+        left is (no plan encodes an asset without a request)."""
+        for aid in list(self.assets):
+            if self.mem_used + need <= self.mem_budget:
+                break
+            refs, nbytes = self.assets[aid]
+            if refs == 0 and self.b.asset_state(aid) != "pending":
+                self.b.evict_asset(aid)
+                del self.assets[aid]
+                self.mem_used -= nbytes
+                self.evictions += 1
+        return self.mem_used + need <= self.mem_budget
 
     def _admit(self, now: float):
         while self.queue and self.free_slots:
             req = self.queue[0]
             need = self.b.request_bytes(req)
-            if self.mem_used + need > self.mem_budget:
+            new_asset = req.asset not in self.assets
+            asset_need = self.b.asset_bytes(req.asset, True) if new_asset else 0.0
+            if not self._evict_for(need + asset_need):
                 break  # FIFO: the head waits for memory, later requests wait behind it
             self.queue.popleft()
             req.slot = self.free_slots.pop()
-            self.mem_used += need
             req.t_admit = now
+            self._charge(need)
+            if new_asset:
+                try:
+                    self.b.load_asset(req.asset)
+                except Exception as e:  # noqa: BLE001 - a failed request must not stop the server
+                    self.mem_used -= need
+                    self.free_slots.append(req.slot)
+                    req.state, req.error, req.t_done = "failed", f"load: {e}", now
+                    self.done.append(req)
+                    continue
+                self.assets[req.asset] = [0, asset_need]
+                self._charge(asset_need)
+            self.assets.move_to_end(req.asset)
+            self.assets[req.asset][0] += 1
             try:
                 self.b.prepare(req)
-            except Exception as e:  # noqa: BLE001 - a failed request must not stop the server
+            except Exception as e:  # noqa: BLE001
                 self._fail(req, f"prepare: {e}")
                 continue
             req.state = "active"
             self.active.append(req)
 
+    def _release(self, req: Request):
+        self.b.release(req)
+        self.mem_used -= self.b.request_bytes(req)
+        self.free_slots.append(req.slot)
+        self.assets[req.asset][0] -= 1
+
     def _fail(self, req: Request, msg: str):
         req.state, req.error = "failed", msg
         req.t_done = time.perf_counter()
         try:
-            self.b.release(req)
+            self._release(req)
         finally:
-            self.mem_used -= self.b.request_bytes(req)
-            self.free_slots.append(req.slot)
             if req in self.active:
                 self.active.remove(req)
             self.done.append(req)
@@ -175,9 +232,16 @@ class Scheduler:
         ones.  Assets that arrived since the last iteration are encoded first
         in the same iteration."""
         state = {a: self.b.asset_state(a) for a in {r.asset for r in self.active}}
-        plan = Plan(encode=sorted(a for a, st in state.items() if st == "needs_encode"))
-        todo = [r for r in self.active
-                if r.next_pixel < r.n_pixels and state[r.asset] != "pending"]
+        plan = Plan()
+        jobs = 0
+        for a in sorted(a for a, st in state.items() if st == "needs_encode"):
+            nj = self.b.encode_jobs(a)
+            if jobs + nj > self.b.max_jobs:
+                continue        # encoded in a later iteration; its frames wait until then
+            plan.encode.append(a)
+            jobs += nj
+        todo = [r for r in self.active if r.next_pixel < r.n_pixels
+                and (state[r.asset] == "ready" or r.asset in plan.encode)]
         per_px = {r.rid: r.spp * 0.5 * (r.l_min + r.l_max) for r in todo}
         todo.sort(key=lambda r: ((r.n_pixels - r.next_pixel) * per_px[r.rid], r.arrival))
         budget = self.iter_vertices
@@ -228,6 +292,12 @@ class Scheduler:
     def _complete(self, now: float):
         while self.inflight and self.b.poll(self.inflight[0][0]):
             _, plan = self.inflight.popleft()
+            for aid in plan.encode:
+                # encoded: the asset's staging copy is gone, only its codes stay
+                if aid in self.assets:
+                    resident = self.b.asset_bytes(aid, False)
+                    self.mem_used -= self.assets[aid][1] - resident
+                    self.assets[aid][1] = resident
             for req in plan.finishing:
                 if req.state != "active":
                     continue
@@ -237,9 +307,7 @@ class Scheduler:
                     req.state = "done"
                 except Exception as e:  # noqa: BLE001
                     req.state, req.error = "failed", f"finish: {e}"
-                self.b.release(req)
-                self.mem_used -= self.b.request_bytes(req)
-                self.free_slots.append(req.slot)
+                self._release(req)
                 self.active.remove(req)
                 self.done.append(req)
 
@@ -255,7 +323,7 @@ class Scheduler:
                 try:
                     handle = self.b.launch(plan)
                 except Exception as e:  # noqa: BLE001
-                    for req in {id(r): r for r in self.active}.values():
+                    for req in list(self.active):
                         if any(sp[0] == req.rid for sp in plan.shade):
                             self._fail(req, f"launch: {e}")
                     return True
@@ -299,9 +367,11 @@ class GpuBackend:
     graph per form.  form: "latent" (encode -> shade -> decode) or
     "spectral" (shade straight to XYZ)."""
 
+    JOB_ROWS = 65536         # spectra rows per encode-table entry
+
     def __init__(self, assets, lights, T, E=None, D=None, form: str = "latent", max_frames: int = 64,
                  max_tiles: int = 8192, max_jobs: int = 4096, grid: int = 0, device="cuda",
-                 use_graph: bool = True, asset_budget: float = 16e9):
+                 use_graph: bool = True, reserve: float = 0.1):
         import torch
 
         from . import ops
@@ -344,10 +414,8 @@ class GpuBackend:
         self.reqs: dict[int, object] = {}
         # asset id -> {"state", "event", "spectral", "tex"}; "tex" is what the
         # frames read (latent codes, or the spectral rows themselves)
-        self.resident: collections.OrderedDict[int, dict] = collections.OrderedDict()
-        self.asset_refs = collections.Counter()
-        self.asset_budget = asset_budget
-        self.asset_bytes = 0.0
+        self.resident: dict[int, dict] = {}
+        self.reserve = reserve
         self.pending_free = {}            # handle -> tensors kept alive until the iteration ends
         self.graph = None
         if use_graph:
@@ -384,15 +452,61 @@ class GpuBackend:
         self.graph = g
 
     # -------------------------------------------------------------- scheduler hooks
+    def memory_budget(self) -> float:
+        """Device memory the scheduler may hand out: what the device has free
+        now (with this backend's tables, lights and graph allocated), less a
+        reserve fraction for the caching allocator's rounding and
+        fragmentation and the path generators' workspaces."""
+        cuda = self.torch.cuda
+        free, _ = cuda.mem_get_info(self.dev)
+        # blocks the caching allocator holds but no tensor uses are free to us
+        free += cuda.memory_reserved(self.dev) - cuda.memory_allocated(self.dev)
+        return max(0.0, (1.0 - self.reserve) * free - 1e9)
+
     def request_bytes(self, req) -> float:
         paths = req.n_pixels * req.spp * (4 + 8 * req.l_max) + 4 * req.n_pixels
         out = req.n_pixels * (12 + (4 * self.ops.latent_width(self.k) if self.form == "latent" else 0))
         return float(paths + out + 4096)
 
-    def _asset_tensor_bytes(self, host):
-        texels = host.shape[0]
-        return texels * 4 * (self.ops.line_stride(self.ops.latent_width(self.k)) if self.form == "latent"
-                             else host.shape[1])
+    def asset_bytes(self, asset, loading: bool) -> float:
+        """Device bytes of an asset: its spectral rows while they arrive and
+        wait for the encode (latent form) plus the codes; the codes alone
+        once encoded.  The spectral form keeps the rows themselves."""
+        host = self.assets[asset]
+        spectral = float(host.shape[0] * host.shape[1] * 4)
+        if self.form != "latent":
+            return spectral
+        codes = float(host.shape[0] * 4 * self.ops.line_stride(self.ops.latent_width(self.k)))
+        return codes + (spectral if loading else 0.0)
+
+    def encode_jobs(self, asset) -> int:
+        return -(-self.assets[asset].shape[0] // self.JOB_ROWS) if self.form == "latent" else 0
+
+    def load_asset(self, asset):
+        """Start the upload of an asset (copy stream); the latent form also
+        allocates its codes, written by the encode of a later iteration."""
+        torch, ops = self.torch, self.ops
+        host = self.assets[asset]
+        if self.encode_jobs(asset) > self.max_jobs:
+            raise RuntimeError(f"asset {asset} needs more encode jobs than the table holds")
+        with torch.cuda.stream(self.copy_stream):
+            spectral = host.to(self.dev, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+        spectral.record_stream(self.stream)
+        if self.form == "latent":
+            with torch.cuda.stream(self.stream):
+                # line-aligned rows: a code never straddles two 128-byte lines
+                tex = torch.empty(host.shape[0], ops.line_stride(ops.latent_width(self.k)), device=self.dev)
+        else:
+            tex = spectral
+        self.resident[asset] = dict(state="pending", event=ev, spectral=spectral, tex=tex)
+
+    def evict_asset(self, asset):
+        """Drop the device copy of an asset no admitted frame uses.  Its
+        memory returns to the allocator pool of the stream it was made on, so
+        work still in flight that read it stays ordered before any reuse."""
+        del self.resident[asset]
 
     def prepare(self, req):
         with _Range(self.torch, f"prepare {req.width}x{req.height}x{req.spp}"):
@@ -400,25 +514,6 @@ class GpuBackend:
 
     def _prepare(self, req):
         torch, ops = self.torch, self.ops
-        if req.asset not in self.resident:
-            self._make_room()
-            host = self.assets[req.asset]
-            with torch.cuda.stream(self.copy_stream):
-                spectral = host.to(self.dev, non_blocking=True)
-                ev = torch.cuda.Event()
-                ev.record(self.copy_stream)
-            spectral.record_stream(self.stream)
-            if self.form == "latent":
-                with torch.cuda.stream(self.stream):
-                    # line-aligned rows: a code never straddles two 128-byte lines
-                    tex = torch.empty(host.shape[0], ops.line_stride(ops.latent_width(self.k)),
-                                      device=self.dev)
-            else:
-                tex = spectral
-            self.resident[req.asset] = dict(state="pending", event=ev, spectral=spectral, tex=tex)
-            self.asset_bytes += self._asset_tensor_bytes(host)
-        self.resident.move_to_end(req.asset)
-        self.asset_refs[req.asset] += 1
         tex = self.resident[req.asset]["tex"]
         with torch.cuda.stream(self.stream):
             P = ops.Paths(torch.empty(req.n_pixels * req.spp, dtype=torch.int32, device=self.dev),
@@ -460,17 +555,6 @@ class GpuBackend:
                                                  P.vtx.shape[0], st), "hc_gen_path_vertices")
         return (ws, total)
 
-    def _make_room(self):
-        while self.asset_bytes > self.asset_budget:
-            for aid in self.resident:
-                if self.asset_refs[aid] == 0 and self.resident[aid]["state"] == "ready":
-                    host = self.assets[aid]
-                    del self.resident[aid]
-                    self.asset_bytes -= self._asset_tensor_bytes(host)
-                    break
-            else:
-                return  # everything resident is in use; go over budget rather than stall
-
     def launch(self, plan):
         with _Range(self.torch, "launch iteration"):
             return self._launch(plan)
@@ -480,25 +564,33 @@ class GpuBackend:
         h = self.h_tables[self.flip]
         if self.h_events[self.flip] is not None:
             self.h_events[self.flip].synchronize()   # the copy that last read this buffer is done
-        hp = h.data_ptr()
-        C.memmove(hp + int(self.offs[0]), C.addressof(self.frames), C.sizeof(self.frames))
-        n_sh = self._put_tiles(hp + int(self.offs[1]), plan.shade)
-        n_de = self._put_tiles(hp + int(self.offs[2]), plan.decode)
+        # every table is checked against its capacity before anything is
+        # written or any asset changes state, so a refused plan leaves the
+        # backend as it was
         jobs = []
-        keep = []
         for aid in plan.encode:
             a = self.resident[aid]
             spectral, tex = a["spectral"], a["tex"]
-            self.stream.wait_event(a["event"])     # already complete; orders the streams
-            for b in range(0, spectral.shape[0], 65536):
+            for b in range(0, spectral.shape[0], self.JOB_ROWS):
                 jobs.append((spectral.data_ptr(), tex.data_ptr(), spectral.stride(0), tex.stride(0), b,
-                             min(spectral.shape[0], b + 65536)))
-            keep.append(spectral)
-            a["state"], a["spectral"] = "ready", None
-        jt = (self.EncodeJob * max(1, len(jobs)))(*[self.EncodeJob(*j) for j in jobs])
-        C.memmove(hp + int(self.offs[3]), C.addressof(jt), C.sizeof(self.EncodeJob) * len(jobs))
+                             min(spectral.shape[0], b + self.JOB_ROWS)))
         if len(jobs) > self.max_jobs:
             raise RuntimeError("iteration exceeds the encode table capacity")
+        shade, decode = span_tiles(plan.shade), span_tiles(plan.decode)
+        if max(shade[0].size, decode[0].size) > self.max_tiles:
+            raise RuntimeError("iteration exceeds the tile table capacity")
+        hp = h.data_ptr()
+        C.memmove(hp + int(self.offs[0]), C.addressof(self.frames), C.sizeof(self.frames))
+        n_sh = self._put_tiles(hp + int(self.offs[1]), plan.shade, shade)
+        n_de = self._put_tiles(hp + int(self.offs[2]), plan.decode, decode)
+        jt = (self.EncodeJob * max(1, len(jobs)))(*[self.EncodeJob(*j) for j in jobs])
+        C.memmove(hp + int(self.offs[3]), C.addressof(jt), C.sizeof(self.EncodeJob) * len(jobs))
+        keep = []
+        for aid in plan.encode:
+            a = self.resident[aid]
+            self.stream.wait_event(a["event"])     # already complete; orders the streams
+            keep.append(a["spectral"])
+            a["state"], a["spectral"] = "ready", None
         counts = np.array([n_sh, n_de, len(jobs), 0], dtype=np.int32)
         C.memmove(hp + int(self.offs[4]), counts.ctypes.data, 16)
         with torch.cuda.stream(self.stream):
@@ -518,11 +610,10 @@ class GpuBackend:
 
     _TILE_DT = np.dtype([("frame", "<i4"), ("pad", "<i4"), ("begin", "<i8"), ("end", "<i8")])
 
-    def _put_tiles(self, dst: int, spans) -> int:
-        """Write the tiles of `spans` into the pinned table at address dst."""
-        idx, begin, end = span_tiles(spans)
-        if idx.size > self.max_tiles:
-            raise RuntimeError("iteration exceeds the tile table capacity")
+    def _put_tiles(self, dst: int, spans, tiles) -> int:
+        """Write the tiles of `spans` (span_tiles(spans)) into the pinned
+        table at address dst."""
+        idx, begin, end = tiles
         arr = np.zeros(idx.size, self._TILE_DT)
         if idx.size:
             span_slot = np.array([self.reqs[sp[0]]["slot"] for sp in spans], dtype=np.int32)
@@ -541,10 +632,8 @@ class GpuBackend:
             req.result = self.reqs[req.rid]["xyz"].cpu().numpy()
 
     def release(self, req):
-        r = self.reqs.pop(req.rid, None)
-        if r is not None:
-            # the slot's table entry stays as is: no tile refers to it any more
-            self.asset_refs[req.asset] -= 1
+        # the slot's table entry stays as is: no tile refers to it any more
+        self.reqs.pop(req.rid, None)
 
     def synchronize(self):
         self.stream.synchronize()
@@ -657,11 +746,12 @@ def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=
             be = GpuBackend(assets, lights, T, E, D, form=form, device=device)
             be.prewarm(24e9)   # no run pays first-touch allocations
             reqs = make_requests(rate, count, len(assets), seed=int(rate))
-            sched = Scheduler(be)
-            wall = run_stream(sched, reqs)
+            sched = Scheduler(be)  # memory budget: the device's free memory
+            wall = run_stream(sched, reqs, time_limit=max(120.0, 3.0 * count / rate))
             be.synchronize()
             s = summarize(reqs, wall)
-            s["iterations"] = sched.iterations
+            s.update(iterations=sched.iterations, mem_budget_bytes=sched.mem_budget,
+                     mem_peak_bytes=sched.mem_peak, asset_evictions=sched.evictions)
             res[str(rate)] = s
             if progress is not None:
                 progress(f"serving {form} {rate} fps: {s['completed']}/{count} requests, "
@@ -687,8 +777,8 @@ def bench_saturation(device, asset, lights, T, E, D, frames: int = 8, width: int
            "mem_budget_bytes": mem_budget, "iteration_vertices": iter_vertices, "grid": grid,
            "target_tiles": target_tiles}
     for form in forms:
-        be = GpuBackend([asset], lights, T, E, D, form=form, device=device, asset_budget=64e9,
-                        grid=grid, max_tiles=max_tiles)
+        be = GpuBackend([asset], lights, T, E, D, form=form, device=device, grid=grid,
+                        max_tiles=max_tiles)
         be.prewarm(mem_budget)
         sched = Scheduler(be, mem_budget=mem_budget, iter_vertices=iter_vertices,
                           target_tiles=target_tiles, max_tiles=max_tiles)

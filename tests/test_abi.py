@@ -200,3 +200,21 @@ def test_upsample_train_step_validates_the_index_draw(lib):
     dr.ctr_scale_dev = 0x1004
     s, msg = _err(lib.hc_upsample_train_step(C.byref(args)))
     assert s == _lib.HC_EALIGN and "counter" in msg
+
+
+def test_gather_probe_rejects_bad_arguments(lib):
+    p = C.c_void_p(0x1000)
+    s, msg = _err(lib.hc_gather_probe(p, 10, p, 4, 8, 8, 3, 1, 4, p, None))
+    assert s == _lib.HC_EINVAL and "unroll" in msg
+    s, msg = _err(lib.hc_gather_probe(p, 10, p, 4, 8, 8, 4, 2, 4, p, None))
+    assert s == _lib.HC_EINVAL and "lanes_per_row" in msg
+    s, msg = _err(lib.hc_gather_probe(p, 10, p, 4, 32, 20, 4, 1, 4, p, None))
+    assert s == _lib.HC_ESHAPE and "row_floats" in msg
+    s, msg = _err(lib.hc_gather_probe(p, 10, p, 4, 6, 6, 4, 1, 4, p, None))
+    assert s == _lib.HC_ESHAPE and "ld" in msg
+    s, msg = _err(lib.hc_gather_probe(p, 10, p, 4, 8, 8, 4, 1, 0, p, None))
+    assert s == _lib.HC_ESHAPE and "grid" in msg
+    s, msg = _err(lib.hc_gather_probe(p, 10, C.c_void_p(0x1004), 4, 8, 8, 4, 1, 4, p, None))
+    assert s == _lib.HC_EALIGN
+    s, msg = _err(lib.hc_gather_probe(p, 10, None, 4, 8, 8, 4, 1, 4, p, None))
+    assert s == _lib.HC_EINVAL

@@ -1,0 +1,39 @@
+"""The random-gather probe reads what it is given: the sum of its per-lane
+outputs is sum_v w_v * (sum of the row's first whole 16-byte chunks covering
+row_floats floats, row t_v), for every issue shape, with records past the
+table clamped to its last row."""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("row_floats,ld,lanes", [(8, 8, 1), (12, 16, 1), (16, 16, 1), (31, 32, 8),
+                                                 (84, 96, 8), (128, 128, 8)])
+@pytest.mark.parametrize("unroll", [1, 2, 4, 8])
+def test_probe_sums_the_gathered_rows(gpu, row_floats, ld, lanes, unroll):
+    from paper_2602_18741_amd import ops
+    rng = np.random.default_rng(row_floats * 10 + unroll)
+    rows, nv = 5000, 100_003
+    table = rng.uniform(-1, 1, (rows, ld)).astype(np.float32)
+    tex = rng.integers(0, rows + 50, nv).astype(np.uint32)         # some past the table
+    w = rng.uniform(0, 1, nv).astype(np.float32)
+    vtx = np.stack([tex, w.view(np.uint32)], axis=1)
+    out = ops.gather_probe(torch.from_numpy(vtx.view(np.int32)).to(gpu), torch.from_numpy(table).to(gpu),
+                           row_floats, unroll=unroll, lanes_per_row=lanes, grid=37)
+    used = 4 * -(-row_floats // 4)
+    rs = table[:, :used].astype(np.float64).sum(axis=1)
+    want = (w.astype(np.float64) * rs[np.minimum(tex, rows - 1)]).sum()
+    got = out.double().sum().item()
+    bound = 1e-5 * (np.abs(w.astype(np.float64) * np.abs(table[:, :used]).sum(axis=1)[
+        np.minimum(tex, rows - 1)]).sum())
+    assert abs(got - want) <= bound
+
+
+def test_probe_of_no_records_writes_zeros(gpu):
+    from paper_2602_18741_amd import ops
+    table = torch.ones(4, 8, device=gpu)
+    out = ops.gather_probe(torch.zeros(0, 2, dtype=torch.int32, device=gpu), table, 8, grid=3)
+    assert torch.equal(out, torch.zeros_like(out))

@@ -104,3 +104,30 @@ def test_tiles_equal_single_frame_calls(env):
     P = ops.gen_paths(req.n_pixels, req.spp, req.l_min, req.l_max, tex.shape[0], lc.shape[0], req.seed)
     direct = ops.decode_xyz(D, T, ops.shade_latent(P, codes, lc, 6), 6).cpu().numpy()
     assert np.array_equal(served, direct)
+
+
+@pytest.mark.parametrize("form", ["latent", "spectral"])
+def test_over_budget_request_is_rejected_and_the_rest_are_unchanged(env, form):
+    """Budget: every frame of the mix and all three assets at once, which a
+    1024 x 1024, 64 spp, path length 8 request exceeds on its own.  It is
+    rejected at submission; the other frames complete bit-identically to a
+    run without it, and the scheduler never charges more than the budget."""
+    serve = env["serve"]
+    be = _backend(env, form)
+    mix = _mix(env)
+    budget = (sum(be.request_bytes(r) for r in mix)
+              + sum(be.asset_bytes(a, True) for a in range(len(env["assets"]))))
+    big = serve.Request(rid=99, asset=0, width=1024, height=1024, spp=64, l_min=1, l_max=8, seed=5,
+                        arrival=0.00025)
+    assert be.request_bytes(big) > budget
+    ref = _run(env, _backend(env, form), _mix(env), tile_pixels=2048, iter_vertices=1e5)
+    sched = serve.Scheduler(be, max_frames=16, mem_budget=budget, max_tiles=1024, tile_pixels=2048,
+                            iter_vertices=1e5)
+    for r in mix:
+        r.keep_result = True
+    serve.run_stream(sched, mix + [big], time_limit=60)
+    assert big.state == "failed" and "budget" in big.error
+    assert all(r.state == "done" for r in mix)
+    assert sched.mem_peak <= budget
+    for r in mix:
+        assert np.array_equal(r.result, ref[r.rid])
