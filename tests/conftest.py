@@ -7,6 +7,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# a planted oracle mistake, for the child runs of tests/test_oracle_mutations.py
+if os.environ.get("HC_ORACLE_MUTANT"):
+    from tests.oracle_mutants import install
+    install(os.environ["HC_ORACLE_MUTANT"])
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")

@@ -297,3 +297,24 @@ def test_record_check_counts_planted_errors():
     last = 99
     pf[last] = vtx.shape[0] - 1                          # runs past the end
     assert records.check(hdr, pf, vtx, 4, 64, 8) == (2, 3, 1)
+
+
+def test_record_fields_round_trip_at_their_extremes():
+    """Header bits 0-23 hold the light id and bits 24-31 the path length, the
+    vertex weight is the float32 whose bits the record holds, and path p of a
+    pixel starts after the pixel's earlier paths: checked with light ids up
+    to 2^24 - 1, lengths up to 255 and weights that are not integers."""
+    from oracle.records import unpack
+    lights = np.array([0, 1, 0xFFFF, 0x10000, 0xABCDEF, 0xFFFFFF], dtype=np.uint32)
+    lengths = np.array([0, 255, 1, 7, 2, 3], dtype=np.uint32)
+    hdr = (lengths << 24) | lights
+    spp = 3
+    pix_first = np.array([5, 5 + int(lengths[:3].sum())], dtype=np.uint32)
+    nv = 5 + int(lengths.sum())
+    w = np.linspace(0.1, 0.9, nv).astype(np.float32)
+    vtx = np.stack([np.arange(nv, dtype=np.uint32) * 7, w.view(np.uint32)], axis=1)
+    L, light, first, texel, weight = unpack(hdr, pix_first, vtx, spp)
+    assert L.tolist() == lengths.tolist() and light.tolist() == lights.tolist()
+    assert first.tolist() == [5, 5, 260, 261, 268, 270]
+    assert texel.tolist() == (np.arange(nv) * 7).tolist()
+    assert np.array_equal(weight, w.astype(np.float64))
