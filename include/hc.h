@@ -343,6 +343,25 @@ typedef struct hc_codec_args {
 size_t hc_codec_workspace_size(int32_t k, int32_t n, int64_t N);
 hc_status hc_codec_step(const hc_codec_args* args);
 
+/*
+ * hc_codec_step without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels and results
+ * as hc_codec_step, except that args->workspace must be NULL and
+ * args->workspace_bytes 0: the scratch is a static device array of
+ * HC_CODEC_STATIC_SCRATCH_BYTES (16 MiB) that each GPU the library runs on
+ * holds until the process ends (its address is looked up once per device,
+ * on the first call there).  A shape whose step needs more scratch than
+ * that (for example float64 with large k x n) is refused with HC_ENOMEM;
+ * float32 steps of the fitting recipe (N = 65,536, n <= 81, k <= 9) fit.
+ * Calls on one GPU share its array, and each call writes every value of it
+ * that it reads before reading it: calls that overlap on one GPU (on
+ * different streams, or from different host threads) race and must be
+ * serialised by the caller.  No device memory is allocated or freed.
+ */
+#define HC_CODEC_STATIC_SCRATCH_BYTES (16u << 20)
+hc_status hc_codec_step_static(const hc_codec_args* args);
+
 /* E = softplus_beta(Wt_E), D = softplus_beta(Wt_D) as float32 (Eq. 5); the
  * matrices hc_encode and hc_decode_xyz take.  dtype of Wt_* as above. */
 hc_status hc_codec_weights(const void* Wt_E, const void* Wt_D, int32_t k, int32_t n,

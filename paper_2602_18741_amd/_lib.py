@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "hc.h")
 HC_OK, HC_EINVAL, HC_ESHAPE, HC_EALIGN, HC_ENOMEM, HC_EDEVICE, HC_EUNSUPPORTED = range(7)
 HC_CODEC_L2, HC_CODEC_EQ8 = 0, 1
 HC_MLP_F32, HC_MLP_F16 = 0, 1
+HC_CODEC_STATIC_SCRATCH_BYTES = 16 << 20
 
 vp = C.c_void_p
 i32, i64, u64, f64, sz = C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
@@ -116,6 +117,7 @@ _PROTOS = {
     "hc_check_paths": (i32, [C.POINTER(Paths), i64, i32, vp, vp]),
     "hc_codec_workspace_size": (sz, [i32, i32, i64]),
     "hc_codec_step": (i32, [C.POINTER(CodecArgs)]),
+    "hc_codec_step_static": (i32, [C.POINTER(CodecArgs)]),
     "hc_codec_weights": (i32, [vp, vp, i32, i32, i32, f64, vp, vp, vp]),
     "hc_upsample": (i32, [vp, i32, vp, i64, i64, vp, i64, vp]),
     "hc_upsample_param_count": (i64, [i32, i32]),

@@ -321,6 +321,19 @@ hc_status hc_codec_step(const hc_codec_args* a) {
     return launch_codec_step(*a);
 }
 
+hc_status hc_codec_step_static(const hc_codec_args* a) {
+    clear_error();
+    const char* fn = "hc_codec_step_static";
+    const hc_status s = check_codec_args(a, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(a->workspace == nullptr && a->workspace_bytes == 0, HC_EINVAL,
+               "%s: takes no workspace (workspace must be NULL and workspace_bytes 0)", fn);
+    const size_t need = codec_static_need(*a);
+    HC_REQUIRE(need <= size_t(HC_CODEC_STATIC_SCRATCH_BYTES), HC_ENOMEM,
+               "%s: this shape needs %zu bytes of scratch, above the %zu of the static array", fn, need,
+               size_t(HC_CODEC_STATIC_SCRATCH_BYTES));
+    return launch_codec_step_static(*a);
+}
 
 hc_status hc_upsample(const hc_mlp* net, int32_t precision, const float* rgb, int64_t m,
                       int64_t ld_rgb, float* Z, int64_t ld_z, void* stream) {

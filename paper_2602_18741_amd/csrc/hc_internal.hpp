@@ -119,6 +119,8 @@ hc_status launch_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, i
 hc_status launch_check_paths(const hc_paths& P, int64_t n_texels, int32_t n_illum,
                              uint64_t* counts, hipStream_t st);
 hc_status launch_codec_step(const hc_codec_args& a);
+size_t codec_static_need(const hc_codec_args& a);
+hc_status launch_codec_step_static(const hc_codec_args& a);
 int64_t upsample_param_count(int k);
 size_t upsample_train_workspace_size(int k, int64_t N);
 hc_status launch_upsample_train(const hc_upsample_train_args& a);

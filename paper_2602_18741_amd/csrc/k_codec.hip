@@ -32,6 +32,7 @@
 //                (after every read of it by the step's pair draw).
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "counter_rng.hpp"
@@ -1100,17 +1101,37 @@ inline void launch_lanes(const PartialArgs<float>& p, bool eq8, int k, int n, in
 // Pairs per workgroup of the few-lanes-per-pair kernel for n (31 or 81).
 inline int64_t lane_pairs(int n) { return n == 31 ? LaneDims<31>::PAIRS : LaneDims<81>::PAIRS; }
 
+// float32 at n = 31 or 81 with k = 6 or 9 takes the few-lanes-per-pair
+// kernel (one partial row per 256 or 64 pairs), which stages softplus(Wt)
+// itself
+template <typename F>
+bool takes_lanes(int k, int n) {
+    return std::is_same<F, float>::value && (n == 31 || n == 81) && (k == 6 || k == 9);
+}
+
+// Partial rows (workgroups of the partials kernel) of a step.
+template <typename F>
+int64_t step_rows(const hc_codec_args& a) {
+    return takes_lanes<F>(a.k, a.n) ? std::min<int64_t>(ceil_div(a.N, lane_pairs(a.n)), kMaxRows)
+                                    : plan(a.k, a.n, a.N, sizeof(F), a.objective).grid;
+}
+
+// Workspace bytes a step uses (the layout of carve).
+template <typename F>
+size_t step_workspace(const hc_codec_args& a) {
+    const size_t kn = size_t(a.k) * a.n;
+    return 2 * align8(kn * sizeof(F)) + size_t(step_rows<F>(a)) * (2 * kn + 1) * sizeof(double) +
+           sizeof(int64_t);
+}
+
 template <typename F>
 hc_status run(const hc_codec_args& a) {
     const int k = a.k, n = a.n, kn = k * n;
     hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
     const bool eq8 = a.objective == HC_CODEC_EQ8;
     const Plan pl = plan(k, n, a.N, sizeof(F), a.objective);
-    // float32 at n = 31 or 81 with k = 6 or 9 takes the few-lanes-per-pair
-    // kernel (one partial row per 256 or 64 pairs), which stages softplus(Wt)
-    // itself
-    const bool lanes = std::is_same<F, float>::value && (n == 31 || n == 81) && (k == 6 || k == 9);
-    const int64_t rows = lanes ? std::min<int64_t>(ceil_div(a.N, lane_pairs(n)), kMaxRows) : pl.grid;
+    const bool lanes = takes_lanes<F>(k, n);
+    const int64_t rows = step_rows<F>(a);
     Workspace ws = carve(a.workspace, k, n, rows, sizeof(F));
     int64_t* adam_step = a.adam ? a.adam->step : nullptr;
     hc_status s = HC_OK;
@@ -1223,6 +1244,68 @@ size_t codec_workspace_size(int k, int n, int64_t N) {
 
 hc_status launch_codec_step(const hc_codec_args& a) {
     return a.dtype == 1 ? run<double>(a) : run<float>(a);
+}
+
+// ------------------------------------------------------------------ step without allocation
+//
+// Scratch of hc_codec_step_static: a device array the code object brings
+// with it, so the entry point never allocates.  Each device holds its own
+// copy at its own address, obtained once per device with
+// hipGetSymbolAddress; host code uses only those addresses (the array's name
+// in host code is a host-side stand-in, not a device address).
+
+static __device__ __align__(256) unsigned char scratch[HC_CODEC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of the scratch array, or NULL (error
+// set) if it cannot be obtained.
+void* scratch_address() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("hc_codec_step_static: no current HIP device (or device index >= %d)", kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("hc_codec_step_static: hipGetSymbolAddress of the scratch array failed on device %d: %s",
+                      dev, hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+size_t codec_static_need(const hc_codec_args& a) {
+    return a.dtype == 1 ? step_workspace<double>(a) : step_workspace<float>(a);
+}
+
+hc_status launch_codec_step_static(const hc_codec_args& a) {
+    const size_t need = codec_static_need(a);
+    if (need > size_t(HC_CODEC_STATIC_SCRATCH_BYTES)) {
+        set_error("hc_codec_step_static: this shape needs %zu bytes of scratch, above the %zu of the "
+                  "static array",
+                  need, size_t(HC_CODEC_STATIC_SCRATCH_BYTES));
+        return HC_ENOMEM;
+    }
+    void* ws = scratch_address();
+    if (ws == nullptr) return HC_EDEVICE;
+    // every partial row, weight and step slot the kernels read is written
+    // earlier in the same step, so nothing needs clearing between calls
+    hc_codec_args b = a;
+    b.workspace = ws;
+    b.workspace_bytes = size_t(HC_CODEC_STATIC_SCRATCH_BYTES);
+    return launch_codec_step(b);
 }
 
 hc_status launch_codec_weights(const void* we, const void* wd, int k, int n, int dtype, double beta,

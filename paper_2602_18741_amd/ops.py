@@ -181,7 +181,8 @@ EQ8_WEIGHTS = (0.5, 0.75, 1.0, 0.5)   # w_e2e, w_rec, w_code, w_col of Eq. 8 (Se
 def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a=None, idx_b=None,
                loss=None, grad_e=None, grad_d=None, adam: dict | None = None,
                workspace: CodecWorkspace | None = None, objective: str = "l2", T=None,
-               weights=EQ8_WEIGHTS, cos_eps: float = 1e-8, draw: dict | None = None):
+               weights=EQ8_WEIGHTS, cos_eps: float = 1e-8, draw: dict | None = None,
+               static_scratch: bool = False):
     """One loss/gradient (and optional Adam) evaluation on the GPU.
 
     A, B: (rows, n) tensors of the parameters' dtype; with idx_a/idx_b the
@@ -192,7 +193,9 @@ def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a
     step (int64 device tensor), lr, beta1, beta2, eps.  objective "l2" is the
     two-term squared error weighted by lam; "eq8" the four-term loss of
     Eq. 8 with `weights` (w_e2e, w_rec, w_code, w_col) and the 3 x n
-    colour-matching matrix T (parameters' dtype).  Returns the loss tensor.
+    colour-matching matrix T (parameters' dtype).  With static_scratch the
+    step runs through hc_codec_step_static (no workspace; the library's static
+    device array).  Returns the loss tensor.
     """
     _dev(we, wd, A, B)
     k, n = we.shape
@@ -206,7 +209,10 @@ def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a
         _dev(T)
     if loss is None:
         loss = torch.empty((), dtype=we.dtype, device=we.device)
-    workspace = workspace or CodecWorkspace(k, n, N, we.device)
+    if static_scratch and workspace is not None:
+        raise ValueError("static_scratch takes no workspace")
+    if not static_scratch:
+        workspace = workspace or CodecWorkspace(k, n, N, we.device)
     ad = None
     if adam is not None:
         ad = _lib.Adam(adam["m_E"].data_ptr(), adam["v_E"].data_ptr(), adam["m_D"].data_ptr(),
@@ -228,10 +234,14 @@ def codec_step(we, wd, A, B, N: int, lam: float = 1.0, beta: float = 10.0, idx_a
         None if idx_a is None else idx_a.data_ptr(), None if idx_b is None else idx_b.data_ptr(),
         N, loss.data_ptr(), None if grad_e is None else grad_e.data_ptr(),
         None if grad_d is None else grad_d.data_ptr(), C.pointer(ad) if ad is not None else None,
-        workspace.buf.data_ptr(), workspace.bytes, torch.cuda.current_stream().cuda_stream,
+        None if static_scratch else workspace.buf.data_ptr(), 0 if static_scratch else workspace.bytes,
+        torch.cuda.current_stream().cuda_stream,
         T.data_ptr() if eq8 else None, *w, cos_eps if eq8 else 0.0,
         C.pointer(dr) if dr is not None else None)
-    check(load().hc_codec_step(C.byref(args)), "hc_codec_step")
+    if static_scratch:
+        check(load().hc_codec_step_static(C.byref(args)), "hc_codec_step_static")
+    else:
+        check(load().hc_codec_step(C.byref(args)), "hc_codec_step")
     return loss
 
 

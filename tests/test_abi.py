@@ -218,3 +218,20 @@ def test_gather_probe_rejects_bad_arguments(lib):
     assert s == _lib.HC_EALIGN
     s, msg = _err(lib.hc_gather_probe(p, 10, None, 4, 8, 8, 4, 1, 4, p, None))
     assert s == _lib.HC_EINVAL
+
+
+def test_codec_step_static_rejects_a_workspace_and_oversized_shapes(lib):
+    """The entry point without allocation takes no workspace, and refuses a
+    shape whose step needs more scratch than its static array, before any
+    device call."""
+    args = _lib.CodecArgs(6, 31, 0, 0, 10.0, 1.0, 0x1000, 0x1000, 0x1000, 0x1000, 31, 31,
+                          65536, 65536, None, None, 65536, 0x1000, None, None, None,
+                          0x1000, 4096, None)
+    s, msg = _err(lib.hc_codec_step_static(C.byref(args)))
+    assert s == _lib.HC_EINVAL and "no workspace" in msg
+    args.workspace, args.workspace_bytes = None, 0
+    args.k, args.n, args.dtype, args.ld_a, args.ld_b = 48, 128, 1, 128, 128
+    s, msg = _err(lib.hc_codec_step_static(C.byref(args)))
+    assert s == _lib.HC_ENOMEM and str(_lib.HC_CODEC_STATIC_SCRATCH_BYTES) in msg
+    args.k = 0
+    assert lib.hc_codec_step_static(C.byref(args)) == _lib.HC_ESHAPE
