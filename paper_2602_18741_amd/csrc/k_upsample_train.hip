@@ -4,15 +4,12 @@
 // generator inside kernel 1.  Deterministic: fixed summation orders, no
 // floating-point atomics.
 //
-//   1. partials: a workgroup (at most one per CU's worth: 256 partial rows)
-//                takes four samples at a time, one per quarter (128 threads,
-//                one per hidden unit).  Forward through the
-//                three layers, the per-sample loss terms and dL/dz, then
-//                backward to the hidden pre-activations, with W2 and W3 in LDS
-//                (odd row stride: row-wise and column-wise reads are both
-//                conflict-free).  Every thread owns a fixed set of gradient
-//                elements and accumulates them over the workgroup's samples
-//                in registers; one partial row per workgroup.
+//   1. partials: a workgroup (at most 256: one partial row each) takes
+//                tiles of 16 samples; the layer products of the tile, forward
+//                and backward, and the weight gradients summed over its
+//                samples are 16x16x4 fp32 matrix-core products with W2, W3
+//                and the tile's activations in LDS (details at the kernel);
+//                the gradient sums stay in registers across tiles.
 //   2. reduce  : a lane per parameter sums the partial rows in a fixed order
 //                (float64, sixteen row loads in flight), divides by N, writes
 //                the gradient, and each block writes its sum of squares;
@@ -32,18 +29,19 @@ namespace hc {
 namespace {
 
 constexpr int kH = 128;            // hidden width
-constexpr int kThreads = 256;
-constexpr int kSamples = 4;        // samples a partials workgroup takes at once
-constexpr int kPThreads = kSamples * kH;
-// LDS row stride of W2 and W3: rows 16-byte aligned for the forward's row
-// reads, 4 banks apart so 16 threads' rows and a row's columns are spread
+constexpr int kThreads = 256;      // reduce and AdamW kernels
+constexpr int kTS = 16;            // samples of a tile (the N of every 16 x 16 x 4 product)
+constexpr int kPThreads = 512;     // partials kernel: 8 wavefronts, wave w owns hidden rows 16w..16w+15
+constexpr int kPWaves = kPThreads / 64;
+static_assert(kPWaves * 16 == kH, "one 16-row block of the hidden layer per wavefront");
+// LDS row strides (floats): W2 and W3 rows 4 banks apart, so the 16 rows x 4
+// columns of a forward operand read are conflict-free; activations are
+// [feature][sample] with 17 floats per feature row
 constexpr int kRS = kH + 4;
-constexpr int kMaxRows = 256;      // partial rows (workgroups of kernel 1): one per CU
+constexpr int kAS = kTS + 1;
+constexpr int kMaxRows = 256;      // partial rows (workgroups of kernel 1)
 static_assert(kMaxRows <= kThreads, "one workgroup sums the per-row losses");
-constexpr int kW3PerThread = kMaxK / kSamples;
-constexpr int kW2PerThread = kH / kSamples;
-static_assert(kRS % 4 == 0 && (6 * kH + 3 * kMaxK + 8) % 4 == 0 && kMaxK % 4 == 0,
-              "16-byte aligned rows and per-sample areas in LDS");
+static_assert(kMaxK <= 48, "three 16-row blocks of output channels");
 
 // packed parameter offsets (floats): W1 (128 x 3), b1, W2 (128 x 128), b2, W3 (k x 128), b3
 constexpr int64_t kOffB1 = 3 * kH;
@@ -52,6 +50,8 @@ constexpr int64_t kOffB2 = kOffW2 + kH * kH;
 constexpr int64_t kOffW3 = kOffB2 + kH;
 __host__ __device__ constexpr int64_t off_b3(int k) { return kOffW3 + int64_t(k) * kH; }
 __host__ __device__ constexpr int64_t param_count(int k) { return off_b3(k) + k; }
+
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 struct TrainArgs {
     int k;
@@ -80,6 +80,12 @@ __device__ __forceinline__ float logistic(float x) {
     return x >= 0.f ? s : e * s;
 }
 
+// d silu / dx = s + x s (1 - s), s = logistic(x)
+__device__ __forceinline__ float dsilu(float x) {
+    const float sg = logistic(x);
+    return sg + x * sg * (1.f - sg);
+}
+
 // CIELAB f and its slope
 __device__ __forceinline__ void lab_f(float t, float& f, float& fp) {
     constexpr float d = 6.0f / 29.0f;
@@ -93,130 +99,173 @@ __device__ __forceinline__ void lab_f(float t, float& f, float& fp) {
     }
 }
 
+__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// LDS areas of the partials kernel, in floats
+struct Lds {
+    float *W2, *W3, *W1, *B2, *B3, *M, *X, *P1, *H1, *P2, *H2, *Z, *G;
+    double* loss;
+};
+
+__device__ __forceinline__ Lds lds_areas(float* sm, int k) {
+    Lds L;
+    L.W2 = sm;                        // 128 x kRS
+    L.W3 = L.W2 + kH * kRS;           // k x kRS
+    L.W1 = L.W3 + k * kRS;            // 128 x 4: (w_r, w_g, w_b, b1), the A operand of layer 1
+    L.B2 = L.W1 + 4 * kH;
+    L.B3 = L.B2 + kH;                 // 48
+    L.M = L.B3 + kMaxK;               // 3 x 48
+    L.X = L.M + 3 * kMaxK;            // 16 samples x (r, g, b, 1)
+    L.P1 = L.X + 4 * kTS;             // 128 x kAS: p1, then dL/dp1
+    L.H1 = L.P1 + kH * kAS;
+    L.P2 = L.H1 + kH * kAS;           // p2, then dL/dp2
+    L.H2 = L.P2 + kH * kAS;
+    L.Z = L.H2 + kH * kAS;            // 48 x kAS: z
+    L.G = L.Z + kMaxK * kAS;          // 48 x kAS: target code, then dL/dz (rows k..47 zero)
+    L.loss = reinterpret_cast<double*>(L.G + kMaxK * kAS);   // an even float offset: 8-byte aligned
+    return L;
+}
+
+size_t lds_bytes(int k) {
+    return sizeof(float) * (size_t(kH) * kRS + size_t(k) * kRS + 4 * kH + kH + kMaxK + 3 * kMaxK + 4 * kTS +
+                            4 * size_t(kH) * kAS + 2 * size_t(kMaxK) * kAS) +
+           sizeof(double) * kTS;
+}
+
+// One workgroup per partial row; it takes tiles of 16 samples in turn.  Per
+// tile, with the activations of the tile in LDS as [feature][sample]:
+//   forward   p1 = W1 c + b1 (one 16x16x4 product per 16 features, the bias
+//             through a constant-1 input), p2 = W2 h1 + b2 (32 products per
+//             16 features), z = W3 h2 + b3 (vector ALU, k x 16 outputs);
+//   loss      per sample: the three terms of Sec. 5.2 and dL/dz;
+//   backward  dL/dh2 = W3^T dL/dz, dL/dp2 = dL/dh2 * silu'(p2), dL/dh1 =
+//             W2^T dL/dp2, dL/dp1 = dL/dh1 * silu'(p1) (matrix cores), and the
+//             weight gradients dW3 += dz h2^T, dW2 += dp2 h1^T, [dW1 db1] +=
+//             dp1 [c 1]^T as 16x16x4 products over the tile's samples,
+//             accumulated in registers across tiles; bias sums on the ALU.
+// Samples past N have dL/dz = 0, so they add nothing.
 __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a) {
     extern __shared__ __align__(16) float sm[];
     const int k = a.k;
-    float* sW2 = sm;                    // 128 x kRS
-    float* sW3 = sW2 + kH * kRS;        // k x kRS
-    float* sW1 = sW3 + k * kRS;         // 128 x 4 (w_r, w_g, w_b, b1)
-    float* sB2 = sW1 + 4 * kH;
-    float* sB3 = sB2 + kH;              // k
-    float* sM = sB3 + kMaxK;            // 3 x k
-    float* sS = sM + 3 * kMaxK;         // per sample: p1, h1, p2, h2, dp2, dp1 (128 each), z, d, dz (48 each), misc 8
-    constexpr int kPer = 6 * kH + 3 * kMaxK + 8;
-
+    const Lds L = lds_areas(sm, k);
     const int tid = threadIdx.x;
+    const int w = tid / 64, lane = tid & 63, g = lane / 16, n = lane % 16;
     const float* P = a.params;
-    for (int e = tid; e < kH * kH; e += kPThreads) sW2[(e / kH) * kRS + e % kH] = P[kOffW2 + e];
-    for (int e = tid; e < k * kH; e += kPThreads) sW3[(e / kH) * kRS + e % kH] = P[kOffW3 + e];
+    for (int e = tid; e < kH * kH; e += kPThreads) L.W2[(e / kH) * kRS + e % kH] = P[kOffW2 + e];
+    for (int e = tid; e < k * kH; e += kPThreads) L.W3[(e / kH) * kRS + e % kH] = P[kOffW3 + e];
     for (int j = tid; j < kH; j += kPThreads) {
-        sW1[4 * j + 0] = P[3 * j];
-        sW1[4 * j + 1] = P[3 * j + 1];
-        sW1[4 * j + 2] = P[3 * j + 2];
-        sW1[4 * j + 3] = P[kOffB1 + j];
-        sB2[j] = P[kOffB2 + j];
+        L.W1[4 * j + 0] = P[3 * j];
+        L.W1[4 * j + 1] = P[3 * j + 1];
+        L.W1[4 * j + 2] = P[3 * j + 2];
+        L.W1[4 * j + 3] = P[kOffB1 + j];
+        L.B2[j] = P[kOffB2 + j];
     }
-    for (int c = tid; c < k; c += kPThreads) sB3[c] = P[off_b3(k) + c];
-    for (int e = tid; e < 3 * k; e += kPThreads) sM[e] = a.M[e];
+    for (int c = tid; c < kMaxK; c += kPThreads) L.B3[c] = c < k ? P[off_b3(k) + c] : 0.f;
+    for (int e = tid; e < 3 * kMaxK; e += kPThreads) L.M[e] = (e % kMaxK) < k ? a.M[(e / kMaxK) * k + e % kMaxK] : 0.f;
+    // rows k..47 of the code arrays stay zero for every tile
+    for (int e = tid; e < 2 * kMaxK * kAS; e += kPThreads) L.Z[e] = 0.f;
 
-    const int smp = tid / kH, j = tid % kH;  // the thread's sample of the four, hidden unit
-    float* S = sS + smp * kPer;
-    float* p1 = S;
-    float* h1 = p1 + kH;
-    float* p2 = h1 + kH;
-    float* h2 = p2 + kH;
-    float* dp2 = h2 + kH;
-    float* dp1 = dp2 + kH;
-    float* zz = dp1 + kH;
-    float* dd = zz + kMaxK;
-    float* dz = dd + kMaxK;
-    float* misc = dz + kMaxK;  // rgb (3), gX (3)
-
-    // gradient elements owned by this thread
-    float aW2[kW2PerThread];
+    const int mc3 = (k + 15) / 16;         // 16-row blocks of output channels
+    const int ksteps = (k + 3) / 4;        // K steps over the channels
+    f4v acc2[8], acc3[3], acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < kW2PerThread; ++q) aW2[q] = 0.f;
-    float aW3[kW3PerThread];
+    for (int b = 0; b < 8; ++b) acc2[b] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < kW3PerThread; ++r) aW3[r] = 0.f;
-    float aB = 0.f, aW1[3] = {0.f, 0.f, 0.f}, aB3 = 0.f;
+    for (int b = 0; b < 3; ++b) acc3[b] = f4v{0.f, 0.f, 0.f, 0.f};
+    float aB2 = 0.f, aB3 = 0.f;
     double loss = 0.0;
     __syncthreads();
 
     const uint64_t ctr_base =
         a.draw ? a.draw_ctr0 + (a.draw_scale ? uint64_t(*a.draw_scale) * uint64_t(a.N) : 0ull) : 0ull;
-    const int64_t groups = (a.N + kSamples - 1) / kSamples;
-    for (int64_t pr = blockIdx.x; pr < groups; pr += gridDim.x) {
-        const int64_t s = kSamples * pr + smp;
-        const bool valid = s < a.N;
-        int64_t row = 0;
-        if (valid)
-            row = a.draw ? int64_t(range32(rand64(a.key, ctr_base + uint64_t(s)), uint64_t(a.rows)))
-                         : (a.idx ? min<int64_t>(a.idx[s], a.rows - 1) : s);
-        // forward
-        const float* cp = a.rgb + row * a.ld_rgb;
-        const float cr = valid ? cp[0] : 0.f, cg = valid ? cp[1] : 0.f, cb = valid ? cp[2] : 0.f;
-        if (j == 0) {
-            misc[0] = cr;
-            misc[1] = cg;
-            misc[2] = cb;
-        }
-        {
-            const float v = fmaf(sW1[4 * j], cr, fmaf(sW1[4 * j + 1], cg, fmaf(sW1[4 * j + 2], cb, sW1[4 * j + 3])));
-            p1[j] = v;
-            h1[j] = v * logistic(v);
-        }
-        __syncthreads();
-        {
-            float v = sB2[j];
-            const float4* wr = reinterpret_cast<const float4*>(sW2 + j * kRS);
-            const float4* hv = reinterpret_cast<const float4*>(h1);
-#pragma unroll 8
-            for (int i = 0; i < kH / 4; ++i) {
-                const float4 w = wr[i], x = hv[i];
-                v = fmaf(w.x, x.x, v);
-                v = fmaf(w.y, x.y, v);
-                v = fmaf(w.z, x.z, v);
-                v = fmaf(w.w, x.w, v);
+    const int64_t tiles = (a.N + kTS - 1) / kTS;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        // ---- inputs of the tile: colours (+ the constant 1) and target codes
+        for (int e = tid; e < kTS * (k + 1); e += kPThreads) {
+            const int i = e % kTS, c = e / kTS - 1;        // c = -1: the colour
+            const int64_t s = tile * kTS + i;
+            const bool valid = s < a.N;
+            int64_t row = 0;
+            if (valid)
+                row = a.draw ? int64_t(range32(rand64(a.key, ctr_base + uint64_t(s)), uint64_t(a.rows)))
+                             : (a.idx ? min<int64_t>(a.idx[s], a.rows - 1) : s);
+            if (c < 0) {
+                const float* cp = a.rgb + row * a.ld_rgb;
+                L.X[4 * i + 0] = valid ? cp[0] : 0.f;
+                L.X[4 * i + 1] = valid ? cp[1] : 0.f;
+                L.X[4 * i + 2] = valid ? cp[2] : 0.f;
+                L.X[4 * i + 3] = valid ? 1.f : 0.f;
+            } else {
+                L.G[c * kAS + i] = valid ? a.zgt[row * a.ld_z + 4 * (c / 3) + c % 3] : 0.f;
             }
-            p2[j] = v;
-            h2[j] = v * logistic(v);
         }
         __syncthreads();
-        if (j < k) {
-            float v = sB3[j];
-            const float4* wr = reinterpret_cast<const float4*>(sW3 + j * kRS);
-            const float4* hv = reinterpret_cast<const float4*>(h2);
-#pragma unroll 8
-            for (int i = 0; i < kH / 4; ++i) {
-                const float4 w = wr[i], x = hv[i];
-                v = fmaf(w.x, x.x, v);
-                v = fmaf(w.y, x.y, v);
-                v = fmaf(w.z, x.z, v);
-                v = fmaf(w.w, x.w, v);
+        const int jrow = 16 * w;           // the wave's 16 hidden rows
+        // ---- layer 1 (K = 4: r, g, b, 1)
+        {
+            const f4v d = mfma4(L.W1[4 * (jrow + n) + g], L.X[4 * n + g], f4v{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jrow + 4 * g + r;
+                L.P1[j * kAS + n] = d[r];
+                L.H1[j * kAS + n] = d[r] * logistic(d[r]);
             }
-            const float g = valid ? a.zgt[row * a.ld_z + 4 * (j / 3) + j % 3] : v;
-            zz[j] = v;
-            dd[j] = v - g;
-            dz[j] = g;  // the target code, until dL/dz replaces it below
         }
         __syncthreads();
-        // per-sample loss terms and the colour gradient (one thread per sample)
-        if (j == 0) {
+        // ---- layer 2: 32 K steps, two independent chains
+        {
+            f4v c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+            for (int st = 0; st < kH / 4; st += 2) {
+                c0 = mfma4(L.W2[(jrow + n) * kRS + 4 * st + g], L.H1[(4 * st + g) * kAS + n], c0);
+                c1 = mfma4(L.W2[(jrow + n) * kRS + 4 * st + 4 + g], L.H1[(4 * st + 4 + g) * kAS + n], c1);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jrow + 4 * g + r;
+                const float v = (c0[r] + c1[r]) + L.B2[j];
+                L.P2[j * kAS + n] = v;
+                L.H2[j * kAS + n] = v * logistic(v);
+            }
+        }
+        __syncthreads();
+        // ---- layer 3 on the vector ALU: output (channel c, sample i)
+        for (int e = tid; e < k * kTS; e += kPThreads) {
+            const int c = e / kTS, i = e % kTS;
+            float v = L.B3[c];
+            const float4* wr = reinterpret_cast<const float4*>(L.W3 + c * kRS);
+#pragma unroll 8
+            for (int q = 0; q < kH / 4; ++q) {
+                const float4 wq = wr[q];
+                v = fmaf(wq.x, L.H2[(4 * q + 0) * kAS + i], v);
+                v = fmaf(wq.y, L.H2[(4 * q + 1) * kAS + i], v);
+                v = fmaf(wq.z, L.H2[(4 * q + 2) * kAS + i], v);
+                v = fmaf(wq.w, L.H2[(4 * q + 3) * kAS + i], v);
+            }
+            L.Z[c * kAS + i] = v;
+        }
+        __syncthreads();
+        // ---- per-sample loss terms and dL/dz (one lane per sample), in place of the target
+        if (tid < kTS) {
+            const int i = tid;
+            const bool valid = tile * kTS + i < a.N;
             float mse = 0.f, amax = -1.f;
             int cs = 0;
             float X[3] = {0.f, 0.f, 0.f}, Xg[3] = {0.f, 0.f, 0.f};
             for (int c = 0; c < k; ++c) {
-                const float d = dd[c];
+                const float z = L.Z[c * kAS + i], gt = L.G[c * kAS + i];
+                const float d = z - gt;
                 mse = fmaf(d, d, mse);
-                if (fabsf(d) > amax) {
+                if (fabsf(d) > amax) {      // the first channel of largest |d|
                     amax = fabsf(d);
                     cs = c;
                 }
 #pragma unroll
                 for (int x = 0; x < 3; ++x) {
-                    X[x] = fmaf(sM[x * k + c], zz[c], X[x]);
-                    Xg[x] = fmaf(sM[x * k + c], dz[c], Xg[x]);
+                    X[x] = fmaf(L.M[x * kMaxK + c], z, X[x]);
+                    Xg[x] = fmaf(L.M[x * kMaxK + c], gt, Xg[x]);
                 }
             }
             const float wh[3] = {a.wx, a.wy, a.wz};
@@ -233,113 +282,109 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
             const float inv = de > 0.f ? 1.f / de : 0.f;
             const float uL = dL * inv, ua = da * inv, ub = db * inv;
             // gradient of DeltaE76 with respect to the predicted XYZ
-            misc[3] = valid ? 500.f * ua * fp[0] / wh[0] : 0.f;
-            misc[4] = valid ? (116.f * uL - 500.f * ua + 200.f * ub) * fp[1] / wh[1] : 0.f;
-            misc[5] = valid ? -200.f * ub * fp[2] / wh[2] : 0.f;
-            misc[6] = __int_as_float(cs);
+            const float g0 = 500.f * ua * fp[0] / wh[0];
+            const float g1 = (116.f * uL - 500.f * ua + 200.f * ub) * fp[1] / wh[1];
+            const float g2 = -200.f * ub * fp[2] / wh[2];
+            for (int c = 0; c < k; ++c) {
+                const float d = L.Z[c * kAS + i] - L.G[c * kAS + i];
+                float gz = (2.0f / k) * d;
+                if (c == cs) gz += a.w_max * (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f));
+                gz += a.w_col * (L.M[c] * g0 + L.M[kMaxK + c] * g1 + L.M[2 * kMaxK + c] * g2);
+                L.G[c * kAS + i] = valid ? gz : 0.f;
+            }
             if (valid) loss += double(mse) / k + double(a.w_max) * amax + double(a.w_col) * de;
         }
         __syncthreads();
-        if (j < k) {
-            const int cs = __float_as_int(misc[6]);
-            const float d = dd[j];
-            float g = (2.0f / k) * d;
-            if (j == cs) g += a.w_max * (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f));
-            g += a.w_col * (sM[j] * misc[3] + sM[k + j] * misc[4] + sM[2 * k + j] * misc[5]);
-            dz[j] = valid ? g : 0.f;
-        }
-        __syncthreads();
-        // backward to the hidden layers
+        // ---- dL/dp2 (in place of p2), dW3 += dz h2^T, db3
         {
-            float v = 0.f;
-            for (int c = 0; c < k; ++c) v = fmaf(sW3[c * kRS + j], dz[c], v);
-            const float x = p2[j], sg = logistic(x);
-            dp2[j] = v * (sg + x * sg * (1.f - sg));
-        }
-        __syncthreads();
-        {
-            float v = 0.f;
-            for (int i = 0; i < kH; ++i) v = fmaf(sW2[i * kRS + j], dp2[i], v);
-            const float x = p1[j], sg = logistic(x);
-            dp1[j] = v * (sg + x * sg * (1.f - sg));
-        }
-        __syncthreads();
-        // accumulate the four samples, in order, into the owned gradient
-        // elements: W2 rows i = 32 hi + q (contiguous: 16-byte reads of dp2),
-        // W3 rows c = 4r + hi, column jj
-        {
-            const int jj = tid % kH, hi = tid / kH;
-            float h1[kSamples], h2[kSamples];
-#pragma unroll
-            for (int u = 0; u < kSamples; ++u) {
-                h1[u] = sS[u * kPer + kH + jj];
-                h2[u] = sS[u * kPer + 3 * kH + jj];
+            f4v d = {0.f, 0.f, 0.f, 0.f};
+            for (int st = 0; st < ksteps; ++st) {
+                const int c = 4 * st + g;
+                d = mfma4(c < k ? L.W3[c * kRS + jrow + n] : 0.f, L.G[c * kAS + n], d);
             }
 #pragma unroll
-            for (int q = 0; q < kW2PerThread; ++q) {
-                const int i = kW2PerThread * hi + q;
-                float v = aW2[q];
-#pragma unroll
-                for (int u = 0; u < kSamples; ++u) v = fmaf(sS[u * kPer + 4 * kH + i], h1[u], v);
-                aW2[q] = v;
+            for (int r = 0; r < 4; ++r) {
+                const int j = jrow + 4 * g + r;
+                L.P2[j * kAS + n] = d[r] * dsilu(L.P2[j * kAS + n]);
             }
 #pragma unroll
-            for (int r = 0; r < kW3PerThread; ++r) {
-                const int c = kSamples * r + hi;
-                if (c < k) {
-                    float v = aW3[r];
+            for (int mc = 0; mc < 3; ++mc) {
+                if (mc < mc3) {
 #pragma unroll
-                    for (int u = 0; u < kSamples; ++u) v = fmaf(sS[u * kPer + 6 * kH + 2 * kMaxK + c], h2[u], v);
-                    aW3[r] = v;
-                }
-            }
-            if (hi == 0) {
-#pragma unroll
-                for (int u = 0; u < kSamples; ++u) aB += sS[u * kPer + 4 * kH + jj];  // b2
-            } else if (hi == 1) {
-#pragma unroll
-                for (int u = 0; u < kSamples; ++u) {
-                    const float d1 = sS[u * kPer + 5 * kH + jj];
-                    const float* mu = sS + u * kPer + 6 * kH + 3 * kMaxK;
-#pragma unroll
-                    for (int x = 0; x < 3; ++x) aW1[x] = fmaf(d1, mu[x], aW1[x]);
-                    aB += d1;  // b1
+                    for (int st = 0; st < kTS / 4; ++st)
+                        acc3[mc] = mfma4(L.G[(16 * mc + n) * kAS + 4 * st + g],
+                                         L.H2[(jrow + n) * kAS + 4 * st + g], acc3[mc]);
                 }
             }
             if (tid < k) {
-#pragma unroll
-                for (int u = 0; u < kSamples; ++u) aB3 += sS[u * kPer + 6 * kH + 2 * kMaxK + tid];
+                float t = 0.f;
+                for (int i = 0; i < kTS; ++i) t += L.G[tid * kAS + i];
+                aB3 += t;
             }
         }
         __syncthreads();
+        // ---- dL/dp1 (in place of p1), dW2 += dp2 h1^T, db2
+        {
+            f4v c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+            for (int st = 0; st < kH / 4; st += 2) {
+                c0 = mfma4(L.W2[(4 * st + g) * kRS + jrow + n], L.P2[(4 * st + g) * kAS + n], c0);
+                c1 = mfma4(L.W2[(4 * st + 4 + g) * kRS + jrow + n], L.P2[(4 * st + 4 + g) * kAS + n], c1);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jrow + 4 * g + r;
+                L.P1[j * kAS + n] = (c0[r] + c1[r]) * dsilu(L.P1[j * kAS + n]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 8; ++nb) {
+#pragma unroll
+                for (int st = 0; st < kTS / 4; ++st)
+                    acc2[nb] = mfma4(L.P2[(jrow + n) * kAS + 4 * st + g], L.H1[(16 * nb + n) * kAS + 4 * st + g],
+                                     acc2[nb]);
+            }
+            if (tid < kH) {
+                float t = 0.f;
+                for (int i = 0; i < kTS; ++i) t += L.P2[tid * kAS + i];
+                aB2 += t;
+            }
+        }
+        __syncthreads();
+        // ---- [dW1 db1] += dp1 [c 1]^T
+#pragma unroll
+        for (int st = 0; st < kTS / 4; ++st)
+            acc1 = mfma4(L.P1[(jrow + n) * kAS + 4 * st + g], n < 4 ? L.X[4 * (4 * st + g) + n] : 0.f, acc1);
+        __syncthreads();
     }
-    // partial row
+    // ---- partial row
     float* prow = a.part + int64_t(blockIdx.x) * param_count(k);
-    {
-        const int jj = tid % kH, hi = tid / kH;
+    const int jrow = 16 * w;
 #pragma unroll
-        for (int q = 0; q < kW2PerThread; ++q) prow[kOffW2 + (kW2PerThread * hi + q) * kH + jj] = aW2[q];
+    for (int nb = 0; nb < 8; ++nb)
 #pragma unroll
-        for (int r = 0; r < kW3PerThread; ++r) {
-            const int c = kSamples * r + hi;
-            if (c < k) prow[kOffW3 + c * kH + jj] = aW3[r];
+        for (int r = 0; r < 4; ++r) prow[kOffW2 + (jrow + 4 * g + r) * kH + 16 * nb + n] = acc2[nb][r];
+#pragma unroll
+    for (int mc = 0; mc < 3; ++mc)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * mc + 4 * g + r;
+            if (mc < mc3 && c < k) prow[kOffW3 + c * kH + jrow + n] = acc3[mc][r];
         }
-        if (hi == 0) {
-            prow[kOffB2 + jj] = aB;
-        } else if (hi == 1) {
+    if (n < 4) {
 #pragma unroll
-            for (int x = 0; x < 3; ++x) prow[3 * jj + x] = aW1[x];
-            prow[kOffB1 + jj] = aB;
+        for (int r = 0; r < 4; ++r) {
+            const int j = jrow + 4 * g + r;
+            prow[n < 3 ? 3 * j + n : kOffB1 + j] = acc1[r];
         }
-        if (tid < k) prow[off_b3(k) + tid] = aB3;
     }
-    // workgroup loss: the per-sample threads (tid 0, 128, 256, 384), fixed order
-    __shared__ double s_loss[kSamples];
-    if (tid % kH == 0) s_loss[tid / kH] = loss;
+    if (tid < kH) prow[kOffB2 + tid] = aB2;
+    if (tid < k) prow[off_b3(k) + tid] = aB3;
+    // workgroup loss: the per-sample lanes 0..15, in order
+    if (tid < kTS) L.loss[tid] = loss;
     __syncthreads();
     if (tid == 0) {
         double t = 0.0;
-        for (int u = 0; u < kSamples; ++u) t += s_loss[u];
+        for (int i = 0; i < kTS; ++i) t += L.loss[i];
         a.loss_part[blockIdx.x] = t;
     }
 }
@@ -458,14 +503,10 @@ __global__ __launch_bounds__(kThreads) void ustrain_adamw_kernel(AdamWArgs a) {
     a.params[e] = float(w - (a.lr / bc1) * mm / (sqrt(vv) / sqrt(bc2) + a.eps));
 }
 
-int64_t grid_rows(int64_t N) { return std::min<int64_t>((N + kSamples - 1) / kSamples, kMaxRows); }
+int64_t grid_rows(int64_t N) { return std::min<int64_t>((N + kTS - 1) / kTS, kMaxRows); }
 static_assert((param_count(kMaxK) + kThreads - 1) / kThreads <= kThreads,
               "one workgroup sums the per-block squares");
 
-size_t lds_bytes(int k) {
-    return sizeof(float) * (size_t(kH) * kRS + size_t(k) * kRS + 4 * kH + kH + kMaxK + 3 * kMaxK +
-                            kSamples * (6 * kH + 3 * kMaxK + 8));
-}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
