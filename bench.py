@@ -240,7 +240,7 @@ def frame_roofline(kernel, bytes_alg, kern_s, nv, ceiling, copy_gbs, limiter):
             "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
 
 
-STRESS_CODEC_STEPS = 2000
+STRESS_CODEC_STEPS = 20000
 
 
 def stress_leg(w, args, dev, copy_gbs, cpu):
@@ -688,11 +688,15 @@ def main():
         return wall, kern
 
     if args.only == "gather":
+        # the sweep of gather_ceiling, then its best issue shape steps times
         latent_step()
+        best = gather_ceiling(P.vtx, codes, 4 * ops.blocks(k), 1, dev)
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
         for _ in range(args.warmup + args.steps):
-            ops.gather_probe(P.vtx, codes, 4 * ops.blocks(k), 4, 1, 4 * 256)
+            ops.gather_probe(P.vtx, codes, 4 * ops.blocks(k), best["unroll"], 1, best["workgroups_per_cu"] * cus)
         torch.cuda.synchronize()
-        log(f"gather probe: {args.warmup + args.steps} launches over {nv} records")
+        log(f"gather probe: best unroll {best['unroll']}, {best['workgroups_per_cu']} workgroups per CU, "
+            f"{best['rows_per_s'] / 1e9:.1f} G rows/s; {args.warmup + args.steps} more launches over {nv} records")
         return
     if args.only:
         wall, kern = timed(latent_step if args.only == "latent" else spectral_step)

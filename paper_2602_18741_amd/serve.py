@@ -52,6 +52,7 @@ class Request:
     error: str | None = None
     result: object = None
     slot: int = -1
+    first_use: bool = False      # its admission brought the asset in
 
     @property
     def n_pixels(self) -> int:
@@ -104,7 +105,8 @@ class Scheduler:
     that could never fit, even with every asset evicted, is rejected at
     submission.
 
-    backend must provide: request_bytes(req); asset_bytes(asset, loading)
+    backend must provide: iteration_vertices() (path-vertices of an
+    iteration when the caller gives none); request_bytes(req); asset_bytes(asset, loading)
     (device bytes of a resident asset, and while it is being brought in);
     load_asset(asset) (start bringing it in); evict_asset(asset);
     asset_state(asset) -> "pending" (still arriving), "needs_encode" or
@@ -117,7 +119,7 @@ class Scheduler:
     """
 
     def __init__(self, backend, max_frames: int = 64, mem_budget: float | None = None,
-                 tile_pixels: int | None = None, iter_vertices: float = 40e6, max_inflight: int = 2,
+                 tile_pixels: int | None = None, iter_vertices: float | None = None, max_inflight: int = 2,
                  max_tiles: int = 8192, decode_pixels: int = 65536, target_tiles: int = 4096):
         self.b = backend
         self.max_frames = max_frames
@@ -127,7 +129,9 @@ class Scheduler:
         # carries enough tiles to occupy every workgroup of the launch
         self.tile_pixels = tile_pixels
         self.target_tiles = target_tiles
-        self.iter_vertices = iter_vertices
+        # path-vertices per iteration: by default what the backend shades in
+        # about the same device time whatever the form (iteration_vertices())
+        self.iter_vertices = float(backend.iteration_vertices() if iter_vertices is None else iter_vertices)
         self.max_inflight = max_inflight
         self.max_tiles = max_tiles
         self.decode_pixels = decode_pixels  # decode tiles are larger: 64 frames x 4K fit one table
@@ -197,6 +201,7 @@ class Scheduler:
                     continue
                 self.assets[req.asset] = [0, asset_need]
                 self._charge(asset_need)
+                req.first_use = True
             self.assets.move_to_end(req.asset)
             self.assets[req.asset][0] += 1
             try:
@@ -452,6 +457,16 @@ class GpuBackend:
         self.graph = g
 
     # -------------------------------------------------------------- scheduler hooks
+    ITER_LINES = 40e6        # texel-row cache lines one iteration gathers (about 0.7 ms)
+
+    def iteration_vertices(self) -> float:
+        """Path-vertices per iteration.  The shading kernels run at the rate
+        of random 128-byte line fetches, one per line of a texel row, so an
+        iteration is sized in lines: a k <= 9 code or an n = 31 spectrum is
+        one line, an n = 81 spectrum three."""
+        row = 4 * (self.ops.latent_width(self.k) if self.form == "latent" else self.ops.line_stride(self.n))
+        return self.ITER_LINES / max(1, -(-row // 128))
+
     def memory_budget(self) -> float:
         """Device memory the scheduler may hand out: what the device has free
         now (with this backend's tables, lights and graph allocated), less a
@@ -690,12 +705,16 @@ def run_stream(sched: Scheduler, requests, time_limit: float = 120.0, idle_sleep
 def summarize(reqs, wall: float) -> dict:
     ok = [r for r in reqs if r.state == "done"]
     lat = np.array([r.latency for r in ok]) * 1e3
+    first = np.array([r.latency for r in ok if r.first_use]) * 1e3
+    warm = np.array([r.latency for r in ok if not r.first_use]) * 1e3
     verts = sum(r.expected_vertices for r in ok)
+    pct = lambda x, q: float(np.percentile(x, q)) if x.size else None  # noqa: E731
     return {"requests": len(reqs), "completed": len(ok),
             "failed": sum(r.state == "failed" for r in reqs),
-            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
-            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
             "mean_ms": float(lat.mean()) if lat.size else None,
+            "first_use": {"requests": int(first.size), "p50_ms": pct(first, 50), "p99_ms": pct(first, 99)},
+            "resident_asset": {"requests": int(warm.size), "p50_ms": pct(warm, 50), "p99_ms": pct(warm, 99)},
             "frames_per_s": len(ok) / wall, "path_vertices_per_s": verts / wall, "wall_s": wall}
 
 

@@ -41,6 +41,9 @@ class FakeBackend:
         self.live_bytes += delta
         self.max_live = max(self.max_live, self.live_bytes)
 
+    def iteration_vertices(self):
+        return 4e7
+
     def request_bytes(self, req):
         return req.n_pixels * 10
 
