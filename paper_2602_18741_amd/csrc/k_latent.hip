@@ -41,7 +41,7 @@ __device__ __forceinline__ void stage_lights(const LatentFrame& f, float4* s_lig
 
 // The calling wave shades pixels [q0, min(q0 + pw, q_end)).  With LDS the
 // light codes come from the staged table s_light, else from global memory.
-template <int NB, bool LDS>
+template <int NB, bool LDS, bool FAR = false>
 __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, int64_t q_end,
                                              const float4* s_light) {
 #pragma clang fp contract(off)
@@ -74,7 +74,10 @@ __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, i
             const uint32_t end = (first < P.n_vertices) ? min(first + len, P.n_vertices) : first;
             // U vertices at a time: all record loads, then all row gathers, are
             // in flight before the first multiply; padding slots multiply by 1
-            constexpr int U = NB <= 4 ? 4 : (NB <= 8 ? 2 : 1);
+            // (FAR: a table past the cache, served from HBM, where fewer
+            // requests in flight per lane are served faster)
+            constexpr int U0 = NB <= 4 ? 4 : (NB <= 8 ? 2 : 1);
+            constexpr int U = FAR && U0 > 1 ? U0 / 2 : U0;
             for (uint32_t jv = first; jv < end; jv += U) {
                 // records first, all U in flight: slots past the path read the
                 // following (in-bounds) records, which the wave fetches anyway;
@@ -132,7 +135,7 @@ __device__ __forceinline__ void latent_group(const LatentFrame& f, int64_t q0, i
     }
 }
 
-template <int NB>
+template <int NB, bool FAR>
 __global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentFrame f, int lights_in_lds) {
     extern __shared__ float4 s_light[];
     if (lights_in_lds) {
@@ -143,9 +146,9 @@ __global__ __launch_bounds__(kBlock) void shade_latent_kernel(LatentFrame f, int
     const int64_t q0 = wave * f.P.pw;
     if (q0 >= f.P.n_pixels) return;  // whole wave leaves together; no barrier follows
     if (lights_in_lds)
-        latent_group<NB, true>(f, q0, f.P.n_pixels, s_light);
+        latent_group<NB, true, FAR>(f, q0, f.P.n_pixels, s_light);
     else
-        latent_group<NB, false>(f, q0, f.P.n_pixels, s_light);
+        latent_group<NB, false, FAR>(f, q0, f.P.n_pixels, s_light);
 }
 
 // Persistent launch over a tile table: block b takes tiles b, b + grid, ...
@@ -219,7 +222,14 @@ hc_status launch_shade_latent(const hc_paths& P, const hc_latent_assets& A, int 
     f.inv_spp = 1.0f / static_cast<float>(P.spp);
     const size_t lds_need = size_t(A.n_illum) * block_count * sizeof(float4);
     const int lights_in_lds = lds_need <= kLightLdsBytes;
-    const size_t lds = lights_in_lds ? lds_need : 0;
+    size_t lds = lights_in_lds ? lds_need : 0;
+    // A code table past the 256 MB cache is read from HBM at random: there
+    // fewer gathers in flight are served faster (measured at 1 GiB: half the
+    // vertices in flight per lane and at most four waves per SIMD, 52.9 ->
+    // 49.0 ms on the 4K / 64 spp frame).  The wave cap is an LDS reservation
+    // of a quarter of the CU's 160 KB per four-wave workgroup.
+    const bool far = double(A.n_texels) * double(A.ld) * sizeof(float) > kCacheBytes;
+    if (far) lds = std::max<size_t>(lds, kFarLdsBytes);
     const int64_t waves = ceil_div(P.n_pixels, f.P.pw);
     const int64_t blocks = ceil_div(waves, kWavesPerBlock);
     if (blocks > 0x7FFFFFFF) {
@@ -227,10 +237,14 @@ hc_status launch_shade_latent(const hc_paths& P, const hc_latent_assets& A, int 
         return HC_ESHAPE;
     }
     switch (block_count) {
-#define HC_CASE(NB)                                                                          \
-    case NB:                                                                                 \
-        hipLaunchKernelGGL(shade_latent_kernel<NB>, dim3(uint32_t(blocks)), dim3(kBlock), lds, st, f, \
-                           lights_in_lds);                                                   \
+#define HC_CASE(NB)                                                                                \
+    case NB:                                                                                       \
+        if (far)                                                                                   \
+            hipLaunchKernelGGL((shade_latent_kernel<NB, true>), dim3(uint32_t(blocks)), dim3(kBlock), lds, \
+                               st, f, lights_in_lds);                                              \
+        else                                                                                       \
+            hipLaunchKernelGGL((shade_latent_kernel<NB, false>), dim3(uint32_t(blocks)), dim3(kBlock), lds, \
+                               st, f, lights_in_lds);                                              \
         break;
         HC_NB_CASES(HC_CASE)
 #undef HC_CASE

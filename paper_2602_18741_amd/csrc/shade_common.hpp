@@ -10,6 +10,8 @@ namespace shade {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr size_t kLightLdsBytes = 16384;
+constexpr double kCacheBytes = 256.0 * 1024 * 1024;   // MI355X Infinity Cache (MALL)
+constexpr size_t kFarLdsBytes = 40960;                 // a quarter of a CU's LDS
 
 struct PathView {
     const uint32_t* hdr;
