@@ -144,7 +144,7 @@ def record_traffic(d_fetch, d_write, d_copy_fetch, d_copy_write, d_req=None):
     d = {"kernel": "shade_latent_kernel<2>", "workload": WORKLOAD,
          "kernel_source_sha": kernel_source_sha(), "fetch_scale": f_scale, "write_scale": w_scale,
          "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
-         "hbm_bytes_per_launch": fetch + write, "note": TRAFFIC_NOTE}
+         "fetch_plus_write_bytes_per_launch": fetch + write, "note": TRAFFIC_NOTE}
     if d_req:
         req = {c: _counter_mean(csv(d_req), kern, c, required=False)
                for c in ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_DRAM_sum")}
@@ -731,12 +731,12 @@ def main():
                           copy_gbs, f"random {4 * ops.blocks(k) * 4}-byte code rows from a "
                           f"{tbl_mb:.0f} MiB table" + (" resident in the 256 MB MALL" if tbl_mb < 256
                                                         else " in HBM") + " (one 128-byte line each)")
-    roof["traffic"] = None if traffic is None else traffic["hbm_bytes_per_launch"]
+    roof["traffic"] = None if traffic is None else traffic["fetch_plus_write_bytes_per_launch"]
     if traffic is not None:
         roof["traffic_note"] = traffic["note"]
         for key in ("fetch_bytes_per_launch", "write_bytes_per_launch", "ea_read_bytes", "dram_read_bytes"):
             roof[f"traffic_{key}"] = traffic.get(key)
-        roof["traffic_GBs"] = traffic["hbm_bytes_per_launch"] / lat_kern / 1e9
+        roof["traffic_GBs"] = traffic["fetch_plus_write_bytes_per_launch"] / lat_kern / 1e9
     roof["gather_ceiling_1GiB_rows_per_s"] = ceil_1g["rows_per_s"]
     roof["gather_ceiling_1GiB"] = ceil_1g
     roof_spe = frame_roofline("shade_spectral_kernel", bytes_spe, spe_kern, nv, ceil_spe, copy_gbs,
