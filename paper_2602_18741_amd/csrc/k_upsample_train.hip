@@ -86,11 +86,58 @@ __device__ __forceinline__ float dsilu(float x) {
     return sg + x * sg * (1.f - sg);
 }
 
+__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// LDS row strides and layout of the partials kernel.  Activations are
+// [feature][sample] arrays with 17 floats per feature row and 16 more after
+// every 32 rows, so the MFMA operand reads of both orientations (16 samples
+// of 4 rows, 16 rows 32 apart, 16 rows of 4 samples) fall on distinct banks.
+__device__ __forceinline__ int act(int r, int s) { return r * kAS + (r >> 5) * 16 + s; }
+constexpr int kActSize = kH * kAS + (kH / 32) * 16;
+
+struct Lds {
+    float *W3, *W1, *B2, *B3, *M, *X, *P1, *H1, *P2, *H2, *Z, *G, *ZP, *S;
+    double* loss;
+};
+
+__device__ __forceinline__ Lds lds_areas(float* sm, int k) {
+    Lds L;
+    L.W3 = sm;                        // k x kRS
+    L.W1 = L.W3 + k * kRS;            // 128 x 4: (w_r, w_g, w_b, b1), the A operand of layer 1
+    L.B2 = L.W1 + 4 * kH;
+    L.B3 = L.B2 + kH;                 // 48
+    L.M = L.B3 + kMaxK;               // 3 x 48
+    L.X = L.M + 3 * kMaxK;            // 16 samples x (r, g, b, 1)
+    L.P1 = L.X + 4 * kTS;             // p1, then dL/dp1
+    L.H1 = L.P1 + kActSize;
+    L.P2 = L.H1 + kActSize;           // p2, then dL/dp2
+    L.H2 = L.P2 + kActSize;
+    L.Z = L.H2 + kActSize;            // 48 x kAS: z
+    L.G = L.Z + kMaxK * kAS;          // 48 x kAS: target code, then dL/dz (rows k..47 zero)
+    L.ZP = L.G + kMaxK * kAS;         // layer-3 partial products: 8 waves x 3 blocks x 256
+    L.S = L.ZP + kPWaves * 3 * 256;   // per sample: channel of the max-abs term, colour gradient (4 x 16)
+    L.loss = reinterpret_cast<double*>(L.S + 4 * kTS);   // an even float offset: 8-byte aligned
+    return L;
+}
+
+size_t lds_bytes(int k) {
+    return sizeof(float) * (size_t(k) * kRS + 4 * kH + kH + kMaxK + 3 * kMaxK + 4 * kTS + 4 * size_t(kActSize) +
+                            2 * size_t(kMaxK) * kAS + kPWaves * 3 * 256 + 4 * kTS) +
+           sizeof(double) * kTS;
+}
+
+// cube root of t > 0 from the hardware base-2 logarithm and exponential
+__device__ __forceinline__ float cbrt_pos(float t) {
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(t) * (1.0f / 3.0f));
+}
+
 // CIELAB f and its slope
 __device__ __forceinline__ void lab_f(float t, float& f, float& fp) {
     constexpr float d = 6.0f / 29.0f;
     if (t > d * d * d) {
-        const float c = cbrtf(t);
+        const float c = cbrt_pos(t);
         f = c;
         fp = 1.0f / (3.0f * c * c);
     } else {
@@ -99,46 +146,13 @@ __device__ __forceinline__ void lab_f(float t, float& f, float& fp) {
     }
 }
 
-__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// LDS areas of the partials kernel, in floats
-struct Lds {
-    float *W2, *W3, *W1, *B2, *B3, *M, *X, *P1, *H1, *P2, *H2, *Z, *G;
-    double* loss;
-};
-
-__device__ __forceinline__ Lds lds_areas(float* sm, int k) {
-    Lds L;
-    L.W2 = sm;                        // 128 x kRS
-    L.W3 = L.W2 + kH * kRS;           // k x kRS
-    L.W1 = L.W3 + k * kRS;            // 128 x 4: (w_r, w_g, w_b, b1), the A operand of layer 1
-    L.B2 = L.W1 + 4 * kH;
-    L.B3 = L.B2 + kH;                 // 48
-    L.M = L.B3 + kMaxK;               // 3 x 48
-    L.X = L.M + 3 * kMaxK;            // 16 samples x (r, g, b, 1)
-    L.P1 = L.X + 4 * kTS;             // 128 x kAS: p1, then dL/dp1
-    L.H1 = L.P1 + kH * kAS;
-    L.P2 = L.H1 + kH * kAS;           // p2, then dL/dp2
-    L.H2 = L.P2 + kH * kAS;
-    L.Z = L.H2 + kH * kAS;            // 48 x kAS: z
-    L.G = L.Z + kMaxK * kAS;          // 48 x kAS: target code, then dL/dz (rows k..47 zero)
-    L.loss = reinterpret_cast<double*>(L.G + kMaxK * kAS);   // an even float offset: 8-byte aligned
-    return L;
-}
-
-size_t lds_bytes(int k) {
-    return sizeof(float) * (size_t(kH) * kRS + size_t(k) * kRS + 4 * kH + kH + kMaxK + 3 * kMaxK + 4 * kTS +
-                            4 * size_t(kH) * kAS + 2 * size_t(kMaxK) * kAS) +
-           sizeof(double) * kTS;
-}
-
 // One workgroup per partial row; it takes tiles of 16 samples in turn.  Per
 // tile, with the activations of the tile in LDS as [feature][sample]:
 //   forward   p1 = W1 c + b1 (one 16x16x4 product per 16 features, the bias
 //             through a constant-1 input), p2 = W2 h1 + b2 (32 products per
-//             16 features), z = W3 h2 + b3 (vector ALU, k x 16 outputs);
+//             16 features, W2's fragments held in registers), z = W3 h2 + b3
+//             (the 128-long sums split over the 8 wavefronts, then added in
+//             a fixed order);
 //   loss      per sample: the three terms of Sec. 5.2 and dL/dz;
 //   backward  dL/dh2 = W3^T dL/dz, dL/dp2 = dL/dh2 * silu'(p2), dL/dh1 =
 //             W2^T dL/dp2, dL/dp1 = dL/dh1 * silu'(p1) (matrix cores), and the
@@ -152,8 +166,17 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
     const Lds L = lds_areas(sm, k);
     const int tid = threadIdx.x;
     const int w = tid / 64, lane = tid & 63, g = lane / 16, n = lane % 16;
+    const int jrow = 16 * w;           // the wave's 16 hidden rows
     const float* P = a.params;
-    for (int e = tid; e < kH * kH; e += kPThreads) L.W2[(e / kH) * kRS + e % kH] = P[kOffW2 + e];
+    // the wave's W2 fragments for the whole kernel, K index 32 g + st: the
+    // forward A operand W2[jrow + n][32 g + st] and the backward one
+    // W2[32 g + st][jrow + n]
+    float wf[32], wb[32];
+#pragma unroll
+    for (int st = 0; st < 32; ++st) {
+        wf[st] = ldg_f32(P + kOffW2 + (jrow + n) * kH + 32 * g + st);
+        wb[st] = ldg_f32(P + kOffW2 + (32 * g + st) * kH + jrow + n);
+    }
     for (int e = tid; e < k * kH; e += kPThreads) L.W3[(e / kH) * kRS + e % kH] = P[kOffW3 + e];
     for (int j = tid; j < kH; j += kPThreads) {
         L.W1[4 * j + 0] = P[3 * j];
@@ -202,52 +225,62 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
             }
         }
         __syncthreads();
-        const int jrow = 16 * w;           // the wave's 16 hidden rows
         // ---- layer 1 (K = 4: r, g, b, 1)
         {
             const f4v d = mfma4(L.W1[4 * (jrow + n) + g], L.X[4 * n + g], f4v{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = jrow + 4 * g + r;
-                L.P1[j * kAS + n] = d[r];
-                L.H1[j * kAS + n] = d[r] * logistic(d[r]);
+                L.P1[act(j, n)] = d[r];
+                L.H1[act(j, n)] = d[r] * logistic(d[r]);
             }
         }
         __syncthreads();
         // ---- layer 2: 32 K steps, two independent chains
         {
             f4v c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-            for (int st = 0; st < kH / 4; st += 2) {
-                c0 = mfma4(L.W2[(jrow + n) * kRS + 4 * st + g], L.H1[(4 * st + g) * kAS + n], c0);
-                c1 = mfma4(L.W2[(jrow + n) * kRS + 4 * st + 4 + g], L.H1[(4 * st + 4 + g) * kAS + n], c1);
+#pragma unroll
+            for (int st = 0; st < 32; st += 2) {
+                c0 = mfma4(wf[st], L.H1[act(32 * g + st, n)], c0);
+                c1 = mfma4(wf[st + 1], L.H1[act(32 * g + st + 1, n)], c1);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = jrow + 4 * g + r;
                 const float v = (c0[r] + c1[r]) + L.B2[j];
-                L.P2[j * kAS + n] = v;
-                L.H2[j * kAS + n] = v * logistic(v);
+                L.P2[act(j, n)] = v;
+                L.H2[act(j, n)] = v * logistic(v);
             }
         }
         __syncthreads();
-        // ---- layer 3 on the vector ALU: output (channel c, sample i)
+        // ---- layer 3: wave w sums hidden rows 16w..16w+15 for every block of
+        // channels; the eight partial products are added in order below
+        {
+#pragma unroll
+            for (int mc = 0; mc < 3; ++mc) {
+                if (mc < mc3) {
+                    const int c = 16 * mc + n;
+                    f4v d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) {
+                        const int i = jrow + 4 * st + g;
+                        d = mfma4(c < k ? L.W3[c * kRS + i] : 0.f, L.H2[act(i, n)], d);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) L.ZP[(w * 3 + mc) * 256 + (4 * g + r) * 16 + n] = d[r];
+                }
+            }
+        }
+        __syncthreads();
         for (int e = tid; e < k * kTS; e += kPThreads) {
-            const int c = e / kTS, i = e % kTS;
-            float v = L.B3[c];
-            const float4* wr = reinterpret_cast<const float4*>(L.W3 + c * kRS);
-#pragma unroll 8
-            for (int q = 0; q < kH / 4; ++q) {
-                const float4 wq = wr[q];
-                v = fmaf(wq.x, L.H2[(4 * q + 0) * kAS + i], v);
-                v = fmaf(wq.y, L.H2[(4 * q + 1) * kAS + i], v);
-                v = fmaf(wq.z, L.H2[(4 * q + 2) * kAS + i], v);
-                v = fmaf(wq.w, L.H2[(4 * q + 3) * kAS + i], v);
-            }
-            L.Z[c * kAS + i] = v;
+            const int c = e / kTS, i = e % kTS, mc = c / 16, cr = c % 16;
+            float v = 0.f;
+#pragma unroll
+            for (int ww = 0; ww < kPWaves; ++ww) v += L.ZP[(ww * 3 + mc) * 256 + cr * 16 + i];
+            L.Z[c * kAS + i] = v + L.B3[c];
         }
         __syncthreads();
-        // ---- per-sample loss terms and dL/dz (one lane per sample), in place of the target
+        // ---- per-sample loss terms and the colour gradient (one lane per sample)
         if (tid < kTS) {
             const int i = tid;
             const bool valid = tile * kTS + i < a.N;
@@ -282,17 +315,23 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
             const float inv = de > 0.f ? 1.f / de : 0.f;
             const float uL = dL * inv, ua = da * inv, ub = db * inv;
             // gradient of DeltaE76 with respect to the predicted XYZ
-            const float g0 = 500.f * ua * fp[0] / wh[0];
-            const float g1 = (116.f * uL - 500.f * ua + 200.f * ub) * fp[1] / wh[1];
-            const float g2 = -200.f * ub * fp[2] / wh[2];
-            for (int c = 0; c < k; ++c) {
-                const float d = L.Z[c * kAS + i] - L.G[c * kAS + i];
-                float gz = (2.0f / k) * d;
-                if (c == cs) gz += a.w_max * (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f));
-                gz += a.w_col * (L.M[c] * g0 + L.M[kMaxK + c] * g1 + L.M[2 * kMaxK + c] * g2);
-                L.G[c * kAS + i] = valid ? gz : 0.f;
-            }
+            L.S[i] = valid ? __int_as_float(cs) : __int_as_float(-1);
+            L.S[kTS + i] = 500.f * ua * fp[0] / wh[0];
+            L.S[2 * kTS + i] = (116.f * uL - 500.f * ua + 200.f * ub) * fp[1] / wh[1];
+            L.S[3 * kTS + i] = -200.f * ub * fp[2] / wh[2];
             if (valid) loss += double(mse) / k + double(a.w_max) * amax + double(a.w_col) * de;
+        }
+        __syncthreads();
+        // ---- dL/dz (one thread per channel and sample), in place of the target
+        for (int e = tid; e < k * kTS; e += kPThreads) {
+            const int c = e / kTS, i = e % kTS;
+            const int cs = __float_as_int(L.S[i]);
+            const float d = L.Z[c * kAS + i] - L.G[c * kAS + i];
+            float gz = (2.0f / k) * d;
+            if (c == cs) gz += a.w_max * (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f));
+            gz += a.w_col * (L.M[c] * L.S[kTS + i] + L.M[kMaxK + c] * L.S[2 * kTS + i] +
+                             L.M[2 * kMaxK + c] * L.S[3 * kTS + i]);
+            L.G[c * kAS + i] = cs >= 0 ? gz : 0.f;       // cs < 0: a sample past N
         }
         __syncthreads();
         // ---- dL/dp2 (in place of p2), dW3 += dz h2^T, db3
@@ -305,15 +344,15 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = jrow + 4 * g + r;
-                L.P2[j * kAS + n] = d[r] * dsilu(L.P2[j * kAS + n]);
+                L.P2[act(j, n)] = d[r] * dsilu(L.P2[act(j, n)]);
             }
 #pragma unroll
             for (int mc = 0; mc < 3; ++mc) {
                 if (mc < mc3) {
 #pragma unroll
                     for (int st = 0; st < kTS / 4; ++st)
-                        acc3[mc] = mfma4(L.G[(16 * mc + n) * kAS + 4 * st + g],
-                                         L.H2[(jrow + n) * kAS + 4 * st + g], acc3[mc]);
+                        acc3[mc] = mfma4(L.G[(16 * mc + n) * kAS + 4 * st + g], L.H2[act(jrow + n, 4 * st + g)],
+                                         acc3[mc]);
                 }
             }
             if (tid < k) {
@@ -326,26 +365,25 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
         // ---- dL/dp1 (in place of p1), dW2 += dp2 h1^T, db2
         {
             f4v c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-            for (int st = 0; st < kH / 4; st += 2) {
-                c0 = mfma4(L.W2[(4 * st + g) * kRS + jrow + n], L.P2[(4 * st + g) * kAS + n], c0);
-                c1 = mfma4(L.W2[(4 * st + 4 + g) * kRS + jrow + n], L.P2[(4 * st + 4 + g) * kAS + n], c1);
+#pragma unroll
+            for (int st = 0; st < 32; st += 2) {
+                c0 = mfma4(wb[st], L.P2[act(32 * g + st, n)], c0);
+                c1 = mfma4(wb[st + 1], L.P2[act(32 * g + st + 1, n)], c1);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = jrow + 4 * g + r;
-                L.P1[j * kAS + n] = (c0[r] + c1[r]) * dsilu(L.P1[j * kAS + n]);
+                L.P1[act(j, n)] = (c0[r] + c1[r]) * dsilu(L.P1[act(j, n)]);
             }
 #pragma unroll
             for (int nb = 0; nb < 8; ++nb) {
 #pragma unroll
                 for (int st = 0; st < kTS / 4; ++st)
-                    acc2[nb] = mfma4(L.P2[(jrow + n) * kAS + 4 * st + g], L.H1[(16 * nb + n) * kAS + 4 * st + g],
-                                     acc2[nb]);
+                    acc2[nb] = mfma4(L.P2[act(jrow + n, 4 * st + g)], L.H1[act(16 * nb + n, 4 * st + g)], acc2[nb]);
             }
             if (tid < kH) {
                 float t = 0.f;
-                for (int i = 0; i < kTS; ++i) t += L.P2[tid * kAS + i];
+                for (int i = 0; i < kTS; ++i) t += L.P2[act(tid, i)];
                 aB2 += t;
             }
         }
@@ -353,12 +391,11 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
         // ---- [dW1 db1] += dp1 [c 1]^T
 #pragma unroll
         for (int st = 0; st < kTS / 4; ++st)
-            acc1 = mfma4(L.P1[(jrow + n) * kAS + 4 * st + g], n < 4 ? L.X[4 * (4 * st + g) + n] : 0.f, acc1);
+            acc1 = mfma4(L.P1[act(jrow + n, 4 * st + g)], n < 4 ? L.X[4 * (4 * st + g) + n] : 0.f, acc1);
         __syncthreads();
     }
     // ---- partial row
     float* prow = a.part + int64_t(blockIdx.x) * param_count(k);
-    const int jrow = 16 * w;
 #pragma unroll
     for (int nb = 0; nb < 8; ++nb)
 #pragma unroll
@@ -401,12 +438,13 @@ struct ReduceArgs {
     int64_t* ws_step;
 };
 
-// Sum of x[0 .. count) (count <= kThreads) by the calling workgroup, in a fixed
-// order: a butterfly inside each wavefront, then the wavefronts in order.  The
-// result is valid in thread 0.
+// Sum of x[0 .. count) by the calling workgroup, in a fixed order: thread t
+// adds x[t], x[t + 256], ..., then a butterfly inside each wavefront, then
+// the wavefronts in order.  The result is valid in thread 0.
 __device__ double block_sum(const double* x, int count) {
     __shared__ double s_w[kThreads / kWave];
-    double v = int(threadIdx.x) < count ? x[threadIdx.x] : 0.0;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < count; i += kThreads) v += x[i];
     for (int m = kWave / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = v;
     __syncthreads();
@@ -416,9 +454,19 @@ __device__ double block_sum(const double* x, int count) {
     return t;
 }
 
+// A block reduces 64 parameters: its four wavefronts sum a quarter of the
+// partial rows each (sixteen row loads in flight per lane), then the quarters
+// are added in order.
+constexpr int kRedParams = kWave;
+constexpr int kRedQuarters = kThreads / kWave;
+
 __global__ __launch_bounds__(kThreads) void ustrain_reduce_kernel(ReduceArgs a) {
-    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    double g = 0.0;
+    const int q = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t e = int64_t(blockIdx.x) * kRedParams + lane;
+    const int per = (a.rows + kRedQuarters - 1) / kRedQuarters;
+    const int r0 = min(a.rows, q * per), r1 = min(a.rows, r0 + per);
+    __shared__ double s_part[kRedQuarters][kRedParams];
+    double part = 0.0;
     if (e < a.P) {
         // sixteen interleaved partial sums keep sixteen row loads in flight
         // (whole batches unguarded: a guarded load becomes a branch per row)
@@ -426,34 +474,38 @@ __global__ __launch_bounds__(kThreads) void ustrain_reduce_kernel(ReduceArgs a) 
         double acc[kIlp];
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) acc[u] = 0.0;
-        int r = 0;
-        for (; r + kIlp <= a.rows; r += kIlp) {
+        int r = r0;
+        for (; r + kIlp <= r1; r += kIlp) {
             float x[kIlp];
 #pragma unroll
             for (int u = 0; u < kIlp; ++u) x[u] = a.part[int64_t(r + u) * a.P + e];
 #pragma unroll
             for (int u = 0; u < kIlp; ++u) acc[u] += double(x[u]);
         }
-        for (; r < a.rows; ++r) acc[0] += double(a.part[int64_t(r) * a.P + e]);
+        for (; r < r1; ++r) acc[0] += double(a.part[int64_t(r) * a.P + e]);
 #pragma unroll
         for (int w = kIlp / 2; w >= 1; w >>= 1)
 #pragma unroll
             for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
-        g = acc[0] / double(a.N);
-        a.grad[e] = float(g);
+        part = acc[0];
     }
-    double sq = g * g;
-    for (int m = kWave / 2; m >= 1; m >>= 1) sq += __shfl_xor(sq, m, kWave);
-    __shared__ double s_sq[kThreads / kWave];
-    if ((threadIdx.x & (kWave - 1)) == 0) s_sq[threadIdx.x / kWave] = sq;
+    s_part[q][lane] = part;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kThreads / kWave; ++w) t += s_sq[w];
-        a.sq_part[blockIdx.x] = t;
+    double sq = 0.0;
+    if (q == 0) {
+        double g = 0.0;
+        if (e < a.P) {
+#pragma unroll
+            for (int u = 0; u < kRedQuarters; ++u) g += s_part[u][lane];
+            g /= double(a.N);
+            a.grad[e] = float(g);
+        }
+        sq = g * g;
+        for (int m = kWave / 2; m >= 1; m >>= 1) sq += __shfl_xor(sq, m, kWave);
+        if (lane == 0) a.sq_part[blockIdx.x] = sq;
     }
     if (blockIdx.x == 0) {
-        const double l = block_sum(a.loss_part, a.rows);  // rows <= kThreads
+        const double l = block_sum(a.loss_part, a.rows);
         if (threadIdx.x == 0) {
             *a.loss = float(l / double(a.N));
             if (a.step) {
@@ -479,33 +531,31 @@ struct AdamWArgs {
 };
 
 __global__ __launch_bounds__(kThreads) void ustrain_adamw_kernel(AdamWArgs a) {
-    __shared__ double s_scale;
-    // every block forms the same norm from the block sums (nsq <= kThreads)
+    __shared__ double s_c[3];
+    // every block forms the same norm from the block sums, and the step's
+    // bias corrections (beta^t = exp(t ln beta), ln beta from the host)
     const double t2 = block_sum(a.sq_part, a.nsq);
     if (threadIdx.x == 0) {
         const double norm = sqrt(t2);
         const double c = a.max_norm / (norm + 1e-6);
-        s_scale = c < 1.0 ? c : 1.0;
+        const double t = double(*a.ws_step);
+        s_c[0] = c < 1.0 ? c : 1.0;
+        s_c[1] = a.lr / (1.0 - exp(t * a.ln_beta1));
+        s_c[2] = 1.0 / sqrt(1.0 - exp(t * a.ln_beta2));
     }
     __syncthreads();
     const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (e >= a.P) return;
-    const double g = double(a.grad[e]) * s_scale;
-    const double t = double(*a.ws_step);
+    const double g = double(a.grad[e]) * s_c[0];
     const double w = double(a.params[e]) * (1.0 - a.lr * a.wd);
     const double mm = a.beta1 * double(a.m[e]) + (1.0 - a.beta1) * g;
     const double vv = a.beta2 * double(a.v[e]) + (1.0 - a.beta2) * g * g;
-    // beta^t = exp(t ln beta), ln beta from the host
-    const double bc1 = 1.0 - exp(t * a.ln_beta1);
-    const double bc2 = 1.0 - exp(t * a.ln_beta2);
     a.m[e] = float(mm);
     a.v[e] = float(vv);
-    a.params[e] = float(w - (a.lr / bc1) * mm / (sqrt(vv) / sqrt(bc2) + a.eps));
+    a.params[e] = float(w - s_c[1] * mm / (sqrt(vv) * s_c[2] + a.eps));
 }
 
 int64_t grid_rows(int64_t N) { return std::min<int64_t>((N + kTS - 1) / kTS, kMaxRows); }
-static_assert((param_count(kMaxK) + kThreads - 1) / kThreads <= kThreads,
-              "one workgroup sums the per-block squares");
 
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -521,7 +571,7 @@ struct Ws {
 Ws carve(void* base, int k, int64_t N) {
     const int64_t P = param_count(k);
     const int64_t rows = grid_rows(N);
-    const int64_t nsq = ceil_div(P, kThreads);
+    const int64_t nsq = ceil_div(P, kRedParams);
     char* p = static_cast<char*>(base);
     Ws w;
     w.part = reinterpret_cast<float*>(p);
@@ -543,7 +593,7 @@ int64_t upsample_param_count(int k) { return param_count(k); }
 size_t upsample_train_workspace_size(int k, int64_t N) {
     const int64_t P = param_count(k);
     return align256(size_t(grid_rows(N)) * P * sizeof(float)) + align256(kMaxRows * sizeof(double)) +
-           align256(size_t(ceil_div(P, kThreads)) * sizeof(double)) + align256(size_t(P) * sizeof(float)) +
+           align256(size_t(ceil_div(P, kRedParams)) * sizeof(double)) + align256(size_t(P) * sizeof(float)) +
            sizeof(int64_t);
 }
 
@@ -590,7 +640,7 @@ hc_status launch_upsample_train(const hc_upsample_train_args& u) {
     r.loss = u.loss;
     r.step = u.opt ? u.opt->step : nullptr;
     r.ws_step = ws.step;
-    const int nsq = int(ceil_div(P, kThreads));
+    const int nsq = int(ceil_div(P, kRedParams));
     hipLaunchKernelGGL(ustrain_reduce_kernel, dim3(nsq), dim3(kThreads), 0, st, r);
     s = launch_status("hc_upsample_train_step");
     if (s != HC_OK || !u.opt) return s;
@@ -613,7 +663,7 @@ hc_status launch_upsample_train(const hc_upsample_train_args& u) {
     w.eps = u.opt->eps;
     w.wd = u.opt->weight_decay;
     w.max_norm = u.opt->max_grad_norm;
-    hipLaunchKernelGGL(ustrain_adamw_kernel, dim3(nsq), dim3(kThreads), 0, st, w);
+    hipLaunchKernelGGL(ustrain_adamw_kernel, dim3(int(ceil_div(P, kThreads))), dim3(kThreads), 0, st, w);
     return launch_status("hc_upsample_train_step");
 }
 
