@@ -372,10 +372,10 @@ class GpuBackend:
     graph per form.  form: "latent" (encode -> shade -> decode) or
     "spectral" (shade straight to XYZ)."""
 
-    JOB_ROWS = 65536         # spectra rows per encode-table entry
+    JOB_ROWS = 2048          # spectra rows per encode-table entry: a 2048^2 asset spreads over 2,048 workgroups
 
     def __init__(self, assets, lights, T, E=None, D=None, form: str = "latent", max_frames: int = 64,
-                 max_tiles: int = 8192, max_jobs: int = 4096, grid: int = 0, device="cuda",
+                 max_tiles: int = 8192, max_jobs: int = 8192, grid: int = 0, device="cuda",
                  use_graph: bool = True, reserve: float = 0.1):
         import torch
 
@@ -582,14 +582,18 @@ class GpuBackend:
         # every table is checked against its capacity before anything is
         # written or any asset changes state, so a refused plan leaves the
         # backend as it was
-        jobs = []
+        parts = []
         for aid in plan.encode:
             a = self.resident[aid]
             spectral, tex = a["spectral"], a["tex"]
-            for b in range(0, spectral.shape[0], self.JOB_ROWS):
-                jobs.append((spectral.data_ptr(), tex.data_ptr(), spectral.stride(0), tex.stride(0), b,
-                             min(spectral.shape[0], b + self.JOB_ROWS)))
-        if len(jobs) > self.max_jobs:
+            b = np.arange(0, spectral.shape[0], self.JOB_ROWS, dtype=np.int64)
+            j = np.zeros(b.size, self._JOB_DT)
+            j["S"], j["Z"] = spectral.data_ptr(), tex.data_ptr()
+            j["ld_s"], j["ld_z"] = spectral.stride(0), tex.stride(0)
+            j["begin"], j["end"] = b, np.minimum(b + self.JOB_ROWS, spectral.shape[0])
+            parts.append(j)
+        jobs = np.concatenate(parts) if parts else np.zeros(0, self._JOB_DT)
+        if jobs.size > self.max_jobs:
             raise RuntimeError("iteration exceeds the encode table capacity")
         shade, decode = span_tiles(plan.shade), span_tiles(plan.decode)
         if max(shade[0].size, decode[0].size) > self.max_tiles:
@@ -598,15 +602,15 @@ class GpuBackend:
         C.memmove(hp + int(self.offs[0]), C.addressof(self.frames), C.sizeof(self.frames))
         n_sh = self._put_tiles(hp + int(self.offs[1]), plan.shade, shade)
         n_de = self._put_tiles(hp + int(self.offs[2]), plan.decode, decode)
-        jt = (self.EncodeJob * max(1, len(jobs)))(*[self.EncodeJob(*j) for j in jobs])
-        C.memmove(hp + int(self.offs[3]), C.addressof(jt), C.sizeof(self.EncodeJob) * len(jobs))
+        if jobs.size:
+            C.memmove(hp + int(self.offs[3]), jobs.ctypes.data, jobs.nbytes)
         keep = []
         for aid in plan.encode:
             a = self.resident[aid]
             self.stream.wait_event(a["event"])     # already complete; orders the streams
             keep.append(a["spectral"])
             a["state"], a["spectral"] = "ready", None
-        counts = np.array([n_sh, n_de, len(jobs), 0], dtype=np.int32)
+        counts = np.array([n_sh, n_de, jobs.size, 0], dtype=np.int32)
         C.memmove(hp + int(self.offs[4]), counts.ctypes.data, 16)
         with torch.cuda.stream(self.stream):
             self.d_tables.copy_(h, non_blocking=True)
@@ -624,6 +628,8 @@ class GpuBackend:
         return ev
 
     _TILE_DT = np.dtype([("frame", "<i4"), ("pad", "<i4"), ("begin", "<i8"), ("end", "<i8")])
+    _JOB_DT = np.dtype([("S", "<u8"), ("Z", "<u8"), ("ld_s", "<i8"), ("ld_z", "<i8"), ("begin", "<i8"),
+                        ("end", "<i8")])
 
     def _put_tiles(self, dst: int, spans, tiles) -> int:
         """Write the tiles of `spans` (span_tiles(spans)) into the pinned

@@ -235,3 +235,14 @@ def test_codec_step_static_rejects_a_workspace_and_oversized_shapes(lib):
     assert s == _lib.HC_ENOMEM and str(_lib.HC_CODEC_STATIC_SCRATCH_BYTES) in msg
     args.k = 0
     assert lib.hc_codec_step_static(C.byref(args)) == _lib.HC_ESHAPE
+
+
+def test_server_table_dtypes_match_the_abi_structs():
+    """The server writes its tile and encode-job tables as numpy records;
+    their layout is the C structs' (hc_tile, hc_encode_job)."""
+    from paper_2602_18741_amd.serve import GpuBackend
+    for dt, st in ((GpuBackend._TILE_DT, _lib.Tile), (GpuBackend._JOB_DT, _lib.EncodeJob)):
+        assert dt.itemsize == C.sizeof(st)
+        for name, _ in st._fields_:
+            want = "pad" if name == "reserved0" else name
+            assert dt.fields[want][1] == getattr(st, name).offset, name
