@@ -1075,6 +1075,327 @@ Workspace carve(void* ws, int k, int n, int64_t rows, size_t esz) {
     return w;
 }
 
+// ------------------------------------------------------------------ kernel 2, matrix-core tiles
+//
+// Float32 step for n = 81 with k <= 16: every product of the step is a
+// 16x16x4 fp32 MFMA on tiles of 16 pairs, one wavefront per tile (four per
+// workgroup, each with its own LDS tiles; no workgroup barrier inside the
+// loop).  Per tile, with the pairs' rows a, b in LDS as [pair][sample]:
+//   codes        U = A E^T, V = B E^T, Tc = (A*B) E^T (pairs x codes, K = n);
+//                H = U*V, Dc = H - Tc (Eq. 8's code term);
+//   residuals    A_hat = U D^T, B_hat = V D^T, S = H D^T (pairs x samples, K = k)
+//                minus a, b and t = a*b, summed per pair across the lanes of a
+//                16-lane row for the loss and the per-pair factors; the
+//                gradient g_3 with respect to the decoded product (Eq. 8: the
+//                cosine-scaled error, the colour term through T) and the scaled
+//                r_a', r_b' are written back as [pair][sample] tiles;
+//   code grads   D^T g_3, D^T r_a', D^T r_b' (pairs x codes, K = n), then
+//                g_u = D^T r_a' + g_h v and g_v = D^T r_b' + g_h u;
+//   weight grads dD += r_a'^T U + r_b'^T V + g_3^T H (samples x codes, K = the
+//                tile's pairs), dE += g_u^T A + g_v^T B - w Dc^T (A*B) (codes x
+//                samples), accumulated in registers across tiles.
+// The wavefronts' sums are added in a fixed order into one float64 partial
+// row per workgroup.  Rows are read with a stride of 84 floats (samples 81-83
+// zero, reads past 84 masked), conflict-free for the 16 rows x 4 columns of a
+// forward operand.
+constexpr int kTileNS = 81;                 // samples
+constexpr int kTileRS = 84;                 // LDS row stride of [pair][sample] tiles
+constexpr int kTileKS = kTileRS / 4;        // K steps over the samples (21)
+constexpr int kTileNB = 6;                  // 16-sample blocks (96 >= 81)
+constexpr int kTileCS = 17;                 // row stride of [pair][code] tiles
+constexpr int kTileWaves = 4;
+constexpr int kTileThreads = kTileWaves * kWave;
+constexpr int kTilePerWave = 5 * 16 * kTileRS + 6 * 16 * kTileCS;   // XA XB R1 R2 R3, U V H Dc GU GV
+constexpr int kTileShared = 16 * kTileRS + kTileRS * kTileCS + 3 * kTileRS;   // E, D, T
+
+size_t tile_lds_bytes() { return sizeof(float) * (size_t(kTileShared) + size_t(kTileWaves) * kTilePerWave); }
+
+// 16-lane row sum (lanes n = 0..15 of one quarter), the same in every lane
+__device__ __forceinline__ float row16_sum(float x) {
+    x += __shfl_xor(x, 1, kWave);
+    x += __shfl_xor(x, 2, kWave);
+    x += __shfl_xor(x, 4, kWave);
+    x += __shfl_xor(x, 8, kWave);
+    return x;
+}
+
+template <bool EQ8, int K>
+__global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<float> a) {
+    extern __shared__ __align__(16) float tsm[];
+    constexpr int NS = kTileNS, RS = kTileRS, CS = kTileCS, KS = kTileKS, NB = kTileNB;
+    constexpr int KC = (K + 3) / 4;                   // K steps over the codes
+    static_assert(K <= 16, "one 16-column block of codes");
+    float* sE = tsm;                                  // [16 codes][RS], rows >= K zero
+    float* sD = sE + 16 * RS;                         // [RS samples][CS], rows >= n and columns >= K zero
+    float* sT = sD + RS * CS;                         // [3][RS]
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave, lane = tid & (kWave - 1), g = lane >> 4, n = lane & 15;
+    float* W = tsm + kTileShared + wave * kTilePerWave;
+    float* XA = W;
+    float* XB = XA + 16 * RS;
+    float* R1 = XB + 16 * RS;                         // r_a' (scaled residual of a)
+    float* R2 = R1 + 16 * RS;                         // r_b'
+    float* R3 = R2 + 16 * RS;                         // g_3
+    float* CU = R3 + 16 * RS;                         // [pair][code] tiles
+    float* CV = CU + 16 * CS;
+    float* CH = CV + 16 * CS;
+    float* CDc = CH + 16 * CS;                        // -w_code (2/k) (h - E t), the third dE coefficient
+    float* CGU = CDc + 16 * CS;
+    float* CGV = CGU + 16 * CS;
+
+    for (int e = tid; e < 16 * RS; e += kTileThreads) {
+        const int j = e / RS, i = e % RS;
+        sE[e] = (j < K && i < NS) ? softplus(a.we[j * NS + i], a.beta) : 0.f;
+    }
+    for (int e = tid; e < RS * CS; e += kTileThreads) {
+        const int i = e / CS, j = e % CS;
+        sD[e] = (i < NS && j < K) ? softplus(a.wd[i * K + j], a.beta) : 0.f;
+    }
+    for (int e = tid; e < 3 * RS; e += kTileThreads) sT[e] = (EQ8 && e % RS < NS) ? a.T[(e / RS) * NS + e % RS] : 0.f;
+    // samples 81..83 of the pair tiles stay zero
+    for (int e = lane; e < 5 * 16 * (RS - NS); e += kWave) {
+        const int t = e / (16 * (RS - NS)), p = (e / (RS - NS)) % 16, i = NS + e % (RS - NS);
+        W[t * 16 * RS + p * RS + i] = 0.f;
+    }
+    if (a.step && blockIdx.x == 0 && tid == 0) *a.ws_step = *a.step + 1;
+    __syncthreads();
+
+    const uint64_t ctr_base = a.draw ? draw_base(a) : 0ull;
+    const float lam = a.lam;
+    const float wr = EQ8 ? float(a.w_rec * 2.0 / NS) : 1.f;
+    const float wk = EQ8 ? float(a.w_code * 2.0 / K) : 0.f;
+    hc_mf4 accD[NB], accE[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) accD[b] = accE[b] = hc_mf4{0.f, 0.f, 0.f, 0.f};
+    double loss_acc = 0.0;
+    // lane (g, n) loads row pieces of pair 4 * (lane / 16) ... : pair p = lane / 4,
+    // samples q, q + 4, ... with q = lane % 4
+    const int lp = lane >> 2, lq = lane & 3;
+    constexpr int PER = (NS + 3) / 4;                 // 21 samples per lane and row
+    const int64_t tiles = (a.N + 15) / 16;
+    const int64_t tstride = int64_t(gridDim.x) * kTileWaves;
+    // the rows of a tile (pairs past N read zeros); loaded one tile ahead, so
+    // they are in flight while the current tile computes
+    float va[PER], vb[PER];
+    auto load_rows = [&](int64_t t) {
+        const int64_t pi = t * 16 + lp;
+        int64_t ra = 0, rb = 0;
+        const bool ok = t < tiles && pi < a.N;
+        if (ok) batch_rows(a, ctr_base, pi, ra, rb);
+        const float* pa = a.A + ra * a.ld_a;
+        const float* pb = a.B + rb * a.ld_b;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = lq + 4 * u;
+            va[u] = (ok && i < NS) ? pa[i] : 0.f;
+            vb[u] = (ok && i < NS) ? pb[i] : 0.f;
+        }
+    };
+    load_rows(int64_t(blockIdx.x) * kTileWaves + wave);
+    for (int64_t tile = int64_t(blockIdx.x) * kTileWaves + wave; tile < tiles; tile += tstride) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = lq + 4 * u;
+            if (i < NS) {
+                XA[lp * RS + i] = va[u];
+                XB[lp * RS + i] = vb[u];
+            }
+        }
+        load_rows(tile + tstride);
+        wave_lds_order();
+        // ---- codes: U, V, Tc (pairs x codes), K = samples
+        hc_mf4 cu = {0.f, 0.f, 0.f, 0.f}, cv = cu, ct = cu;
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+            const int i = 4 * st + g;
+            const float e = sE[n * RS + i];
+            const float xa = XA[n * RS + i], xb = XB[n * RS + i];
+            cu = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, e, cu, 0, 0, 0);
+            cv = __builtin_amdgcn_mfma_f32_16x16x4f32(xb, e, cv, 0, 0, 0);
+            if (EQ8) ct = __builtin_amdgcn_mfma_f32_16x16x4f32(xa * xb, e, ct, 0, 0, 0);
+        }
+        // lane (g, n): pairs 4g + r, code n
+        float s_dd[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 4 * g + r;
+            const float h = cu[r] * cv[r];
+            const float dc = EQ8 ? h - ct[r] : 0.f;
+            CU[p * CS + n] = cu[r];
+            CV[p * CS + n] = cv[r];
+            CH[p * CS + n] = h;
+            CDc[p * CS + n] = -wk * dc;
+            s_dd[r] = row16_sum(n < K ? dc * dc : 0.f);
+            ct[r] = dc;                               // kept for g_h
+        }
+        wave_lds_order();
+        // ---- reconstructions and residuals per 16-sample block
+        float s_rr[4] = {0.f, 0.f, 0.f, 0.f}, s_rh[4] = {0.f, 0.f, 0.f, 0.f}, s_st[4] = {0.f, 0.f, 0.f, 0.f};
+        float s_ss[4] = {0.f, 0.f, 0.f, 0.f}, s_tt[4] = {0.f, 0.f, 0.f, 0.f};
+        float s_c0[4] = {0.f, 0.f, 0.f, 0.f}, s_c1[4] = {0.f, 0.f, 0.f, 0.f}, s_c2[4] = {0.f, 0.f, 0.f, 0.f};
+        hc_mf4 ra[NB], rb[NB], sh[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            ra[b] = rb[b] = sh[b] = hc_mf4{0.f, 0.f, 0.f, 0.f};
+            const int i = 16 * b + n;                 // the lane's sample of the block
+#pragma unroll
+            for (int st = 0; st < KC; ++st) {
+                const int j = 4 * st + g;
+                const float d = i < NS ? sD[i * CS + j] : 0.f;
+                ra[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CU[n * CS + j], d, ra[b], 0, 0, 0);
+                rb[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CV[n * CS + j], d, rb[b], 0, 0, 0);
+                sh[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CH[n * CS + j], d, sh[b], 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = 4 * g + r;
+                const bool in = i < NS;
+                const float av = in ? XA[p * RS + i] : 0.f, bv = in ? XB[p * RS + i] : 0.f;
+                const float ti = av * bv;
+                const float rai = ra[b][r] - av, rbi = rb[b][r] - bv, rh = sh[b][r] - ti;
+                ra[b][r] = rai;
+                rb[b][r] = rbi;
+                s_rr[r] = fmaf(rai, rai, fmaf(rbi, rbi, s_rr[r]));
+                s_rh[r] = fmaf(rh, rh, s_rh[r]);
+                if (EQ8) {
+                    const float si = sh[b][r];
+                    s_st[r] = fmaf(si, ti, s_st[r]);
+                    s_ss[r] = fmaf(si, si, s_ss[r]);
+                    s_tt[r] = fmaf(ti, ti, s_tt[r]);
+                    const float t0 = in ? sT[i] : 0.f, t1 = in ? sT[RS + i] : 0.f, t2 = in ? sT[2 * RS + i] : 0.f;
+                    s_c0[r] = fmaf(t0, rh, s_c0[r]);
+                    s_c1[r] = fmaf(t1, rh, s_c1[r]);
+                    s_c2[r] = fmaf(t2, rh, s_c2[r]);
+                }
+            }
+        }
+        // per-pair sums across the 16 lanes of the row, then the per-pair factors
+        float al[4], bt[4], bs[4], gc0[4], gc1[4], gc2[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float rr = row16_sum(s_rr[r]), rhh = row16_sum(s_rh[r]);
+            const bool valid = tile * 16 + 4 * g + r < a.N;
+            if (EQ8) {
+                const float st_ = row16_sum(s_st[r]), ss = row16_sum(s_ss[r]), tt = row16_sum(s_tt[r]);
+                const float c0 = row16_sum(s_c0[r]), c1 = row16_sum(s_c1[r]), c2 = row16_sum(s_c2[r]);
+                const double M = double(rhh) / NS;
+                const double sn = sqrt(double(ss));
+                const double ns = sn > a.eps ? sn : a.eps;
+                const double tn = sqrt(double(tt));
+                const double nt = tn > a.eps ? tn : a.eps;
+                const double cs = double(st_) / (ns * nt);
+                if (valid && n == 0)
+                    loss_acc += a.w_e2e * M * (2.0 - cs) + a.w_rec * double(rr) / NS +
+                                a.w_code * double(s_dd[r]) / K +
+                                a.w_col * (double(c0) * c0 + double(c1) * c1 + double(c2) * c2) / 3.0;
+                al[r] = float(a.w_e2e * (2.0 - cs) * 2.0 / NS);
+                bt[r] = float(a.w_e2e * M / (ns * nt));
+                bs[r] = float(sn > a.eps ? a.w_e2e * M * cs / double(ss) : 0.0);
+                gc0[r] = float(a.w_col * (2.0 / 3.0) * c0);
+                gc1[r] = float(a.w_col * (2.0 / 3.0) * c1);
+                gc2[r] = float(a.w_col * (2.0 / 3.0) * c2);
+            } else {
+                if (valid && n == 0) loss_acc += double(rr) + double(lam) * double(rhh);
+                al[r] = lam;
+                bt[r] = bs[r] = gc0[r] = gc1[r] = gc2[r] = 0.f;
+            }
+        }
+        // g_3 and the scaled residuals as [pair][sample] tiles
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = 16 * b + n;
+            if (i < RS) {
+                const bool in = i < NS;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int p = 4 * g + r;
+                    const float av = in ? XA[p * RS + i] : 0.f, bv = in ? XB[p * RS + i] : 0.f;
+                    const float ti = av * bv, si = sh[b][r];
+                    float g3 = al[r] * (si - ti) - bt[r] * ti + bs[r] * si;
+                    if (EQ8 && in) g3 += gc0[r] * sT[i] + gc1[r] * sT[RS + i] + gc2[r] * sT[2 * RS + i];
+                    R1[p * RS + i] = in ? wr * ra[b][r] : 0.f;
+                    R2[p * RS + i] = in ? wr * rb[b][r] : 0.f;
+                    R3[p * RS + i] = in ? g3 : 0.f;
+                }
+            }
+        }
+        wave_lds_order();
+        // ---- code-space gradients: D^T g_3, D^T r_a', D^T r_b' (pairs x codes), K = samples
+        hc_mf4 gh = {0.f, 0.f, 0.f, 0.f}, g1 = gh, g2 = gh;
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+            const int i = 4 * st + g;
+            const float d = sD[i * CS + n];
+            gh = __builtin_amdgcn_mfma_f32_16x16x4f32(R3[n * RS + i], d, gh, 0, 0, 0);
+            g1 = __builtin_amdgcn_mfma_f32_16x16x4f32(R1[n * RS + i], d, g1, 0, 0, 0);
+            g2 = __builtin_amdgcn_mfma_f32_16x16x4f32(R2[n * RS + i], d, g2, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 4 * g + r;
+            const float h = gh[r] + (EQ8 ? wk * ct[r] : 0.f);
+            CGU[p * CS + n] = g1[r] + h * cv[r];
+            CGV[p * CS + n] = g2[r] + h * cu[r];
+        }
+        wave_lds_order();
+        // ---- weight gradients over the tile's pairs
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = 16 * b + n;                 // dE: the lane's sample column
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int p = 4 * st + g;
+                // dD (samples x codes): rows 16b + m, columns codes
+                const int ir = 16 * b + n;            // A operand: sample row n of block b
+                const bool rin = ir < RS;
+                accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rin ? R1[p * RS + ir] : 0.f, CU[p * CS + n], accD[b], 0, 0, 0);
+                accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rin ? R2[p * RS + ir] : 0.f, CV[p * CS + n], accD[b], 0, 0, 0);
+                accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rin ? R3[p * RS + ir] : 0.f, CH[p * CS + n], accD[b], 0, 0, 0);
+                // dE (codes x samples): rows codes, columns 16b + n
+                const bool cin = i < RS;
+                const float xa = cin ? XA[p * RS + i] : 0.f, xb = cin ? XB[p * RS + i] : 0.f;
+                accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CGU[p * CS + n], xa, accE[b], 0, 0, 0);
+                accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CGV[p * CS + n], xb, accE[b], 0, 0, 0);
+                if (EQ8) accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CDc[p * CS + n], xa * xb, accE[b], 0, 0, 0);
+            }
+        }
+        wave_lds_order();   // the tiles are read before the next tile's rows land
+    }
+
+    // ---- the wavefronts' sums into the partial row, in a fixed order:
+    // [0, kn) dL/dE (k x n), [kn, 2kn) dL/dD (n x k)
+    constexpr int kn = K * NS;
+    static_assert(kTileWaves * 2 * kn <= kTileWaves * kTilePerWave, "scratch fits the wave tiles");
+    __shared__ double s_loss[kTileWaves];
+    for (int mm = kWave / 2; mm >= 1; mm >>= 1) loss_acc += __shfl_xor(loss_acc, mm, kWave);
+    __syncthreads();
+    float* scr = tsm + kTileShared + wave * 2 * kn;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * b + 4 * g + r, j = n;          // dD element (sample i, code j)
+            if (i < NS && j < K) scr[kn + i * K + j] = accD[b][r];
+            const int j2 = 4 * g + r, i2 = 16 * b + n;        // dE element (code j2, sample i2)
+            if (j2 < K && i2 < NS) scr[j2 * NS + i2] = accE[b][r];
+        }
+    }
+    if (lane == 0) s_loss[wave] = loss_acc;
+    __syncthreads();
+    double* prow = a.part + int64_t(blockIdx.x) * (2 * kn + 1);
+    for (int e = tid; e < 2 * kn; e += kTileThreads) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kTileWaves; ++w) t += double(tsm[kTileShared + w * 2 * kn + e]);
+        prow[e] = t;
+    }
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kTileWaves; ++w) t += s_loss[w];
+        prow[2 * kn] = t;
+    }
+}
+
 // float64 never takes the few-lanes-per-pair kernel (`lanes` is false for it);
 // this overload only lets run<double> compile.
 inline void launch_lanes(const PartialArgs<double>&, bool, int, int, int64_t, hipStream_t) {}
@@ -1098,20 +1419,44 @@ inline void launch_lanes(const PartialArgs<float>& p, bool eq8, int k, int n, in
         launch_lanes_n<81>(p, eq8, k, rows, st);
 }
 
+// float64 never takes the tile kernel; this overload only lets run<double> compile.
+inline void launch_tiles(const PartialArgs<double>&, bool, int, int64_t, hipStream_t) {}
+
+inline void launch_tiles(const PartialArgs<float>& p, bool eq8, int k, int64_t rows, hipStream_t st) {
+    const dim3 grid(static_cast<uint32_t>(rows)), block(kTileThreads);
+    const size_t lds = tile_lds_bytes();
+    if (k == 6) {
+        if (eq8) hipLaunchKernelGGL((codec_tile_kernel<true, 6>), grid, block, lds, st, p);
+        else hipLaunchKernelGGL((codec_tile_kernel<false, 6>), grid, block, lds, st, p);
+    } else {
+        if (eq8) hipLaunchKernelGGL((codec_tile_kernel<true, 9>), grid, block, lds, st, p);
+        else hipLaunchKernelGGL((codec_tile_kernel<false, 9>), grid, block, lds, st, p);
+    }
+}
+
 // Pairs per workgroup of the few-lanes-per-pair kernel for n (31 or 81).
 inline int64_t lane_pairs(int n) { return n == 31 ? LaneDims<31>::PAIRS : LaneDims<81>::PAIRS; }
 
 // float32 at n = 31 or 81 with k = 6 or 9 takes the few-lanes-per-pair
 // kernel (one partial row per 256 or 64 pairs), which stages softplus(Wt)
 // itself
+// float32 at n = 81 with k = 6 or 9 takes the matrix-core tile kernel
+template <typename F>
+bool takes_tiles(int k, int n) {
+    return std::is_same<F, float>::value && n == kTileNS && (k == 6 || k == 9);
+}
+
 template <typename F>
 bool takes_lanes(int k, int n) {
-    return std::is_same<F, float>::value && (n == 31 || n == 81) && (k == 6 || k == 9);
+    return std::is_same<F, float>::value && (n == 31 || n == 81) && (k == 6 || k == 9) && !takes_tiles<F>(k, n);
 }
+
+constexpr int64_t kTileGrid = 256;   // workgroups of the tile kernel (one per CU)
 
 // Partial rows (workgroups of the partials kernel) of a step.
 template <typename F>
 int64_t step_rows(const hc_codec_args& a) {
+    if (takes_tiles<F>(a.k, a.n)) return std::min<int64_t>(ceil_div(ceil_div(a.N, 16), kTileWaves), kTileGrid);
     return takes_lanes<F>(a.k, a.n) ? std::min<int64_t>(ceil_div(a.N, lane_pairs(a.n)), kMaxRows)
                                     : plan(a.k, a.n, a.N, sizeof(F), a.objective).grid;
 }
@@ -1130,12 +1475,13 @@ hc_status run(const hc_codec_args& a) {
     hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
     const bool eq8 = a.objective == HC_CODEC_EQ8;
     const Plan pl = plan(k, n, a.N, sizeof(F), a.objective);
+    const bool tiles = takes_tiles<F>(k, n);
     const bool lanes = takes_lanes<F>(k, n);
     const int64_t rows = step_rows<F>(a);
     Workspace ws = carve(a.workspace, k, n, rows, sizeof(F));
     int64_t* adam_step = a.adam ? a.adam->step : nullptr;
     hc_status s = HC_OK;
-    if (!lanes && !pl.ed_in_lds) {
+    if (!lanes && !tiles && !pl.ed_in_lds) {
         // the partials kernel reads E and D from the workspace
         const int g0 = int(ceil_div(kn, kThreads));
         hipLaunchKernelGGL(codec_weights_kernel<F>, dim3(g0), dim3(kThreads), 0, st,
@@ -1174,7 +1520,7 @@ hc_status run(const hc_codec_args& a) {
     p.we = static_cast<const F*>(a.Wt_E);
     p.wd = static_cast<const F*>(a.Wt_D);
     p.beta = F(a.beta);
-    p.step = (lanes || pl.ed_in_lds) ? adam_step : nullptr;
+    p.step = (lanes || tiles || pl.ed_in_lds) ? adam_step : nullptr;
     p.ws_step = ws.step;
     p.T = static_cast<const F*>(a.T);
     p.w_e2e = a.w_e2e;
@@ -1182,7 +1528,9 @@ hc_status run(const hc_codec_args& a) {
     p.w_code = a.w_code;
     p.w_col = a.w_col;
     p.eps = a.cos_eps;
-    if (lanes)
+    if (tiles)
+        launch_tiles(p, eq8, k, rows, st);
+    else if (lanes)
         launch_lanes(p, eq8, k, n, rows, st);
     else if (eq8)
         hipLaunchKernelGGL(codec_partials_eq8_kernel<F>, dim3(uint32_t(pl.grid)), dim3(kThreads), pl.lds,
