@@ -1110,13 +1110,25 @@ constexpr int kTileShared = 16 * kTileRS + kTileRS * kTileCS + 3 * kTileRS;   //
 
 size_t tile_lds_bytes() { return sizeof(float) * (size_t(kTileShared) + size_t(kTileWaves) * kTilePerWave); }
 
-// 16-lane row sum (lanes n = 0..15 of one quarter), the same in every lane
+// 16-lane row sum (lanes n = 0..15 of one quarter) by data-parallel
+// primitives within the row: the xor-1 and xor-2 partners, then lane 7 - i of
+// the eight, then lane 15 - i of the sixteen.  Each step adds two equal-sized
+// partial sums in either order, so every lane of the row ends with the same
+// value.
 __device__ __forceinline__ float row16_sum(float x) {
-    x += __shfl_xor(x, 1, kWave);
-    x += __shfl_xor(x, 2, kWave);
-    x += __shfl_xor(x, 4, kWave);
-    x += __shfl_xor(x, 8, kWave);
+    x = x + dpp<0xB1>(x);                     // quad_perm 1,0,3,2
+    x = x + dpp<0x4E>(x);                     // quad_perm 2,3,0,1
+    x = x + dpp<0x141>(x);                    // row_half_mirror
+    x = x + dpp<0x140>(x);                    // row_mirror
     return x;
+}
+
+// The value of quad lane Q (0..3), in every lane of each quad.
+template <int Q>
+__device__ __forceinline__ float quad_bcast(float x) { return dpp<Q * 0x55>(x); }
+
+__device__ __forceinline__ float pick4(const float (&v)[4], int r) {
+    return r == 0 ? v[0] : r == 1 ? v[1] : r == 2 ? v[2] : v[3];
 }
 
 template <bool EQ8, int K>
@@ -1229,32 +1241,40 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
             ct[r] = dc;                               // kept for g_h
         }
         wave_lds_order();
-        // ---- reconstructions and residuals per 16-sample block
+        // ---- reconstructions and residuals per 16-sample block; r_a' and r_b'
+        // go to their tiles at once, t = a*b and S are kept for g_3
         float s_rr[4] = {0.f, 0.f, 0.f, 0.f}, s_rh[4] = {0.f, 0.f, 0.f, 0.f}, s_st[4] = {0.f, 0.f, 0.f, 0.f};
         float s_ss[4] = {0.f, 0.f, 0.f, 0.f}, s_tt[4] = {0.f, 0.f, 0.f, 0.f};
         float s_c0[4] = {0.f, 0.f, 0.f, 0.f}, s_c1[4] = {0.f, 0.f, 0.f, 0.f}, s_c2[4] = {0.f, 0.f, 0.f, 0.f};
-        hc_mf4 ra[NB], rb[NB], sh[NB];
+        hc_mf4 sh[NB];
+        float tv[NB][4];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            ra[b] = rb[b] = sh[b] = hc_mf4{0.f, 0.f, 0.f, 0.f};
+            hc_mf4 ra = {0.f, 0.f, 0.f, 0.f}, rb = ra;
+            sh[b] = ra;
             const int i = 16 * b + n;                 // the lane's sample of the block
 #pragma unroll
             for (int st = 0; st < KC; ++st) {
                 const int j = 4 * st + g;
                 const float d = i < NS ? sD[i * CS + j] : 0.f;
-                ra[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CU[n * CS + j], d, ra[b], 0, 0, 0);
-                rb[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CV[n * CS + j], d, rb[b], 0, 0, 0);
+                ra = __builtin_amdgcn_mfma_f32_16x16x4f32(CU[n * CS + j], d, ra, 0, 0, 0);
+                rb = __builtin_amdgcn_mfma_f32_16x16x4f32(CV[n * CS + j], d, rb, 0, 0, 0);
                 sh[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CH[n * CS + j], d, sh[b], 0, 0, 0);
             }
+            const bool in = i < NS;
+            const float t0 = EQ8 && in ? sT[i] : 0.f, t1 = EQ8 && in ? sT[RS + i] : 0.f;
+            const float t2 = EQ8 && in ? sT[2 * RS + i] : 0.f;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int p = 4 * g + r;
-                const bool in = i < NS;
                 const float av = in ? XA[p * RS + i] : 0.f, bv = in ? XB[p * RS + i] : 0.f;
                 const float ti = av * bv;
-                const float rai = ra[b][r] - av, rbi = rb[b][r] - bv, rh = sh[b][r] - ti;
-                ra[b][r] = rai;
-                rb[b][r] = rbi;
+                const float rai = ra[r] - av, rbi = rb[r] - bv, rh = sh[b][r] - ti;
+                tv[b][r] = ti;
+                if (i < RS) {
+                    R1[p * RS + i] = in ? wr * rai : 0.f;
+                    R2[p * RS + i] = in ? wr * rbi : 0.f;
+                }
                 s_rr[r] = fmaf(rai, rai, fmaf(rbi, rbi, s_rr[r]));
                 s_rh[r] = fmaf(rh, rh, s_rh[r]);
                 if (EQ8) {
@@ -1262,59 +1282,82 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
                     s_st[r] = fmaf(si, ti, s_st[r]);
                     s_ss[r] = fmaf(si, si, s_ss[r]);
                     s_tt[r] = fmaf(ti, ti, s_tt[r]);
-                    const float t0 = in ? sT[i] : 0.f, t1 = in ? sT[RS + i] : 0.f, t2 = in ? sT[2 * RS + i] : 0.f;
                     s_c0[r] = fmaf(t0, rh, s_c0[r]);
                     s_c1[r] = fmaf(t1, rh, s_c1[r]);
                     s_c2[r] = fmaf(t2, rh, s_c2[r]);
                 }
             }
         }
-        // per-pair sums across the 16 lanes of the row, then the per-pair factors
-        float al[4], bt[4], bs[4], gc0[4], gc1[4], gc2[4];
+        // per-pair sums across the 16 lanes of the row; lane n then takes the
+        // factors of pair 4g + (n & 3) alone, and each quad shares them
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float rr = row16_sum(s_rr[r]), rhh = row16_sum(s_rh[r]);
-            const bool valid = tile * 16 + 4 * g + r < a.N;
+            s_rr[r] = row16_sum(s_rr[r]);
+            s_rh[r] = row16_sum(s_rh[r]);
             if (EQ8) {
-                const float st_ = row16_sum(s_st[r]), ss = row16_sum(s_ss[r]), tt = row16_sum(s_tt[r]);
-                const float c0 = row16_sum(s_c0[r]), c1 = row16_sum(s_c1[r]), c2 = row16_sum(s_c2[r]);
-                const double M = double(rhh) / NS;
+                s_st[r] = row16_sum(s_st[r]);
+                s_ss[r] = row16_sum(s_ss[r]);
+                s_tt[r] = row16_sum(s_tt[r]);
+                s_c0[r] = row16_sum(s_c0[r]);
+                s_c1[r] = row16_sum(s_c1[r]);
+                s_c2[r] = row16_sum(s_c2[r]);
+            }
+        }
+        const int rq = n & 3;
+        const bool own = n < 4 && tile * 16 + 4 * g + rq < a.N;    // one lane adds each pair's loss
+        float f_al, f_bt = 0.f, f_bs = 0.f, f_c0 = 0.f, f_c1 = 0.f, f_c2 = 0.f;
+        {
+            const float rr = pick4(s_rr, rq), rhh = pick4(s_rh, rq);
+            if (EQ8) {
+                const float st_ = pick4(s_st, rq), ss = pick4(s_ss, rq), tt = pick4(s_tt, rq);
+                const float c0 = pick4(s_c0, rq), c1 = pick4(s_c1, rq), c2 = pick4(s_c2, rq);
+                const float dd = pick4(s_dd, rq);
+                const double M = double(rhh) * (1.0 / NS);
                 const double sn = sqrt(double(ss));
                 const double ns = sn > a.eps ? sn : a.eps;
                 const double tn = sqrt(double(tt));
                 const double nt = tn > a.eps ? tn : a.eps;
-                const double cs = double(st_) / (ns * nt);
-                if (valid && n == 0)
-                    loss_acc += a.w_e2e * M * (2.0 - cs) + a.w_rec * double(rr) / NS +
-                                a.w_code * double(s_dd[r]) / K +
-                                a.w_col * (double(c0) * c0 + double(c1) * c1 + double(c2) * c2) / 3.0;
-                al[r] = float(a.w_e2e * (2.0 - cs) * 2.0 / NS);
-                bt[r] = float(a.w_e2e * M / (ns * nt));
-                bs[r] = float(sn > a.eps ? a.w_e2e * M * cs / double(ss) : 0.0);
-                gc0[r] = float(a.w_col * (2.0 / 3.0) * c0);
-                gc1[r] = float(a.w_col * (2.0 / 3.0) * c1);
-                gc2[r] = float(a.w_col * (2.0 / 3.0) * c2);
+                const double inv_nn = 1.0 / (ns * nt);
+                const double cs = double(st_) * inv_nn;
+                if (own)
+                    loss_acc += a.w_e2e * M * (2.0 - cs) + a.w_rec * double(rr) * (1.0 / NS) +
+                                a.w_code * double(dd) * (1.0 / K) +
+                                a.w_col * (double(c0) * c0 + double(c1) * c1 + double(c2) * c2) * (1.0 / 3.0);
+                f_al = float(a.w_e2e * (2.0 - cs) * (2.0 / NS));
+                f_bt = float(a.w_e2e * M * inv_nn);
+                f_bs = float(sn > a.eps ? a.w_e2e * M * cs / double(ss) : 0.0);
+                f_c0 = float(a.w_col * (2.0 / 3.0) * c0);
+                f_c1 = float(a.w_col * (2.0 / 3.0) * c1);
+                f_c2 = float(a.w_col * (2.0 / 3.0) * c2);
             } else {
-                if (valid && n == 0) loss_acc += double(rr) + double(lam) * double(rhh);
-                al[r] = lam;
-                bt[r] = bs[r] = gc0[r] = gc1[r] = gc2[r] = 0.f;
+                if (own) loss_acc += double(rr) + double(lam) * double(rhh);
+                f_al = lam;
             }
         }
-        // g_3 and the scaled residuals as [pair][sample] tiles
+        // g_3 as a [pair][sample] tile
+        const float al[4] = {quad_bcast<0>(f_al), quad_bcast<1>(f_al), quad_bcast<2>(f_al), quad_bcast<3>(f_al)};
+        float bt[4] = {0.f, 0.f, 0.f, 0.f}, bs[4] = {0.f, 0.f, 0.f, 0.f};
+        float gc0[4] = {0.f, 0.f, 0.f, 0.f}, gc1[4] = {0.f, 0.f, 0.f, 0.f}, gc2[4] = {0.f, 0.f, 0.f, 0.f};
+        if (EQ8) {
+            bt[0] = quad_bcast<0>(f_bt); bt[1] = quad_bcast<1>(f_bt); bt[2] = quad_bcast<2>(f_bt); bt[3] = quad_bcast<3>(f_bt);
+            bs[0] = quad_bcast<0>(f_bs); bs[1] = quad_bcast<1>(f_bs); bs[2] = quad_bcast<2>(f_bs); bs[3] = quad_bcast<3>(f_bs);
+            gc0[0] = quad_bcast<0>(f_c0); gc0[1] = quad_bcast<1>(f_c0); gc0[2] = quad_bcast<2>(f_c0); gc0[3] = quad_bcast<3>(f_c0);
+            gc1[0] = quad_bcast<0>(f_c1); gc1[1] = quad_bcast<1>(f_c1); gc1[2] = quad_bcast<2>(f_c1); gc1[3] = quad_bcast<3>(f_c1);
+            gc2[0] = quad_bcast<0>(f_c2); gc2[1] = quad_bcast<1>(f_c2); gc2[2] = quad_bcast<2>(f_c2); gc2[3] = quad_bcast<3>(f_c2);
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int i = 16 * b + n;
             if (i < RS) {
                 const bool in = i < NS;
+                const float t0 = EQ8 && in ? sT[i] : 0.f, t1 = EQ8 && in ? sT[RS + i] : 0.f;
+                const float t2 = EQ8 && in ? sT[2 * RS + i] : 0.f;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int p = 4 * g + r;
-                    const float av = in ? XA[p * RS + i] : 0.f, bv = in ? XB[p * RS + i] : 0.f;
-                    const float ti = av * bv, si = sh[b][r];
+                    const float ti = tv[b][r], si = sh[b][r];
                     float g3 = al[r] * (si - ti) - bt[r] * ti + bs[r] * si;
-                    if (EQ8 && in) g3 += gc0[r] * sT[i] + gc1[r] * sT[RS + i] + gc2[r] * sT[2 * RS + i];
-                    R1[p * RS + i] = in ? wr * ra[b][r] : 0.f;
-                    R2[p * RS + i] = in ? wr * rb[b][r] : 0.f;
+                    if (EQ8) g3 += gc0[r] * t0 + gc1[r] * t1 + gc2[r] * t2;
                     R3[p * RS + i] = in ? g3 : 0.f;
                 }
             }
