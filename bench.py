@@ -347,13 +347,14 @@ CODEC_STEPS_PER_GRAPH = 8   # fit steps (codec, upsampler) recorded in one HIP g
 
 
 def codec_only(args):
-    """--codec-steps graph-replayed codec steps of each objective (n = 31,
-    k = args.k, batch 65,536, pools of 2^20): the step time alone."""
+    """--codec-steps graph-replayed codec steps of each objective (n =
+    args.codec_n, k = args.k, batch 65,536, pools of 2^20): the step time
+    alone."""
     import numpy as np
     import torch
     import synth
     from paper_2602_18741_amd.codec_fit import CodecFit
-    n, k = 31, args.k
+    n, k = args.codec_n, args.k
     pa, pb = synth.workloads.codec_pools(n, 1 << 20)
     pa, pb = torch.from_numpy(pa).cuda(), torch.from_numpy(pb).cuda()
     we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
@@ -521,6 +522,8 @@ def main():
     ap.add_argument("--codec-steps", type=int, default=20000,
                     help="Adam steps of the codec fit (the step time and the loss after 2,000 "
                          "steps, the fitting recipe's length, are reported as well)")
+    ap.add_argument("--codec-n", type=int, default=31, choices=[31, 81],
+                    help="samples per spectrum of the --only codec run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-upsample", action="store_true")

@@ -960,25 +960,34 @@ struct FinishArgs {
     int adam;
 };
 
+// One workgroup per 64 consecutive elements of the partial rows (lane l of
+// every wavefront holds element 64 * block + l, so each row load is one
+// coalesced 512-byte piece); its 16 wavefronts take every 16th row, eight
+// loads in flight per lane, and their sums are added in wavefront order
+// through LDS.  Wavefront 0 then applies the step to its 64 elements.
+constexpr int kFinishWaves = 16;
+constexpr int kFinishThreads = kFinishWaves * kWave;
+
 template <typename F>
-__global__ __launch_bounds__(kThreads) void codec_finish_kernel(FinishArgs<F> a) {
+__global__ __launch_bounds__(kFinishThreads) void codec_finish_kernel(FinishArgs<F> a) {
+    __shared__ double s_part[kFinishWaves][kWave];
     const int kn = a.k * a.n;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int e = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int e = blockIdx.x * kWave + lane;
     // the incremented step reaches the counter only now, after the pair draw
     // of this step has read it
-    if (a.adam && e == 0 && lane == 0) *a.step = *a.ws_step;
-    if (e > 2 * kn) return;
+    if (a.adam && blockIdx.x == 0 && threadIdx.x == 0) *a.step = *a.ws_step;
     const int64_t stride = 2 * kn + 1;
+    const bool live = e <= 2 * kn;
     const bool isE = e < kn;
     const int idx = isE ? e : e - kn;
     F* w = isE ? a.we : a.wd;
     F* m = isE ? a.m_e : a.m_d;
     F* v = isE ? a.v_e : a.v_d;
-    // lane 0's parameter, Adam state and step are fetched with the partial
-    // rows, so their latency overlaps that of the sums
+    // wavefront 0's parameters, Adam state and step are fetched with the
+    // partial rows, so their latency overlaps that of the sums
     double wt = 0.0, m0 = 0.0, v0 = 0.0, t = 0.0;
-    if (lane == 0 && e < 2 * kn) {
+    if (wave == 0 && e < 2 * kn) {
         wt = double(w[idx]);
         if (a.adam) {
             m0 = double(m[idx]);
@@ -986,26 +995,27 @@ __global__ __launch_bounds__(kThreads) void codec_finish_kernel(FinishArgs<F> a)
             t = double(*a.ws_step);
         }
     }
-    // eight interleaved partial sums per lane keep eight row loads in flight
-    // (the rows of one element are a column: every load is its own line);
     // rows past the table add 0
     constexpr int kIlp = 8;
     double acc[kIlp];
 #pragma unroll
     for (int u = 0; u < kIlp; ++u) acc[u] = 0.0;
-    for (int r0 = lane; r0 < a.rows; r0 += kIlp * kWave) {
+    for (int r0 = wave; r0 < a.rows; r0 += kIlp * kFinishWaves) {
         double x[kIlp];
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) {
-            const int r = r0 + u * kWave;
-            x[u] = r < a.rows ? a.part[int64_t(r) * stride + e] : 0.0;
+            const int r = r0 + u * kFinishWaves;
+            x[u] = live && r < a.rows ? a.part[int64_t(r) * stride + e] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) acc[u] += x[u];
     }
-    double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    for (int mm = kWave / 2; mm >= 1; mm >>= 1) s += __shfl_xor(s, mm, kWave);
-    if (lane != 0) return;
+    s_part[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    if (wave != 0 || !live) return;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kFinishWaves; ++q) s += s_part[q][lane];
     if (e == 2 * kn) {
         *a.loss = F(s * a.inv_n);
         return;
@@ -1078,35 +1088,48 @@ Workspace carve(void* ws, int k, int n, int64_t rows, size_t esz) {
 // ------------------------------------------------------------------ kernel 2, matrix-core tiles
 //
 // Float32 step for n = 81 with k <= 16: every product of the step is a
-// 16x16x4 fp32 MFMA on tiles of 16 pairs, one wavefront per tile (four per
-// workgroup, each with its own LDS tiles; no workgroup barrier inside the
-// loop).  Per tile, with the pairs' rows a, b in LDS as [pair][sample]:
-//   codes        U = A E^T, V = B E^T, Tc = (A*B) E^T (pairs x codes, K = n);
-//                H = U*V, Dc = H - Tc (Eq. 8's code term);
-//   residuals    A_hat = U D^T, B_hat = V D^T, S = H D^T (pairs x samples, K = k)
-//                minus a, b and t = a*b, summed per pair across the lanes of a
-//                16-lane row for the loss and the per-pair factors; the
-//                gradient g_3 with respect to the decoded product (Eq. 8: the
-//                cosine-scaled error, the colour term through T) and the scaled
-//                r_a', r_b' are written back as [pair][sample] tiles;
-//   code grads   D^T g_3, D^T r_a', D^T r_b' (pairs x codes, K = n), then
-//                g_u = D^T r_a' + g_h v and g_v = D^T r_b' + g_h u;
-//   weight grads dD += r_a'^T U + r_b'^T V + g_3^T H (samples x codes, K = the
-//                tile's pairs), dE += g_u^T A + g_v^T B - w Dc^T (A*B) (codes x
-//                samples), accumulated in registers across tiles.
-// The wavefronts' sums are added in a fixed order into one float64 partial
-// row per workgroup.  Rows are read with a stride of 84 floats (samples 81-83
-// zero, reads past 84 masked), conflict-free for the 16 rows x 4 columns of a
-// forward operand.
+// 16x16x4 fp32 MFMA on tiles of 16 pairs, one wavefront per tile, eight
+// wavefronts per workgroup (two per SIMD, so that one wavefront's matrix
+// products overlap the other's LDS and vector work; no workgroup barrier
+// inside the loop).  Per tile, with the pairs' spectra a, b in LDS as
+// [pair][sample]:
+//   codes        U = A E^T, V = B E^T, Tc = (A*B) E^T and P_a = A D,
+//                P_b = B D, P_t = (A*B) D (pairs x codes, K = samples, one
+//                pass over the spectra); H = U*V, Dc = H - Tc (Eq. 8's code
+//                term);
+//   residuals    A_hat = U D^T, B_hat = V D^T, S = H D^T (pairs x samples,
+//                K = codes) minus a, b and t = a*b, summed per pair across
+//                the lanes of a 16-lane row for the loss and the per-pair
+//                factors of g_3, the gradient with respect to the decoded
+//                product (Eq. 8: the cosine-scaled error, the colour term
+//                through T);
+//   code grads   with G = D^T D (k x k) the code-space gradients need no
+//                pass over the samples: D^T r_a = U G - P_a, D^T r_b =
+//                V G - P_b, D^T g_3 = al (H G - P_t) - bt P_t + bs H G +
+//                sum_c gc_c (T_c D); then g_u = D^T r_a' + g_h v and
+//                g_v = D^T r_b' + g_h u;
+//   weight grads dD^T += U^T r_a' + V^T r_b' + H^T g_3 and dE += g_u^T A +
+//                g_v^T B - w Dc^T (A*B) (codes x samples, K = the tile's
+//                pairs), accumulated in registers across tiles.
+// The contractions over the tile's pairs take both operands from registers:
+// an MFMA output holds pair 4g + r of lane (g, n) in register r, which is
+// the K index g of the product's r-th step.  So the residuals and the
+// code-space gradients never pass through LDS; per wavefront LDS holds a,
+// b and the [pair][code] tiles of U, V, H that the K = codes products read
+// transposed.  The wavefronts' sums are added in a fixed order into one
+// float64 partial row per workgroup.  Rows are read with a stride of 84
+// floats (samples 81-83 zero, reads past 84 masked), conflict-free for the
+// 16 rows x 4 columns of a forward operand.
 constexpr int kTileNS = 81;                 // samples
 constexpr int kTileRS = 84;                 // LDS row stride of [pair][sample] tiles
 constexpr int kTileKS = kTileRS / 4;        // K steps over the samples (21)
 constexpr int kTileNB = 6;                  // 16-sample blocks (96 >= 81)
-constexpr int kTileCS = 17;                 // row stride of [pair][code] tiles
-constexpr int kTileWaves = 4;
+constexpr int kTileCS = 17;                 // row stride of [pair][code] and [code][code] tiles
+constexpr int kTileWaves = 8;
 constexpr int kTileThreads = kTileWaves * kWave;
-constexpr int kTilePerWave = 5 * 16 * kTileRS + 6 * 16 * kTileCS;   // XA XB R1 R2 R3, U V H Dc GU GV
-constexpr int kTileShared = 16 * kTileRS + kTileRS * kTileCS + 3 * kTileRS;   // E, D, T
+constexpr int kTilePerWave = 2 * 16 * kTileRS + 3 * 16 * kTileCS;   // a, b; U, V, H
+// E [16][RS], D [RS][CS], T [3][RS], G [16][CS], T D [3][16]
+constexpr int kTileShared = 16 * kTileRS + kTileRS * kTileCS + 3 * kTileRS + 16 * kTileCS + 3 * 16;
 
 size_t tile_lds_bytes() { return sizeof(float) * (size_t(kTileShared) + size_t(kTileWaves) * kTilePerWave); }
 
@@ -1125,10 +1148,23 @@ __device__ __forceinline__ float row16_sum(float x) {
 
 // The value of quad lane Q (0..3), in every lane of each quad.
 template <int Q>
-__device__ __forceinline__ float quad_bcast(float x) { return dpp<Q * 0x55>(x); }
+__device__ __forceinline__ float quad_bcast(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), Q * 0x55, 0xF, 0xF, true));
+}
 
+// v[r] by selects on values (an index into the array would place it in
+// private memory)
 __device__ __forceinline__ float pick4(const float (&v)[4], int r) {
-    return r == 0 ? v[0] : r == 1 ? v[1] : r == 2 ? v[2] : v[3];
+    const float x0 = v[0], x1 = v[1], x2 = v[2], x3 = v[3];
+    const float lo = (r & 1) ? x1 : x0, hi = (r & 1) ? x3 : x2;
+    return (r & 2) ? hi : lo;
+}
+
+__device__ __forceinline__ void quad_bcast4(float x, float (&v)[4]) {
+    v[0] = quad_bcast<0>(x);
+    v[1] = quad_bcast<1>(x);
+    v[2] = quad_bcast<2>(x);
+    v[3] = quad_bcast<3>(x);
 }
 
 template <bool EQ8, int K>
@@ -1140,20 +1176,15 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
     float* sE = tsm;                                  // [16 codes][RS], rows >= K zero
     float* sD = sE + 16 * RS;                         // [RS samples][CS], rows >= n and columns >= K zero
     float* sT = sD + RS * CS;                         // [3][RS]
+    float* sG = sT + 3 * RS;                          // [16][CS]: G = D^T D
+    float* sTD = sG + 16 * CS;                        // [3][16]: T D
     const int tid = threadIdx.x;
     const int wave = tid / kWave, lane = tid & (kWave - 1), g = lane >> 4, n = lane & 15;
-    float* W = tsm + kTileShared + wave * kTilePerWave;
-    float* XA = W;
+    float* XA = tsm + kTileShared + wave * kTilePerWave;
     float* XB = XA + 16 * RS;
-    float* R1 = XB + 16 * RS;                         // r_a' (scaled residual of a)
-    float* R2 = R1 + 16 * RS;                         // r_b'
-    float* R3 = R2 + 16 * RS;                         // g_3
-    float* CU = R3 + 16 * RS;                         // [pair][code] tiles
+    float* CU = XB + 16 * RS;                         // [pair][code] tiles
     float* CV = CU + 16 * CS;
     float* CH = CV + 16 * CS;
-    float* CDc = CH + 16 * CS;                        // -w_code (2/k) (h - E t), the third dE coefficient
-    float* CGU = CDc + 16 * CS;
-    float* CGV = CGU + 16 * CS;
 
     for (int e = tid; e < 16 * RS; e += kTileThreads) {
         const int j = e / RS, i = e % RS;
@@ -1164,19 +1195,33 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
         sD[e] = (i < NS && j < K) ? softplus(a.wd[i * K + j], a.beta) : 0.f;
     }
     for (int e = tid; e < 3 * RS; e += kTileThreads) sT[e] = (EQ8 && e % RS < NS) ? a.T[(e / RS) * NS + e % RS] : 0.f;
-    // samples 81..83 of the pair tiles stay zero
-    for (int e = lane; e < 5 * 16 * (RS - NS); e += kWave) {
+    // samples 81..83 of the row tiles stay zero
+    for (int e = lane; e < 2 * 16 * (RS - NS); e += kWave) {
         const int t = e / (16 * (RS - NS)), p = (e / (RS - NS)) % 16, i = NS + e % (RS - NS);
-        W[t * 16 * RS + p * RS + i] = 0.f;
+        XA[t * 16 * RS + p * RS + i] = 0.f;
     }
     if (a.step && blockIdx.x == 0 && tid == 0) *a.ws_step = *a.step + 1;
+    __syncthreads();
+    // G = D^T D and T D: each entry one thread's sum over the samples in order
+    if (tid < 256) {
+        const int j = tid >> 4, j2 = tid & 15;
+        float s = 0.f;
+        for (int i = 0; i < NS; ++i) s = fmaf(sD[i * CS + j], sD[i * CS + j2], s);
+        sG[j * CS + j2] = s;
+    } else if (tid < 256 + 48) {
+        const int c = (tid - 256) >> 4, j = tid & 15;
+        float s = 0.f;
+        for (int i = 0; i < NS; ++i) s = fmaf(sT[c * RS + i], sD[i * CS + j], s);
+        sTD[c * 16 + j] = s;
+    }
     __syncthreads();
 
     const uint64_t ctr_base = a.draw ? draw_base(a) : 0ull;
     const float lam = a.lam;
     const float wr = EQ8 ? float(a.w_rec * 2.0 / NS) : 1.f;
     const float wk = EQ8 ? float(a.w_code * 2.0 / K) : 0.f;
-    hc_mf4 accD[NB], accE[NB];
+    const float td0 = EQ8 ? sTD[n] : 0.f, td1 = EQ8 ? sTD[16 + n] : 0.f, td2 = EQ8 ? sTD[32 + n] : 0.f;
+    hc_mf4 accD[NB], accE[NB];                        // dD^T and dE: code 4g + r, sample 16b + n
 #pragma unroll
     for (int b = 0; b < NB; ++b) accD[b] = accE[b] = hc_mf4{0.f, 0.f, 0.f, 0.f};
     double loss_acc = 0.0;
@@ -1186,8 +1231,8 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
     constexpr int PER = (NS + 3) / 4;                 // 21 samples per lane and row
     const int64_t tiles = (a.N + 15) / 16;
     const int64_t tstride = int64_t(gridDim.x) * kTileWaves;
-    // the rows of a tile (pairs past N read zeros); loaded one tile ahead, so
-    // they are in flight while the current tile computes
+    // the rows of a tile (pairs past N read zeros); the next tile's are
+    // loaded during the current tile's last phase
     float va[PER], vb[PER];
     auto load_rows = [&](int64_t t) {
         const int64_t pi = t * 16 + lp;
@@ -1213,21 +1258,22 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
                 XB[lp * RS + i] = vb[u];
             }
         }
-        load_rows(tile + tstride);
         wave_lds_order();
-        // ---- codes: U, V, Tc (pairs x codes), K = samples
-        hc_mf4 cu = {0.f, 0.f, 0.f, 0.f}, cv = cu, ct = cu;
-#pragma unroll
+        // ---- codes and the spectra's projections on D (pairs x codes), K = samples
+        hc_mf4 cu = {0.f, 0.f, 0.f, 0.f}, cv = cu, ct = cu, pa = cu, pb = cu, pt = cu;
+#pragma unroll 3
         for (int st = 0; st < KS; ++st) {
             const int i = 4 * st + g;
-            const float e = sE[n * RS + i];
-            const float xa = XA[n * RS + i], xb = XB[n * RS + i];
+            const float e = sE[n * RS + i], d = sD[i * CS + n];
+            const float xa = XA[n * RS + i], xb = XB[n * RS + i], xt = xa * xb;
             cu = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, e, cu, 0, 0, 0);
             cv = __builtin_amdgcn_mfma_f32_16x16x4f32(xb, e, cv, 0, 0, 0);
-            if (EQ8) ct = __builtin_amdgcn_mfma_f32_16x16x4f32(xa * xb, e, ct, 0, 0, 0);
+            if (EQ8) ct = __builtin_amdgcn_mfma_f32_16x16x4f32(xt, e, ct, 0, 0, 0);
+            pa = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, d, pa, 0, 0, 0);
+            pb = __builtin_amdgcn_mfma_f32_16x16x4f32(xb, d, pb, 0, 0, 0);
+            pt = __builtin_amdgcn_mfma_f32_16x16x4f32(xt, d, pt, 0, 0, 0);
         }
-        // lane (g, n): pairs 4g + r, code n
-        float s_dd[4];
+        // lane (g, n): pairs 4g + r, code n; the code term's loss is added here
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int p = 4 * g + r;
@@ -1236,170 +1282,190 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
             CU[p * CS + n] = cu[r];
             CV[p * CS + n] = cv[r];
             CH[p * CS + n] = h;
-            CDc[p * CS + n] = -wk * dc;
-            s_dd[r] = row16_sum(n < K ? dc * dc : 0.f);
+            if (EQ8) {
+                const float dd = row16_sum(n < K ? dc * dc : 0.f);
+                if (n == 0 && tile * 16 + p < a.N) loss_acc += a.w_code * double(dd) * (1.0 / K);
+            }
             ct[r] = dc;                               // kept for g_h
         }
         wave_lds_order();
+        // ---- the codes as [pair n][code 4st + g] operands; U G - P_a, V G - P_b,
+        // H G (pairs x codes, K = codes)
+        float cuT[KC], cvT[KC], chT[KC];
+        hc_mf4 ug = -pa, vg = -pb, hg = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < KC; ++st) {
+            const int j = 4 * st + g;
+            cuT[st] = CU[n * CS + j];
+            cvT[st] = CV[n * CS + j];
+            chT[st] = CH[n * CS + j];
+            const float gv = sG[j * CS + n];
+            ug = __builtin_amdgcn_mfma_f32_16x16x4f32(cuT[st], gv, ug, 0, 0, 0);
+            vg = __builtin_amdgcn_mfma_f32_16x16x4f32(cvT[st], gv, vg, 0, 0, 0);
+            hg = __builtin_amdgcn_mfma_f32_16x16x4f32(chT[st], gv, hg, 0, 0, 0);
+        }
+        // S.S = sum_j H_j (H G)_j and S.t = sum_j H_j (t D)_j per pair (sums of
+        // non-negative terms), for lane n's pair 4g + (n & 3)
+        const int rq = n & 3;
+        float q_ss = 0.f, q_st = 0.f;
+        if (EQ8) {
+            float x_ss[4], x_st[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float h = cu[r] * cv[r];
+                x_ss[r] = row16_sum(h * hg[r]);
+                x_st[r] = row16_sum(h * pt[r]);
+            }
+            q_ss = pick4(x_ss, rq);
+            q_st = pick4(x_st, rq);
+        }
         // ---- reconstructions and residuals per 16-sample block; r_a' and r_b'
-        // go to their tiles at once, t = a*b and S are kept for g_3
-        float s_rr[4] = {0.f, 0.f, 0.f, 0.f}, s_rh[4] = {0.f, 0.f, 0.f, 0.f}, s_st[4] = {0.f, 0.f, 0.f, 0.f};
-        float s_ss[4] = {0.f, 0.f, 0.f, 0.f}, s_tt[4] = {0.f, 0.f, 0.f, 0.f};
+        // go straight into dD^T, S is kept for g_3
+        float s_rr[4] = {0.f, 0.f, 0.f, 0.f}, s_rh[4] = {0.f, 0.f, 0.f, 0.f}, s_tt[4] = {0.f, 0.f, 0.f, 0.f};
         float s_c0[4] = {0.f, 0.f, 0.f, 0.f}, s_c1[4] = {0.f, 0.f, 0.f, 0.f}, s_c2[4] = {0.f, 0.f, 0.f, 0.f};
         hc_mf4 sh[NB];
-        float tv[NB][4];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             hc_mf4 ra = {0.f, 0.f, 0.f, 0.f}, rb = ra;
             sh[b] = ra;
             const int i = 16 * b + n;                 // the lane's sample of the block
+            // past the samples, reads land on sample 81, zero in every tile
+            const int ic = i < NS ? i : NS;
 #pragma unroll
             for (int st = 0; st < KC; ++st) {
-                const int j = 4 * st + g;
-                const float d = i < NS ? sD[i * CS + j] : 0.f;
-                ra = __builtin_amdgcn_mfma_f32_16x16x4f32(CU[n * CS + j], d, ra, 0, 0, 0);
-                rb = __builtin_amdgcn_mfma_f32_16x16x4f32(CV[n * CS + j], d, rb, 0, 0, 0);
-                sh[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CH[n * CS + j], d, sh[b], 0, 0, 0);
+                const float d = sD[ic * CS + 4 * st + g];
+                ra = __builtin_amdgcn_mfma_f32_16x16x4f32(cuT[st], d, ra, 0, 0, 0);
+                rb = __builtin_amdgcn_mfma_f32_16x16x4f32(cvT[st], d, rb, 0, 0, 0);
+                sh[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(chT[st], d, sh[b], 0, 0, 0);
             }
-            const bool in = i < NS;
-            const float t0 = EQ8 && in ? sT[i] : 0.f, t1 = EQ8 && in ? sT[RS + i] : 0.f;
-            const float t2 = EQ8 && in ? sT[2 * RS + i] : 0.f;
+            const float t0 = EQ8 ? sT[ic] : 0.f, t1 = EQ8 ? sT[RS + ic] : 0.f, t2 = EQ8 ? sT[2 * RS + ic] : 0.f;
+            float r1[4], r2[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int p = 4 * g + r;
-                const float av = in ? XA[p * RS + i] : 0.f, bv = in ? XB[p * RS + i] : 0.f;
+                const float av = XA[p * RS + ic], bv = XB[p * RS + ic];
                 const float ti = av * bv;
+                // zero past the samples: the reconstruction and the spectrum both are
                 const float rai = ra[r] - av, rbi = rb[r] - bv, rh = sh[b][r] - ti;
-                tv[b][r] = ti;
-                if (i < RS) {
-                    R1[p * RS + i] = in ? wr * rai : 0.f;
-                    R2[p * RS + i] = in ? wr * rbi : 0.f;
-                }
+                r1[r] = wr * rai;
+                r2[r] = wr * rbi;
                 s_rr[r] = fmaf(rai, rai, fmaf(rbi, rbi, s_rr[r]));
                 s_rh[r] = fmaf(rh, rh, s_rh[r]);
                 if (EQ8) {
-                    const float si = sh[b][r];
-                    s_st[r] = fmaf(si, ti, s_st[r]);
-                    s_ss[r] = fmaf(si, si, s_ss[r]);
                     s_tt[r] = fmaf(ti, ti, s_tt[r]);
                     s_c0[r] = fmaf(t0, rh, s_c0[r]);
                     s_c1[r] = fmaf(t1, rh, s_c1[r]);
                     s_c2[r] = fmaf(t2, rh, s_c2[r]);
                 }
             }
+            // dD^T (codes x the block's samples) += U^T r_a' + V^T r_b', K = pairs
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(cu[r], r1[r], accD[b], 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[r], r2[r], accD[b], 0, 0, 0);
         }
         // per-pair sums across the 16 lanes of the row; lane n then takes the
         // factors of pair 4g + (n & 3) alone, and each quad shares them
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            s_rr[r] = row16_sum(s_rr[r]);
-            s_rh[r] = row16_sum(s_rh[r]);
-            if (EQ8) {
-                s_st[r] = row16_sum(s_st[r]);
-                s_ss[r] = row16_sum(s_ss[r]);
-                s_tt[r] = row16_sum(s_tt[r]);
-                s_c0[r] = row16_sum(s_c0[r]);
-                s_c1[r] = row16_sum(s_c1[r]);
-                s_c2[r] = row16_sum(s_c2[r]);
-            }
-        }
-        const int rq = n & 3;
-        const bool own = n < 4 && tile * 16 + 4 * g + rq < a.N;    // one lane adds each pair's loss
-        float f_al, f_bt = 0.f, f_bs = 0.f, f_c0 = 0.f, f_c1 = 0.f, f_c2 = 0.f;
+        float rr, rhh, tt = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
         {
-            const float rr = pick4(s_rr, rq), rhh = pick4(s_rh, rq);
+            float x[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x[r] = row16_sum(s_rr[r]);
+            rr = pick4(x, rq);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x[r] = row16_sum(s_rh[r]);
+            rhh = pick4(x, rq);
             if (EQ8) {
-                const float st_ = pick4(s_st, rq), ss = pick4(s_ss, rq), tt = pick4(s_tt, rq);
-                const float c0 = pick4(s_c0, rq), c1 = pick4(s_c1, rq), c2 = pick4(s_c2, rq);
-                const float dd = pick4(s_dd, rq);
-                const double M = double(rhh) * (1.0 / NS);
-                const double sn = sqrt(double(ss));
-                const double ns = sn > a.eps ? sn : a.eps;
-                const double tn = sqrt(double(tt));
-                const double nt = tn > a.eps ? tn : a.eps;
-                const double inv_nn = 1.0 / (ns * nt);
-                const double cs = double(st_) * inv_nn;
-                if (own)
-                    loss_acc += a.w_e2e * M * (2.0 - cs) + a.w_rec * double(rr) * (1.0 / NS) +
-                                a.w_code * double(dd) * (1.0 / K) +
-                                a.w_col * (double(c0) * c0 + double(c1) * c1 + double(c2) * c2) * (1.0 / 3.0);
-                f_al = float(a.w_e2e * (2.0 - cs) * (2.0 / NS));
-                f_bt = float(a.w_e2e * M * inv_nn);
-                f_bs = float(sn > a.eps ? a.w_e2e * M * cs / double(ss) : 0.0);
-                f_c0 = float(a.w_col * (2.0 / 3.0) * c0);
-                f_c1 = float(a.w_col * (2.0 / 3.0) * c1);
-                f_c2 = float(a.w_col * (2.0 / 3.0) * c2);
-            } else {
-                if (own) loss_acc += double(rr) + double(lam) * double(rhh);
-                f_al = lam;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x[r] = row16_sum(s_tt[r]);
+                tt = pick4(x, rq);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x[r] = row16_sum(s_c0[r]);
+                c0 = pick4(x, rq);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x[r] = row16_sum(s_c1[r]);
+                c1 = pick4(x, rq);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x[r] = row16_sum(s_c2[r]);
+                c2 = pick4(x, rq);
             }
         }
-        // g_3 as a [pair][sample] tile
-        const float al[4] = {quad_bcast<0>(f_al), quad_bcast<1>(f_al), quad_bcast<2>(f_al), quad_bcast<3>(f_al)};
-        float bt[4] = {0.f, 0.f, 0.f, 0.f}, bs[4] = {0.f, 0.f, 0.f, 0.f};
-        float gc0[4] = {0.f, 0.f, 0.f, 0.f}, gc1[4] = {0.f, 0.f, 0.f, 0.f}, gc2[4] = {0.f, 0.f, 0.f, 0.f};
+        const bool own = n < 4 && tile * 16 + 4 * g + rq < a.N;    // one lane adds each pair's loss
+        // g_3 = fs S - ft t + sum_c gc_c T_c (fs = al + bs, ft = al + bt)
+        float f_s, f_t, f_c0 = 0.f, f_c1 = 0.f, f_c2 = 0.f;
         if (EQ8) {
-            bt[0] = quad_bcast<0>(f_bt); bt[1] = quad_bcast<1>(f_bt); bt[2] = quad_bcast<2>(f_bt); bt[3] = quad_bcast<3>(f_bt);
-            bs[0] = quad_bcast<0>(f_bs); bs[1] = quad_bcast<1>(f_bs); bs[2] = quad_bcast<2>(f_bs); bs[3] = quad_bcast<3>(f_bs);
-            gc0[0] = quad_bcast<0>(f_c0); gc0[1] = quad_bcast<1>(f_c0); gc0[2] = quad_bcast<2>(f_c0); gc0[3] = quad_bcast<3>(f_c0);
-            gc1[0] = quad_bcast<0>(f_c1); gc1[1] = quad_bcast<1>(f_c1); gc1[2] = quad_bcast<2>(f_c1); gc1[3] = quad_bcast<3>(f_c1);
-            gc2[0] = quad_bcast<0>(f_c2); gc2[1] = quad_bcast<1>(f_c2); gc2[2] = quad_bcast<2>(f_c2); gc2[3] = quad_bcast<3>(f_c2);
+            const double M = double(rhh) * (1.0 / NS);
+            const double sn = sqrt(double(q_ss));
+            const double ns = sn > a.eps ? sn : a.eps;
+            const double tn = sqrt(double(tt));
+            const double nt = tn > a.eps ? tn : a.eps;
+            const double inv_nn = 1.0 / (ns * nt);
+            const double cs = double(q_st) * inv_nn;
+            if (own)
+                loss_acc += a.w_e2e * M * (2.0 - cs) + a.w_rec * double(rr) * (1.0 / NS) +
+                            a.w_col * (double(c0) * c0 + double(c1) * c1 + double(c2) * c2) * (1.0 / 3.0);
+            const double al = a.w_e2e * (2.0 - cs) * (2.0 / NS);
+            const double bt = a.w_e2e * M * inv_nn;
+            const double bs = sn > a.eps ? a.w_e2e * M * cs / double(q_ss) : 0.0;
+            f_s = float(al + bs);
+            f_t = float(al + bt);
+            f_c0 = float(a.w_col * (2.0 / 3.0) * c0);
+            f_c1 = float(a.w_col * (2.0 / 3.0) * c1);
+            f_c2 = float(a.w_col * (2.0 / 3.0) * c2);
+        } else {
+            if (own) loss_acc += double(rr) + double(lam) * double(rhh);
+            f_s = f_t = lam;
         }
+        float fs[4], ft[4], gc0[4] = {0.f, 0.f, 0.f, 0.f}, gc1[4] = {0.f, 0.f, 0.f, 0.f};
+        float gc2[4] = {0.f, 0.f, 0.f, 0.f};
+        quad_bcast4(f_s, fs);
+        quad_bcast4(f_t, ft);
+        if (EQ8) {
+            quad_bcast4(f_c0, gc0);
+            quad_bcast4(f_c1, gc1);
+            quad_bcast4(f_c2, gc2);
+        }
+        // ---- code-space gradients (pair 4g + r, code n) through G
+        float cgu[4], cgv[4], cdc[4];
+        {
+            const float td0 = EQ8 ? sTD[n] : 0.f, td1 = EQ8 ? sTD[16 + n] : 0.f, td2 = EQ8 ? sTD[32 + n] : 0.f;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int i = 16 * b + n;
-            if (i < RS) {
-                const bool in = i < NS;
-                const float t0 = EQ8 && in ? sT[i] : 0.f, t1 = EQ8 && in ? sT[RS + i] : 0.f;
-                const float t2 = EQ8 && in ? sT[2 * RS + i] : 0.f;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int p = 4 * g + r;
-                    const float ti = tv[b][r], si = sh[b][r];
-                    float g3 = al[r] * (si - ti) - bt[r] * ti + bs[r] * si;
-                    if (EQ8) g3 += gc0[r] * t0 + gc1[r] * t1 + gc2[r] * t2;
-                    R3[p * RS + i] = in ? g3 : 0.f;
-                }
+            for (int r = 0; r < 4; ++r) {
+                float gh = fs[r] * hg[r] - ft[r] * pt[r];
+                if (EQ8) gh += (gc0[r] * td0 + gc1[r] * td1 + gc2[r] * td2) + wk * ct[r];
+                cgu[r] = wr * ug[r] + gh * cv[r];
+                cgv[r] = wr * vg[r] + gh * cu[r];
+                cdc[r] = -wk * ct[r];
             }
         }
-        wave_lds_order();
-        // ---- code-space gradients: D^T g_3, D^T r_a', D^T r_b' (pairs x codes), K = samples
-        hc_mf4 gh = {0.f, 0.f, 0.f, 0.f}, g1 = gh, g2 = gh;
-#pragma unroll
-        for (int st = 0; st < KS; ++st) {
-            const int i = 4 * st + g;
-            const float d = sD[i * CS + n];
-            gh = __builtin_amdgcn_mfma_f32_16x16x4f32(R3[n * RS + i], d, gh, 0, 0, 0);
-            g1 = __builtin_amdgcn_mfma_f32_16x16x4f32(R1[n * RS + i], d, g1, 0, 0, 0);
-            g2 = __builtin_amdgcn_mfma_f32_16x16x4f32(R2[n * RS + i], d, g2, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int p = 4 * g + r;
-            const float h = gh[r] + (EQ8 ? wk * ct[r] : 0.f);
-            CGU[p * CS + n] = g1[r] + h * cv[r];
-            CGV[p * CS + n] = g2[r] + h * cu[r];
-        }
-        wave_lds_order();
-        // ---- weight gradients over the tile's pairs
+        // ---- g_3 (pair 4g + r, sample 16b + n) into dD^T += H^T g_3
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int i = 16 * b + n;                 // dE: the lane's sample column
+            const int i = 16 * b + n, ic = i < NS ? i : NS;
+            const float t0 = EQ8 ? sT[ic] : 0.f, t1 = EQ8 ? sT[RS + ic] : 0.f, t2 = EQ8 ? sT[2 * RS + ic] : 0.f;
+            float g3[4];                              // zero past the samples: S, t and T all are
 #pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                const int p = 4 * st + g;
-                // dD (samples x codes): rows 16b + m, columns codes
-                const int ir = 16 * b + n;            // A operand: sample row n of block b
-                const bool rin = ir < RS;
-                accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rin ? R1[p * RS + ir] : 0.f, CU[p * CS + n], accD[b], 0, 0, 0);
-                accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rin ? R2[p * RS + ir] : 0.f, CV[p * CS + n], accD[b], 0, 0, 0);
-                accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rin ? R3[p * RS + ir] : 0.f, CH[p * CS + n], accD[b], 0, 0, 0);
-                // dE (codes x samples): rows codes, columns 16b + n
-                const bool cin = i < RS;
-                const float xa = cin ? XA[p * RS + i] : 0.f, xb = cin ? XB[p * RS + i] : 0.f;
-                accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CGU[p * CS + n], xa, accE[b], 0, 0, 0);
-                accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CGV[p * CS + n], xb, accE[b], 0, 0, 0);
-                if (EQ8) accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(CDc[p * CS + n], xa * xb, accE[b], 0, 0, 0);
+            for (int r = 0; r < 4; ++r) {
+                const int p = 4 * g + r;
+                const float ti = XA[p * RS + ic] * XB[p * RS + ic];
+                g3[r] = fs[r] * sh[b][r] - ft[r] * ti;
+                if (EQ8) g3[r] += gc0[r] * t0 + gc1[r] * t1 + gc2[r] * t2;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accD[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(cu[r] * cv[r], g3[r], accD[b], 0, 0, 0);
+        }
+        load_rows(tile + tstride);
+        // ---- dE += g_u^T A + g_v^T B - w Dc^T (A*B), K = the tile's pairs
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = 16 * b + n, ic = i < NS ? i : NS;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = 4 * g + r;
+                const float xa = XA[p * RS + ic], xb = XB[p * RS + ic];
+                accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(cgu[r], xa, accE[b], 0, 0, 0);
+                accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(cgv[r], xb, accE[b], 0, 0, 0);
+                if (EQ8) accE[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(cdc[r], xa * xb, accE[b], 0, 0, 0);
             }
         }
         wave_lds_order();   // the tiles are read before the next tile's rows land
@@ -1417,10 +1483,11 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
     for (int b = 0; b < NB; ++b) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = 16 * b + 4 * g + r, j = n;          // dD element (sample i, code j)
-            if (i < NS && j < K) scr[kn + i * K + j] = accD[b][r];
-            const int j2 = 4 * g + r, i2 = 16 * b + n;        // dE element (code j2, sample i2)
-            if (j2 < K && i2 < NS) scr[j2 * NS + i2] = accE[b][r];
+            const int j = 4 * g + r, i = 16 * b + n;          // code j, sample i
+            if (j < K && i < NS) {
+                scr[j * NS + i] = accE[b][r];
+                scr[kn + i * K + j] = accD[b][r];
+            }
         }
     }
     if (lane == 0) s_loss[wave] = loss_acc;
@@ -1617,8 +1684,8 @@ hc_status run(const hc_codec_args& a) {
     }
     f.ws_step = ws.step;
     f.step = adam_step;
-    const int g2 = int(ceil_div(2 * kn + 1, kThreads / kWave));
-    hipLaunchKernelGGL(codec_finish_kernel<F>, dim3(g2), dim3(kThreads), 0, st, f);
+    const int g2 = int(ceil_div(2 * kn + 1, kWave));
+    hipLaunchKernelGGL(codec_finish_kernel<F>, dim3(g2), dim3(kFinishThreads), 0, st, f);
     return launch_status("hc_codec_step");
 }
 

@@ -12,7 +12,7 @@ import torch
 
 import synth
 from oracle import codec as oc
-from tests.gpu_util import to_np
+from tests.gpu_util import box_codec, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -25,10 +25,12 @@ def ops():
     return o
 
 
-def _grad_ok(g, ref, rel=1e-4):
+def _grad_ok(g, ref, rel=1e-4, scale=None):
     g, ref = np.asarray(g, np.float64), np.asarray(ref, np.float64)
-    floor = 1e-3 * np.abs(ref).max()
-    elem = (np.abs(g - ref) <= rel * np.maximum(np.abs(ref), floor)).all()
+    floor = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    if scale is not None:
+        floor = np.maximum(floor, scale)
+    elem = (np.abs(g - ref) <= rel * floor).all()
     norm = np.linalg.norm(g - ref) <= rel * np.linalg.norm(ref)
     return bool(elem and norm)
 
@@ -55,6 +57,40 @@ def test_loss_and_gradient_fp32(ops, n, k, seed):
     L, rge, rgd = oc.loss_and_grad(we, wd, A, B, 1.0, 10.0)
     assert abs(float(loss) - L) <= 1e-5 * L
     assert _grad_ok(to_np(ge), rge) and _grad_ok(to_np(gd), rgd)
+
+
+def _magnitude(grad_fn, A, B, chunk=16):
+    """Per element, the gradient's sum of magnitudes over chunks of `chunk`
+    pairs: sum_c |N_c g_c| / N, with g_c the oracle's gradient on chunk c.
+    The error of a floating-point sum is bounded by a multiple of the unit
+    round-off times the sum of the magnitudes of its terms, not of the sum."""
+    N = A.shape[0]
+    se = sd = 0.0
+    for c in range(0, N, chunk):
+        _, ge, gd = grad_fn(A[c:c + chunk], B[c:c + chunk])
+        m = A[c:c + chunk].shape[0] / N
+        se, sd = se + m * np.abs(ge), sd + m * np.abs(gd)
+    return se, sd
+
+
+@pytest.mark.parametrize("n,k", [(81, 9), (81, 6), (31, 6)])
+def test_near_fit_fp32(ops, n, k):
+    """A near-fit codec (box filters), where each gradient element is a sum
+    of per-pair terms of both signs much larger than the sum: per element
+    |g - g_ref| <= 1e-4 max(|g_ref|, 1e-3 |g_ref|_inf, m) with m the sum of
+    the terms' magnitudes (over 16-pair chunks), normwise 1e-4."""
+    N = 8192
+    we, wd = (w.astype(np.float32) for w in box_codec(k, n))
+    A, B = _pairs(n, N, 78)
+    ge = torch.empty(k, n, device="cuda")
+    gd = torch.empty(n, k, device="cuda")
+    f32 = lambda x: torch.from_numpy(np.asarray(x, np.float32)).cuda()
+    loss = ops.codec_step(f32(we), f32(wd), f32(A), f32(B), N, grad_e=ge, grad_d=gd)
+    torch.cuda.synchronize()
+    L, rge, rgd = oc.loss_and_grad(we, wd, A, B, 1.0, 10.0)
+    me, md = _magnitude(lambda a, b: oc.loss_and_grad(we, wd, a, b, 1.0, 10.0), A, B)
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert _grad_ok(to_np(ge), rge, scale=me) and _grad_ok(to_np(gd), rgd, scale=md)
 
 
 @pytest.mark.parametrize("seed", range(16))

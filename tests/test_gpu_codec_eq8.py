@@ -12,7 +12,7 @@ import torch
 
 import synth
 from oracle import codec as oc
-from tests.gpu_util import to_np
+from tests.gpu_util import box_codec, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -27,10 +27,12 @@ def ops():
     return o
 
 
-def _grad_ok(g, ref, rel=1e-4):
+def _grad_ok(g, ref, rel=1e-4, scale=None):
     g, ref = np.asarray(g, np.float64), np.asarray(ref, np.float64)
-    floor = 1e-3 * np.abs(ref).max()
-    elem = (np.abs(g - ref) <= rel * np.maximum(np.abs(ref), floor)).all()
+    floor = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    if scale is not None:
+        floor = np.maximum(floor, scale)
+    elem = (np.abs(g - ref) <= rel * floor).all()
     norm = np.linalg.norm(g - ref) <= rel * np.linalg.norm(ref)
     return bool(elem and norm)
 
@@ -61,6 +63,31 @@ def test_eq8_loss_and_gradient_fp32(ops, n, k, seed):
     L, rge, rgd = oc.loss_eq8_and_grad(we, wd, A, B, T, W)
     assert abs(float(loss) - L) <= 1e-5 * L
     assert _grad_ok(to_np(ge), rge) and _grad_ok(to_np(gd), rgd)
+
+
+@pytest.mark.parametrize("n,k", [(81, 9), (81, 6), (31, 6)])
+def test_eq8_near_fit_fp32(ops, n, k):
+    """A near-fit codec (box filters), where each gradient element is a sum
+    of per-pair terms of both signs much larger than the sum: per element
+    |g - g_ref| <= 1e-4 max(|g_ref|, 1e-3 |g_ref|_inf, m) with m the sum of
+    the terms' magnitudes (over 16-pair chunks; the error of a floating-point
+    sum is bounded through the magnitudes of its terms), normwise 1e-4."""
+    N = 8192
+    we, wd = (w.astype(np.float32) for w in box_codec(k, n))
+    A, B = _pairs(n, N, 77)
+    T = synth.cmf_matrix(n)
+    ge = torch.empty(k, n, device="cuda")
+    gd = torch.empty(n, k, device="cuda")
+    loss = ops.codec_step(_t(we), _t(wd), _t(A), _t(B), N, grad_e=ge, grad_d=gd, objective="eq8",
+                          T=_t(T), weights=W)
+    torch.cuda.synchronize()
+    L, rge, rgd = oc.loss_eq8_and_grad(we, wd, A, B, T, W)
+    me = md = 0.0
+    for c in range(0, N, 16):
+        _, ge_c, gd_c = oc.loss_eq8_and_grad(we, wd, A[c:c + 16], B[c:c + 16], T, W)
+        me, md = me + np.abs(ge_c) * 16 / N, md + np.abs(gd_c) * 16 / N
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert _grad_ok(to_np(ge), rge, scale=me) and _grad_ok(to_np(gd), rgd, scale=md)
 
 
 @pytest.mark.parametrize("weights", [W, (1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1),
