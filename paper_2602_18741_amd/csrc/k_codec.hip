@@ -9,10 +9,12 @@
 //                incremented Adam step into the workspace.  Only when E and D
 //                do not fit the partials kernel's LDS; otherwise that kernel
 //                stages softplus(Wt) itself and its block 0 writes the step.
-//   2. partials, float32 with n = 31 or 81 and k = 6 or 9: a few lanes per
-//                pair with the pair in registers and the sums over pairs of
-//                outer products on the fp32 matrix cores (kernel 2 below,
-//                "a few lanes per pair").  Otherwise each workgroup takes
+//   2. partials, float32 with n = 31 and k = 6 or 9: two lanes per pair
+//                with the pair in registers and the sums over pairs of outer
+//                products on the fp32 matrix cores (kernel 2 below, "a few
+//                lanes per pair"); float32 with n = 81 and k = 6 or 9: every
+//                product on the matrix cores, 16 pairs per wavefront tile
+//                (kernel 2 below, "matrix-core tiles").  Otherwise each workgroup takes
 //                tiles of TP pairs; `lpp` lanes per pair compute u = E a,
 //                v = E b, h = u*v, the residuals r_a = D u - a, r_b = D v - b,
 //                r_h = D h - a*b, and the back-propagated code gradients,
@@ -24,7 +26,7 @@
 //                of Eq. 8 (which also needs the per-pair norms and dot product
 //                of the cosine factor, reduced across the pair's lanes, and
 //                the code of the spectral product for L_code).
-//   3. finish  : one wavefront per gradient element sums the partial rows
+//   3. finish  : a workgroup per 64 gradient elements sums the partial rows
 //                (fixed order, float64), scales by 2/N (two-term) or 1/N
 //                (Eq. 8, whose per-pair terms carry their own factors),
 //                applies the softplus slope logistic(beta Wt) and optionally
@@ -473,9 +475,8 @@ __global__ __launch_bounds__(kThreads) void codec_partials_eq8_kernel(PartialArg
 
 // ------------------------------------------------------------------ kernel 2, a few lanes per pair
 //
-// float32 with n = 31 (400-700 nm at 10 nm) or n = 81 (380-780 nm at 5 nm) and
-// k = 6 or 9.  LPP consecutive lanes of a wavefront own one pair (two at
-// n = 31, eight at n = 81): lane q of the group holds samples
+// float32 with n = 31 (400-700 nm at 10 nm) and k = 6 or 9.  LPP = 2
+// consecutive lanes of a wavefront own one pair: lane q of the group holds samples
 // [q SPL, (q + 1) SPL) of a and b in registers (samples past n are zero
 // padding up to whole 16-sample tiles), and every loop has compile-time
 // bounds.  Sums over the samples (the codes E a, E b, E t, the per-pair norms,
@@ -503,13 +504,6 @@ struct LaneShape<31> {
     static constexpr int LPP = 2;       // lanes per pair
     static constexpr int THREADS = 512;
     static constexpr int XBLOCKS = 1;   // sample blocks per wavefront (1 or 2)
-};
-template <>
-struct LaneShape<81> {
-    static constexpr int NP = 96;
-    static constexpr int LPP = 8;       // 12 samples per lane (at 4 lanes, 24 samples: one wave per SIMD)
-    static constexpr int THREADS = 512;
-    static constexpr int XBLOCKS = 1;
 };
 
 template <int N>
@@ -1118,8 +1112,8 @@ Workspace carve(void* ws, int k, int n, int64_t rows, size_t esz) {
 // b and the [pair][code] tiles of U, V, H that the K = codes products read
 // transposed.  The wavefronts' sums are added in a fixed order into one
 // float64 partial row per workgroup.  Rows are read with a stride of 84
-// floats (samples 81-83 zero, reads past 84 masked), conflict-free for the
-// 16 rows x 4 columns of a forward operand.
+// floats (samples 81-83 zero; reads past sample 81 are clamped onto it),
+// conflict-free for the 16 rows x 4 columns of a forward operand.
 constexpr int kTileNS = 81;                 // samples
 constexpr int kTileRS = 84;                 // LDS row stride of [pair][sample] tiles
 constexpr int kTileKS = kTileRS / 4;        // K steps over the samples (21)
@@ -1522,11 +1516,8 @@ void launch_lanes_n(const PartialArgs<float>& p, bool eq8, int k, int64_t rows, 
     }
 }
 
-inline void launch_lanes(const PartialArgs<float>& p, bool eq8, int k, int n, int64_t rows, hipStream_t st) {
-    if (n == 31)
-        launch_lanes_n<31>(p, eq8, k, rows, st);
-    else
-        launch_lanes_n<81>(p, eq8, k, rows, st);
+inline void launch_lanes(const PartialArgs<float>& p, bool eq8, int k, int, int64_t rows, hipStream_t st) {
+    launch_lanes_n<31>(p, eq8, k, rows, st);
 }
 
 // float64 never takes the tile kernel; this overload only lets run<double> compile.
@@ -1544,13 +1535,12 @@ inline void launch_tiles(const PartialArgs<float>& p, bool eq8, int k, int64_t r
     }
 }
 
-// Pairs per workgroup of the few-lanes-per-pair kernel for n (31 or 81).
-inline int64_t lane_pairs(int n) { return n == 31 ? LaneDims<31>::PAIRS : LaneDims<81>::PAIRS; }
+// Pairs per workgroup of the few-lanes-per-pair kernel (n = 31).
+inline int64_t lane_pairs(int) { return LaneDims<31>::PAIRS; }
 
-// float32 at n = 31 or 81 with k = 6 or 9 takes the few-lanes-per-pair
-// kernel (one partial row per 256 or 64 pairs), which stages softplus(Wt)
-// itself
-// float32 at n = 81 with k = 6 or 9 takes the matrix-core tile kernel
+// float32 at n = 81 with k = 6 or 9 takes the matrix-core tile kernel, at
+// n = 31 the few-lanes-per-pair kernel (one partial row per 256 pairs); both
+// stage softplus(Wt) themselves
 template <typename F>
 bool takes_tiles(int k, int n) {
     return std::is_same<F, float>::value && n == kTileNS && (k == 6 || k == 9);
@@ -1558,7 +1548,7 @@ bool takes_tiles(int k, int n) {
 
 template <typename F>
 bool takes_lanes(int k, int n) {
-    return std::is_same<F, float>::value && (n == 31 || n == 81) && (k == 6 || k == 9) && !takes_tiles<F>(k, n);
+    return std::is_same<F, float>::value && n == 31 && (k == 6 || k == 9);
 }
 
 constexpr int64_t kTileGrid = 256;   // workgroups of the tile kernel (one per CU)

@@ -168,30 +168,118 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
     const int w = tid / 64, lane = tid & 63, g = lane / 16, n = lane % 16;
     const int jrow = 16 * w;           // the wave's 16 hidden rows
     const float* P = a.params;
+    const int mc3 = (k + 15) / 16;         // 16-row blocks of output channels
+    const int ksteps = (k + 3) / 4;        // K steps over the channels
+    const uint64_t ctr_base =
+        a.draw ? a.draw_ctr0 + (a.draw_scale ? uint64_t(*a.draw_scale) * uint64_t(a.N) : 0ull) : 0ull;
+    const int64_t tiles = (a.N + kTS - 1) / kTS;
+
+    // Loads are issued oldest-first in the order their values are needed:
+    // the parameters staged in LDS, the first tile's inputs, then the W2
+    // fragments (not read before layer 2), so that waiting for the first two
+    // leaves the 64 fragment loads in flight.
+    constexpr int kW3Per = (kMaxK * kH + kPThreads - 1) / kPThreads;
+    float w3v[kW3Per];
+#pragma unroll
+    for (int u = 0; u < kW3Per; ++u) {
+        const int e = tid + u * kPThreads;
+        w3v[u] = e < k * kH ? P[kOffW3 + e] : 0.f;
+    }
+    float w1v[4] = {0.f, 0.f, 0.f, 0.f}, b2v = 0.f;
+    if (tid < kH) {
+        w1v[0] = P[3 * tid];
+        w1v[1] = P[3 * tid + 1];
+        w1v[2] = P[3 * tid + 2];
+        w1v[3] = P[kOffB1 + tid];
+        b2v = P[kOffB2 + tid];
+    }
+    const float b3v = tid < kMaxK && tid < k ? P[off_b3(k) + tid] : 0.f;
+    const float mv = tid < 3 * kMaxK && (tid % kMaxK) < k ? a.M[(tid / kMaxK) * k + tid % kMaxK] : 0.f;
+    // a tile's inputs: item e < kTS (k + 1) of thread tid is (sample e % 16,
+    // channel e / 16 - 1), channel -1 being the colour (r, g, b, 1)
+    constexpr int kInPer = (kTS * (kMaxK + 1) + kPThreads - 1) / kPThreads;
+    float inv[kInPer][4];
+    auto fetch_inputs = [&](int64_t tile) {
+#pragma unroll
+        for (int u = 0; u < kInPer; ++u) {
+            const int e = tid + u * kPThreads;
+            inv[u][0] = inv[u][1] = inv[u][2] = inv[u][3] = 0.f;
+            if (e < kTS * (k + 1)) {
+                const int i = e % kTS, c = e / kTS - 1;
+                const int64_t s = tile * kTS + i;
+                if (s < a.N) {
+                    const int64_t row =
+                        a.draw ? int64_t(range32(rand64(a.key, ctr_base + uint64_t(s)), uint64_t(a.rows)))
+                               : (a.idx ? min<int64_t>(a.idx[s], a.rows - 1) : s);
+                    if (c < 0) {
+                        const float* cp = a.rgb + row * a.ld_rgb;
+                        inv[u][0] = cp[0];
+                        inv[u][1] = cp[1];
+                        inv[u][2] = cp[2];
+                        inv[u][3] = 1.f;
+                    } else {
+                        inv[u][0] = a.zgt[row * a.ld_z + 4 * (c / 3) + c % 3];
+                    }
+                }
+            }
+        }
+    };
+    auto store_inputs = [&]() {
+#pragma unroll
+        for (int u = 0; u < kInPer; ++u) {
+            const int e = tid + u * kPThreads;
+            if (e < kTS * (k + 1)) {
+                const int i = e % kTS, c = e / kTS - 1;
+                if (c < 0) {
+                    L.X[4 * i + 0] = inv[u][0];
+                    L.X[4 * i + 1] = inv[u][1];
+                    L.X[4 * i + 2] = inv[u][2];
+                    L.X[4 * i + 3] = inv[u][3];
+                } else {
+                    L.G[c * kAS + i] = inv[u][0];
+                }
+            }
+        }
+    };
+    fetch_inputs(blockIdx.x);
     // the wave's W2 fragments for the whole kernel, K index 32 g + st: the
     // forward A operand W2[jrow + n][32 g + st] and the backward one
     // W2[32 g + st][jrow + n]
+    // (the forward ones are 32 consecutive floats of a row: eight 16-byte
+    // loads when the parameters are 16-byte aligned)
     float wf[32], wb[32];
+    if ((reinterpret_cast<uintptr_t>(P) & 15) == 0) {
 #pragma unroll
-    for (int st = 0; st < 32; ++st) {
-        wf[st] = ldg_f32(P + kOffW2 + (jrow + n) * kH + 32 * g + st);
-        wb[st] = ldg_f32(P + kOffW2 + (32 * g + st) * kH + jrow + n);
+        for (int q = 0; q < 8; ++q) {
+            const float4 v = ld4(P + kOffW2 + (jrow + n) * kH + 32 * g + 4 * q);
+            wf[4 * q] = v.x;
+            wf[4 * q + 1] = v.y;
+            wf[4 * q + 2] = v.z;
+            wf[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int st = 0; st < 32; ++st) wf[st] = ldg_f32(P + kOffW2 + (jrow + n) * kH + 32 * g + st);
     }
-    for (int e = tid; e < k * kH; e += kPThreads) L.W3[(e / kH) * kRS + e % kH] = P[kOffW3 + e];
-    for (int j = tid; j < kH; j += kPThreads) {
-        L.W1[4 * j + 0] = P[3 * j];
-        L.W1[4 * j + 1] = P[3 * j + 1];
-        L.W1[4 * j + 2] = P[3 * j + 2];
-        L.W1[4 * j + 3] = P[kOffB1 + j];
-        L.B2[j] = P[kOffB2 + j];
+#pragma unroll
+    for (int st = 0; st < 32; ++st) wb[st] = ldg_f32(P + kOffW2 + (32 * g + st) * kH + jrow + n);
+#pragma unroll
+    for (int u = 0; u < kW3Per; ++u) {
+        const int e = tid + u * kPThreads;
+        if (e < k * kH) L.W3[(e / kH) * kRS + e % kH] = w3v[u];
     }
-    for (int c = tid; c < kMaxK; c += kPThreads) L.B3[c] = c < k ? P[off_b3(k) + c] : 0.f;
-    for (int e = tid; e < 3 * kMaxK; e += kPThreads) L.M[e] = (e % kMaxK) < k ? a.M[(e / kMaxK) * k + e % kMaxK] : 0.f;
+    if (tid < kH) {
+        L.W1[4 * tid + 0] = w1v[0];
+        L.W1[4 * tid + 1] = w1v[1];
+        L.W1[4 * tid + 2] = w1v[2];
+        L.W1[4 * tid + 3] = w1v[3];
+        L.B2[tid] = b2v;
+    }
+    if (tid < kMaxK) L.B3[tid] = b3v;
+    if (tid < 3 * kMaxK) L.M[tid] = mv;
     // rows k..47 of the code arrays stay zero for every tile
     for (int e = tid; e < 2 * kMaxK * kAS; e += kPThreads) L.Z[e] = 0.f;
 
-    const int mc3 = (k + 15) / 16;         // 16-row blocks of output channels
-    const int ksteps = (k + 3) / 4;        // K steps over the channels
     f4v acc2[8], acc3[3], acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int b = 0; b < 8; ++b) acc2[b] = f4v{0.f, 0.f, 0.f, 0.f};
@@ -201,29 +289,10 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
     double loss = 0.0;
     __syncthreads();
 
-    const uint64_t ctr_base =
-        a.draw ? a.draw_ctr0 + (a.draw_scale ? uint64_t(*a.draw_scale) * uint64_t(a.N) : 0ull) : 0ull;
-    const int64_t tiles = (a.N + kTS - 1) / kTS;
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         // ---- inputs of the tile: colours (+ the constant 1) and target codes
-        for (int e = tid; e < kTS * (k + 1); e += kPThreads) {
-            const int i = e % kTS, c = e / kTS - 1;        // c = -1: the colour
-            const int64_t s = tile * kTS + i;
-            const bool valid = s < a.N;
-            int64_t row = 0;
-            if (valid)
-                row = a.draw ? int64_t(range32(rand64(a.key, ctr_base + uint64_t(s)), uint64_t(a.rows)))
-                             : (a.idx ? min<int64_t>(a.idx[s], a.rows - 1) : s);
-            if (c < 0) {
-                const float* cp = a.rgb + row * a.ld_rgb;
-                L.X[4 * i + 0] = valid ? cp[0] : 0.f;
-                L.X[4 * i + 1] = valid ? cp[1] : 0.f;
-                L.X[4 * i + 2] = valid ? cp[2] : 0.f;
-                L.X[4 * i + 3] = valid ? 1.f : 0.f;
-            } else {
-                L.G[c * kAS + i] = valid ? a.zgt[row * a.ld_z + 4 * (c / 3) + c % 3] : 0.f;
-            }
-        }
+        if (tile != blockIdx.x) fetch_inputs(tile);
+        store_inputs();
         __syncthreads();
         // ---- layer 1 (K = 4: r, g, b, 1)
         {
