@@ -956,7 +956,7 @@ struct FinishArgs {
 
 // One workgroup per 64 consecutive elements of the partial rows (lane l of
 // every wavefront holds element 64 * block + l, so each row load is one
-// coalesced 512-byte piece); its 16 wavefronts take every 16th row, eight
+// coalesced 512-byte piece); its 16 wavefronts take every 16th row, sixteen
 // loads in flight per lane, and their sums are added in wavefront order
 // through LDS.  Wavefront 0 then applies the step to its 64 elements.
 constexpr int kFinishWaves = 16;
@@ -989,12 +989,23 @@ __global__ __launch_bounds__(kFinishThreads) void codec_finish_kernel(FinishArgs
             t = double(*a.ws_step);
         }
     }
-    // rows past the table add 0
-    constexpr int kIlp = 8;
+    // sixteen rows per lane in flight at once (256 rows in one round); rows
+    // past the table add 0
+    constexpr int kIlp = 16;
     double acc[kIlp];
 #pragma unroll
-    for (int u = 0; u < kIlp; ++u) acc[u] = 0.0;
-    for (int r0 = wave; r0 < a.rows; r0 += kIlp * kFinishWaves) {
+    for (int u = 0; u < kIlp; ++u) {
+        const int r = wave + u * kFinishWaves;
+        acc[u] = live && r < a.rows ? a.part[int64_t(r) * stride + e] : 0.0;
+    }
+    // the step's bias corrections while the rows are in flight (beta^t =
+    // exp(t ln beta), ln beta from the host)
+    double bc1 = 1.0, bc2 = 1.0;
+    if (a.adam && wave == 0) {
+        bc1 = 1.0 - exp(t * a.ln_beta1);
+        bc2 = 1.0 - exp(t * a.ln_beta2);
+    }
+    for (int r0 = wave + kIlp * kFinishWaves; r0 < a.rows; r0 += kIlp * kFinishWaves) {
         double x[kIlp];
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) {
@@ -1004,7 +1015,11 @@ __global__ __launch_bounds__(kFinishThreads) void codec_finish_kernel(FinishArgs
 #pragma unroll
         for (int u = 0; u < kIlp; ++u) acc[u] += x[u];
     }
-    s_part[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+#pragma unroll
+    for (int w2 = kIlp / 2; w2 >= 1; w2 >>= 1)
+#pragma unroll
+        for (int u = 0; u < w2; ++u) acc[u] += acc[u + w2];
+    s_part[wave][lane] = acc[0];
     __syncthreads();
     if (wave != 0 || !live) return;
     double s = 0.0;
@@ -1020,9 +1035,6 @@ __global__ __launch_bounds__(kFinishThreads) void codec_finish_kernel(FinishArgs
     if (a.adam) {
         const double mm = a.beta1 * m0 + (1.0 - a.beta1) * g;
         const double vv = a.beta2 * v0 + (1.0 - a.beta2) * g * g;
-        // beta^t = exp(t ln beta), ln beta from the host
-        const double bc1 = 1.0 - exp(t * a.ln_beta1);
-        const double bc2 = 1.0 - exp(t * a.ln_beta2);
         const double denom = sqrt(vv) / sqrt(bc2) + a.eps;
         m[idx] = F(mm);
         v[idx] = F(vv);
