@@ -37,6 +37,27 @@ def test_ciede2000_neutral_lightness_closed_form():
     assert colour.ciede2000(np.array([45.0, 0, 0]), np.array([55.0, 0, 0])) == pytest.approx(10.0)
 
 
+def test_ciede2000_chroma_on_the_axes_closed_forms():
+    """Equal lightness, both colours on the positive a* axis (b* = 0): both
+    hue angles are 0, so the hue difference and the rotation term vanish and
+    the difference is |dC'| / S_C with a' = (1 + G) a,
+    G = (1 - sqrt(Cbar^7 / (Cbar^7 + 25^7))) / 2 (Cbar the mean of the two
+    chromas before the adjustment) and S_C = 1 + 0.045 Cbar'.  On the b*
+    axis (a* = 0) the adjustment, which scales a* only, has no effect:
+    |db| / (1 + 0.045 (b1 + b2) / 2)."""
+    for a1, a2 in [(10.0, 14.0), (30.0, 42.0), (2.0, 3.0)]:
+        cbar = 0.5 * (a1 + a2)
+        G = 0.5 * (1 - np.sqrt(cbar ** 7 / (cbar ** 7 + 25.0 ** 7)))
+        c1, c2 = (1 + G) * a1, (1 + G) * a2
+        want = abs(c2 - c1) / (1 + 0.045 * 0.5 * (c1 + c2))
+        got = colour.ciede2000(np.array([50.0, a1, 0.0]), np.array([50.0, a2, 0.0]))
+        assert got == pytest.approx(want, rel=1e-12)
+    for b1, b2 in [(10.0, 14.0), (30.0, 42.0)]:
+        want = abs(b2 - b1) / (1 + 0.045 * 0.5 * (b1 + b2))
+        got = colour.ciede2000(np.array([60.0, 0.0, b1]), np.array([60.0, 0.0, b2]))
+        assert got == pytest.approx(want, rel=1e-12)
+
+
 def test_cie94_lightness_only_and_zero():
     a = np.array([50.0, 20.0, -10.0])
     assert colour.cie94(a, a) == 0.0
