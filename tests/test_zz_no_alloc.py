@@ -2,8 +2,9 @@
 against hc_codec_step with a caller workspace: loss, gradients and Adam state
 bit for bit, on two calls in a row, the second with a smaller batch, so that
 what the first call left in the shared scratch cannot leak into the second.
-Covers the float32 few-lanes-per-pair kernels (n = 31 and 81), the tiled
-float32 kernels, float64, both objectives and the device pair draw."""
+Covers the float32 few-lanes-per-pair kernel (n = 31), the matrix-core tile
+kernel (n = 81), the generic tiled kernels, float64, both objectives and the
+device pair draw."""
 
 import numpy as np
 import pytest
@@ -50,6 +51,7 @@ def _step(ops, we, wd, A, B, T, N, objective, static, adam, draw):
 @pytest.mark.parametrize("k,n,dtype,objective,adam,draw", [
     (6, 31, torch.float32, "eq8", True, True),
     (9, 81, torch.float32, "l2", False, False),
+    (9, 81, torch.float32, "eq8", True, True),
     (9, 31, torch.float32, "eq8", False, True),
     (5, 40, torch.float32, "l2", True, False),
     (6, 31, torch.float64, "eq8", False, False),
