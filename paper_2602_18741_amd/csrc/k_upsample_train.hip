@@ -463,28 +463,28 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
             acc1 = mfma4(L.P1[act(jrow + n, 4 * st + g)], n < 4 ? L.X[4 * (4 * st + g) + n] : 0.f, acc1);
         __syncthreads();
     }
-    // ---- partial row
+    // ---- partial row, with non-temporal stores (read once, by kernel 2)
     float* prow = a.part + int64_t(blockIdx.x) * param_count(k);
 #pragma unroll
     for (int nb = 0; nb < 8; ++nb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) prow[kOffW2 + (jrow + 4 * g + r) * kH + 16 * nb + n] = acc2[nb][r];
+        for (int r = 0; r < 4; ++r) __builtin_nontemporal_store(acc2[nb][r], &prow[kOffW2 + (jrow + 4 * g + r) * kH + 16 * nb + n]);
 #pragma unroll
     for (int mc = 0; mc < 3; ++mc)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int c = 16 * mc + 4 * g + r;
-            if (mc < mc3 && c < k) prow[kOffW3 + c * kH + jrow + n] = acc3[mc][r];
+            if (mc < mc3 && c < k) __builtin_nontemporal_store(acc3[mc][r], &prow[kOffW3 + c * kH + jrow + n]);
         }
     if (n < 4) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = jrow + 4 * g + r;
-            prow[n < 3 ? 3 * j + n : kOffB1 + j] = acc1[r];
+            __builtin_nontemporal_store(acc1[r], &prow[n < 3 ? 3 * j + n : kOffB1 + j]);
         }
     }
-    if (tid < kH) prow[kOffB2 + tid] = aB2;
-    if (tid < k) prow[off_b3(k) + tid] = aB3;
+    if (tid < kH) __builtin_nontemporal_store(aB2, &prow[kOffB2 + tid]);
+    if (tid < k) __builtin_nontemporal_store(aB3, &prow[off_b3(k) + tid]);
     // workgroup loss: the per-sample lanes 0..15, in order
     if (tid < kTS) L.loss[tid] = loss;
     __syncthreads();
