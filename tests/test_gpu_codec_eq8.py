@@ -90,6 +90,26 @@ def test_eq8_near_fit_fp32(ops, n, k):
     assert _grad_ok(to_np(ge), rge, scale=me) and _grad_ok(to_np(gd), rgd, scale=md)
 
 
+@pytest.mark.parametrize("n,k", [(81, 9), (81, 6), (31, 6)])
+@pytest.mark.parametrize("weights", [(1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1)])
+def test_eq8_each_term_fp32(ops, n, k, weights):
+    """Each term alone on the float32 kernels (the n = 81 one forms the
+    code-space gradients of every term through D^T D), at the float32 bounds."""
+    N = 4099
+    rng = np.random.default_rng(31 + n + k)
+    we, wd = synth.codec_init(rng, k, n)
+    A, B = _pairs(n, N, 32 + n)
+    T = synth.cmf_matrix(n)
+    ge = torch.empty(k, n, device="cuda")
+    gd = torch.empty(n, k, device="cuda")
+    loss = ops.codec_step(_t(we), _t(wd), _t(A), _t(B), N, grad_e=ge, grad_d=gd, objective="eq8",
+                          T=_t(T), weights=weights)
+    torch.cuda.synchronize()
+    L, rge, rgd = oc.loss_eq8_and_grad(we, wd, A, B, T, weights)
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert _grad_ok(to_np(ge), rge) and _grad_ok(to_np(gd), rgd)
+
+
 @pytest.mark.parametrize("weights", [W, (1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1),
                                      (2.0, 0.5, 0.25, 1.0)])
 def test_eq8_each_term_fp64(ops, weights):
