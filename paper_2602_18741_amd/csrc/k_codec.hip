@@ -1231,8 +1231,8 @@ __global__ __launch_bounds__(kTileThreads) void codec_tile_kernel(PartialArgs<fl
 #pragma unroll
     for (int b = 0; b < NB; ++b) accD[b] = accE[b] = hc_mf4{0.f, 0.f, 0.f, 0.f};
     double loss_acc = 0.0;
-    // lane (g, n) loads row pieces of pair 4 * (lane / 16) ... : pair p = lane / 4,
-    // samples q, q + 4, ... with q = lane % 4
+    // the tile's rows are loaded with lane l taking pair l / 4 of the tile and
+    // its samples q, q + 4, q + 8, ... with q = l % 4
     const int lp = lane >> 2, lq = lane & 3;
     constexpr int PER = (NS + 3) / 4;                 // 21 samples per lane and row
     const int64_t tiles = (a.N + 15) / 16;
