@@ -34,6 +34,12 @@ STRESS = ("3840x2160 px, 64 spp, path length 1-8, 4096^2 x 81 texture, 256 light
           "(75% narrow-band), latent k=9")
 
 
+def codec_config() -> dict:
+    """The codec-fit workload's configuration (batch, Adam, steps, loss weights)."""
+    import synth
+    return synth.config(2)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -240,9 +246,6 @@ def frame_roofline(kernel, bytes_alg, kern_s, nv, ceiling, copy_gbs, limiter):
             "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
 
 
-STRESS_CODEC_STEPS = 20000
-
-
 def stress_leg(w, args, dev, copy_gbs, cpu):
     """Config-4 frame (3840 x 2160, 64 spp, path length 1..8, 4096^2 x 81
     texture, 256 lights): both forms timed as single frames with the codec
@@ -268,14 +271,16 @@ def stress_leg(w, args, dev, copy_gbs, cpu):
     pa, pb = synth.workloads.codec_pools(n, 1 << 18)
     pa, pb = torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev)
     we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
-    fit = CodecFit(we0, wd0, pa, pb, batch=65536, seed=2, objective="eq8", T=w["T"])
+    cc = codec_config()
+    fit = CodecFit(we0, wd0, pa, pb, batch=cc["batch"], lr=cc["adam"]["lr"], seed=2, objective="eq8",
+                   T=w["T"])
     fit.run(1)
     fit.capture(CODEC_STEPS_PER_GRAPH)
-    loss = float(fit.run(STRESS_CODEC_STEPS - 1))
+    loss = float(fit.run(cc["steps"] - 1))
     E, D = fit.weights()
     del pa, pb, fit
     log(f"stress frame: {npx} px, {npath} paths, {nv} path-vertices; inputs on the GPU and codec "
-        f"fitted ({STRESS_CODEC_STEPS} steps, loss {loss:.4g}) in {time.time() - t0:.1f} s")
+        f"fitted ({cc['steps']} steps, loss {loss:.4g}) in {time.time() - t0:.1f} s")
     codes = torch.empty(spec.n_tex, ld_z, device=dev)
     lcodes = torch.empty(spec.n_illum, ld_z, device=dev)
     zimg = torch.empty(npx, latent_width(k), device=dev)
@@ -329,7 +334,7 @@ def stress_leg(w, args, dev, copy_gbs, cpu):
                          "random 384-byte spectral rows from a 6.4 GB table in HBM (three 128-byte "
                          "lines each)")
     out = {"workload": STRESS, "pixels": npx, "spp": spec.spp, "paths": npath, "path_vertices": nv,
-           "n": n, "k": k, "codec": {"objective": "eq8", "steps": STRESS_CODEC_STEPS, "loss": loss},
+           "n": n, "k": k, "codec": {"objective": "eq8", "steps": cc["steps"], "loss": loss},
            "latent": {"value": nv / res["latent"][0], "unit": "path-vertices/s",
                       "ms_per_step": res["latent"][0] * 1e3, "roofline": lat},
            "spectral": {"value": nv / res["spectral"][0], "unit": "path-vertices/s",
@@ -342,7 +347,6 @@ def stress_leg(w, args, dev, copy_gbs, cpu):
     return out
 
 
-MB_CHAINS = 1 << 18
 CODEC_STEPS_PER_GRAPH = 8   # fit steps (codec, upsampler) recorded in one HIP graph
 
 
@@ -359,7 +363,7 @@ def codec_only(args):
     pa, pb = torch.from_numpy(pa).cuda(), torch.from_numpy(pb).cuda()
     we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
     for objective in ("eq8", "l2"):
-        fit = CodecFit(we0, wd0, pa, pb, batch=65536, seed=2, objective=objective,
+        fit = CodecFit(we0, wd0, pa, pb, batch=codec_config()["batch"], seed=2, objective=objective,
                        T=synth.cmf_matrix(n))
         fit.run(1)
         fit.capture(CODEC_STEPS_PER_GRAPH)
@@ -381,9 +385,10 @@ def codec_step_timing(n, k, steps, dev):
     pa, pb = synth.workloads.codec_pools(n, 1 << 18)
     pa, pb = torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev)
     we0, wd0 = synth.codec_init(np.random.default_rng([2, 3]), k, n)
-    out = {"n": n, "k": k, "batch": 65536, "steps": steps}
+    batch = codec_config()["batch"]
+    out = {"n": n, "k": k, "batch": batch, "steps": steps}
     for objective in ("eq8", "l2"):
-        fit = CodecFit(we0, wd0, pa, pb, batch=65536, seed=2, objective=objective, T=synth.cmf_matrix(n))
+        fit = CodecFit(we0, wd0, pa, pb, batch=batch, seed=2, objective=objective, T=synth.cmf_matrix(n))
         fit.run(1)
         fit.capture(CODEC_STEPS_PER_GRAPH)
         torch.cuda.synchronize()
@@ -395,18 +400,19 @@ def codec_step_timing(n, k, steps, dev):
 
 
 def multibounce_leg(args, dev, n, k, T, codecs):
-    """Multi-bounce chains (Eq. 10): both forms on MB_CHAINS held-out chains
+    """Multi-bounce chains (Eq. 10): both forms on the codec-fit configuration's held-out chains
     of 3 bounces for each fitted codec; GPU time of one evaluation (encode,
     both shades, decode) and the CIE94 report per bounce."""
     import torch
     import synth
     from paper_2602_18741_amd import multibounce, ops
-    bounces = 3
-    r, l = synth.workloads.bounce_chains(n, MB_CHAINS, bounces)
+    mb = codec_config()["multibounce"]
+    chains, bounces = mb["chains"], mb["bounces"]
+    r, l = synth.workloads.bounce_chains(n, chains, bounces)
     r = ops.padded(torch.from_numpy(r).to(dev))
     l = ops.padded(torch.from_numpy(l).to(dev))
-    paths = multibounce.chain_paths(MB_CHAINS, bounces, dev)
-    out = {"chains": MB_CHAINS, "bounces": bounces, "white": "equal-energy at the light's Y",
+    paths = multibounce.chain_paths(chains, bounces, dev)
+    out = {"chains": chains, "bounces": bounces, "white": "equal-energy at the light's Y",
            "cie94": {}}
     for name, ((E_, D_), _) in codecs.items():
         res = multibounce.chain_xyz(E_, D_, T, r, l, k, n, bounces, paths=paths)
@@ -423,7 +429,7 @@ def multibounce_leg(args, dev, n, k, T, codecs):
     out["ms_per_evaluation"] = e0.elapsed_time(e1) / reps
     log("multi-bounce CIE94 mean per bounce: " + "; ".join(
         f"{name} " + ", ".join(f"{b['mean']:.3f}" for b in rep) for name, rep in out["cie94"].items())
-        + f"; {out['ms_per_evaluation']:.3f} ms per evaluation of {MB_CHAINS} chains")
+        + f"; {out['ms_per_evaluation']:.3f} ms per evaluation of {chains} chains")
     return out
 
 
@@ -519,9 +525,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--k", type=int, default=6)
-    ap.add_argument("--codec-steps", type=int, default=20000,
-                    help="Adam steps of the codec fit (the step time and the loss after 2,000 "
-                         "steps, the fitting recipe's length, are reported as well)")
+    ap.add_argument("--config", type=int, choices=[1, 4], default=1,
+                    help="the main frame's workload configuration (synth/configs/cfg<N>.json): 1 the "
+                         "1920x1080 frame, 4 the 3840x2160 stress frame (as --stress)")
+    ap.add_argument("--codec-steps", type=int, default=None,
+                    help="Adam steps of the codec fit (default: the codec-fit configuration's; the "
+                         "step time and the loss after 2,000 steps, the fitting recipe's length, are "
+                         "reported as well)")
     ap.add_argument("--codec-n", type=int, default=31, choices=[31, 81],
                     help="samples per spectrum of the --only codec run")
     ap.add_argument("--no-cpu", action="store_true")
@@ -531,8 +541,9 @@ def main():
                     help="frames in the burst of the stress workload's serving run")
     ap.add_argument("--upsample-steps", type=int, default=5000,
                     help="AdamW steps of the upsampling network's fit")
-    ap.add_argument("--serve-count", type=int, default=2000,
-                    help="requests per arrival rate in the serving measurement")
+    ap.add_argument("--serve-count", type=int, default=None,
+                    help="requests per arrival rate in the serving measurement (default: the "
+                         "serving configuration's)")
     ap.add_argument("--no-stress", action="store_true",
                     help="leave out the 3840x2160 / 64 spp / n=81 / k=9 single-frame leg")
     ap.add_argument("--stress-steps", type=int, default=3,
@@ -548,6 +559,13 @@ def main():
                          "random-gather probe over the frame's records and code table), for "
                          "profilers; prints no JSON")
     args = ap.parse_args()
+    import synth
+    if args.codec_steps is None:
+        args.codec_steps = synth.config(2)["steps"]
+    if args.serve_count is None:
+        args.serve_count = synth.config(3)["requests_per_rate"]
+    if args.config == 4:
+        args.stress = True
     if args.record_traffic:
         record_traffic(*args.record_traffic)
         return
@@ -624,8 +642,9 @@ def main():
     codec_steps = 1 if args.only else args.codec_steps
 
     def fit_codec(objective):
-        fit = CodecFit(we0, wd0, pa, pb, batch=65536, lam=1.0, beta=10.0, lr=1e-3, seed=2,
-                       objective=objective, T=w["T"])
+        cc = codec_config()
+        fit = CodecFit(we0, wd0, pa, pb, batch=cc["batch"], lam=cc["lambda"], beta=cc["softplus_beta"],
+                       lr=cc["adam"]["lr"], seed=2, objective=objective, T=w["T"])
         recipe_steps = min(2000, codec_steps)
         fit.run(1)
         fit.capture(CODEC_STEPS_PER_GRAPH)
@@ -637,7 +656,7 @@ def main():
         loss = float(fit.run(codec_steps - recipe_steps))
         log(f"codec fit ({objective}): loss {loss_recipe:.4g} after {recipe_steps} steps, "
             f"{loss:.4g} after {fit.steps_done}; {us:.1f} us/step")
-        info = {"objective": objective, "steps": fit.steps_done, "batch": 65536, "lr": 1e-3,
+        info = {"objective": objective, "steps": fit.steps_done, "batch": cc["batch"], "lr": cc["adam"]["lr"],
                 "final_loss": loss, "loss_after_2000_steps": loss_recipe, "us_per_step": us}
         return fit.weights(), info
 

@@ -671,19 +671,26 @@ class GpuBackend:
 
 # ------------------------------------------------------------------ workload and driver
 
-RESOLUTIONS = [(256, 256), (1280, 720), (1920, 1080), (3840, 2160)]
+def _serving_config() -> dict:
+    import synth
+    return synth.config(3)
 
 
 def make_requests(rate: float, count: int, n_assets: int, seed: int, t0: float = 0.0,
-                  spps=(1, 4, 16), l_range=(1, 4)):
+                  spps=None, l_range=None, resolutions=None):
     """Poisson arrivals at `rate` frames/s with resolution, spp and asset drawn
-    uniformly (the serving workload's distributions)."""
+    uniformly (the serving workload's distributions; by default those of the
+    serving configuration)."""
+    cfg = _serving_config()
+    spps = tuple(cfg["spp"]) if spps is None else spps
+    l_range = tuple(cfg["path_length"]) if l_range is None else l_range
+    resolutions = [tuple(r) for r in cfg["resolutions"]] if resolutions is None else resolutions
     rng = np.random.default_rng([3, 5, seed])
     t = t0
     out = []
     for i in range(count):
         t += rng.exponential(1.0 / rate)
-        w, h = RESOLUTIONS[rng.integers(len(RESOLUTIONS))]
+        w, h = resolutions[rng.integers(len(resolutions))]
         out.append(Request(rid=i, asset=int(rng.integers(n_assets)), width=w, height=h,
                            spp=int(rng.choice(spps)), l_min=l_range[0], l_max=l_range[1],
                            seed=10_000 + i, arrival=t))
@@ -724,45 +731,54 @@ def summarize(reqs, wall: float) -> dict:
             "frames_per_s": len(ok) / wall, "path_vertices_per_s": verts / wall, "wall_s": wall}
 
 
-def make_assets(n_assets: int = 32, n: int = 31, seed: int = 3):
-    """Spectral textures in pinned host memory: sides 512, 1024, 2048 in turn,
-    each a Perlin-weighted blend of its own 16 basis reflectances (weight maps
-    of the larger sides are the 512^2 map repeated per texel block)."""
+def make_assets(n_assets: int | None = None, n: int | None = None, seed: int = 3):
+    """Spectral textures in pinned host memory, the serving configuration's
+    sides (512, 1024, 2048) in turn, each a Perlin-weighted blend of its own
+    16 basis reflectances (weight maps of the larger sides are the 512^2 map
+    repeated per texel block)."""
     import torch
 
     import synth
     from .layout import line_stride
-    w512 = synth.perlin_weights(3001, 512)
+    cfg = _serving_config()
+    tx = cfg["texture"]
+    n_assets = cfg["assets"] if n_assets is None else n_assets
+    n = cfg["n"] if n is None else n
+    ps = tx["perlin_side"]
+    wmap = synth.perlin_weights(tx["perlin_seed"], ps)
     rng = np.random.default_rng([3, 1, seed])
     ld = line_stride(n)
     out = []
     for a in range(n_assets):
-        side = (512, 1024, 2048)[a % 3]
-        f = side // 512
-        w = w512.reshape(512, 512, -1)
+        side = tx["sides"][a % len(tx["sides"])]
+        f = side // ps
+        w = wmap.reshape(ps, ps, -1)
         if f > 1:
             w = np.repeat(np.repeat(w, f, axis=0), f, axis=1)
-        basis = synth.reflectances(rng, n, 16).astype(np.float32)
+        basis = synth.reflectances(rng, n, tx["basis"]).astype(np.float32)
         tex = torch.zeros(side * side, ld, dtype=torch.float32).pin_memory()
         tex[:, :n] = torch.from_numpy(w.reshape(side * side, -1).astype(np.float32) @ basis)
         out.append(tex)
     return out
 
 
-def bench_serving(device, rates=(30, 60, 120, 240), count: int = 200, E=None, D=None, assets=None,
+def bench_serving(device, rates=None, count: int | None = None, E=None, D=None, assets=None,
                   progress=None):
     """p50 / p99 frame latency and throughput of latent and spectral serving of
     the same request streams.  progress(str), if given, gets a line per run."""
     import torch
 
     import synth
-    n = 31
+    cfg = _serving_config()
+    rates = tuple(cfg["rates_fps"]) if rates is None else rates
+    count = cfg["requests_per_rate"] if count is None else count
+    n, lt = cfg["n"], cfg["lights"]
     rng = np.random.default_rng([3, 0])
-    lights = torch.from_numpy(synth.illuminant_table(rng, n, 16, 16))
+    lights = torch.from_numpy(synth.illuminant_table(rng, n, lt["planck"], lt["narrow"], *lt["narrow_sigma_nm"]))
     T = torch.from_numpy(synth.cmf_matrix(n))
     if E is None:
-        E, D = (torch.from_numpy(x) for x in synth.codec_uniform(np.random.default_rng([3, 3]), 6, n))
-    assets = assets if assets is not None else make_assets(32, n)
+        E, D = (torch.from_numpy(x) for x in synth.codec_uniform(np.random.default_rng([3, 3]), cfg["k"], n))
+    assets = assets if assets is not None else make_assets(cfg["assets"], n)
     out = {"rates_fps": list(rates), "requests_per_rate": count,
            "start": "each (form, rate) run starts with no asset resident"}
     for form in ("latent", "spectral"):

@@ -39,4 +39,5 @@ from .paths import (  # noqa: F401
     chain_records,
     uniform_indices,
 )
+from .config import config  # noqa: F401
 from .workloads import workload  # noqa: F401

@@ -1,9 +1,11 @@
 """The five synthetic workloads (shapes and distributions of the paper's use).
 
-Seeds: every random draw for workload c and purpose j comes from
-``numpy.random.default_rng([c, j])`` with j = 0 spectra tables, 1 texture,
-3 codec, 4 codec-fit pools, 5 serving arrivals, 6 multi-bounce chains; the counter-based path
-generator takes the integer seed ``1000 * c + 2``.
+Their parameters live in ``configs/cfg{c}.json`` (see ``config``); this module
+builds the inputs.  Seeds: every random draw for workload c and purpose j
+comes from ``numpy.random.default_rng([c, j])`` with j = 0 spectra tables,
+1 texture, 3 codec, 4 codec-fit pools, 5 serving arrivals, 6 multi-bounce
+chains; the counter-based path generator takes the configuration's
+``path_seed`` (1000 c + 2).
 
 * c = 0  tiny parity case: n = 31, k = 6, random U[0,1] codec, 64
   reflectances, 8 lights (4 Planck, 4 narrow-band), 256 x 256 px, 1 spp,
@@ -23,6 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .config import config
 from .paths import PathSpec
 from .spectra import (cmf_matrix, codec_uniform, illuminant_table, reflectances,
                       wavelengths)
@@ -42,30 +45,25 @@ def workload(c: int, *, width: int | None = None, height: int | None = None,
     float32), n_tex, illum (n_illum x n), E (k x n), D (n x k), paths
     (PathSpec), width, height.
     """
-    if c == 0:
-        n, kk = 31, 6
-        t0 = _rng(0, 0)
-        refl = reflectances(t0, n, 64)
-        illum = illuminant_table(t0, n, 4, 4, 5.0, 15.0)
-        w, h, s, lmin, lmax = 256, 256, 1, 1, 1
-    elif c == 1:
-        n, kk = 31, 6
-        t0 = _rng(1, 0)
-        basis = reflectances(t0, n, 16)
-        illum = illuminant_table(t0, n, 16, 16, 5.0, 15.0)
-        side = texture_side or 1024
-        refl = perlin_texture(1001, side, basis, ld=ld_tex)
-        w, h, s, lmin, lmax = 1920, 1080, 16, 1, 4
-    elif c == 4:
-        n, kk = 81, 9
-        t0 = _rng(4, 0)
-        basis = reflectances(t0, n, 16)
-        illum = illuminant_table(t0, n, 64, 192, 5.0, 10.0)
-        side = texture_side or 4096
-        refl = perlin_texture(4001, side, basis, ld=ld_tex, base=min(side, 512))
-        w, h, s, lmin, lmax = 3840, 2160, 64, 1, 8
-    else:
+    if c not in (0, 1, 4):
         raise ValueError(f"workload {c} has no frame inputs")
+    cfg = config(c)
+    n, kk = cfg["n"], cfg["k"]
+    t0 = _rng(c, 0)
+    lt = cfg["lights"]
+    if c == 0:
+        refl = reflectances(t0, n, cfg["reflectances"])
+        illum = illuminant_table(t0, n, lt["planck"], lt["narrow"], *lt["narrow_sigma_nm"])
+    else:
+        tx = cfg["texture"]
+        basis = reflectances(t0, n, tx["basis"])
+        illum = illuminant_table(t0, n, lt["planck"], lt["narrow"], *lt["narrow_sigma_nm"])
+        side = texture_side or tx["side"]
+        base = min(side, tx["perlin_side"]) if "perlin_side" in tx else None
+        refl = perlin_texture(tx["perlin_seed"], side, basis, ld=ld_tex, base=base)
+    fr = cfg["frame"]
+    w, h, s = fr["width"], fr["height"], fr["spp"]
+    lmin, lmax = fr["path_length"]
     if ld_tex is not None and c == 0:
         pad = np.zeros((refl.shape[0], ld_tex), dtype=np.float32)
         pad[:, :n] = refl
@@ -74,7 +72,7 @@ def workload(c: int, *, width: int | None = None, height: int | None = None,
     e, d = codec_uniform(_rng(c, 3), kk, n)
     w, h, s = width or w, height or h, spp or s
     spec = PathSpec(n_pixels=w * h, spp=s, l_min=lmin, l_max=lmax,
-                    n_tex=refl.shape[0], n_illum=illum.shape[0], seed=1000 * c + 2)
+                    n_tex=refl.shape[0], n_illum=illum.shape[0], seed=cfg["path_seed"])
     return dict(n=n, k=kk, lam=wavelengths(n), T=cmf_matrix(n), refl=refl,
                 n_tex=refl.shape[0], illum=illum, E=e, D=d, paths=spec,
                 width=w, height=h)
@@ -85,7 +83,8 @@ def codec_pools(n: int, count: int, seed_c: int = 2):
     lights half Planckian, half narrow-band).  Returns two (count, n) float32."""
     rng = _rng(seed_c, 4)
     refl = reflectances(rng, n, count)
-    illum = illuminant_table(rng, n, count // 2, count - count // 2, 5.0, 15.0)
+    sigma = config(2)["lights"]["narrow_sigma_nm"]
+    illum = illuminant_table(rng, n, count // 2, count - count // 2, *sigma)
     return refl, illum
 
 
@@ -97,5 +96,6 @@ def bounce_chains(n: int, count: int, bounces: int = 3):
     c * bounces .. c * bounces + bounces - 1, lights (count, n)), float32."""
     rng = _rng(2, 6)
     refl = reflectances(rng, n, count * bounces)
-    lights = illuminant_table(rng, n, count // 2, count - count // 2, 5.0, 15.0)
+    sigma = config(2)["lights"]["narrow_sigma_nm"]
+    lights = illuminant_table(rng, n, count // 2, count - count // 2, *sigma)
     return refl, lights
