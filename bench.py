@@ -162,23 +162,35 @@ def record_traffic(d_fetch, d_write, d_copy_fetch, d_copy_write, d_req=None):
     print(json.dumps(d))
 
 
-def copy_bandwidth(dev) -> float:
-    """GB/s of a plain 1 GiB device-to-device copy (2 GiB moved per copy),
-    HIP events around 10 back-to-back copies."""
+def stream_bandwidth(dev, reps: int = 10) -> dict:
+    """Sequential bandwidth of the device from the streaming probe
+    (hc_stream_probe) over 1 GiB: copy (2 GiB moved per pass, read + write)
+    and read-only, each the best of grids of 1, 2, 4 and 8 workgroups per
+    CU, HIP events around `reps` back-to-back passes."""
     import torch
-    x = torch.ones(1 << 28, device=dev)
-    y = torch.empty_like(x)
-    for _ in range(2):
-        y.copy_(x)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        y.copy_(x)
-    e1.record()
-    torch.cuda.synchronize()
-    gbs = 10 * 2 * x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del x, y
-    return gbs
+    from paper_2602_18741_amd import ops
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    src = torch.ones(1 << 28, device=dev)
+    dst = torch.empty_like(src)
+    out = {}
+    for mode, moved in (("copy", 2), ("read", 1)):
+        best = None
+        for per_cu in (1, 2, 4, 8):
+            grid = per_cu * cus
+            ops.stream_probe(src, dst, mode, grid)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                ops.stream_probe(src, dst, mode, grid)
+            e1.record()
+            torch.cuda.synchronize()
+            gbs = reps * moved * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+            if best is None or gbs > best[0]:
+                best = (gbs, per_cu)
+        out[f"{mode}_GBs"], out[f"{mode}_workgroups_per_cu"] = best
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def measured_traffic():
@@ -729,8 +741,9 @@ def main():
     log(f"latent step {lat_wall * 1e3:.3f} ms (shade {lat_kern * 1e3:.3f} ms); "
         f"spectral step {spe_wall * 1e3:.3f} ms")
 
-    copy_gbs = copy_bandwidth(dev)
-    log(f"device copy: {copy_gbs:.0f} GB/s")
+    stream = stream_bandwidth(dev)
+    copy_gbs = stream["copy_GBs"]
+    log(f"streaming probe: copy {copy_gbs:.0f} GB/s (read + write), read {stream['read_GBs']:.0f} GB/s")
     bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
     bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
     traffic = None if stress else measured_traffic()
@@ -832,6 +845,7 @@ def main():
                    "lights": spec.n_illum, "step": "encode texture+lights, shade latent, decode"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "stream_probe": stream,
         "spectral": {"value": nv / spe_wall, "unit": "path-vertices/s", "ms_per_step": spe_wall * 1e3,
                      "kernel_ms": spe_kern * 1e3, "achieved_GBs": bytes_spe / spe_kern / 1e9,
                      "algorithmic_bytes": bytes_spe, "roofline": roof_spe},

@@ -521,6 +521,20 @@ hc_status hc_gather_probe(const uint32_t* vtx, int64_t n_vertices, const float* 
                           int64_t ld, int32_t row_floats, int32_t unroll, int32_t lanes_per_row,
                           int32_t grid, float* out, void* stream);
 
+/*
+ * Streaming probe (measurement, not part of the method): the device's
+ * sequential bandwidth, the reference the gather rates and the streaming
+ * kernels (encode, decode) are compared with.  src holds n16 16-byte chunks.
+ *   mode 0 (read)  every chunk is read and its four floats added into a
+ *                  per-lane sum; each of the grid * 256 lanes writes its sum
+ *                  to dst[lane] (dst holds grid * 256 floats, 4-byte aligned);
+ *   mode 1 (copy)  the chunks are copied to dst (n16 chunks, 16-byte aligned).
+ *   grid           workgroups of 256 lanes, [1, 2^20]; chunks are taken in a
+ *                  grid-stride loop, four per lane in flight.
+ * src needs 16-byte alignment; n16 in [0, 2^40).
+ */
+hc_status hc_stream_probe(const float* src, float* dst, int64_t n16, int32_t mode, int32_t grid, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -511,4 +511,17 @@ hc_status hc_gather_probe(const uint32_t* vtx, int64_t n_vertices, const float* 
                                grid, as_stream(stream));
 }
 
+hc_status hc_stream_probe(const float* src, float* dst, int64_t n16, int32_t mode, int32_t grid, void* stream) {
+    clear_error();
+    const char* fn = "hc_stream_probe";
+    HC_REQUIRE(mode == 0 || mode == 1, HC_EINVAL, "%s: mode must be 0 (read) or 1 (copy), got %d", fn, mode);
+    HC_REQUIRE(n16 >= 0 && n16 < (int64_t(1) << 40), HC_ESHAPE, "%s: n16 outside [0, 2^40)", fn);
+    HC_REQUIRE(grid >= 1 && grid <= (1 << 20), HC_ESHAPE, "%s: grid outside [1, 2^20]", fn);
+    HC_REQUIRE(dst && (src || n16 == 0), HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned16(src) && (mode == 0 ? aligned4(dst) : aligned16(dst)), HC_EALIGN,
+               "%s: src needs 16-byte alignment, dst 4 (read) or 16 (copy)", fn);
+    if (mode == 1 && n16 == 0) return HC_OK;
+    return launch_stream_probe(src, dst, uint64_t(n16), mode, grid, as_stream(stream));
+}
+
 }  // extern "C"

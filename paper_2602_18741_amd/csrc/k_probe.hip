@@ -1,5 +1,6 @@
 // Random-gather probe: the memory system's rate for the texel gathers of a
-// vertex-record stream, with none of the shading arithmetic.
+// vertex-record stream, with none of the shading arithmetic; and a streaming
+// probe for the device's sequential read and copy bandwidth.
 //
 // Both shading forms spend their time gathering one texel row per path
 // vertex at the record's texel index; for uniformly random indices no
@@ -86,7 +87,47 @@ hc_status by_unroll(int unroll, const uint2* vtx, uint32_t nv, const float* tabl
     }
 }
 
+// Streaming probe: chunk i of src (16 bytes) is read (MODE 0: its floats
+// added into a per-lane sum, written once per lane) or copied to dst
+// (MODE 1), in a grid-stride loop with four chunks per lane in flight.
+template <int MODE>
+__global__ __launch_bounds__(kProbeBlock) void stream_probe_kernel(const float* __restrict__ src,
+                                                                   float* __restrict__ dst, uint64_t n16) {
+    constexpr int U = 4;
+    const uint64_t stride = uint64_t(gridDim.x) * kProbeBlock;
+    uint64_t i = uint64_t(blockIdx.x) * kProbeBlock + threadIdx.x;
+    float acc = 0.f;
+    for (; i + (U - 1) * stride < n16; i += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ld4(src + 4 * (i + u * stride));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (MODE == 0)
+                acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+            else
+                st4(dst + 4 * (i + u * stride), v[u]);
+        }
+    }
+    for (; i < n16; i += stride) {
+        const float4 v = ld4(src + 4 * i);
+        if (MODE == 0)
+            acc += (v.x + v.y) + (v.z + v.w);
+        else
+            st4(dst + 4 * i, v);
+    }
+    if (MODE == 0) stg_f32(dst + uint64_t(blockIdx.x) * kProbeBlock + threadIdx.x, acc);
+}
+
 }  // namespace
+
+hc_status launch_stream_probe(const float* src, float* dst, uint64_t n16, int mode, int grid, hipStream_t st) {
+    if (mode == 0)
+        hipLaunchKernelGGL(stream_probe_kernel<0>, dim3(grid), dim3(kProbeBlock), 0, st, src, dst, n16);
+    else
+        hipLaunchKernelGGL(stream_probe_kernel<1>, dim3(grid), dim3(kProbeBlock), 0, st, src, dst, n16);
+    return launch_status("hc_stream_probe");
+}
 
 hc_status launch_gather_probe(const uint2* vtx, uint32_t nv, const float* table, uint32_t n_rows,
                               uint32_t ld, int row_floats, int unroll, int lanes_per_row, float* out,

@@ -369,6 +369,22 @@ def gen_indices(seed: int, count: int, n: int, ctr0: int = 0, step: torch.Tensor
     return out
 
 
+def stream_probe(src: torch.Tensor, dst: torch.Tensor, mode: str = "read", grid: int = 2048) -> torch.Tensor:
+    """Streaming probe (see hc_stream_probe): mode "read" reads every
+    16-byte chunk of src and writes grid * 256 per-lane sums into dst;
+    "copy" copies src into dst.  src and dst are contiguous float32."""
+    _dev(src, dst)
+    if src.numel() % 4 or not src.is_contiguous() or not dst.is_contiguous():
+        raise ValueError("stream_probe: src must be contiguous with a multiple of 4 floats")
+    m = {"read": 0, "copy": 1}[mode]
+    need = grid * 256 if m == 0 else src.numel()
+    if dst.numel() < need:
+        raise ValueError(f"stream_probe: dst holds {dst.numel()} floats, needs {need}")
+    check(load().hc_stream_probe(_ptr(src), _ptr(dst), src.numel() // 4, m, grid, _stream()),
+          "hc_stream_probe")
+    return dst
+
+
 def gather_probe(vtx: torch.Tensor, table: torch.Tensor, row_floats: int, unroll: int = 4,
                  lanes_per_row: int = 1, grid: int = 2048, out: torch.Tensor | None = None) -> torch.Tensor:
     """Random-gather probe over a record stream (see hc_gather_probe): the

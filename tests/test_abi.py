@@ -246,3 +246,19 @@ def test_server_table_dtypes_match_the_abi_structs():
         for name, _ in st._fields_:
             want = "pad" if name == "reserved0" else name
             assert dt.fields[want][1] == getattr(st, name).offset, name
+
+
+def test_stream_probe_rejects_bad_arguments(lib):
+    p = C.c_void_p(0x1000)
+    s, msg = _err(lib.hc_stream_probe(p, p, 16, 2, 4, None))
+    assert s == _lib.HC_EINVAL and "mode" in msg
+    s, msg = _err(lib.hc_stream_probe(p, p, 16, 0, 0, None))
+    assert s == _lib.HC_ESHAPE and "grid" in msg
+    s, msg = _err(lib.hc_stream_probe(C.c_void_p(0x1004), p, 16, 1, 4, None))
+    assert s == _lib.HC_EALIGN
+    s, msg = _err(lib.hc_stream_probe(p, C.c_void_p(0x1004), 16, 1, 4, None))
+    assert s == _lib.HC_EALIGN
+    s, msg = _err(lib.hc_stream_probe(None, p, 16, 0, 4, None))
+    assert s == _lib.HC_EINVAL
+    # an empty copy enqueues nothing
+    assert lib.hc_stream_probe(None, p, 0, 1, 4, None) == _lib.HC_OK

@@ -37,3 +37,20 @@ def test_probe_of_no_records_writes_zeros(gpu):
     table = torch.ones(4, 8, device=gpu)
     out = ops.gather_probe(torch.zeros(0, 2, dtype=torch.int32, device=gpu), table, 8, grid=3)
     assert torch.equal(out, torch.zeros_like(out))
+
+
+@pytest.mark.parametrize("grid", [1, 37, 1024])
+def test_stream_probe_reads_and_copies_everything(gpu, grid):
+    """Streaming probe: the per-lane sums of the read mode add up to the sum
+    of the data (integer values: every partial sum is exact), and the copy
+    mode reproduces the source bit for bit, with a ragged tail of chunks."""
+    from paper_2602_18741_amd import ops
+    rng = np.random.default_rng(grid)
+    n16 = 250_003
+    src = torch.from_numpy(rng.integers(0, 8, 4 * n16).astype(np.float32)).to(gpu)
+    sums = torch.empty(grid * 256, device=gpu)
+    ops.stream_probe(src, sums, "read", grid)
+    assert sums.double().sum().item() == src.double().sum().item()
+    dst = torch.full_like(src, -1.0)
+    ops.stream_probe(src, dst, "copy", grid)
+    assert torch.equal(dst, src)
