@@ -65,6 +65,11 @@ hc_status check_paths_struct(const hc_paths* P, const char* fn) {
 
 }  // namespace
 
+namespace hc {
+// csrc/k_probe.hip
+hc_status launch_stream_probe(const float* src, float* dst, uint64_t n16, int mode, int grid, hipStream_t st);
+}  // namespace hc
+
 extern "C" {
 
 const char* hc_status_string(hc_status s) {

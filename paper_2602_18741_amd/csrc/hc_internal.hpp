@@ -136,7 +136,6 @@ hc_status launch_gen_vertices(const hc_path_gen& g, const uint32_t* pix_first, u
                               int64_t n_vertices, hipStream_t st);
 hc_status launch_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* scale, int64_t count,
                              int64_t n, uint32_t* out, hipStream_t st);
-hc_status launch_stream_probe(const float* src, float* dst, uint64_t n16, int mode, int grid, hipStream_t st);
 hc_status launch_gather_probe(const uint2* vtx, uint32_t nv, const float* table, uint32_t n_rows,
                               uint32_t ld, int row_floats, int unroll, int lanes_per_row, float* out,
                               int grid, hipStream_t st);
