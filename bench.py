@@ -744,6 +744,35 @@ def main():
     stream = stream_bandwidth(dev)
     copy_gbs = stream["copy_GBs"]
     log(f"streaming probe: copy {copy_gbs:.0f} GB/s (read + write), read {stream['read_GBs']:.0f} GB/s")
+
+    # the latent step's streaming kernels, timed inside the step: the texture
+    # encode (4n + 4k algorithmic bytes per texel) and the decode to XYZ
+    # (4k + 12 per pixel), against the streaming probe's read bandwidth
+    def streaming_kernels(reps=10):
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+        for e in evs:
+            e[0].record()
+            ops.encode(E, refl, n=n, out=codes)
+            e[1].record()
+            ops.encode(E, illum, n=n, out=lcodes)
+            ops.shade_latent(P, codes, lcodes, k, out=zimg)
+            e[2].record()
+            ops.decode_xyz(D, T, zimg, k, out=xyz_l)
+            e[3].record()
+        torch.cuda.synchronize()
+        out = {}
+        for name, (i, j), nbytes in (("encode_texture", (0, 1), spec.n_tex * (4 * n + 4 * k)),
+                                     ("decode_xyz", (2, 3), npx * (4 * k + 12))):
+            sec = sum(e[i].elapsed_time(e[j]) for e in evs) / reps / 1e3
+            gbs = nbytes / sec / 1e9
+            out[name] = {"us": sec * 1e6, "algorithmic_bytes": nbytes, "GBs": gbs,
+                         "frac_of_stream_read": gbs / stream["read_GBs"]}
+        return out
+
+    streaming = streaming_kernels()
+    log("in-step streaming kernels: " + ", ".join(
+        f"{key} {v['us']:.1f} us ({v['GBs']:.0f} GB/s, {v['frac_of_stream_read']:.2f} of the read probe)"
+        for key, v in streaming.items()))
     bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
     bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
     traffic = None if stress else measured_traffic()
@@ -846,6 +875,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "stream_probe": stream,
+        "streaming_kernels": streaming,
         "spectral": {"value": nv / spe_wall, "unit": "path-vertices/s", "ms_per_step": spe_wall * 1e3,
                      "kernel_ms": spe_kern * 1e3, "achieved_GBs": bytes_spe / spe_kern / 1e9,
                      "algorithmic_bytes": bytes_spe, "roofline": roof_spe},

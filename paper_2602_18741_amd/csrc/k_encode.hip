@@ -181,9 +181,45 @@ template <int NB>
 __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
     __shared__ float s_M[3 * kMaxK];
     extern __shared__ float s_D[];  // n x k, only when spectra are requested
-    stage_decoder<NB>(a.D, a.T, a.n, a.k, s_M, a.spectra ? s_D : nullptr);
-    __syncthreads();
     const int64_t q0 = int64_t(blockIdx.x) * kThreads * kDecodePixels + threadIdx.x;
+    if (!a.spectra) {
+        // the latent pixels of all kDecodePixels pixels are in flight while
+        // M is staged (pixels past the image read pixel 0 and are dropped)
+        float4 zv[kDecodePixels][NB];
+#pragma unroll
+        for (int i = 0; i < kDecodePixels; ++i) {
+            const int64_t q = q0 + int64_t(i) * kThreads;
+            const float* row = a.zimg + (q < a.n_pixels ? q : 0) * a.ld_z;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) zv[i][b] = ld4(row + 4 * b);
+        }
+        stage_decoder<NB>(a.D, a.T, a.n, a.k, s_M, nullptr);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kDecodePixels; ++i) {
+            const int64_t q = q0 + int64_t(i) * kThreads;
+            if (q >= a.n_pixels) break;
+            float x = 0.f, y = 0.f, w = 0.f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float z3[3] = {zv[i][b].x, zv[i][b].y, zv[i][b].z};
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const int c = 3 * b + e;
+                    x += s_M[c] * z3[e];
+                    y += s_M[3 * NB + c] * z3[e];
+                    w += s_M[6 * NB + c] * z3[e];
+                }
+            }
+            float* o = a.xyz + q * 3;
+            stg_f32(o + 0, x);
+            stg_f32(o + 1, y);
+            stg_f32(o + 2, w);
+        }
+        return;
+    }
+    stage_decoder<NB>(a.D, a.T, a.n, a.k, s_M, s_D);
+    __syncthreads();
     for (int i = 0; i < kDecodePixels; ++i) {
         const int64_t q = q0 + int64_t(i) * kThreads;
         if (q >= a.n_pixels) return;
@@ -219,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void decode_tiles_kernel(const hc_frame* 
 #define HC_NB_CASES(M) \
     M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
 
-int rows_per_block(int nq) { return nq <= 8 ? 256 : (nq <= 16 ? 128 : 64); }
+int rows_per_block(int nq) { return nq <= 8 ? 64 : (nq <= 16 ? 32 : 16); }
 
 }  // namespace
 
