@@ -109,7 +109,7 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "shade_latent_1080p16_traffic.json
 def kernel_source_sha():
     """Digest of the sources the latent shading kernel is built from."""
     h = hashlib.sha256()
-    for f in ("k_latent.hip", "shade_common.hpp", "hc_internal.hpp"):
+    for f in ("k_latent.hip", "shade_common.hpp", "decode_common.hpp", "hc_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2602_18741_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -147,7 +147,7 @@ def record_traffic(d_fetch, d_write, d_copy_fetch, d_copy_write, d_req=None):
     w_scale = gib_kib / _counter_mean(csv(d_copy_write), "copyBuffer", "WRITE_SIZE")
     fetch = _counter_mean(csv(d_fetch), kern, "FETCH_SIZE") * 1024 * f_scale
     write = _counter_mean(csv(d_write), kern, "WRITE_SIZE") * 1024 * w_scale
-    d = {"kernel": "shade_latent_kernel<2>", "workload": WORKLOAD,
+    d = {"kernel": "shade_latent_kernel<2> (decode in the epilogue)", "workload": WORKLOAD,
          "kernel_source_sha": kernel_source_sha(), "fetch_scale": f_scale, "write_scale": w_scale,
          "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
          "fetch_plus_write_bytes_per_launch": fetch + write, "note": TRAFFIC_NOTE}
@@ -295,19 +295,19 @@ def stress_leg(w, args, dev, copy_gbs, cpu):
         f"fitted ({cc['steps']} steps, loss {loss:.4g}) in {time.time() - t0:.1f} s")
     codes = torch.empty(spec.n_tex, ld_z, device=dev)
     lcodes = torch.empty(spec.n_illum, ld_z, device=dev)
-    zimg = torch.empty(npx, latent_width(k), device=dev)
+    Mdec = torch.empty(3, 3 * ops.blocks(k), device=dev)
     xyz_l = torch.empty(npx, 3, device=dev)
     xyz_s = torch.empty(npx, 3, device=dev)
 
     def latent_step(ev=None):
         ops.encode(E, refl, n=n, out=codes)
         ops.encode(E, illum, n=n, out=lcodes)
+        ops.decode_matrix(D, T, k, out=Mdec)
         if ev:
             ev[0].record()
-        ops.shade_latent(P, codes, lcodes, k, out=zimg)
+        ops.shade_latent_xyz(P, codes, lcodes, Mdec, k, out=xyz_l)
         if ev:
             ev[1].record()
-        ops.decode_xyz(D, T, zimg, k, out=xyz_l)
 
     def spectral_step(ev=None):
         if ev:
@@ -332,14 +332,15 @@ def stress_leg(w, args, dev, copy_gbs, cpu):
         log(f"stress {name}: step {wall * 1e3:.2f} ms, shade kernel {kern * 1e3:.2f} ms")
     de = colour.frame_difference(xyz_s.cpu().numpy(), xyz_l.cpu().numpy())
     log(f"stress CIEDE2000 latent vs spectral: mean {de['mean']:.3f}, p95 {de['p95']:.3f}")
-    del zimg, xyz_l, xyz_s
+    del xyz_l, xyz_s
     ceil_l = gather_ceiling(P.vtx, codes, 4 * ops.blocks(k), 1, dev, reps=2)
     ceil_s = gather_ceiling(P.vtx, refl, 4 * ((n + 3) // 4), 8, dev, reps=2)
     log(f"stress gather ceilings: codes {ceil_l['rows_per_s'] / 1e9:.1f} G rows/s, "
         f"spectra {ceil_s['rows_per_s'] / 1e9:.1f} G rows/s")
-    bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
+    bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (12 + 4)
     bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
-    lat = frame_roofline(f"shade_latent_kernel<{ops.blocks(k)}>", bytes_lat, res["latent"][1], nv, ceil_l,
+    lat = frame_roofline(f"shade_latent_kernel<{ops.blocks(k)}> (decode in the epilogue)", bytes_lat,
+                         res["latent"][1], nv, ceil_l,
                          copy_gbs, "random 64-byte code rows from a 1 GiB table in HBM (one 128-byte "
                          "line each)")
     spe = frame_roofline("shade_spectral_kernel (n = 81)", bytes_spe, res["spectral"][1], nv, ceil_s, copy_gbs,
@@ -687,18 +688,21 @@ def main():
     codes = torch.empty(spec.n_tex, ld_z, device=dev)
     lcodes = torch.empty(spec.n_illum, ld_z, device=dev)
     zimg = torch.zeros(npx, ops.latent_width(k), device=dev)
+    Mdec = torch.empty(3, 3 * ops.blocks(k), device=dev)
     xyz_l = torch.empty(npx, 3, device=dev)
     xyz_s = torch.empty(npx, 3, device=dev)
 
+    # one frame: encode the texture and the lights, form the decoder matrix
+    # M = T D, shade all B passes with the per-pixel decode in the epilogue
     def latent_step(ev=None):
         ops.encode(E, refl, n=n, out=codes)
         ops.encode(E, illum, n=n, out=lcodes)
+        ops.decode_matrix(D, T, k, out=Mdec)
         if ev:
             ev[0].record()
-        ops.shade_latent(P, codes, lcodes, k, out=zimg)
+        ops.shade_latent_xyz(P, codes, lcodes, Mdec, k, out=xyz_l)
         if ev:
             ev[1].record()
-        ops.decode_xyz(D, T, zimg, k, out=xyz_l)
 
     def spectral_step(ev=None):
         if ev:
@@ -745,19 +749,24 @@ def main():
     copy_gbs = stream["copy_GBs"]
     log(f"streaming probe: copy {copy_gbs:.0f} GB/s (read + write), read {stream['read_GBs']:.0f} GB/s")
 
-    # the latent step's streaming kernels, timed inside the step: the texture
-    # encode (4n + 4k algorithmic bytes per texel) and the decode to XYZ
-    # (4k + 12 per pixel), against the streaming probe's read bandwidth
+    # the streaming kernels against the streaming probe's read bandwidth: the
+    # texture encode timed inside the step (4n + 4k algorithmic bytes per
+    # texel), and the decode of a latent image to XYZ as its own launch (4k +
+    # 12 per pixel; the step decodes in the shading kernel's epilogue, and its
+    # XYZ must equal this launch's bit for bit)
     def streaming_kernels(reps=10):
+        ops.shade_latent(P, codes, lcodes, k, out=zimg)
+        xyz_d = torch.empty_like(xyz_l)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
         for e in evs:
             e[0].record()
             ops.encode(E, refl, n=n, out=codes)
             e[1].record()
             ops.encode(E, illum, n=n, out=lcodes)
-            ops.shade_latent(P, codes, lcodes, k, out=zimg)
+            ops.decode_matrix(D, T, k, out=Mdec)
+            ops.shade_latent_xyz(P, codes, lcodes, Mdec, k, out=xyz_l)
             e[2].record()
-            ops.decode_xyz(D, T, zimg, k, out=xyz_l)
+            ops.decode_xyz(D, T, zimg, k, out=xyz_d)
             e[3].record()
         torch.cuda.synchronize()
         out = {}
@@ -767,13 +776,16 @@ def main():
             gbs = nbytes / sec / 1e9
             out[name] = {"us": sec * 1e6, "algorithmic_bytes": nbytes, "GBs": gbs,
                          "frac_of_stream_read": gbs / stream["read_GBs"]}
+        out["decode_xyz"]["in_step"] = False
+        out["fused_decode_equals_decode_launch"] = bool(torch.equal(xyz_l, xyz_d))
         return out
 
     streaming = streaming_kernels()
-    log("in-step streaming kernels: " + ", ".join(
+    log("streaming kernels: " + ", ".join(
         f"{key} {v['us']:.1f} us ({v['GBs']:.0f} GB/s, {v['frac_of_stream_read']:.2f} of the read probe)"
-        for key, v in streaming.items()))
-    bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (4 * k + 4)
+        for key, v in streaming.items() if isinstance(v, dict))
+        + f"; fused decode equals the decode launch: {streaming['fused_decode_equals_decode_launch']}")
+    bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (12 + 4)
     bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
     traffic = None if stress else measured_traffic()
 
@@ -791,7 +803,8 @@ def main():
         f"{ceil_spe['rows_per_s'] / 1e9:.1f} G rows/s, 1 GiB table of 32-byte rows "
         f"{ceil_1g['rows_per_s'] / 1e9:.1f} G rows/s")
     tbl_mb = codes.numel() * 4 / 2 ** 20
-    roof = frame_roofline(f"shade_latent_kernel<{ops.blocks(k)}>", bytes_lat, lat_kern, nv, ceil_lat,
+    roof = frame_roofline(f"shade_latent_kernel<{ops.blocks(k)}> (decode in the epilogue)", bytes_lat,
+                          lat_kern, nv, ceil_lat,
                           copy_gbs, f"random {4 * ops.blocks(k) * 4}-byte code rows from a "
                           f"{tbl_mb:.0f} MiB table" + (" resident in the 256 MB MALL" if tbl_mb < 256
                                                         else " in HBM") + " (one 128-byte line each)")

@@ -169,6 +169,33 @@ hc_status hc_decode_xyz(const float* D, int32_t n, int32_t k, const float* T,
                         float* spectra, int64_t ld_spectra, void* stream);
 
 /*
+ * hc_decode_matrix -- the per-pixel decode of Eq. 4 (right) as one matrix,
+ * M = T D, so that xyz = M z for a latent pixel z.
+ *   D: n x k row-major float32 (W_dec).  T: 3 x n row-major float32.
+ *   M: 3 rows of 3*ceil(k/3) float32, row-major, columns in the blocked
+ *      channel order of the latent layout (channel c of block b at column
+ *      3b + c); the columns past k are written 0.  Caller-owned, 4-byte
+ *      aligned.
+ * Entry (r, c) is summed over the n samples in order; hc_decode_xyz stages
+ * the same entries, so an image decoded by either route has the same bits.
+ */
+hc_status hc_decode_matrix(const float* D, int32_t n, int32_t k, const float* T, float* M,
+                           void* stream);
+
+/*
+ * hc_shade_latent_xyz -- the latent frame in one launch (Eq. 6 products over
+ * all ceil(k/3) blocks, Sec. 6.1, then the per-pixel decode of Eq. 4 / Fig. 2b):
+ *   xyz[q] = M zimg[q],
+ * where zimg[q] is the pixel mean hc_shade_latent computes (not stored) and
+ * M comes from hc_decode_matrix.  xyz: n_pixels x 3 float32, contiguous,
+ * 4-byte aligned.  The result equals hc_shade_latent (all blocks) followed by
+ * hc_decode_xyz with the D and T that gave M, bit for bit.  Shape, record
+ * and alignment requirements are those of hc_shade_latent.
+ */
+hc_status hc_shade_latent_xyz(const hc_paths* paths, const hc_latent_assets* assets, const float* M,
+                              float* xyz, void* stream);
+
+/*
  * hc_check_paths -- count invalid records (see hc_paths).
  *   counts: 3 device uint64: [0] paths whose light id >= n_illum,
  *   [1] vertex records (counted once per pixel range covering them) whose
@@ -226,6 +253,14 @@ typedef struct hc_tile {
 hc_status hc_shade_latent_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
                                 const int32_t* n_tiles, int32_t max_tiles, int32_t k, int32_t grid,
                                 void* stream);
+/* Latent shading of the tiles with the per-pixel decode in the epilogue (as
+ * hc_shade_latent_xyz): the tiles' pixels of frame xyz, with one decoder
+ * matrix M (hc_decode_matrix, 3 x 3*ceil(k/3)) for every frame; the frames'
+ * latent images are neither read nor written.  Bit for bit equal to
+ * hc_shade_latent_tiles followed by hc_decode_tiles with the D and T of M. */
+hc_status hc_shade_latent_xyz_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
+                                    const int32_t* n_tiles, int32_t max_tiles, int32_t k, const float* M,
+                                    int32_t grid, void* stream);
 /* Spectral shading of the tiles (n samples, T = T_cmf 3 x n) into frame xyz. */
 hc_status hc_shade_spectral_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
                                   const int32_t* n_tiles, int32_t max_tiles, int32_t n,

@@ -114,6 +114,8 @@ _PROTOS = {
     "hc_shade_spectral": (i32, [C.POINTER(Paths), C.POINTER(SpectralAssets), vp, vp, vp]),
     "hc_shade_latent": (i32, [C.POINTER(Paths), C.POINTER(LatentAssets), i32, i32, vp, i64, vp]),
     "hc_decode_xyz": (i32, [vp, i32, i32, vp, vp, i64, i64, vp, vp, i64, vp]),
+    "hc_shade_latent_xyz": (i32, [C.POINTER(Paths), C.POINTER(LatentAssets), vp, vp, vp]),
+    "hc_decode_matrix": (i32, [vp, i32, i32, vp, vp, vp]),
     "hc_check_paths": (i32, [C.POINTER(Paths), i64, i32, vp, vp]),
     "hc_codec_workspace_size": (sz, [i32, i32, i64]),
     "hc_codec_step": (i32, [C.POINTER(CodecArgs)]),
@@ -124,6 +126,7 @@ _PROTOS = {
     "hc_upsample_train_workspace_size": (sz, [i32, i64]),
     "hc_upsample_train_step": (i32, [vp]),
     "hc_shade_latent_tiles": (i32, [vp, i32, vp, vp, i32, i32, i32, vp]),
+    "hc_shade_latent_xyz_tiles": (i32, [vp, i32, vp, vp, i32, i32, vp, i32, vp]),
     "hc_shade_spectral_tiles": (i32, [vp, i32, vp, vp, i32, i32, vp, i32, vp]),
     "hc_decode_tiles": (i32, [vp, i32, vp, vp, i32, vp, i32, i32, vp, i32, vp]),
     "hc_encode_jobs": (i32, [vp, vp, i32, vp, i32, i32, i32, vp]),

@@ -65,11 +65,6 @@ hc_status check_paths_struct(const hc_paths* P, const char* fn) {
 
 }  // namespace
 
-namespace hc {
-// csrc/k_probe.hip
-hc_status launch_stream_probe(const float* src, float* dst, uint64_t n16, int mode, int grid, hipStream_t st);
-}  // namespace hc
-
 extern "C" {
 
 const char* hc_status_string(hc_status s) {
@@ -161,6 +156,41 @@ hc_status hc_shade_latent(const hc_paths* paths, const hc_latent_assets* A, int3
                                as_stream(stream));
 }
 
+hc_status hc_shade_latent_xyz(const hc_paths* paths, const hc_latent_assets* A, const float* M, float* xyz,
+                              void* stream) {
+    clear_error();
+    const char* fn = "hc_shade_latent_xyz";
+    hc_status s = check_paths_struct(paths, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(A != nullptr, HC_EINVAL, "%s: assets is NULL", fn);
+    HC_REQUIRE(A->k >= 1 && A->k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, A->k, kMaxK);
+    const int nb = int(ceil_div(A->k, 3));
+    HC_REQUIRE(A->ld >= 4 * nb && A->ld % 4 == 0 && A->ld_illum >= 4 * nb && A->ld_illum % 4 == 0,
+               HC_ESHAPE, "%s: ld/ld_illum must be >= 4*ceil(k/3) and multiples of 4", fn);
+    HC_REQUIRE(A->ld < (int64_t(1) << 31), HC_ESHAPE, "%s: ld must be < 2^31", fn);
+    HC_REQUIRE(A->n_texels >= 1 && A->n_texels < (int64_t(1) << 32), HC_ESHAPE,
+               "%s: n_texels outside [1, 2^32)", fn);
+    HC_REQUIRE(A->n_illum >= 1 && A->n_illum <= (1 << 24), HC_ESHAPE, "%s: n_illum outside [1, 2^24]",
+               fn);
+    if (paths->n_pixels == 0) return HC_OK;
+    HC_REQUIRE(A->codes && A->illum_codes && M && xyz, HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned16(A->codes) && aligned16(A->illum_codes), HC_EALIGN,
+               "%s: codes/illum_codes need 16-byte alignment", fn);
+    HC_REQUIRE(aligned4(M) && aligned4(xyz), HC_EALIGN, "%s: M/xyz need 4-byte alignment", fn);
+    return launch_shade_latent_xyz(*paths, *A, M, xyz, as_stream(stream));
+}
+
+hc_status hc_decode_matrix(const float* D, int32_t n, int32_t k, const float* T, float* M, void* stream) {
+    clear_error();
+    const char* fn = "hc_decode_matrix";
+    HC_REQUIRE(k >= 1 && k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, k, kMaxK);
+    HC_REQUIRE(n >= 1 && n <= kMaxN, HC_ESHAPE, "%s: n=%d outside [1, %d]", fn, n, kMaxN);
+    HC_REQUIRE(D && T && M, HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned4(D) && aligned4(T) && aligned4(M), HC_EALIGN, "%s: D/T/M need 4-byte alignment",
+               fn);
+    return launch_decode_matrix(D, n, k, T, M, as_stream(stream));
+}
+
 hc_status hc_decode_xyz(const float* D, int32_t n, int32_t k, const float* T, const float* zimg,
                         int64_t n_pixels, int64_t ld_zimg, float* xyz, float* spectra,
                         int64_t ld_spectra, void* stream) {
@@ -203,6 +233,19 @@ hc_status hc_shade_latent_tiles(const hc_frame* frames, int32_t n_frames, const 
     HC_REQUIRE(k >= 1 && k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, k, kMaxK);
     return launch_shade_latent_tiles(frames, n_frames, tiles, n_tiles, max_tiles, k, grid,
                                      as_stream(stream));
+}
+
+hc_status hc_shade_latent_xyz_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,
+                                    const int32_t* n_tiles, int32_t max_tiles, int32_t k, const float* M,
+                                    int32_t grid, void* stream) {
+    clear_error();
+    const char* fn = "hc_shade_latent_xyz_tiles";
+    hc_status s = check_tables(frames, n_frames, tiles, n_tiles, max_tiles, grid, fn);
+    if (s != HC_OK) return s;
+    HC_REQUIRE(k >= 1 && k <= kMaxK, HC_ESHAPE, "%s: k=%d outside [1, %d]", fn, k, kMaxK);
+    HC_REQUIRE(M && aligned4(M), HC_EINVAL, "%s: M NULL or misaligned", fn);
+    return launch_shade_latent_xyz_tiles(frames, n_frames, tiles, n_tiles, max_tiles, k, M, grid,
+                                         as_stream(stream));
 }
 
 hc_status hc_shade_spectral_tiles(const hc_frame* frames, int32_t n_frames, const hc_tile* tiles,

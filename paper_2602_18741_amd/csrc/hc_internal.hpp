@@ -105,9 +105,15 @@ hc_status launch_shade_spectral(const hc_paths& P, const hc_spectral_assets& A, 
                                 float* xyz, hipStream_t st);
 hc_status launch_shade_latent(const hc_paths& P, const hc_latent_assets& A, int block_first,
                               int block_count, float* zimg, int64_t ld_zimg, hipStream_t st);
+hc_status launch_shade_latent_xyz(const hc_paths& P, const hc_latent_assets& A, const float* M, float* xyz,
+                                  hipStream_t st);
+hc_status launch_decode_matrix(const float* D, int n, int k, const float* T, float* M, hipStream_t st);
 hc_status launch_shade_latent_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
                                     const int32_t* n_tiles, int max_tiles, int k, int grid,
                                     hipStream_t st);
+hc_status launch_shade_latent_xyz_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
+                                        const int32_t* n_tiles, int max_tiles, int k, const float* M, int grid,
+                                        hipStream_t st);
 hc_status launch_shade_spectral_tiles(const hc_frame* frames, int n_frames, const hc_tile* tiles,
                                       const int32_t* n_tiles, int max_tiles, int n, const float* T,
                                       int grid, hipStream_t st);
@@ -139,5 +145,6 @@ hc_status launch_gen_indices(uint64_t seed, uint64_t ctr0, const int64_t* scale,
 hc_status launch_gather_probe(const uint2* vtx, uint32_t nv, const float* table, uint32_t n_rows,
                               uint32_t ld, int row_floats, int unroll, int lanes_per_row, float* out,
                               int grid, hipStream_t st);
+hc_status launch_stream_probe(const float* src, float* dst, uint64_t n16, int mode, int grid, hipStream_t st);
 
 }  // namespace hc

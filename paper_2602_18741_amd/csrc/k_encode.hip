@@ -3,7 +3,7 @@
 // with k <= 48, n <= 128) done in registers against matrices staged in LDS;
 // the kernels stream rows, so HBM bandwidth bounds them.
 
-#include "hc_internal.hpp"
+#include "decode_common.hpp"
 
 namespace hc {
 namespace {
@@ -127,13 +127,7 @@ struct DecodeArgs {
 template <int NB>
 __device__ __forceinline__ void stage_decoder(const float* D, const float* T, int n, int k, float* s_M,
                                               float* s_D) {
-    for (int e = threadIdx.x; e < 9 * NB; e += kThreads) {
-        const int ch = e / (3 * NB), c = e % (3 * NB);
-        float acc = 0.f;
-        if (c < k)
-            for (int i = 0; i < n; ++i) acc += T[ch * n + i] * D[i * k + c];
-        s_M[e] = acc;
-    }
+    for (int e = threadIdx.x; e < 9 * NB; e += kThreads) s_M[e] = decoder_entry<NB>(D, T, n, k, e);
     if (s_D)
         for (int e = threadIdx.x; e < n * k; e += kThreads) s_D[e] = D[e];
 }
@@ -151,14 +145,8 @@ __device__ __forceinline__ void decode_pixel(const float* s_M, const float* s_D,
         z[3 * b + 1] = v.y;
         z[3 * b + 2] = v.z;
     }
-    // M has zero columns past k, so padded channels add nothing
-    float x = 0.f, y = 0.f, w = 0.f;
-#pragma unroll
-    for (int c = 0; c < 3 * NB; ++c) {
-        x += s_M[c] * z[c];
-        y += s_M[3 * NB + c] * z[c];
-        w += s_M[6 * NB + c] * z[c];
-    }
+    float x, y, w;
+    decode_dot<NB>(s_M, z, x, y, w);
     float* o = xyz + q * 3;
     stg_f32(o + 0, x);
     stg_f32(o + 1, y);
@@ -199,18 +187,15 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
         for (int i = 0; i < kDecodePixels; ++i) {
             const int64_t q = q0 + int64_t(i) * kThreads;
             if (q >= a.n_pixels) break;
-            float x = 0.f, y = 0.f, w = 0.f;
+            float z[3 * NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const float z3[3] = {zv[i][b].x, zv[i][b].y, zv[i][b].z};
-#pragma unroll
-                for (int e = 0; e < 3; ++e) {
-                    const int c = 3 * b + e;
-                    x += s_M[c] * z3[e];
-                    y += s_M[3 * NB + c] * z3[e];
-                    w += s_M[6 * NB + c] * z3[e];
-                }
+                z[3 * b] = zv[i][b].x;
+                z[3 * b + 1] = zv[i][b].y;
+                z[3 * b + 2] = zv[i][b].z;
             }
+            float x, y, w;
+            decode_dot<NB>(s_M, z, x, y, w);
             float* o = a.xyz + q * 3;
             stg_f32(o + 0, x);
             stg_f32(o + 1, y);
@@ -250,6 +235,22 @@ __global__ __launch_bounds__(kThreads) void decode_tiles_kernel(const hc_frame* 
         for (int64_t q = begin + threadIdx.x; q < end; q += kThreads)
             decode_pixel<NB>(s_M, nullptr, n, k, fr.image, fr.ld_image, fr.xyz, nullptr, 0, q);
     }
+}
+
+// M = T D written out (3 x 3NB, zero columns past k), for the shading
+// kernel's fused decode.  One workgroup: D and T are staged in LDS with one
+// load per thread in flight, so each entry's chain of n multiply-adds reads
+// LDS instead of waiting on global loads (the same operands, so the same
+// bits as the decode kernels' staging).
+template <int NB>
+__global__ __launch_bounds__(kThreads) void decode_matrix_kernel(const float* D, const float* T, int n, int k,
+                                                                 float* M) {
+    __shared__ float s_D[kMaxN * kMaxK];
+    __shared__ float s_T[3 * kMaxN];
+    for (int i = threadIdx.x; i < n * k; i += kThreads) s_D[i] = D[i];
+    for (int i = threadIdx.x; i < 3 * n; i += kThreads) s_T[i] = T[i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 9 * NB; e += kThreads) stg_f32(M + e, decoder_entry<NB>(s_D, s_T, n, k, e));
 }
 
 #define HC_NB_CASES(M) \
@@ -320,6 +321,19 @@ hc_status launch_decode(const float* D, int n, int k, const float* T, const floa
             return HC_EUNSUPPORTED;
     }
     return launch_status("hc_decode_xyz");
+}
+
+hc_status launch_decode_matrix(const float* D, int n, int k, const float* T, float* M, hipStream_t st) {
+    switch ((k + 2) / 3) {
+#define HC_DECM(NB) \
+    case NB: hipLaunchKernelGGL(decode_matrix_kernel<NB>, dim3(1), dim3(kThreads), 0, st, D, T, n, k, M); break;
+        HC_NB_CASES(HC_DECM)
+#undef HC_DECM
+        default:
+            set_error("hc_decode_matrix: k=%d unsupported", k);
+            return HC_EUNSUPPORTED;
+    }
+    return launch_status("hc_decode_matrix");
 }
 
 hc_status launch_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, int max_jobs,

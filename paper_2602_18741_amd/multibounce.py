@@ -41,8 +41,8 @@ def chain_xyz(E, D, T, refl, lights, k: int, n: int, bounces: int = 3, paths=Non
         raise ValueError(f"refl needs {C * bounces} rows (C x bounces), has {refl.shape[0]}")
     paths = paths or chain_paths(C, bounces, refl.device)
     xs = ops.shade_spectral(paths, refl, lights, T, n)
-    z = ops.shade_latent(paths, ops.encode(E, refl, n), ops.encode(E, lights, n), k)
-    xl = ops.decode_xyz(D, T, z, k)
+    xl = ops.shade_latent_xyz(paths, ops.encode(E, refl, n), ops.encode(E, lights, n),
+                              ops.decode_matrix(D, T, k), k)
     return xs[:C], xs[C:].view(bounces, C, 3), xl[C:].view(bounces, C, 3)
 
 

@@ -132,6 +132,35 @@ def shade_latent(paths: Paths, codes: torch.Tensor, illum_codes: torch.Tensor, k
     return out
 
 
+def shade_latent_xyz(paths: Paths, codes: torch.Tensor, illum_codes: torch.Tensor, M: torch.Tensor,
+                     k: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """XYZ of the latent frame in one launch: the pixel means over all B
+    passes, decoded with M = decode_matrix(D, T, k)."""
+    _dev(codes, illum_codes, M, out)
+    if tuple(M.shape) != (3, 3 * blocks(k)) or not M.is_contiguous():
+        raise ValueError(f"M must be a contiguous (3, {3 * blocks(k)}) tensor from decode_matrix")
+    if out is None:
+        out = torch.empty(paths.n_pixels, 3, dtype=torch.float32, device=codes.device)
+    A = _lib.LatentAssets(codes.data_ptr(), codes.shape[0], k, 0, codes.stride(0),
+                          illum_codes.data_ptr(), illum_codes.shape[0], 0, illum_codes.stride(0))
+    P = paths.c()
+    check(load().hc_shade_latent_xyz(C.byref(P), C.byref(A), _ptr(M), _ptr(out), _stream()),
+          "hc_shade_latent_xyz")
+    return out
+
+
+def decode_matrix(D: torch.Tensor, T: torch.Tensor, k: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """M = T D as 3 rows of 3 * blocks(k) columns (blocked channel order,
+    zero past k), the decoder argument of shade_latent_xyz."""
+    _dev(D, T, out)
+    n = D.shape[0]
+    if out is None:
+        out = torch.empty(3, 3 * blocks(k), dtype=torch.float32, device=D.device)
+    check(load().hc_decode_matrix(_ptr(D.contiguous()), n, k, _ptr(T.contiguous()), _ptr(out), _stream()),
+          "hc_decode_matrix")
+    return out
+
+
 def decode_xyz(D: torch.Tensor, T: torch.Tensor, zimg: torch.Tensor, k: int, spectra: bool = False,
                out: torch.Tensor | None = None):
     """XYZ (and optionally decoded spectra) of a blocked latent image."""

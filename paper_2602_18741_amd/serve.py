@@ -10,7 +10,8 @@ instead of waiting for that frame to finish.  Frames whose last tile is in an
 iteration are decoded in the same iteration.
 
 On the GPU an iteration is one replay of a captured HIP graph holding the
-table-driven encode -> shade -> decode launches; the host only rewrites the
+table-driven launches (latent form: encode, then shading with the per-pixel
+decode in its epilogue, or a separate decode launch); the host only rewrites the
 small frame / tile / job tables (copied to the device before the replay) and
 launches the per-request path generators.  Up to two iterations are in
 flight, so table building overlaps device work.
@@ -370,13 +371,17 @@ class _Range:
 class GpuBackend:
     """Executes plans with the table-driven libhc launches, one captured
     graph per form.  form: "latent" (encode -> shade -> decode) or
-    "spectral" (shade straight to XYZ)."""
+    "spectral" (shade straight to XYZ).  In the latent form fused_decode
+    (the default) decodes each shaded pixel in the shading launch with the
+    decoder matrix M = T D, formed once here: no latent image is kept and
+    the plan's decode tiles are not needed; fused_decode=False keeps the
+    latent images and runs the decode launch over them (same bits)."""
 
     JOB_ROWS = 2048          # spectra rows per encode-table entry: a 2048^2 asset spreads over 2,048 workgroups
 
     def __init__(self, assets, lights, T, E=None, D=None, form: str = "latent", max_frames: int = 64,
                  max_tiles: int = 8192, max_jobs: int = 8192, grid: int = 0, device="cuda",
-                 use_graph: bool = True, reserve: float = 0.1):
+                 use_graph: bool = True, reserve: float = 0.1, fused_decode: bool = True):
         import torch
 
         from . import ops
@@ -385,6 +390,7 @@ class GpuBackend:
         self.Frame, self.Tile, self.EncodeJob = Frame, Tile, EncodeJob
         self.dev = torch.device(device)
         self.form = form
+        self.fused = fused_decode and form == "latent"
         self.assets = assets              # list of pinned host float32 (texels, ld) tensors
         self.n = T.shape[1]
         self.k = E.shape[0] if E is not None else 0
@@ -399,6 +405,7 @@ class GpuBackend:
             if form == "latent":
                 self.lights = torch.empty(lights.shape[0], ops.latent_width(self.k), device=self.dev)
                 ops.encode(self.E, lights_d, n=self.n, out=self.lights)
+                self.M = ops.decode_matrix(self.D, self.T, self.k)
             else:
                 self.lights = lights_d
         self.stream.synchronize()
@@ -434,12 +441,17 @@ class GpuBackend:
         if self.form == "latent":
             self.check(self.lib.hc_encode_jobs(self.d_jobs, cnt + 8, self.max_jobs, self.E.data_ptr(),
                                                self.k, self.n, self.grid, st), "hc_encode_jobs")
-            self.check(self.lib.hc_shade_latent_tiles(self.d_frames, self.max_frames, self.d_tiles, cnt,
-                                                      self.max_tiles, self.k, self.grid, st),
-                       "hc_shade_latent_tiles")
-            self.check(self.lib.hc_decode_tiles(self.d_frames, self.max_frames, self.d_dtiles, cnt + 4,
-                                                self.max_tiles, self.D.data_ptr(), self.n, self.k,
-                                                self.T.data_ptr(), self.grid, st), "hc_decode_tiles")
+            if self.fused:
+                self.check(self.lib.hc_shade_latent_xyz_tiles(self.d_frames, self.max_frames, self.d_tiles, cnt,
+                                                              self.max_tiles, self.k, self.M.data_ptr(),
+                                                              self.grid, st), "hc_shade_latent_xyz_tiles")
+            else:
+                self.check(self.lib.hc_shade_latent_tiles(self.d_frames, self.max_frames, self.d_tiles, cnt,
+                                                          self.max_tiles, self.k, self.grid, st),
+                           "hc_shade_latent_tiles")
+                self.check(self.lib.hc_decode_tiles(self.d_frames, self.max_frames, self.d_dtiles, cnt + 4,
+                                                    self.max_tiles, self.D.data_ptr(), self.n, self.k,
+                                                    self.T.data_ptr(), self.grid, st), "hc_decode_tiles")
         else:
             self.check(self.lib.hc_shade_spectral_tiles(self.d_frames, self.max_frames, self.d_tiles, cnt,
                                                         self.max_tiles, self.n, self.T.data_ptr(),
@@ -480,7 +492,9 @@ class GpuBackend:
 
     def request_bytes(self, req) -> float:
         paths = req.n_pixels * req.spp * (4 + 8 * req.l_max) + 4 * req.n_pixels
-        out = req.n_pixels * (12 + (4 * self.ops.latent_width(self.k) if self.form == "latent" else 0))
+        # XYZ, plus the latent image when the decode is a launch of its own
+        image = 4 * self.ops.latent_width(self.k) if self.form == "latent" and not self.fused else 0
+        out = req.n_pixels * (12 + image)
         return float(paths + out + 4096)
 
     def asset_bytes(self, asset, loading: bool) -> float:
@@ -537,7 +551,7 @@ class GpuBackend:
                                       device=self.dev), req.n_pixels, req.spp)
             g = self._gen(req, P, tex.shape[0])
             image = (torch.empty(req.n_pixels, ops.latent_width(self.k), device=self.dev)
-                     if self.form == "latent" else None)
+                     if self.form == "latent" and not self.fused else None)
             xyz = torch.empty(req.n_pixels, 3, device=self.dev)
         f = self.frames[req.slot]
         f.hdr, f.pix_first, f.vtx = P.hdr.data_ptr(), P.pix_first.data_ptr(), P.vtx.data_ptr()
@@ -595,7 +609,9 @@ class GpuBackend:
         jobs = np.concatenate(parts) if parts else np.zeros(0, self._JOB_DT)
         if jobs.size > self.max_jobs:
             raise RuntimeError("iteration exceeds the encode table capacity")
-        shade, decode = span_tiles(plan.shade), span_tiles(plan.decode)
+        shade = span_tiles(plan.shade)
+        # the fused latent launch decodes as it shades: no decode tiles
+        decode = span_tiles([] if self.fused else plan.decode)
         if max(shade[0].size, decode[0].size) > self.max_tiles:
             raise RuntimeError("iteration exceeds the tile table capacity")
         hp = h.data_ptr()

@@ -262,3 +262,49 @@ def test_stream_probe_rejects_bad_arguments(lib):
     assert s == _lib.HC_EINVAL
     # an empty copy enqueues nothing
     assert lib.hc_stream_probe(None, p, 0, 1, 4, None) == _lib.HC_OK
+
+
+def test_fused_latent_frame_and_decode_matrix_validate(lib):
+    P = _lib.Paths(10, 4, 0, 0x1000, 0x1000, 0x1000, 5)
+    L = _lib.LatentAssets(0x1000, 4, 6, 0, 8, 0x1000, 2, 0, 8)
+    M, xyz = C.c_void_p(0x2000), C.c_void_p(0x3000)
+    s, msg = _err(lib.hc_shade_latent_xyz(C.byref(P), C.byref(L), None, xyz, None))
+    assert s == _lib.HC_EINVAL and "NULL" in msg
+    s, msg = _err(lib.hc_shade_latent_xyz(C.byref(P), C.byref(L), C.c_void_p(0x2002), xyz, None))
+    assert s == _lib.HC_EALIGN and "M/xyz" in msg
+    s, msg = _err(lib.hc_shade_latent_xyz(C.byref(P), C.byref(L), M, C.c_void_p(0x3001), None))
+    assert s == _lib.HC_EALIGN
+    s, msg = _err(lib.hc_shade_latent_xyz(C.byref(P), C.byref(_lib.LatentAssets(0x1000, 4, 49, 0, 68, 0x1000, 2,
+                                                                                  0, 68)), M, xyz, None))
+    assert s == _lib.HC_ESHAPE and "k=49" in msg
+    s, msg = _err(lib.hc_shade_latent_xyz(C.byref(P), C.byref(_lib.LatentAssets(0x1000, 4, 6, 0, 4, 0x1000, 2,
+                                                                                  0, 8)), M, xyz, None))
+    assert s == _lib.HC_ESHAPE and "ld" in msg
+    s, msg = _err(lib.hc_shade_latent_xyz(C.byref(_lib.Paths(10, 4, 0, 0x1000, 0x1000, 0x1004, 5)), C.byref(L),
+                                          M, xyz, None))
+    assert s == _lib.HC_EALIGN and "vtx" in msg
+    # an empty frame is a valid no-op, whatever the pointers
+    assert lib.hc_shade_latent_xyz(C.byref(_lib.Paths(0, 4, 0, None, None, None, 0)), C.byref(L), None, None,
+                                   None) == _lib.HC_OK
+    s, msg = _err(lib.hc_decode_matrix(M, 31, 0, M, M, None))
+    assert s == _lib.HC_ESHAPE and "k=0" in msg
+    s, msg = _err(lib.hc_decode_matrix(M, 0, 6, M, M, None))
+    assert s == _lib.HC_ESHAPE and "n=0" in msg
+    s, msg = _err(lib.hc_decode_matrix(M, 31, 6, None, M, None))
+    assert s == _lib.HC_EINVAL
+    s, msg = _err(lib.hc_decode_matrix(M, 31, 6, M, C.c_void_p(0x2002), None))
+    assert s == _lib.HC_EALIGN
+
+
+def test_fused_latent_tiles_validate(lib):
+    T = C.c_void_p(0x1000)
+    s, msg = _err(lib.hc_shade_latent_xyz_tiles(T, 1, T, T, 16, 6, None, 0, None))
+    assert s == _lib.HC_EINVAL and "M" in msg
+    s, msg = _err(lib.hc_shade_latent_xyz_tiles(T, 1, T, T, 16, 6, C.c_void_p(0x2002), 0, None))
+    assert s == _lib.HC_EINVAL
+    s, msg = _err(lib.hc_shade_latent_xyz_tiles(T, 1, T, T, 16, 0, T, 0, None))
+    assert s == _lib.HC_ESHAPE and "k=0" in msg
+    s, msg = _err(lib.hc_shade_latent_xyz_tiles(None, 1, T, T, 16, 6, T, 0, None))
+    assert s == _lib.HC_EINVAL and "table" in msg
+    s, msg = _err(lib.hc_shade_latent_xyz_tiles(T, 1, T, T, 16, 6, T, 70000, None))
+    assert s == _lib.HC_ESHAPE and "grid" in msg

@@ -29,11 +29,11 @@ def env():
     return dict(serve=serve, assets=assets, lights=lights, T=synth.cmf_matrix(n), E=E, D=D)
 
 
-def _backend(env, form, use_graph=True):
+def _backend(env, form, use_graph=True, fused_decode=True):
     t = torch.from_numpy
     return env["serve"].GpuBackend(env["assets"], t(env["lights"]), t(env["T"]), t(env["E"]), t(env["D"]),
                                    form=form, max_frames=16, max_tiles=1024, max_jobs=256, grid=256,
-                                   use_graph=use_graph)
+                                   use_graph=use_graph, fused_decode=fused_decode)
 
 
 def _run(env, be, reqs, **kw):
@@ -90,6 +90,19 @@ def test_graph_replay_equals_direct_launches(env):
     b = _run(env, _backend(env, "latent", use_graph=False), _mix(env), tile_pixels=4096, iter_vertices=2e5)
     for rid in a:
         assert np.array_equal(a[rid], b[rid])
+
+
+def test_fused_decode_equals_the_decode_launch(env):
+    """Latent serving with the decode in the shading launch (no latent
+    images) and with latent images and a decode launch give the same bits,
+    and the oracle's frames."""
+    fused = _run(env, _backend(env, "latent"), _mix(env), tile_pixels=2048, iter_vertices=2e5)
+    split = _run(env, _backend(env, "latent", fused_decode=False), _mix(env), tile_pixels=2048,
+                 iter_vertices=2e5)
+    reqs = _mix(env)
+    for r in reqs:
+        assert np.array_equal(fused[r.rid], split[r.rid]), r.rid
+        assert xyz_close(fused[r.rid], _oracle_frame(env, r, "latent")) <= 1.0, r.rid
 
 
 def test_tiles_equal_single_frame_calls(env):
