@@ -75,6 +75,84 @@ def _oracle_chunk(job):
     return int(vtx.shape[0]), dt
 
 
+def cpu_baseline_small_frame(w0, reps=3):
+    """The oracle on the small frame (256 x 256, 1 spp, one vertex per path)
+    in full, one process: its spectral and latent (encode, shade, decode)
+    pipelines, best of `reps`."""
+    from oracle import shade as osh
+    from synth import gen_paths
+    hdr, pf, vtx = gen_paths(w0["paths"])
+    spp = w0["paths"].spp
+    out = {}
+    for form in ("spectral", "latent"):
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            if form == "spectral":
+                osh.shade_spectral(hdr, pf, vtx, spp, w0["refl"], w0["illum"], w0["T"])
+            else:
+                osh.render_latent_xyz(hdr, pf, vtx, spp, w0["refl"], w0["illum"], w0["E"], w0["D"], w0["T"])
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        out[f"{form}_ms"] = best * 1e3
+    out.update(path_vertices=int(vtx.shape[0]), cores=1, kind="oracle",
+               value=int(vtx.shape[0]) / (out["latent_ms"] * 1e-3), unit="path-vertices/s (latent)")
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def small_frame_gpu(w0, dev, reps=50):
+    """The small frame (256 x 256, 1 spp, 64 materials, 8 lights, k = 6) in
+    full on the GPU: the latent step (encode materials and lights, decoder
+    matrix, shading with the decode) and the spectral step, HIP events over
+    `reps` back-to-back steps each (launch-bound at this size)."""
+    import torch
+    from paper_2602_18741_amd import ops
+    spec = w0["paths"]
+    P = ops.gen_paths(spec.n_pixels, spec.spp, spec.l_min, spec.l_max, spec.n_tex, spec.n_illum, spec.seed,
+                      device=dev)
+    refl = ops.padded(torch.from_numpy(w0["refl"]).to(dev))
+    illum = ops.padded(torch.from_numpy(w0["illum"]).to(dev))
+    E, D, T = (torch.from_numpy(w0[x]).to(dev) for x in ("E", "D", "T"))
+    k, n = E.shape
+    codes = torch.empty(refl.shape[0], ops.latent_width(k), device=dev)
+    lcodes = torch.empty(illum.shape[0], ops.latent_width(k), device=dev)
+    M = torch.empty(3, 3 * ops.blocks(k), device=dev)
+    xyz = torch.empty(spec.n_pixels, 3, device=dev)
+
+    def latent():
+        ops.encode(E, refl, n=n, out=codes)
+        ops.encode(E, illum, n=n, out=lcodes)
+        ops.decode_matrix(D, T, k, out=M)
+        ops.shade_latent_xyz(P, codes, lcodes, M, k, out=xyz)
+
+    def spectral():
+        ops.shade_spectral(P, refl, illum, T, n, out=xyz)
+
+    out = {"pixels": spec.n_pixels, "spp": spec.spp, "path_vertices": int(P.n_vertices)}
+    for name, step in (("latent", latent), ("spectral", spectral)):
+        for _ in range(5):
+            step()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{name}_step_ms"] = e0.elapsed_time(e1) / reps
+    out["latent_path_vertices_per_s"] = out["path_vertices"] / (out["latent_step_ms"] * 1e-3)
+    return out
+
+
 def cpu_baseline(w, n_pixels=None, chunk=32768, subset=False, what="the frame"):
     """Time the oracle on a pixel sample of the frame with a pool of worker
     processes (forked before any GPU use, one BLAS thread each)."""
@@ -619,6 +697,11 @@ def main():
     cpu = None if (args.no_cpu or args.only or stress) else cpu_baseline(w)
     if cpu:
         log("cpu baseline:", cpu["sample"])
+    w0 = synth.workload(0) if not (args.only or stress) else None
+    cpu0 = None if (w0 is None or args.no_cpu) else cpu_baseline_small_frame(w0)
+    if cpu0:
+        log(f"cpu baseline, small frame in full: spectral {cpu0['spectral_ms']:.1f} ms, latent "
+            f"{cpu0['latent_ms']:.1f} ms ({cpu0['path_vertices']} path-vertices, one process)")
     w4 = cpu4 = None
     if not (args.only or stress or args.no_stress):
         t_setup = time.time()
@@ -744,6 +827,13 @@ def main():
     spe_wall, spe_kern = timed(spectral_step)
     log(f"latent step {lat_wall * 1e3:.3f} ms (shade {lat_kern * 1e3:.3f} ms); "
         f"spectral step {spe_wall * 1e3:.3f} ms")
+    small = None
+    if w0 is not None:
+        small = small_frame_gpu(w0, dev)
+        small["workload"] = "256x256 px, 1 spp, path length 1, 64 materials, 8 lights, latent k=6 vs n=31"
+        small["cpu_baseline"] = cpu0
+        log(f"small frame in full: latent step {small['latent_step_ms'] * 1e3:.1f} us, spectral "
+            f"{small['spectral_step_ms'] * 1e3:.1f} us ({small['path_vertices']} path-vertices)")
 
     stream = stream_bandwidth(dev)
     copy_gbs = stream["copy_GBs"]
@@ -901,11 +991,12 @@ def main():
         "multibounce": bounce,
         "upsample": up,
         "stress": stress_out,
+        "small_frame": small,
         "serving": serving,
         "env": {"device": torch.cuda.get_device_name(dev),
                 "arch": getattr(torch.cuda.get_device_properties(dev), "gcnArchName", None),
                 "hip": torch.version.hip,
-                "torch": torch.__version__, "host_cores": os.cpu_count(),
+                "torch": torch.__version__, "host_cores": os.cpu_count(), "host_cpu": cpu_model(),
                 "seeds": {"paths": spec.seed, "texture": "perlin 1001 / 4001 (workloads 1 / 4)",
                           "codec_init": [2, 3]},
                 "row_strides_floats": {"spectral": ld_tex, "codes": ld_z}},
