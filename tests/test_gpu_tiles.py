@@ -1,7 +1,8 @@
 """Tile-table launches (the serving kernels) against the single-frame calls.
 
-hc_shade_spectral_tiles / hc_shade_latent_tiles / hc_decode_tiles walk a
-device table of frames and pixel-range tiles with a fixed grid.  Each pixel's
+hc_shade_spectral_tiles / hc_shade_latent_tiles / hc_decode_tiles /
+hc_shade_latent_xyz_tiles walk a device table of frames and pixel-range tiles
+with a fixed grid.  Each pixel's
 samples are reduced inside one wavefront in the same order as in
 hc_shade_spectral / hc_shade_latent, so the results must be equal bit for bit.
 The cases cover every spectral chunk count (n = 31, 50, 81, 128), light tables in
@@ -137,3 +138,36 @@ def test_latent_tiles_equal_single_frame_calls(ops, k, n_illum, grid):
         # whole blocked rows: each slot's 4th float is written 0 as well
         assert np.array_equal(to_np(img), to_np(ref_img))
         assert np.array_equal(to_np(xyz), to_np(ref_xyz))
+
+
+@pytest.mark.parametrize("grid", [64, 0])
+@pytest.mark.parametrize("k,n_illum", [(1, 12), (6, 12), (9, 300), (12, 20), (15, 20), (48, 20), (48, 600)])
+def test_fused_latent_tiles_equal_the_fused_frame_call(ops, k, n_illum, grid):
+    """hc_shade_latent_xyz_tiles against hc_shade_latent_xyz per frame, bit
+    for bit; the frames' latent images are left untouched.  k <= 12 holds M
+    in scalar registers, wider codes stage it in LDS."""
+    from paper_2602_18741_amd._lib import check, load
+    n = 31
+    rng = np.random.default_rng(k * 13 + n_illum)
+    E = torch.from_numpy(rng.uniform(size=(k, n)).astype(np.float32)).cuda()
+    D = torch.from_numpy(rng.uniform(size=(n, k)).astype(np.float32)).cuda()
+    T = torch.from_numpy(synth.cmf_matrix(n)).cuda()
+    codes = ops.encode(E, dev_f32(synth.reflectances(rng, n, 400)), n=n)
+    lcodes = ops.encode(E, dev_f32(synth.illuminant_table(rng, n, n_illum // 2, n_illum - n_illum // 2)), n=n)
+    M = ops.decode_matrix(D, T, k)
+    paths = _frames(ops, n_illum, 400, seed=k + 3 * n_illum)
+    w = ops.latent_width(k)
+    images = [torch.full((P.n_pixels, w), float("nan"), device="cuda") for P in paths]
+    xyzs = [torch.full((P.n_pixels, 3), float("nan"), device="cuda") for P in paths]
+    frames = _device_bytes(_table(paths, codes, lcodes, images, xyzs))
+    tiles, nt = _tiles(rng, [P.n_pixels for P in paths])
+    d_tiles = _device_bytes(tiles)
+    cnt = torch.tensor([nt], dtype=torch.int32, device="cuda")
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    check(load().hc_shade_latent_xyz_tiles(frames.data_ptr(), len(paths), d_tiles.data_ptr(), cnt.data_ptr(),
+                                           nt, k, M.data_ptr(), grid, st), "hc_shade_latent_xyz_tiles")
+    for P, img, xyz in zip(paths, images, xyzs):
+        ref = ops.shade_latent_xyz(P, codes, lcodes, M, k)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(xyz), to_np(ref))
+        assert torch.isnan(img).all()
