@@ -5,7 +5,10 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 
 #include "../../include/hc.h"
 
@@ -37,6 +40,37 @@ int tile_grid(int grid, K kernel, int threads, size_t lds, const char* what) {
         return 0;
     }
     return 2 * cus * per_cu;
+}
+
+// Workgroups of `kernel` (with `threads` threads and `lds` bytes of dynamic
+// LDS) the current device holds at once, for persistent launches; the
+// occupancy query is made once per device, kernel and LDS size.  Returns 0
+// (with the error set) if the device cannot be queried.
+template <typename K>
+int resident_grid(K kernel, int threads, size_t lds, const char* what) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("%s: no current device", what);
+        return 0;
+    }
+    const auto key = std::make_tuple(dev, reinterpret_cast<const void*>(kernel), lds);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        const auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+        cus <= 0 || per_cu <= 0) {
+        set_error("%s: occupancy query failed", what);
+        return 0;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = cus * per_cu;
+    return cus * per_cu;
 }
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }

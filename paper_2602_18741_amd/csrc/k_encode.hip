@@ -17,7 +17,7 @@ struct EncodeArgs {
     int64_t m, ld_s;
     float* Z;
     int64_t ld_z;
-    int rows;        // rows per block (256 / 128 / 64)
+    int rows;        // rows per block (64 or 32)
 };
 
 // Stage E into LDS as 3NB rows of nq float4 chunks, zero past k rows and
@@ -80,6 +80,95 @@ __device__ __forceinline__ void encode_rows(const float4* s_E, float4* s_rows, i
     }
 }
 
+// Long rows (n > 32).  A group of rows [r0, r0 + nrows) (nrows <= rows
+// per block) is read as nrows * nq float4 chunks, chunk i by thread
+// i % kThreads (coalesced), at most kLoadLong per thread, into registers;
+// samples past n (row padding) are zeroed as above.
+constexpr int kLoadLong = 6;  // 64 rows x 24 chunks or 32 rows x 32 chunks over 256 threads
+
+template <int L>
+__device__ __forceinline__ void load_group(const float* S, int64_t ld_s, int n, int nq, int64_t r0, int nrows,
+                                           float4 (&v)[L]) {
+    const int total = nrows * nq;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int i = int(threadIdx.x) + t * kThreads;
+        if (i < total) {
+            const int r = i / nq, c = i % nq;
+            float4 x = ld4(S + (r0 + r) * ld_s + 4 * c);
+            if (4 * c + 3 >= n) {
+                if (4 * c + 1 >= n) x.y = 0.f;
+                if (4 * c + 2 >= n) x.z = 0.f;
+                x.w = 0.f;
+            }
+            v[t] = x;
+        }
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void put_group(float4* s_rows, int nq, int nrows, const float4 (&v)[L]) {
+    const int stride = nq + 1;  // float4 chunks; odd: a row's reads spread over banks
+    const int total = nrows * nq;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int i = int(threadIdx.x) + t * kThreads;
+        if (i < total) s_rows[(i / nq) * stride + i % nq] = v[t];
+    }
+}
+
+// Codes of the staged group of long rows: kThreads / rows threads share a
+// row, each accumulating its channels (q, q + that count, ...) over the
+// samples in order (each channel's sums as in encode_rows, so the results
+// are the same bits); the codes go through LDS (s_z, rows x NB float4) to
+// whole-row float4 stores.  Called with the group staged and a barrier
+// passed; ends with the stores.
+template <int NB>
+__device__ __forceinline__ void encode_group(const float4* s_E, const float4* s_rows, float4* s_z, int nq,
+                                             int rows, float* Z, int64_t ld_z, int64_t r0, int nrows) {
+    const int tid = threadIdx.x;
+    // at least 4 threads per row (rows <= 64): at most ceil(3NB / 4) channels each
+    constexpr int kChan = (3 * NB + 3) / 4;
+    const int tpr = kThreads / rows;
+    const int r = tid / tpr, q = tid % tpr;
+    if (r < nrows) {
+        const float4* s = s_rows + r * (nq + 1);
+        // channels past k read zero rows of E (staged that way), so they stay 0
+        float z[kChan];
+#pragma unroll
+        for (int i = 0; i < kChan; ++i) z[i] = 0.f;
+        for (int j = 0; j < nq; ++j) {
+            const float4 sj = s[j];
+#pragma unroll
+            for (int i = 0; i < kChan; ++i) {
+                const int c = q + i * tpr;
+                if (c < 3 * NB) {
+                    const float4 e = s_E[c * nq + j];
+                    z[i] += e.x * sj.x;
+                    z[i] += e.y * sj.y;
+                    z[i] += e.z * sj.z;
+                    z[i] += e.w * sj.w;
+                }
+            }
+        }
+        float* zr = reinterpret_cast<float*>(s_z + r * NB);
+#pragma unroll
+        for (int i = 0; i < kChan; ++i) {
+            const int c = q + i * tpr;
+            if (c < 3 * NB) zr[4 * (c / 3) + c % 3] = z[i];
+        }
+        for (int b = q; b < NB; b += tpr) zr[4 * b + 3] = 0.f;
+    }
+    __syncthreads();
+    // the row's float4 chunks by its threads in turn (consecutive lanes,
+    // consecutive chunks): the codes, then zero columns up to the stride
+    if (r < nrows) {
+        float* out = Z + (r0 + r) * ld_z;
+        for (int64_t f = q; 4 * f < ld_z; f += tpr)
+            st4(out + 4 * f, f < NB ? s_z[r * NB + f] : make_float4(0.f, 0.f, 0.f, 0.f));
+    }
+}
+
 template <int NB>
 __global__ __launch_bounds__(kThreads) void encode_kernel(EncodeArgs a) {
     extern __shared__ float4 smem[];
@@ -90,9 +179,36 @@ __global__ __launch_bounds__(kThreads) void encode_kernel(EncodeArgs a) {
     encode_rows<NB>(s_E, smem, a.n, a.nq, a.S, a.ld_s, a.Z, a.ld_z, r0, nrows);
 }
 
+// Long rows: a persistent grid (the workgroups the device holds at once),
+// each staging E once and walking the row groups blockIdx.x, + gridDim.x,
+// ...; the next group's rows are loaded into registers while the current
+// one is encoded.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void encode_long_kernel(EncodeArgs a) {
+    extern __shared__ float4 smem[];
+    float4* s_E = smem + a.rows * (a.nq + 1);
+    float4* s_z = s_E + 3 * NB * a.nq;
+    stage_encoder<NB>(a.E, a.k, a.n, a.nq, s_E);
+    const int64_t groups = (a.m + a.rows - 1) / a.rows;
+    int64_t g = blockIdx.x;
+    float4 v[kLoadLong];
+    if (g < groups) load_group(a.S, a.ld_s, a.n, a.nq, g * a.rows, int(min<int64_t>(a.rows, a.m - g * a.rows)), v);
+    for (; g < groups; g += gridDim.x) {
+        const int64_t r0 = g * a.rows;
+        const int nrows = int(min<int64_t>(a.rows, a.m - r0));
+        __syncthreads();  // E staged; the previous group's reads of LDS are done
+        put_group(smem, a.nq, nrows, v);
+        __syncthreads();
+        const int64_t gn = g + gridDim.x;
+        if (gn < groups)
+            load_group(a.S, a.ld_s, a.n, a.nq, gn * a.rows, int(min<int64_t>(a.rows, a.m - gn * a.rows)), v);
+        encode_group<NB>(s_E, smem, s_z, a.nq, a.rows, a.Z, a.ld_z, r0, nrows);
+    }
+}
+
 // Persistent launch over an encode job table (rows [begin, end) of one
 // spectra array each); block b takes jobs b, b + grid, ...
-template <int NB>
+template <int NB, bool LONG>
 __global__ __launch_bounds__(kThreads) void encode_jobs_kernel(const hc_encode_job* __restrict__ jobs,
                                                                const int32_t* __restrict__ n_jobs_dev,
                                                                int max_jobs,
@@ -100,13 +216,23 @@ __global__ __launch_bounds__(kThreads) void encode_jobs_kernel(const hc_encode_j
     extern __shared__ float4 smem[];
     const int nq = (n + 3) / 4;
     float4* s_E = smem + rows * (nq + 1);
+    float4* s_z = s_E + 3 * NB * nq;
     stage_encoder<NB>(E, k, n, nq, s_E);
     const int n_jobs = min(*n_jobs_dev, max_jobs);
     for (int j = blockIdx.x; j < n_jobs; j += gridDim.x) {
         const hc_encode_job job = jobs[j];
         for (int64_t r0 = job.begin; r0 < job.end; r0 += rows) {
             const int nrows = int(min<int64_t>(rows, job.end - r0));
-            encode_rows<NB>(s_E, smem, n, nq, job.S, job.ld_s, job.Z, job.ld_z, r0, nrows);
+            if constexpr (LONG) {
+                float4 v[kLoadLong];
+                load_group(job.S, job.ld_s, n, nq, r0, nrows, v);
+                __syncthreads();  // E staged; the previous rows' reads of LDS are done
+                put_group(smem, nq, nrows, v);
+                __syncthreads();
+                encode_group<NB>(s_E, smem, s_z, nq, rows, job.Z, job.ld_z, r0, nrows);
+            } else {
+                encode_rows<NB>(s_E, smem, n, nq, job.S, job.ld_s, job.Z, job.ld_z, r0, nrows);
+            }
         }
     }
 }
@@ -256,7 +382,15 @@ __global__ __launch_bounds__(kThreads) void decode_matrix_kernel(const float* D,
 #define HC_NB_CASES(M) \
     M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
 
-int rows_per_block(int nq) { return nq <= 8 ? 64 : (nq <= 16 ? 32 : 16); }
+// Rows longer than 32 samples take the pipelined kernels.  Rows per block:
+// 64 (short rows: one thread per row; long ones: four) up to 96 samples, 32
+// (eight threads per row) beyond.
+bool long_rows(int nq) { return nq > 8; }
+int rows_per_block(int nq) { return nq <= 24 ? 64 : 32; }
+
+size_t encode_lds(int rows, int nq, int nb, bool lng) {
+    return (size_t(rows) * (nq + 1) + size_t(3 * nb) * nq + (lng ? size_t(rows) * nb : 0)) * sizeof(float4);
+}
 
 }  // namespace
 
@@ -274,11 +408,25 @@ hc_status launch_encode(const float* E, int k, int n, const float* S, int64_t m,
     a.ld_z = ld_z;
     a.rows = rows_per_block(a.nq);
     const int nb = (k + 2) / 3;
-    const size_t lds = (size_t(a.rows) * (a.nq + 1) + size_t(3 * nb) * a.nq) * sizeof(float4);
-    const uint32_t blocks = uint32_t(ceil_div(m, a.rows));
+    const bool lng = long_rows(a.nq);
+    const size_t lds = encode_lds(a.rows, a.nq, nb, lng);
+    const int64_t groups = ceil_div(m, a.rows);
+    if (!lng && groups > 0x7FFFFFFF) {
+        set_error("hc_encode: too many rows for one launch");
+        return HC_ESHAPE;
+    }
     switch (nb) {
-#define HC_ENC(NB) \
-    case NB: hipLaunchKernelGGL(encode_kernel<NB>, dim3(blocks), dim3(kThreads), lds, st, a); break;
+#define HC_ENC(NB)                                                                                  \
+    case NB:                                                                                        \
+        if (!lng) {                                                                                 \
+            hipLaunchKernelGGL(encode_kernel<NB>, dim3(uint32_t(groups)), dim3(kThreads), lds, st, a); \
+        } else {                                                                                    \
+            const int res = resident_grid(encode_long_kernel<NB>, kThreads, lds, "hc_encode");     \
+            if (res <= 0) return HC_EDEVICE;                                                        \
+            const int grid = int(std::max<int64_t>(1, std::min<int64_t>(groups, res)));             \
+            hipLaunchKernelGGL(encode_long_kernel<NB>, dim3(grid), dim3(kThreads), lds, st, a);     \
+        }                                                                                           \
+        break;
         HC_NB_CASES(HC_ENC)
 #undef HC_ENC
         default:
@@ -341,18 +489,25 @@ hc_status launch_encode_jobs(const hc_encode_job* jobs, const int32_t* n_jobs, i
     const int nq = (n + 3) / 4;
     const int rows = rows_per_block(nq);
     const int nb = (k + 2) / 3;
-    const size_t lds = (size_t(rows) * (nq + 1) + size_t(3 * nb) * nq) * sizeof(float4);
+    const size_t lds = encode_lds(rows, nq, nb, long_rows(nq));
     switch (nb) {
-#define HC_ENCJ(NB)                                                                                  \
-    case NB: {                                                                                       \
-        const int g = tile_grid(grid, encode_jobs_kernel<NB>, kThreads, lds, "hc_encode_jobs");      \
+#define HC_ENCJ_L(NB, L)                                                                             \
+    {                                                                                                \
+        const int g = tile_grid(grid, encode_jobs_kernel<NB, L>, kThreads, lds, "hc_encode_jobs");   \
         if (g <= 0) return HC_EDEVICE;                                                               \
-        hipLaunchKernelGGL(encode_jobs_kernel<NB>, dim3(g), dim3(kThreads), lds, st, jobs, n_jobs,   \
-                           max_jobs, E, k, n, rows);                                                 \
-        break;                                                                                       \
+        hipLaunchKernelGGL((encode_jobs_kernel<NB, L>), dim3(g), dim3(kThreads), lds, st, jobs,      \
+                           n_jobs, max_jobs, E, k, n, rows);                                         \
     }
+#define HC_ENCJ(NB)                                                                                  \
+    case NB:                                                                                         \
+        if (long_rows(nq))                                                                           \
+            HC_ENCJ_L(NB, true)                                                                      \
+        else                                                                                         \
+            HC_ENCJ_L(NB, false)                                                                     \
+        break;
         HC_NB_CASES(HC_ENCJ)
 #undef HC_ENCJ
+#undef HC_ENCJ_L
         default:
             set_error("hc_encode_jobs: k=%d unsupported", k);
             return HC_EUNSUPPORTED;

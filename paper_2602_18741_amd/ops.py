@@ -156,6 +156,8 @@ def decode_matrix(D: torch.Tensor, T: torch.Tensor, k: int, out: torch.Tensor | 
     n = D.shape[0]
     if out is None:
         out = torch.empty(3, 3 * blocks(k), dtype=torch.float32, device=D.device)
+    elif tuple(out.shape) != (3, 3 * blocks(k)) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous float32 (3, {3 * blocks(k)}) tensor")
     check(load().hc_decode_matrix(_ptr(D.contiguous()), n, k, _ptr(T.contiguous()), _ptr(out), _stream()),
           "hc_decode_matrix")
     return out
