@@ -287,12 +287,15 @@ __device__ __forceinline__ void decode_pixel(const float* s_M, const float* s_D,
     }
 }
 
-// kDecodePixels pixels per thread (consecutive blocks of kThreads pixels), so
-// a workgroup's set-up of M is shared by that many pixels.
-constexpr int kDecodePixels = 8;
+// decode_pixels<NB>() pixels per thread (consecutive blocks of kThreads
+// pixels), so a workgroup's set-up of M is shared by that many pixels; fewer
+// for wide codes, whose preloaded rows would not fit the registers.
+template <int NB>
+constexpr int decode_pixels() { return NB <= 4 ? 8 : (NB <= 8 ? 4 : 2); }
 
 template <int NB>
 __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeArgs a) {
+    constexpr int kDecodePixels = decode_pixels<NB>();
     __shared__ float s_M[3 * kMaxK];
     extern __shared__ float s_D[];  // n x k, only when spectra are requested
     const int64_t q0 = int64_t(blockIdx.x) * kThreads * kDecodePixels + threadIdx.x;
@@ -452,16 +455,18 @@ hc_status launch_decode(const float* D, int n, int k, const float* T, const floa
     a.spectra = spectra;
     a.ld_s = ld_spectra;
     const size_t lds = spectra ? size_t(n) * k * sizeof(float) : 0;
-    const int64_t blocks = ceil_div(n_pixels, int64_t(kThreads) * kDecodePixels);
-    if (blocks > 0x7FFFFFFF) {
+    // the fewest pixels per thread (2) bounds the grid
+    if (ceil_div(n_pixels, int64_t(kThreads) * 2) > 0x7FFFFFFF) {
         set_error("hc_decode_xyz: too many pixels for one launch");
         return HC_ESHAPE;
     }
     switch (a.nb) {
 #define HC_DEC(NB)                                                                               \
-    case NB:                                                                                     \
+    case NB: {                                                                                   \
+        const int64_t blocks = ceil_div(n_pixels, int64_t(kThreads) * decode_pixels<NB>());      \
         hipLaunchKernelGGL(decode_kernel<NB>, dim3(uint32_t(blocks)), dim3(kThreads), lds, st, a); \
-        break;
+        break;                                                                                   \
+    }
         HC_NB_CASES(HC_DEC)
 #undef HC_DEC
         default:
