@@ -182,6 +182,7 @@ def cpu_baseline(w, n_pixels=None, chunk=32768, subset=False, what="the frame"):
 # ------------------------------------------------------------------ GPU part
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "shade_latent_1080p16_traffic.json")
+TRAFFIC_STRESS_JSON = os.path.join(ROOT, "profiles", "shade_stress_4k64_traffic.json")
 
 
 def kernel_source_sha():
@@ -211,13 +212,14 @@ TRAFFIC_NOTE = ("fetch/write: FETCH_SIZE and WRITE_SIZE of the kernel, each scal
                 "memory; the L2 counters cannot tell a MALL hit from an HBM read.")
 
 
-def record_traffic(d_fetch, d_write, d_copy_fetch, d_copy_write, d_req=None):
+def record_traffic(d_fetch, d_write, d_copy_fetch, d_copy_write, d_req=None, stress=False):
     """Write the traffic record of one latent shading launch from rocprofv3
     --pmc CSVs (run_counter_collection.csv in each directory): FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch) of the kernel scaled by the ratio of the
     true bytes of a 1 GiB device copy to what the same counter reads for that
     copy; with d_req also the L2-to-fabric read requests (TCC_EA0_RDREQ,
-    TCC_EA0_RDREQ_128B, TCC_EA0_RDREQ_DRAM)."""
+    TCC_EA0_RDREQ_128B, TCC_EA0_RDREQ_DRAM).  With `stress` the record is the
+    stress frame's (its own file)."""
     csv = lambda d: os.path.join(d, "run_counter_collection.csv")  # noqa: E731
     gib_kib = float(1 << 20)
     kern = "shade_latent_kernel"
@@ -225,7 +227,9 @@ def record_traffic(d_fetch, d_write, d_copy_fetch, d_copy_write, d_req=None):
     w_scale = gib_kib / _counter_mean(csv(d_copy_write), "copyBuffer", "WRITE_SIZE")
     fetch = _counter_mean(csv(d_fetch), kern, "FETCH_SIZE") * 1024 * f_scale
     write = _counter_mean(csv(d_write), kern, "WRITE_SIZE") * 1024 * w_scale
-    d = {"kernel": "shade_latent_kernel<2> (decode in the epilogue)", "workload": WORKLOAD,
+    d = {"kernel": ("shade_latent_kernel<3> (decode in the epilogue, table past the cache)" if stress
+                    else "shade_latent_kernel<2> (decode in the epilogue)"),
+         "workload": STRESS if stress else WORKLOAD,
          "kernel_source_sha": kernel_source_sha(), "fetch_scale": f_scale, "write_scale": w_scale,
          "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
          "fetch_plus_write_bytes_per_launch": fetch + write, "note": TRAFFIC_NOTE}
@@ -236,7 +240,7 @@ def record_traffic(d_fetch, d_write, d_copy_fetch, d_copy_write, d_req=None):
         d["ea_read_bytes"] = None if req["TCC_EA0_RDREQ_128B_sum"] is None else 128 * req["TCC_EA0_RDREQ_128B_sum"]
         d["dram_read_requests"] = req["TCC_EA0_RDREQ_DRAM_sum"]
         d["dram_read_bytes"] = None if req["TCC_EA0_RDREQ_DRAM_sum"] is None else 128 * req["TCC_EA0_RDREQ_DRAM_sum"]
-    json.dump(d, open(TRAFFIC_JSON, "w"), indent=1)
+    json.dump(d, open(TRAFFIC_STRESS_JSON if stress else TRAFFIC_JSON, "w"), indent=1)
     print(json.dumps(d))
 
 
@@ -271,12 +275,26 @@ def stream_bandwidth(dev, reps: int = 10) -> dict:
     return out
 
 
-def measured_traffic():
-    """Traffic record of the latent shading launch from the committed counter
-    profile, if it was taken with the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_JSON):
+def attach_traffic(roof, traffic, kern_s):
+    """Add a traffic record (or None) to a roofline entry: `traffic` is the
+    counted fetch + write bytes per launch, `traffic_GBs` their rate over
+    the kernel time measured in this run."""
+    roof["traffic"] = None if traffic is None else traffic["fetch_plus_write_bytes_per_launch"]
+    if traffic is not None:
+        roof["traffic_note"] = traffic["note"]
+        for key in ("fetch_bytes_per_launch", "write_bytes_per_launch", "ea_read_bytes", "dram_read_bytes"):
+            roof[f"traffic_{key}"] = traffic.get(key)
+        roof["traffic_GBs"] = traffic["fetch_plus_write_bytes_per_launch"] / kern_s / 1e9
+
+
+def measured_traffic(stress=False):
+    """Traffic record of the latent shading launch (the 1080p frame, or the
+    stress frame) from the committed counter profile, if it was taken with the
+    current kernel source; else None."""
+    path = TRAFFIC_STRESS_JSON if stress else TRAFFIC_JSON
+    if not os.path.exists(path):
         return None
-    d = json.load(open(TRAFFIC_JSON))
+    d = json.load(open(path))
     if d.get("kernel_source_sha") != kernel_source_sha():
         return None
     d.setdefault("note", TRAFFIC_NOTE)
@@ -421,6 +439,7 @@ def stress_leg(w, args, dev, copy_gbs, cpu):
                          res["latent"][1], nv, ceil_l,
                          copy_gbs, "random 64-byte code rows from a 1 GiB table in HBM (one 128-byte "
                          "line each)")
+    attach_traffic(lat, measured_traffic(stress=True), res["latent"][1])
     spe = frame_roofline("shade_spectral_kernel (n = 81)", bytes_spe, res["spectral"][1], nv, ceil_s, copy_gbs,
                          "random 384-byte spectral rows from a 6.4 GB table in HBM (three 128-byte "
                          "lines each)")
@@ -658,7 +677,7 @@ def main():
     if args.config == 4:
         args.stress = True
     if args.record_traffic:
-        record_traffic(*args.record_traffic)
+        record_traffic(*args.record_traffic, stress=args.stress)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -877,7 +896,7 @@ def main():
         + f"; fused decode equals the decode launch: {streaming['fused_decode_equals_decode_launch']}")
     bytes_lat = npath * 4 + nv * (8 + 4 * k) + npx * (12 + 4)
     bytes_spe = npath * 4 + nv * (8 + 4 * n) + npx * (12 + 4)
-    traffic = None if stress else measured_traffic()
+    traffic = measured_traffic(stress=stress)
 
     # the random-gather ceiling of the frame's records: over the code table
     # and the spectral table the kernels read, and over a 1 GiB table of
@@ -898,12 +917,7 @@ def main():
                           copy_gbs, f"random {4 * ops.blocks(k) * 4}-byte code rows from a "
                           f"{tbl_mb:.0f} MiB table" + (" resident in the 256 MB MALL" if tbl_mb < 256
                                                         else " in HBM") + " (one 128-byte line each)")
-    roof["traffic"] = None if traffic is None else traffic["fetch_plus_write_bytes_per_launch"]
-    if traffic is not None:
-        roof["traffic_note"] = traffic["note"]
-        for key in ("fetch_bytes_per_launch", "write_bytes_per_launch", "ea_read_bytes", "dram_read_bytes"):
-            roof[f"traffic_{key}"] = traffic.get(key)
-        roof["traffic_GBs"] = traffic["fetch_plus_write_bytes_per_launch"] / lat_kern / 1e9
+    attach_traffic(roof, traffic, lat_kern)
     roof["gather_ceiling_1GiB_rows_per_s"] = ceil_1g["rows_per_s"]
     roof["gather_ceiling_1GiB"] = ceil_1g
     roof_spe = frame_roofline("shade_spectral_kernel", bytes_spe, spe_kern, nv, ceil_spe, copy_gbs,
