@@ -294,11 +294,12 @@ __global__ __launch_bounds__(kThreads) void upsample_f32_kernel(UpArgs a) {
     }
 }
 
-// 16-texel tiles per wave per step.  F16 with k <= 16: two tiles share each
-// weight fragment read from LDS (112 registers); wider outputs keep one tile,
-// as does F32.
+// 16-texel tiles per wave per step: two tiles share each weight fragment
+// read from LDS and give the matrix cores two independent accumulation chains
+// (F16 with k <= 16: 112 registers, wider outputs keep one tile; F32: 196-236
+// registers, 6.97 -> 6.52 ms on 4096^2 texels).
 constexpr int kNT16 = 2;
-constexpr int kNT32 = 1;
+constexpr int kNT32 = 2;
 constexpr int kMaxGrid = 2048;
 
 int64_t grid_for(const UpArgs& a) {
