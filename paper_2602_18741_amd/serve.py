@@ -6,8 +6,9 @@ memory budget allow (FIFO), keeps encoded assets resident across requests
 (encode on first use), and runs *iterations*: each iteration shades a
 bounded number of pixel tiles taken from all admitted frames, so a request
 that arrives while a large frame is in flight joins the next iteration
-instead of waiting for that frame to finish.  Frames whose last tile is in an
-iteration are decoded in the same iteration.
+instead of waiting for that frame to finish.  The latent form decodes each
+pixel in the launch that shades it; with a separate decode launch, frames
+whose last tile is in an iteration are decoded in the same iteration.
 
 On the GPU an iteration is one replay of a captured HIP graph holding the
 table-driven launches (latent form: encode, then shading with the per-pixel
