@@ -41,30 +41,36 @@ Seg seg_of(int spp) {
     return s;
 }
 
+// Both record kernels run a fixed grid: wavefront w takes the pixel groups
+// w, w + (wavefronts in the grid), ... (a group is `pw` pixels), so the
+// per-wavefront set-up is paid once per many groups.
+
 // hdr of every path (stores coalesced across the lanes), and each pixel's
 // vertex count into pix_first (sum over the pixel's lanes by xor shuffles)
 __global__ __launch_bounds__(kThreads) void gen_headers_kernel(GenArgs g, Seg s, uint32_t* hdr,
                                                                uint32_t* counts) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (int64_t(blockIdx.x) * kThreads + threadIdx.x) / kWave;
-    if (wave * s.pw >= g.n_pixels) return;  // whole wavefront
+    const int64_t waves = int64_t(gridDim.x) * (kThreads / kWave);
     const int j0 = lane % s.seg;
-    const int64_t q = wave * s.pw + lane / s.seg;
-    const bool pix_ok = q < g.n_pixels;
-    uint32_t sum = 0;
-    for (int r = 0; r < s.rounds; ++r) {
-        const int j = j0 + r * s.seg;
-        if (pix_ok && j < g.spp) {
-            const uint64_t p = uint64_t(q) * g.spp + j;
-            const uint64_t rr = rand64(g.key_path, p);
-            const uint32_t len = uint32_t(g.l_min) + range32(rr, uint64_t(g.l_span));
-            const uint32_t light = static_cast<uint32_t>(((rr >> 32) * g.n_illum) >> 32);
-            hdr[p] = light | (len << 24);
-            sum += len;
+    for (int64_t wave = (int64_t(blockIdx.x) * kThreads + threadIdx.x) / kWave; wave * s.pw < g.n_pixels;
+         wave += waves) {
+        const int64_t q = wave * s.pw + lane / s.seg;
+        const bool pix_ok = q < g.n_pixels;
+        uint32_t sum = 0;
+        for (int r = 0; r < s.rounds; ++r) {
+            const int j = j0 + r * s.seg;
+            if (pix_ok && j < g.spp) {
+                const uint64_t p = uint64_t(q) * g.spp + j;
+                const uint64_t rr = rand64(g.key_path, p);
+                const uint32_t len = uint32_t(g.l_min) + range32(rr, uint64_t(g.l_span));
+                const uint32_t light = static_cast<uint32_t>(((rr >> 32) * g.n_illum) >> 32);
+                hdr[p] = light | (len << 24);
+                sum += len;
+            }
         }
+        for (int m = 1; m < s.seg; m <<= 1) sum += __shfl_xor(sum, m, kWave);
+        if (pix_ok && j0 == 0) counts[q] = sum;
     }
-    for (int m = 1; m < s.seg; m <<= 1) sum += __shfl_xor(sum, m, kWave);
-    if (pix_ok && j0 == 0) counts[q] = sum;
 }
 
 // Exclusive scan of the per-pixel counts (reduce, scan of block sums, scan).
@@ -175,52 +181,54 @@ __global__ __launch_bounds__(kThreads) void gen_vertices_kernel(GenArgs g, Seg s
     __shared__ uint32_t s_off[kThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
-    const int64_t wave = (int64_t(blockIdx.x) * kThreads + threadIdx.x) / kWave;
-    if (wave * s.pw >= g.n_pixels) return;  // whole wavefront
+    const int64_t waves = int64_t(gridDim.x) * (kThreads / kWave);
     const int seg_log2 = __builtin_ctz(unsigned(s.seg));
     const int j0 = lane & (s.seg - 1);
-    const int64_t q = wave * s.pw + (lane >> seg_log2);
-    const bool pix_ok = q < g.n_pixels;
     const int last = (lane & ~(s.seg - 1)) + s.seg - 1;  // the segment's last lane
     uint2* out = reinterpret_cast<uint2*>(vtx);
-    uint64_t next = pix_ok ? pix_first[q] : 0;
-    for (int r = 0; r < s.rounds; ++r) {
-        const int j = j0 + r * s.seg;
-        const bool live = pix_ok && j < g.spp;
-        const uint64_t p = uint64_t(q) * g.spp + j;
-        const uint32_t len = live ? path_length(g, p) : 0u;
-        uint32_t incl = len;
-        for (int d = 1; d < s.seg; d <<= 1) {
-            const uint32_t y = __shfl_up(incl, d, kWave);
-            if (j0 >= d) incl += y;
-        }
-        const uint32_t total = __shfl(incl, last, kWave);
-        const uint64_t first = next + (incl - len);
-        next += total;
-        // the round's flat range starts at lane 0's first record (lane 0 is
-        // always a live path) and ends at the largest end over the lanes
-        const uint64_t base = first_lane_u64(first);
-        const uint32_t off = pix_ok ? uint32_t(first - base) : 0u;  // past the frame: no records
-        uint32_t span = off + len;
-        for (int m = 1; m < kWave; m <<= 1) span = max(span, uint32_t(__shfl_xor(int(span), m, kWave)));
-        if (span <= uint32_t(kOwnerCap)) {
-            s_off[wv][lane] = off;
-            for (uint32_t v = 0; v < len; ++v) s_owner[wv][off + v] = uint8_t(lane);
-            wave_lds_sync();
-            for (uint32_t i = lane; i < span; i += kWave) {
-                const int pl = s_owner[wv][i];
-                const uint32_t v = i - s_off[wv][pl];
-                const uint64_t pq = uint64_t(wave * s.pw + (pl >> seg_log2));
-                const uint64_t pp = pq * g.spp + ((pl & (s.seg - 1)) + r * s.seg);
-                const uint64_t jv = base + i;
-                if (jv < n_vertices) out[jv] = vertex_record(g, pp, v);
+    for (int64_t wave = (int64_t(blockIdx.x) * kThreads + threadIdx.x) / kWave; wave * s.pw < g.n_pixels;
+         wave += waves) {
+        const int64_t q = wave * s.pw + (lane >> seg_log2);
+        const bool pix_ok = q < g.n_pixels;
+        uint64_t next = pix_ok ? pix_first[q] : 0;
+        for (int r = 0; r < s.rounds; ++r) {
+            const int j = j0 + r * s.seg;
+            const bool live = pix_ok && j < g.spp;
+            const uint64_t p = uint64_t(q) * g.spp + j;
+            const uint32_t len = live ? path_length(g, p) : 0u;
+            uint32_t incl = len;
+            for (int d = 1; d < s.seg; d <<= 1) {
+                const uint32_t y = __shfl_up(incl, d, kWave);
+                if (j0 >= d) incl += y;
             }
-            wave_lds_sync();  // the next round overwrites the maps
-        } else {
-            for (uint32_t v = 0; v < len; ++v) {
-                const uint64_t jv = first + v;
-                if (jv >= n_vertices) break;
-                out[jv] = vertex_record(g, p, v);
+            const uint32_t total = __shfl(incl, last, kWave);
+            const uint64_t first = next + (incl - len);
+            next += total;
+            // the round's flat range starts at lane 0's first record (lane 0 is
+            // always a live path) and ends at the largest end over the lanes
+            const uint64_t base = first_lane_u64(first);
+            const uint32_t off = pix_ok ? uint32_t(first - base) : 0u;  // past the frame: no records
+            uint32_t span = off + len;
+            for (int m = 1; m < kWave; m <<= 1) span = max(span, uint32_t(__shfl_xor(int(span), m, kWave)));
+            if (span <= uint32_t(kOwnerCap)) {
+                s_off[wv][lane] = off;
+                for (uint32_t v = 0; v < len; ++v) s_owner[wv][off + v] = uint8_t(lane);
+                wave_lds_sync();
+                for (uint32_t i = lane; i < span; i += kWave) {
+                    const int pl = s_owner[wv][i];
+                    const uint32_t v = i - s_off[wv][pl];
+                    const uint64_t pq = uint64_t(wave * s.pw + (pl >> seg_log2));
+                    const uint64_t pp = pq * g.spp + ((pl & (s.seg - 1)) + r * s.seg);
+                    const uint64_t jv = base + i;
+                    if (jv < n_vertices) out[jv] = vertex_record(g, pp, v);
+                }
+                wave_lds_sync();  // the next round overwrites the maps
+            } else {
+                for (uint32_t v = 0; v < len; ++v) {
+                    const uint64_t jv = first + v;
+                    if (jv >= n_vertices) break;
+                    out[jv] = vertex_record(g, p, v);
+                }
             }
         }
     }
@@ -233,6 +241,18 @@ __global__ __launch_bounds__(kThreads) void gen_indices_kernel(uint64_t key, uin
     if (i >= count) return;
     const uint64_t base = ctr0 + (scale ? uint64_t(*scale) * uint64_t(count) : 0ull);
     out[i] = range32(rand64(key, base + uint64_t(i)), n);
+}
+
+// Workgroups of a record kernel: enough for `groups` pixel groups, at most
+// kGenRounds times the workgroups the device holds at once.
+constexpr int kGenRounds = 4;
+
+template <typename K>
+int gen_grid(int64_t groups, K kernel, size_t lds, const char* what) {
+    const int res = resident_grid(kernel, kThreads, lds, what);
+    if (res <= 0) return 0;
+    const int64_t want = ceil_div(groups, kThreads / kWave);
+    return int(std::max<int64_t>(1, std::min<int64_t>(want, int64_t(kGenRounds) * res)));
 }
 
 GenArgs make_args(const hc_path_gen& g) {
@@ -261,9 +281,9 @@ hc_status launch_gen_headers(const hc_path_gen& g, uint32_t* hdr, uint32_t* pix_
     const int64_t nb = ceil_div(g.n_pixels, kScanTile);
     if (g.n_pixels > 0) {
         const Seg sg = seg_of(g.spp);
-        const int64_t waves = ceil_div(g.n_pixels, sg.pw);
-        hipLaunchKernelGGL(gen_headers_kernel, dim3(uint32_t(ceil_div(waves, kThreads / kWave))),
-                           dim3(kThreads), 0, st, a, sg, hdr, pix_first);
+        const int grid = gen_grid(ceil_div(g.n_pixels, sg.pw), gen_headers_kernel, 0, "hc_gen_path_headers");
+        if (grid <= 0) return HC_EDEVICE;
+        hipLaunchKernelGGL(gen_headers_kernel, dim3(grid), dim3(kThreads), 0, st, a, sg, hdr, pix_first);
         hc_status s = launch_status("hc_gen_path_headers");
         if (s != HC_OK) return s;
         hipLaunchKernelGGL(scan_reduce_kernel, dim3(uint32_t(nb)), dim3(kThreads), 0, st, pix_first,
@@ -285,9 +305,10 @@ hc_status launch_gen_vertices(const hc_path_gen& g, const uint32_t* pix_first, u
     const GenArgs a = make_args(g);
     if (g.n_pixels == 0) return HC_OK;
     const Seg sg = seg_of(g.spp);
-    const int64_t waves = ceil_div(g.n_pixels, sg.pw);
-    hipLaunchKernelGGL(gen_vertices_kernel, dim3(uint32_t(ceil_div(waves, kThreads / kWave))),
-                       dim3(kThreads), 0, st, a, sg, pix_first, vtx, uint64_t(n_vertices));
+    const int grid = gen_grid(ceil_div(g.n_pixels, sg.pw), gen_vertices_kernel, 0, "hc_gen_path_vertices");
+    if (grid <= 0) return HC_EDEVICE;
+    hipLaunchKernelGGL(gen_vertices_kernel, dim3(grid), dim3(kThreads), 0, st, a, sg, pix_first, vtx,
+                       uint64_t(n_vertices));
     return launch_status("hc_gen_path_vertices");
 }
 
