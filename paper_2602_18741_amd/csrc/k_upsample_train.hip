@@ -96,6 +96,7 @@ __device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
 // of 4 rows, 16 rows 32 apart, 16 rows of 4 samples) fall on distinct banks.
 __device__ __forceinline__ int act(int r, int s) { return r * kAS + (r >> 5) * 16 + s; }
 constexpr int kActSize = kH * kAS + (kH / 32) * 16;
+static_assert(kPWaves * 8 * kRS <= 4 * kActSize, "W2 staging slices fit in P1..H2");
 
 struct Lds {
     float *W3, *W1, *B2, *B3, *M, *X, *P1, *H1, *P2, *H2, *Z, *G, *ZP, *S;
@@ -174,10 +175,27 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
         a.draw ? a.draw_ctr0 + (a.draw_scale ? uint64_t(*a.draw_scale) * uint64_t(a.N) : 0ull) : 0ull;
     const int64_t tiles = (a.N + kTS - 1) / kTS;
 
-    // Loads are issued oldest-first in the order their values are needed:
-    // the parameters staged in LDS, the first tile's inputs, then the W2
-    // fragments (not read before layer 2), so that waiting for the first two
-    // leaves the 64 fragment loads in flight.
+    // Loads are issued in this order: W2 (most of the bytes), the parameters
+    // staged in LDS, then the first tile's inputs, whose row indices wait for
+    // the step counter's load.  Each wave holds W2 fragments for the whole
+    // kernel, K index 32 g + st: the forward A operand W2[jrow + n][32 g + st]
+    // in wf and the backward one W2[32 g + st][jrow + n] in wb.  A lane's wf
+    // values are 32 consecutive floats of one row, but the lanes of a load
+    // would span 64 rows and chunks; so (parameters 16-byte aligned) the
+    // wave's 16 rows are loaded whole, 1 KB per load, and handed to the lanes
+    // through the wave's own slice of the activation arrays below.
+    const bool al16 = (reinterpret_cast<uintptr_t>(P) & 15) == 0;
+    float wf[32], wb[32];
+    float4 rows4[8];   // rows jrow + 2u and jrow + 2u + 1 of W2, 4 floats a lane
+    if (al16) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rows4[u] = ld4(P + kOffW2 + (jrow + 2 * u) * kH + 4 * lane);
+    } else {
+#pragma unroll
+        for (int st = 0; st < 32; ++st) wf[st] = ldg_f32(P + kOffW2 + (jrow + n) * kH + 32 * g + st);
+    }
+#pragma unroll
+    for (int st = 0; st < 32; ++st) wb[st] = ldg_f32(P + kOffW2 + (32 * g + st) * kH + jrow + n);
     constexpr int kW3Per = (kMaxK * kH + kPThreads - 1) / kPThreads;
     float w3v[kW3Per];
 #pragma unroll
@@ -242,27 +260,29 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
         }
     };
     fetch_inputs(blockIdx.x);
-    // the wave's W2 fragments for the whole kernel, K index 32 g + st: the
-    // forward A operand W2[jrow + n][32 g + st] and the backward one
-    // W2[32 g + st][jrow + n]
-    // (the forward ones are 32 consecutive floats of a row: eight 16-byte
-    // loads when the parameters are 16-byte aligned)
-    float wf[32], wb[32];
-    if ((reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+    if (al16) {
+        // wf from the staged rows, 8 rows a pass, in the wave's own 8 x kRS
+        // floats of P1..H2 (not in use before the first tile's layer 1; the
+        // wave's LDS accesses complete in order, so pass 1 may overwrite
+        // what pass 0 read)
+        float* stg = L.P1 + w * (8 * kRS);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float4 v = ld4(P + kOffW2 + (jrow + n) * kH + 32 * g + 4 * q);
-            wf[4 * q] = v.x;
-            wf[4 * q + 1] = v.y;
-            wf[4 * q + 2] = v.z;
-            wf[4 * q + 3] = v.w;
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                *reinterpret_cast<float4*>(stg + (2 * u + lane / 32) * kRS + 4 * (lane % 32)) = rows4[4 * h + u];
+            if ((n >> 3) == h) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float4 v = *reinterpret_cast<const float4*>(stg + (n - 8 * h) * kRS + 32 * g + 4 * q);
+                    wf[4 * q] = v.x;
+                    wf[4 * q + 1] = v.y;
+                    wf[4 * q + 2] = v.z;
+                    wf[4 * q + 3] = v.w;
+                }
+            }
         }
-    } else {
-#pragma unroll
-        for (int st = 0; st < 32; ++st) wf[st] = ldg_f32(P + kOffW2 + (jrow + n) * kH + 32 * g + st);
     }
-#pragma unroll
-    for (int st = 0; st < 32; ++st) wb[st] = ldg_f32(P + kOffW2 + (32 * g + st) * kH + jrow + n);
 #pragma unroll
     for (int u = 0; u < kW3Per; ++u) {
         const int e = tid + u * kPThreads;
@@ -349,46 +369,48 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
             L.Z[c * kAS + i] = v + L.B3[c];
         }
         __syncthreads();
-        // ---- per-sample loss terms and the colour gradient (one lane per sample)
-        if (tid < kTS) {
-            const int i = tid;
+        // ---- per-sample loss terms and the colour gradient: lanes i, i + 16 and
+        // i + 32 of wavefront 0 take sample i's X, Y and Z (and its CIELAB f),
+        // exchange the three f values, and each forms the rest of the sample's
+        // terms; the lane of X also sums the code terms
+        if (tid < 3 * kTS) {
+            const int i = tid % kTS, x = tid / kTS;
             const bool valid = tile * kTS + i < a.N;
-            float mse = 0.f, amax = -1.f;
-            int cs = 0;
-            float X[3] = {0.f, 0.f, 0.f}, Xg[3] = {0.f, 0.f, 0.f};
+            const float wh = x == 0 ? a.wx : (x == 1 ? a.wy : a.wz);
+            float Xx = 0.f, Xgx = 0.f;
             for (int c = 0; c < k; ++c) {
-                const float z = L.Z[c * kAS + i], gt = L.G[c * kAS + i];
-                const float d = z - gt;
-                mse = fmaf(d, d, mse);
-                if (fabsf(d) > amax) {      // the first channel of largest |d|
-                    amax = fabsf(d);
-                    cs = c;
-                }
-#pragma unroll
-                for (int x = 0; x < 3; ++x) {
-                    X[x] = fmaf(L.M[x * kMaxK + c], z, X[x]);
-                    Xg[x] = fmaf(L.M[x * kMaxK + c], gt, Xg[x]);
-                }
+                Xx = fmaf(L.M[x * kMaxK + c], L.Z[c * kAS + i], Xx);
+                Xgx = fmaf(L.M[x * kMaxK + c], L.G[c * kAS + i], Xgx);
             }
-            const float wh[3] = {a.wx, a.wy, a.wz};
-            float f[3], fp[3], fg[3], unused;
-#pragma unroll
-            for (int x = 0; x < 3; ++x) {
-                lab_f(X[x] / wh[x], f[x], fp[x]);
-                lab_f(Xg[x] / wh[x], fg[x], unused);
-            }
-            const float dL = 116.f * (f[1] - fg[1]);
-            const float da = 500.f * ((f[0] - f[1]) - (fg[0] - fg[1]));
-            const float db = 200.f * ((f[1] - f[2]) - (fg[1] - fg[2]));
+            float f, fp, fg, unused;
+            lab_f(Xx / wh, f, fp);
+            lab_f(Xgx / wh, fg, unused);
+            const float f0 = __shfl(f, i, kWave), f1 = __shfl(f, i + kTS, kWave), f2 = __shfl(f, i + 2 * kTS, kWave);
+            const float g0 = __shfl(fg, i, kWave), g1 = __shfl(fg, i + kTS, kWave),
+                        g2 = __shfl(fg, i + 2 * kTS, kWave);
+            const float dL = 116.f * (f1 - g1);
+            const float da = 500.f * ((f0 - f1) - (g0 - g1));
+            const float db = 200.f * ((f1 - f2) - (g1 - g2));
             const float de = sqrtf(dL * dL + da * da + db * db);
             const float inv = de > 0.f ? 1.f / de : 0.f;
             const float uL = dL * inv, ua = da * inv, ub = db * inv;
             // gradient of DeltaE76 with respect to the predicted XYZ
-            L.S[i] = valid ? __int_as_float(cs) : __int_as_float(-1);
-            L.S[kTS + i] = 500.f * ua * fp[0] / wh[0];
-            L.S[2 * kTS + i] = (116.f * uL - 500.f * ua + 200.f * ub) * fp[1] / wh[1];
-            L.S[3 * kTS + i] = -200.f * ub * fp[2] / wh[2];
-            if (valid) loss += double(mse) / k + double(a.w_max) * amax + double(a.w_col) * de;
+            const float gx = x == 0 ? 500.f * ua : (x == 1 ? 116.f * uL - 500.f * ua + 200.f * ub : -200.f * ub);
+            L.S[(1 + x) * kTS + i] = gx * fp / wh;
+            if (x == 0) {
+                float mse = 0.f, amax = -1.f;
+                int cs = 0;
+                for (int c = 0; c < k; ++c) {
+                    const float d = L.Z[c * kAS + i] - L.G[c * kAS + i];
+                    mse = fmaf(d, d, mse);
+                    if (fabsf(d) > amax) {      // the first channel of largest |d|
+                        amax = fabsf(d);
+                        cs = c;
+                    }
+                }
+                L.S[i] = valid ? __int_as_float(cs) : __int_as_float(-1);
+                if (valid) loss += double(mse) / k + double(a.w_max) * amax + double(a.w_col) * de;
+            }
         }
         __syncthreads();
         // ---- dL/dz (one thread per channel and sample), in place of the target
@@ -463,6 +485,15 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
             acc1 = mfma4(L.P1[act(jrow + n, 4 * st + g)], n < 4 ? L.X[4 * (4 * st + g) + n] : 0.f, acc1);
         __syncthreads();
     }
+    // workgroup loss: the per-sample lanes 0..15, in order (before the row's stores,
+    // so that no barrier waits for them)
+    if (tid < kTS) L.loss[tid] = loss;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kTS; ++i) t += L.loss[i];
+        a.loss_part[blockIdx.x] = t;
+    }
     // ---- partial row, with non-temporal stores (read once, by kernel 2)
     float* prow = a.part + int64_t(blockIdx.x) * param_count(k);
 #pragma unroll
@@ -485,14 +516,6 @@ __global__ __launch_bounds__(kPThreads) void ustrain_partials_kernel(TrainArgs a
     }
     if (tid < kH) __builtin_nontemporal_store(aB2, &prow[kOffB2 + tid]);
     if (tid < k) __builtin_nontemporal_store(aB3, &prow[off_b3(k) + tid]);
-    // workgroup loss: the per-sample lanes 0..15, in order
-    if (tid < kTS) L.loss[tid] = loss;
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kTS; ++i) t += L.loss[i];
-        a.loss_part[blockIdx.x] = t;
-    }
 }
 
 struct ReduceArgs {
@@ -508,12 +531,18 @@ struct ReduceArgs {
 };
 
 // Sum of x[0 .. count) by the calling workgroup, in a fixed order: thread t
-// adds x[t], x[t + 256], ..., then a butterfly inside each wavefront, then
-// the wavefronts in order.  The result is valid in thread 0.
-__device__ double block_sum(const double* x, int count) {
-    __shared__ double s_w[kThreads / kWave];
+// adds x[t], x[t + 256], ... (thread_terms, issued early so that its loads
+// overlap the kernel's other loads), then block_sum adds those with a
+// butterfly inside each wavefront, then the wavefronts in order.  The result
+// is valid in thread 0.
+__device__ __forceinline__ double thread_terms(const double* x, int count) {
     double v = 0.0;
     for (int i = threadIdx.x; i < count; i += kThreads) v += x[i];
+    return v;
+}
+
+__device__ double block_sum(double v) {
+    __shared__ double s_w[kThreads / kWave];
     for (int m = kWave / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = v;
     __syncthreads();
@@ -535,6 +564,9 @@ __global__ __launch_bounds__(kThreads) void ustrain_reduce_kernel(ReduceArgs a) 
     const int per = (a.rows + kRedQuarters - 1) / kRedQuarters;
     const int r0 = min(a.rows, q * per), r1 = min(a.rows, r0 + per);
     __shared__ double s_part[kRedQuarters][kRedParams];
+    // block 0's share of the loss sum and the step counter, read first
+    const double loss_terms = blockIdx.x == 0 ? thread_terms(a.loss_part, a.rows) : 0.0;
+    const int64_t step0 = blockIdx.x == 0 && a.step ? *a.step : 0;
     double part = 0.0;
     if (e < a.P) {
         // sixteen interleaved partial sums keep sixteen row loads in flight
@@ -574,11 +606,11 @@ __global__ __launch_bounds__(kThreads) void ustrain_reduce_kernel(ReduceArgs a) 
         if (lane == 0) a.sq_part[blockIdx.x] = sq;
     }
     if (blockIdx.x == 0) {
-        const double l = block_sum(a.loss_part, a.rows);
+        const double l = block_sum(loss_terms);
         if (threadIdx.x == 0) {
             *a.loss = float(l / double(a.N));
             if (a.step) {
-                const int64_t t1 = *a.step + 1;
+                const int64_t t1 = step0 + 1;
                 *a.ws_step = t1;
                 *a.step = t1;
             }
@@ -601,24 +633,35 @@ struct AdamWArgs {
 
 __global__ __launch_bounds__(kThreads) void ustrain_adamw_kernel(AdamWArgs a) {
     __shared__ double s_c[3];
+    // the parameter's operands and the step counter are loaded with the
+    // block sums, in one round of loads
+    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const bool live = e < a.P;
+    float g0 = 0.f, w0 = 0.f, m0 = 0.f, v0 = 0.f;
+    if (live) {
+        g0 = a.grad[e];
+        w0 = a.params[e];
+        m0 = a.m[e];
+        v0 = a.v[e];
+    }
+    const int64_t step = *a.ws_step;
     // every block forms the same norm from the block sums, and the step's
     // bias corrections (beta^t = exp(t ln beta), ln beta from the host)
-    const double t2 = block_sum(a.sq_part, a.nsq);
+    const double t2 = block_sum(thread_terms(a.sq_part, a.nsq));
     if (threadIdx.x == 0) {
         const double norm = sqrt(t2);
         const double c = a.max_norm / (norm + 1e-6);
-        const double t = double(*a.ws_step);
+        const double t = double(step);
         s_c[0] = c < 1.0 ? c : 1.0;
         s_c[1] = a.lr / (1.0 - exp(t * a.ln_beta1));
         s_c[2] = 1.0 / sqrt(1.0 - exp(t * a.ln_beta2));
     }
     __syncthreads();
-    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (e >= a.P) return;
-    const double g = double(a.grad[e]) * s_c[0];
-    const double w = double(a.params[e]) * (1.0 - a.lr * a.wd);
-    const double mm = a.beta1 * double(a.m[e]) + (1.0 - a.beta1) * g;
-    const double vv = a.beta2 * double(a.v[e]) + (1.0 - a.beta2) * g * g;
+    if (!live) return;
+    const double g = double(g0) * s_c[0];
+    const double w = double(w0) * (1.0 - a.lr * a.wd);
+    const double mm = a.beta1 * double(m0) + (1.0 - a.beta1) * g;
+    const double vv = a.beta2 * double(v0) + (1.0 - a.beta2) * g * g;
     a.m[e] = float(mm);
     a.v[e] = float(vv);
     a.params[e] = float(w - s_c[1] * mm / (sqrt(vv) * s_c[2] + a.eps));
