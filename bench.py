@@ -548,6 +548,70 @@ MFMA_F16_PEAK_TFS = 2500.0
 MFMA_F32_PEAK_TFS = 157.3
 
 
+ENGINE_CLOCK_GHZ = 2.4     # peak engine clock
+SIMDS = 256 * 4            # 256 compute units of 4 SIMDs
+
+
+def alu_issue_rates(dev, grid: int = 2048) -> dict:
+    """Cycles per wavefront instruction per SIMD, at the peak engine clock,
+    of each kind of the issue-rate probe (hc_alu_probe) with 8 wavefronts per
+    SIMD: the cost of the activation's exponential and reciprocal, in fp32
+    and fp16, against a multiply-add."""
+    import torch
+    from paper_2602_18741_amd import ops
+    out = torch.empty(grid * 256, dtype=torch.float32, device=dev)
+    instr = grid * 4 * ops.ALU_PROBE_CHAINS * ops.ALU_PROBE_ITERS
+    rates = {}
+    for op in ops.ALU_PROBE_OPS:
+        ops.alu_probe(op, out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            ops.alu_probe(op, out)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / reps
+        rates[op] = sec * ENGINE_CLOCK_GHZ * 1e9 * SIMDS / instr
+    return rates
+
+
+def upsample_throughput(net: dict, k: int, dev) -> dict:
+    """The upsampling network on a 4096^2 RGB texture in both precisions
+    (HIP events over 10 back-to-back launches), with the issue rates of the
+    fp16 kernel's instructions (hc_alu_probe)."""
+    import torch
+    from paper_2602_18741_amd import ops
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    rgb_big = torch.rand(UP_SIDE * UP_SIDE, 4, device=dev, generator=g)
+    out = torch.empty(UP_SIDE * UP_SIDE, ops.latent_width(k), device=dev)
+    flop = 2.0 * (3 * 128 + 128 * 128 + 128 * k) * rgb_big.shape[0]
+    timing = {}
+    for prec, peak in (("f16", MFMA_F16_PEAK_TFS), ("f32", MFMA_F32_PEAK_TFS)):
+        for _ in range(2):
+            ops.upsample(net, rgb_big, k, precision=prec, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            ops.upsample(net, rgb_big, k, precision=prec, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tfs = flop / (ms * 1e-3) / 1e12
+        timing[prec] = {"ms": ms, "texels_per_s": rgb_big.shape[0] / (ms * 1e-3), "TFLOP_s": tfs,
+                        "mfma_peak_TFLOP_s": peak, "frac": tfs / peak}
+    log("upsampling 4096^2 texels: " + ", ".join(
+        f"{p} {v['ms']:.3f} ms ({v['TFLOP_s']:.0f} TFLOP/s)" for p, v in timing.items()))
+    # the f16 kernel's time goes mostly to its vector instructions (an
+    # exponential and a reciprocal per activation), not the matrix cores
+    timing["f16"]["alu_issue_cycles"] = alu_issue_rates(dev)
+    log("issue cycles per wavefront instruction: " + ", ".join(
+        f"{op} {c:.2f}" for op, c in timing["f16"]["alu_issue_cycles"].items()))
+    return timing
+
+
 def upsample_leg(args, dev, n, k, T, E, D, refl, illum, P, xyz_s, codes, lcodes, zimg, xyz_l):
     """RGB-to-latent upsampling (Sec. 5): fit the network on the GPU against
     the frozen codec (reflectance pool, AdamW), time it on a 4096^2 RGB
@@ -591,29 +655,7 @@ def upsample_leg(args, dev, n, k, T, E, D, refl, illum, P, xyz_s, codes, lcodes,
                "de76_upsampled_vs_codec": de(xyz_codec, xyz_up),
                "de76_codec_vs_spectral": de(xyz_true, xyz_codec)}
 
-    # throughput on a 4096^2 RGB texture
-    g = torch.Generator(device=dev)
-    g.manual_seed(5)
-    rgb_big = torch.rand(UP_SIDE * UP_SIDE, 4, device=dev, generator=g)
-    out = torch.empty(UP_SIDE * UP_SIDE, ops.latent_width(k), device=dev)
-    flop = 2.0 * (3 * 128 + 128 * 128 + 128 * k) * rgb_big.shape[0]
-    timing = {}
-    for prec, peak in (("f16", MFMA_F16_PEAK_TFS), ("f32", MFMA_F32_PEAK_TFS)):
-        for _ in range(2):
-            ops.upsample(net, rgb_big, k, precision=prec, out=out)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 10
-        e0.record()
-        for _ in range(reps):
-            ops.upsample(net, rgb_big, k, precision=prec, out=out)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        tfs = flop / (ms * 1e-3) / 1e12
-        timing[prec] = {"ms": ms, "texels_per_s": rgb_big.shape[0] / (ms * 1e-3), "TFLOP_s": tfs,
-                        "mfma_peak_TFLOP_s": peak, "frac": tfs / peak}
-    log("upsampling 4096^2 texels: " + ", ".join(
-        f"{p} {v['ms']:.3f} ms ({v['TFLOP_s']:.0f} TFLOP/s)" for p, v in timing.items()))
+    timing = upsample_throughput(net, k, dev)
 
     # the frame shaded with upsampled texture codes
     rgb_tex, _ = training_pairs(E, T, refl, n)
@@ -663,11 +705,12 @@ def main():
                          "[, requests] -> traffic record of the latent shading kernel")
     ap.add_argument("--stress", action="store_true",
                     help="the 4K / 64 spp / n=81 / k=9 stress frame instead of the default frame")
-    ap.add_argument("--only", choices=["latent", "spectral", "copy", "codec", "gather"],
+    ap.add_argument("--only", choices=["latent", "spectral", "copy", "codec", "gather", "upsample"],
                     help="run only the timed steps of one form (or a 1 GiB device copy, or "
                          "--codec-steps graph-replayed codec steps of each objective, or the "
-                         "random-gather probe over the frame's records and code table), for "
-                         "profilers; prints no JSON")
+                         "random-gather probe over the frame's records and code table, or the "
+                         "upsampling network's 4096^2 launches with random-init weights and the "
+                         "issue-rate probe), for profilers; prints no JSON")
     args = ap.parse_args()
     import synth
     if args.codec_steps is None:
@@ -690,6 +733,14 @@ def main():
 
     if args.only == "codec":
         codec_only(args)
+        return
+    if args.only == "upsample":
+        import torch
+        from paper_2602_18741_amd import ops
+        from paper_2602_18741_amd.upsample_fit import default_init
+        params = torch.from_numpy(default_init(args.k, 0)).to("cuda:0")
+        net = {name: v.contiguous() for name, v in ops.unpack_mlp(params, args.k).items()}
+        upsample_throughput(net, args.k, torch.device("cuda:0"))
         return
     if args.only == "copy":
         import torch

@@ -570,6 +570,24 @@ hc_status hc_gather_probe(const uint32_t* vtx, int64_t n_vertices, const float* 
  */
 hc_status hc_stream_probe(const float* src, float* dst, int64_t n16, int32_t mode, int32_t grid, void* stream);
 
+/*
+ * Issue-rate probe (measurement, not part of the method): the cost of single
+ * vector instructions, the reference for a kernel bound by its arithmetic
+ * issue (the upsampling network's activation: an exponential and a
+ * reciprocal per value).  Each of the grid * 256 lanes runs
+ * HC_ALU_PROBE_CHAINS independent chains of HC_ALU_PROBE_ITERS applications
+ * of one instruction, then writes the sum of its chains to out[lane] (out
+ * holds grid * 256 floats, 4-byte aligned; the values carry no meaning).
+ *   op  0 fp32 multiply-add, 1 v_exp_f32, 2 v_rcp_f32, 3 v_exp_f16,
+ *       4 v_rcp_f16, 5 packed fp16 multiply-add (two values an instruction);
+ *   grid  workgroups of 256 lanes (4 wavefronts), [1, 2^20].
+ * Time the launch on the stream: cycles per wavefront instruction per SIMD =
+ * seconds * clock * SIMDs / (grid * 4 * chains * iters).
+ */
+#define HC_ALU_PROBE_CHAINS 8
+#define HC_ALU_PROBE_ITERS 2048
+hc_status hc_alu_probe(int32_t op, float* out, int32_t grid, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

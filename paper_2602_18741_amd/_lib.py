@@ -136,6 +136,7 @@ _PROTOS = {
     "hc_gen_indices": (i32, [u64, u64, vp, i64, i64, vp, vp]),
     "hc_gather_probe": (i32, [vp, i64, vp, i64, i64, i32, i32, i32, i32, vp, vp]),
     "hc_stream_probe": (i32, [vp, vp, i64, i32, i32, vp]),
+    "hc_alu_probe": (i32, [i32, vp, i32, vp]),
 }
 
 _lib = None

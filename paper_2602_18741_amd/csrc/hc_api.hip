@@ -28,6 +28,10 @@ hc_status launch_status(const char* what) {
     return HC_OK;
 }
 
+// the issue-rate probe (k_probe.hip); a measurement only, so declared here
+// rather than with the path's launchers
+hc_status launch_alu_probe(int op, float* out, int grid, hipStream_t st);
+
 }  // namespace hc
 
 using namespace hc;
@@ -570,6 +574,16 @@ hc_status hc_stream_probe(const float* src, float* dst, int64_t n16, int32_t mod
                "%s: src needs 16-byte alignment, dst 4 (read) or 16 (copy)", fn);
     if (mode == 1 && n16 == 0) return HC_OK;
     return launch_stream_probe(src, dst, uint64_t(n16), mode, grid, as_stream(stream));
+}
+
+hc_status hc_alu_probe(int32_t op, float* out, int32_t grid, void* stream) {
+    clear_error();
+    const char* fn = "hc_alu_probe";
+    HC_REQUIRE(op >= 0 && op <= 5, HC_EINVAL, "%s: op must be in [0, 5], got %d", fn, op);
+    HC_REQUIRE(grid >= 1 && grid <= (1 << 20), HC_ESHAPE, "%s: grid outside [1, 2^20]", fn);
+    HC_REQUIRE(out != nullptr, HC_EINVAL, "%s: NULL pointer", fn);
+    HC_REQUIRE(aligned4(out), HC_EALIGN, "%s: out needs 4-byte alignment", fn);
+    return hc::launch_alu_probe(op, out, grid, as_stream(stream));
 }
 
 }  // extern "C"

@@ -1,6 +1,8 @@
 // Random-gather probe: the memory system's rate for the texel gathers of a
-// vertex-record stream, with none of the shading arithmetic; and a streaming
-// probe for the device's sequential read and copy bandwidth.
+// vertex-record stream, with none of the shading arithmetic; a streaming
+// probe for the device's sequential read and copy bandwidth; and an issue-rate
+// probe for single vector instructions (the cost of the activation's
+// exponential and reciprocal against a multiply-add, in fp32 and fp16).
 //
 // Both shading forms spend their time gathering one texel row per path
 // vertex at the record's texel index; for uniformly random indices no
@@ -119,6 +121,45 @@ __global__ __launch_bounds__(kProbeBlock) void stream_probe_kernel(const float* 
     if (MODE == 0) stg_f32(dst + uint64_t(blockIdx.x) * kProbeBlock + threadIdx.x, acc);
 }
 
+// Issue-rate probe: each lane runs kAluChains independent chains of
+// kAluIters applications of one instruction (OP 0 fp32 multiply-add, 1
+// v_exp_f32, 2 v_rcp_f32, 3 v_exp_f16, 4 v_rcp_f16, 5 packed fp16
+// multiply-add), so that the SIMD issues them back to back; the chains' final
+// values are summed and written once per lane (no work is dead).  The values
+// themselves run to 0 / 1 / inf and do not matter: these instructions take
+// the same time for any operand.
+constexpr int kAluChains = 8, kAluIters = 2048;   // 16,384 instructions per lane
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+template <int OP>
+__global__ __launch_bounds__(kProbeBlock) void alu_probe_kernel(float* __restrict__ out) {
+    float x[kAluChains];
+    _Float16 h[kAluChains];
+    h2v p[kAluChains];
+#pragma unroll
+    for (int i = 0; i < kAluChains; ++i) {
+        x[i] = float(threadIdx.x + i) * 1e-3f;
+        h[i] = _Float16(x[i]);
+        p[i] = h2v{h[i], _Float16(0.5f * x[i])};
+    }
+    const h2v pa = {_Float16(0.999f), _Float16(0.999f)}, pb = {_Float16(1e-3f), _Float16(1e-3f)};
+    for (int it = 0; it < kAluIters; ++it) {
+#pragma unroll
+        for (int i = 0; i < kAluChains; ++i) {
+            if constexpr (OP == 0) x[i] = __builtin_fmaf(x[i], 0.999f, 1e-3f);
+            if constexpr (OP == 1) x[i] = __builtin_amdgcn_exp2f(x[i]);
+            if constexpr (OP == 2) x[i] = __builtin_amdgcn_rcpf(x[i]);
+            if constexpr (OP == 3) h[i] = __builtin_exp2f16(h[i]);
+            if constexpr (OP == 4) h[i] = __builtin_amdgcn_rcph(h[i]);
+            if constexpr (OP == 5) p[i] = p[i] * pa + pb;
+        }
+    }
+    float sum = 0.f;
+#pragma unroll
+    for (int i = 0; i < kAluChains; ++i) sum += x[i] + float(h[i]) + float(p[i].x) + float(p[i].y);
+    stg_f32(out + uint64_t(blockIdx.x) * kProbeBlock + threadIdx.x, sum);
+}
+
 }  // namespace
 
 hc_status launch_stream_probe(const float* src, float* dst, uint64_t n16, int mode, int grid, hipStream_t st) {
@@ -147,6 +188,18 @@ hc_status launch_gather_probe(const uint2* vtx, uint32_t nv, const float* table,
         case 3: return by_unroll<8, 3>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
         default: return by_unroll<8, 4>(unroll, vtx, nv, table, n_rows, ld, chunks, out, grid, st);
     }
+}
+
+hc_status launch_alu_probe(int op, float* out, int grid, hipStream_t st) {
+    switch (op) {
+        case 0: hipLaunchKernelGGL(alu_probe_kernel<0>, dim3(grid), dim3(kProbeBlock), 0, st, out); break;
+        case 1: hipLaunchKernelGGL(alu_probe_kernel<1>, dim3(grid), dim3(kProbeBlock), 0, st, out); break;
+        case 2: hipLaunchKernelGGL(alu_probe_kernel<2>, dim3(grid), dim3(kProbeBlock), 0, st, out); break;
+        case 3: hipLaunchKernelGGL(alu_probe_kernel<3>, dim3(grid), dim3(kProbeBlock), 0, st, out); break;
+        case 4: hipLaunchKernelGGL(alu_probe_kernel<4>, dim3(grid), dim3(kProbeBlock), 0, st, out); break;
+        default: hipLaunchKernelGGL(alu_probe_kernel<5>, dim3(grid), dim3(kProbeBlock), 0, st, out); break;
+    }
+    return launch_status("hc_alu_probe");
 }
 
 }  // namespace hc

@@ -416,6 +416,22 @@ def stream_probe(src: torch.Tensor, dst: torch.Tensor, mode: str = "read", grid:
     return dst
 
 
+ALU_PROBE_OPS = ("fma_f32", "exp_f32", "rcp_f32", "exp_f16", "rcp_f16", "pk_fma_f16")
+ALU_PROBE_CHAINS, ALU_PROBE_ITERS = 8, 2048   # per lane (HC_ALU_PROBE_CHAINS, HC_ALU_PROBE_ITERS)
+
+
+def alu_probe(op: str, out: torch.Tensor) -> torch.Tensor:
+    """Issue-rate probe (see hc_alu_probe): each of the out.numel() lanes
+    (a multiple of 256) issues ALU_PROBE_CHAINS * ALU_PROBE_ITERS
+    instructions of kind op (one of ALU_PROBE_OPS) and writes one float."""
+    _dev(out)
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() % 256 or out.numel() == 0:
+        raise ValueError("alu_probe: out must be contiguous float32 with a positive multiple of 256 elements")
+    check(load().hc_alu_probe(ALU_PROBE_OPS.index(op), _ptr(out), out.numel() // 256, _stream()),
+          "hc_alu_probe")
+    return out
+
+
 def gather_probe(vtx: torch.Tensor, table: torch.Tensor, row_floats: int, unroll: int = 4,
                  lanes_per_row: int = 1, grid: int = 2048, out: torch.Tensor | None = None) -> torch.Tensor:
     """Random-gather probe over a record stream (see hc_gather_probe): the

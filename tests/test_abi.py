@@ -264,6 +264,19 @@ def test_stream_probe_rejects_bad_arguments(lib):
     assert lib.hc_stream_probe(None, p, 0, 1, 4, None) == _lib.HC_OK
 
 
+def test_alu_probe_rejects_bad_arguments(lib):
+    p = C.c_void_p(0x1000)
+    for op in (-1, 6):
+        s, msg = _err(lib.hc_alu_probe(op, p, 4, None))
+        assert s == _lib.HC_EINVAL and "op" in msg
+    s, msg = _err(lib.hc_alu_probe(0, p, 0, None))
+    assert s == _lib.HC_ESHAPE and "grid" in msg
+    s, msg = _err(lib.hc_alu_probe(0, None, 4, None))
+    assert s == _lib.HC_EINVAL
+    s, msg = _err(lib.hc_alu_probe(0, C.c_void_p(0x1002), 4, None))
+    assert s == _lib.HC_EALIGN
+
+
 def test_fused_latent_frame_and_decode_matrix_validate(lib):
     P = _lib.Paths(10, 4, 0, 0x1000, 0x1000, 0x1000, 5)
     L = _lib.LatentAssets(0x1000, 4, 6, 0, 8, 0x1000, 2, 0, 8)

@@ -54,3 +54,29 @@ def test_stream_probe_reads_and_copies_everything(gpu, grid):
     dst = torch.full_like(src, -1.0)
     ops.stream_probe(src, dst, "copy", grid)
     assert torch.equal(dst, src)
+
+
+def test_alu_probe_fma_chains_and_every_lane(gpu):
+    """Issue-rate probe: the multiply-add kind leaves each lane the sum of its
+    8 chains x <- 0.999 x + 0.001 (2048 steps from x0 = (lane + i) / 1000)
+    plus the untouched fp16 seeds, as the host computes them; every kind
+    writes every lane (no NaN left from the fill)."""
+    from paper_2602_18741_amd import ops
+    grid = 3
+    out = torch.full((grid * 256,), float("nan"), device=gpu)
+    ops.alu_probe("fma_f32", out)
+    lane = np.arange(256, dtype=np.float64)
+    want = np.zeros(256)
+    for i in range(ops.ALU_PROBE_CHAINS):
+        x0 = ((lane + i) * np.float32(1e-3)).astype(np.float32)
+        h = x0.astype(np.float16).astype(np.float64)
+        ph = (np.float32(0.5) * x0).astype(np.float16).astype(np.float64)
+        x = 1.0 - (1.0 - x0.astype(np.float64)) * 0.999 ** ops.ALU_PROBE_ITERS
+        want += x + h + h + ph
+    got = out.double().cpu().numpy().reshape(grid, 256)
+    assert np.abs(got - want).max() <= 1e-3
+    for op in ops.ALU_PROBE_OPS[1:]:
+        out.fill_(float("nan"))
+        ops.alu_probe(op, out)
+        torch.cuda.synchronize()
+        assert not torch.isnan(out).any(), op
