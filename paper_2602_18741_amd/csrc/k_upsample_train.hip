@@ -7,9 +7,10 @@
 //   1. partials: a workgroup (at most 256: one partial row each) takes
 //                tiles of 16 samples; the layer products of the tile, forward
 //                and backward, and the weight gradients summed over its
-//                samples are 16x16x4 fp32 matrix-core products with W2, W3
-//                and the tile's activations in LDS (details at the kernel);
-//                the gradient sums stay in registers across tiles.
+//                samples are 16x16x4 fp32 matrix-core products with W3 and
+//                the tile's activations in LDS and each wavefront's W2
+//                fragments in registers (details at the kernel); the
+//                gradient sums stay in registers across tiles.
 //   2. reduce  : a lane per parameter sums the partial rows in a fixed order
 //                (float64, sixteen row loads in flight), divides by N, writes
 //                the gradient, and each block writes its sum of squares;
