@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kProbeBlock) void stream_probe_kernel(const float* 
 // values are summed and written once per lane (no work is dead).  The values
 // themselves run to 0 / 1 / inf and do not matter: these instructions take
 // the same time for any operand.
-constexpr int kAluChains = 8, kAluIters = 2048;   // 16,384 instructions per lane
+constexpr int kAluChains = HC_ALU_PROBE_CHAINS, kAluIters = HC_ALU_PROBE_ITERS;   // 16,384 instructions a lane
 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 
 template <int OP>

@@ -277,6 +277,21 @@ def test_alu_probe_rejects_bad_arguments(lib):
     assert s == _lib.HC_EALIGN
 
 
+def test_alu_probe_constants_match_the_header():
+    """The binding's chain and iteration counts (which turn the probe's time
+    into cycles per instruction) are the header's, and its op order is the
+    header's list."""
+    import os
+    import re
+    from paper_2602_18741_amd import ops
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hc.h")).read()
+    assert int(re.search(r"#define HC_ALU_PROBE_CHAINS (\d+)", hdr).group(1)) == ops.ALU_PROBE_CHAINS
+    assert int(re.search(r"#define HC_ALU_PROBE_ITERS (\d+)", hdr).group(1)) == ops.ALU_PROBE_ITERS
+    doc = re.search(r"op  0 fp32 multiply-add, 1 v_exp_f32, 2 v_rcp_f32, 3 v_exp_f16,\s+\*\s+4 v_rcp_f16, 5 packed fp16", hdr)
+    assert doc is not None
+    assert ops.ALU_PROBE_OPS == ("fma_f32", "exp_f32", "rcp_f32", "exp_f16", "rcp_f16", "pk_fma_f16")
+
+
 def test_fused_latent_frame_and_decode_matrix_validate(lib):
     P = _lib.Paths(10, 4, 0, 0x1000, 0x1000, 0x1000, 5)
     L = _lib.LatentAssets(0x1000, 4, 6, 0, 8, 0x1000, 2, 0, 8)
